@@ -1,0 +1,310 @@
+"""FP64 CPU oracle for the SMIwiz modelling / imaging path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may import
+this module.  It wraps the plain C stepper in ``smi_oracle.c`` (built with gcc, loaded
+with ctypes) and adds the host-side arithmetic of the method in plain numpy:
+
+  * eq. (5)  CFL number                                    -> :func:`cfl_number`
+  * eq. (6)  L2 misfit and residual adjoint source         -> :func:`misfit`
+  * eq. (7)  kappa gradient, chain rule to Vp (rho fixed)  -> :func:`fwi_grad`
+  * eq. (10) cross-correlation image                       -> :func:`rtm_image`
+  * Alg. 2   forward loop, adjoint source, reverse loop, sum over shots
+
+Positions in metres are turned into padded grid nodes by rounding (on-grid positions only).
+Arrays follow the memory order of the paper's files: n1 = z fastest, i.e. numpy shape
+(n2, n1) in 2D and (n3, n2, n1) in 3D.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "smi_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+class OgGrid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
+                ("d1", C.c_double), ("d2", C.c_double), ("d3", C.c_double),
+                ("nb", C.c_int), ("order", C.c_int), ("nt", C.c_int),
+                ("dt", C.c_double), ("fm", C.c_double), ("vmax", C.c_double),
+                ("pml", C.c_int), ("box", C.c_int), ("margin", C.c_int), ("dr", C.c_int),
+                ("band_p", C.c_int), ("band_v", C.c_int)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, IEEE semantics, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        gp = C.POINTER(OgGrid)
+        L.og_fd_coef.argtypes = [C.c_int, dp]
+        L.og_cpml_profile.argtypes = [gp, C.c_int, C.c_int, dp, dp]
+        L.og_fwd_box.argtypes = [gp, ip, C.c_int, ip, ip]
+        L.og_band_size.argtypes = [gp]
+        L.og_band_size.restype = C.c_size_t
+        L.og_forward.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, C.c_int,
+                                 ip, dp]
+        L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp]
+        L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp]
+        L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+# ------------------------------------------------------------------ grid helpers
+
+def fd_coef(order: int) -> np.ndarray:
+    a = np.zeros(order // 2)
+    if lib().og_fd_coef(order, _d(a)) != 0:
+        raise ValueError("unsupported order")
+    return a
+
+
+def og_grid(g, *, vmax: float, pml: int = 1, box: Optional[int] = None,
+            band_p: int = 0, band_v: int = 0) -> OgGrid:
+    """Build the C grid record from any object with the paper's keywords."""
+    margin = getattr(g, "margin", -1)
+    if margin is None or margin < 0:
+        margin = g.order
+    return OgGrid(g.ndim, g.n1, g.n2, g.n3 if g.ndim == 3 else 1,
+                  float(g.d1), float(g.d2), float(g.d3 if g.ndim == 3 else 1.0),
+                  g.nb, g.order, g.nt, float(g.dt), float(g.fm), float(vmax), int(pml),
+                  int(g.box if box is None else box), int(margin), int(getattr(g, "dr", 1)),
+                  int(band_p), int(band_v))
+
+
+def cfl_number(g, vmax: float) -> float:
+    """Left-hand side of eq. (5): dt Vmax sqrt(sum 1/d^2) sum |a_l| (stable iff <= 1)."""
+    inv = 1.0 / g.d1 ** 2 + 1.0 / g.d2 ** 2 + (1.0 / g.d3 ** 2 if g.ndim == 3 else 0.0)
+    return g.dt * vmax * math.sqrt(inv) * float(np.sum(np.abs(fd_coef(g.order))))
+
+
+def node(g, pos) -> np.ndarray:
+    """Padded node of a position (z, x, y) in metres (nearest node)."""
+    ds = [g.d1, g.d2, g.d3]
+    out = np.zeros(3, np.int32)
+    for a in range(g.ndim):
+        out[a] = g.nb + int(round(float(pos[a]) / ds[a]))
+    return out
+
+
+def shot_nodes(g, acq, s: int):
+    src = node(g, acq.src[s])
+    a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
+    rec = np.zeros((b - a, 3), np.int32)
+    for k in range(b - a):
+        rec[k] = node(g, acq.rec[a + k])
+    return src, np.ascontiguousarray(rec)
+
+
+def cpml_profile(gr: OgGrid, axis: int, half: int):
+    n = [gr.n1, gr.n2, gr.n3][axis] + 2 * gr.nb
+    a = np.zeros(n)
+    b = np.zeros(n)
+    lib().og_cpml_profile(C.byref(gr), axis, half, _d(a), _d(b))
+    return a, b
+
+
+def fwd_box(gr: OgGrid, src: np.ndarray, it: int):
+    lo = np.zeros(3, np.int32)
+    hi = np.zeros(3, np.int32)
+    lib().og_fwd_box(C.byref(gr), _i(src), it, _i(lo), _i(hi))
+    return lo, hi
+
+
+def band_size(gr: OgGrid) -> int:
+    return int(lib().og_band_size(C.byref(gr)))
+
+
+def padded_size(gr: OgGrid) -> int:
+    P = (gr.n1 + 2 * gr.nb) * (gr.n2 + 2 * gr.nb)
+    if gr.ndim == 3:
+        P *= gr.n3 + 2 * gr.nb
+    return P
+
+
+def interior_size(gr: OgGrid) -> int:
+    return gr.n1 * gr.n2 * (gr.n3 if gr.ndim == 3 else 1)
+
+
+# ------------------------------------------------------------------ single-shot drivers
+
+def forward(gr: OgGrid, vp, rho, src, stf, rec, *, init=None, hist=False, bands=False,
+            final=False, snaps: Sequence[int] = ()):
+    """Forward loop of Alg. 2 for one shot.  Returns dict(dcal[nt, nrec], hist, bands,
+    final, snaps)."""
+    vp = np.ascontiguousarray(vp, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    stf = np.ascontiguousarray(stf, np.float64)
+    src = np.ascontiguousarray(src, np.int32)
+    rec = np.ascontiguousarray(np.asarray(rec, np.int32).reshape(-1, 3))
+    nrec = rec.shape[0]
+    P = padded_size(gr)
+    out = {"dcal": np.zeros((gr.nt, nrec))}
+    out["hist"] = np.zeros((gr.nt + 1, 4, P)) if hist else None
+    out["bands"] = np.zeros(((gr.nt + gr.dr - 1) // gr.dr, band_size(gr))) if bands else None
+    out["final"] = np.zeros((4, P)) if final else None
+    snap_it = np.ascontiguousarray(np.asarray(list(snaps), np.int32))
+    out["snaps"] = np.zeros((len(snap_it), interior_size(gr)))
+    init_a = None if init is None else np.ascontiguousarray(init, np.float64)
+    rc = lib().og_forward(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), nrec, _i(rec),
+                          _d(out["dcal"]), _d(init_a), _d(out["hist"]), _d(out["bands"]),
+                          _d(out["final"]), len(snap_it), _i(snap_it) if len(snap_it) else None,
+                          _d(out["snaps"]) if len(snap_it) else None)
+    if rc:
+        raise RuntimeError("og_forward failed: %d" % rc)
+    return out
+
+
+def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int]):
+    vp = np.ascontiguousarray(vp, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    stf = np.ascontiguousarray(stf, np.float64)
+    src = np.ascontiguousarray(src, np.int32)
+    snap_it = np.ascontiguousarray(np.asarray(list(snaps), np.int32))
+    out = np.zeros((len(snap_it), interior_size(gr)))
+    rc = lib().og_reconstruct(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf),
+                              _d(np.ascontiguousarray(bands)), _d(np.ascontiguousarray(final)),
+                              len(snap_it), _i(snap_it), _d(out))
+    if rc:
+        raise RuntimeError("og_reconstruct failed: %d" % rc)
+    return out
+
+
+def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, final=None,
+            want=("gk", "image", "illum")):
+    """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum."""
+    vp = np.ascontiguousarray(vp, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    stf = np.ascontiguousarray(stf, np.float64)
+    src = np.ascontiguousarray(src, np.int32)
+    rec = np.ascontiguousarray(np.asarray(rec, np.int32).reshape(-1, 3))
+    G = np.ascontiguousarray(G, np.float64)
+    I = interior_size(gr)
+    gk = np.zeros(I) if "gk" in want else None
+    im = np.zeros(I) if "image" in want else None
+    il = np.zeros(I) if "illum" in want else None
+    rc = lib().og_adjoint(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
+                          _d(G), _d(None if hist is None else np.ascontiguousarray(hist)),
+                          _d(None if bands is None else np.ascontiguousarray(bands)),
+                          _d(None if final is None else np.ascontiguousarray(final)),
+                          _d(gk), _d(im), _d(il))
+    if rc:
+        raise RuntimeError("og_adjoint failed: %d" % rc)
+    return {"gk": gk, "image": im, "illum": il}
+
+
+def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa):
+    vp = np.ascontiguousarray(vp, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    stf = np.ascontiguousarray(stf, np.float64)
+    src = np.ascontiguousarray(src, np.int32)
+    rec = np.ascontiguousarray(np.asarray(rec, np.int32).reshape(-1, 3))
+    dk = np.ascontiguousarray(dkappa, np.float64).ravel()
+    dd = np.zeros((gr.nt, rec.shape[0]))
+    rc = lib().og_born(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
+                       _d(dk), _d(dd))
+    if rc:
+        raise RuntimeError("og_born failed: %d" % rc)
+    return dd
+
+
+# ------------------------------------------------------------------ multi-shot jobs
+
+def misfit(dcal: np.ndarray, dobs: np.ndarray, dt: float):
+    """eq. (6) with the rectangle rule: J = 1/2 dt sum r^2; adjoint source G = dt r."""
+    r = np.asarray(dcal, np.float64) - np.asarray(dobs, np.float64)
+    return 0.5 * dt * float(np.sum(r * r)), dt * r
+
+
+def model_vmax(job) -> float:
+    return float(job.grid.vpmax) if getattr(job.grid, "vpmax", 0) else float(np.max(job.vp))
+
+
+def forward_job(job, shots=None, vp=None, box=None, pml=1, vmax=None):
+    """Seismograms of every (or the listed) shot: list of [nt, nrec_s] arrays."""
+    vp = job.vp if vp is None else vp
+    vmax = model_vmax(job) if vmax is None else vmax
+    gr = og_grid(job.grid, vmax=vmax, pml=pml, box=box)
+    shots = range(job.acq.nshot) if shots is None else shots
+    out = []
+    for s in shots:
+        src, rec = shot_nodes(job.grid, job.acq, s)
+        out.append(forward(gr, vp, job.rho, src, job.stf[s], rec)["dcal"])
+    return out
+
+
+def fwi_grad(job, dobs, shots=None, vp=None, box=None, vmax=None, use_history=False):
+    """dJ/dVp (rho fixed) summed over shots in order, and J (eq. 6, 7; Alg. 2)."""
+    vp = job.vp if vp is None else vp
+    vmax = model_vmax(job) if vmax is None else vmax
+    gr = og_grid(job.grid, vmax=vmax, box=box)
+    shots = list(range(job.acq.nshot)) if shots is None else list(shots)
+    gk = np.zeros(interior_size(gr))
+    J = 0.0
+    for k, s in enumerate(shots):
+        src, rec = shot_nodes(job.grid, job.acq, s)
+        fw = forward(gr, vp, job.rho, src, job.stf[s], rec, hist=use_history,
+                     bands=not use_history, final=not use_history)
+        Js, G = misfit(fw["dcal"], dobs[k], gr.dt)
+        J += Js
+        r = adjoint(gr, vp, job.rho, src, job.stf[s], rec, G, hist=fw["hist"],
+                    bands=fw["bands"], final=fw["final"], want=("gk",))
+        gk += r["gk"]
+    vp64 = np.asarray(vp, np.float64).ravel()
+    rho64 = np.asarray(job.rho, np.float64).ravel()
+    return (2.0 * rho64 * vp64 * gk).reshape(job.vp.shape), J
+
+
+def rtm_image(job, dobs, shots=None, box=None, vmax=None):
+    """eq. (10): image and source illumination, summed over shots (G = dt dobs)."""
+    vmax = model_vmax(job) if vmax is None else vmax
+    gr = og_grid(job.grid, vmax=vmax, box=box)
+    shots = list(range(job.acq.nshot)) if shots is None else list(shots)
+    I = interior_size(gr)
+    im = np.zeros(I)
+    il = np.zeros(I)
+    for k, s in enumerate(shots):
+        src, rec = shot_nodes(job.grid, job.acq, s)
+        fw = forward(gr, job.vp, job.rho, src, job.stf[s], rec, bands=True, final=True)
+        r = adjoint(gr, job.vp, job.rho, src, job.stf[s], rec, gr.dt * np.asarray(dobs[k]),
+                    bands=fw["bands"], final=fw["final"], want=("image", "illum"))
+        im += r["image"]
+        il += r["illum"]
+    return im.reshape(job.vp.shape), il.reshape(job.vp.shape)

@@ -1,0 +1,455 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test ties one part of the oracle to something other than itself: exact rationals,
+closed-form Green's functions, conserved energy, reciprocity, the adjoint dot product,
+finite differences, exact invertibility of the leap-frog step.  A plausible slip in the
+oracle (a dropped term, a sign, an index shift, a transposed operand) breaks one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2311_02293_amd import inputs as I
+
+
+# ----------------------------------------------------------------------------- helpers
+
+def smooth_random_model(n1, n2, seed, vmin=1800.0, vmax=2600.0, n3=None):
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    shape = (n3, n2, n1) if n3 else (n2, n1)
+    v = gaussian_filter(rng.standard_normal(shape), 3.0, mode="nearest")
+    v = (v - v.min()) / (v.max() - v.min())
+    vp = (vmin + (vmax - vmin) * v).astype(np.float32)
+    r = gaussian_filter(rng.standard_normal(shape), 3.0, mode="nearest")
+    r = (r - r.min()) / (r.max() - r.min())
+    rho = (1000.0 + 1500.0 * r).astype(np.float32)
+    return vp, rho
+
+
+def small_grid(order=8, n1=48, n2=64, nt=300, nb=10, dt=1e-3, fm=15.0, ndim=2, n3=1, d=10.0,
+               box=0, dr=1):
+    return I.Grid(ndim=ndim, n1=n1, n2=n2, n3=n3, d1=d, d2=d, d3=d, nb=nb, order=order, nt=nt,
+                  dt=dt, fm=fm, box=box, dr=dr)
+
+
+def padded_model(vp, rho, nb, ndim):
+    """kappa and beta_a on the padded grid, written out for the energy pin."""
+    pad = [(nb, nb)] * ndim
+    v = np.pad(vp.astype(np.float64), pad, mode="edge")
+    r = np.pad(rho.astype(np.float64), pad, mode="edge")
+    kap = r * v * v
+    bets = []
+    # numpy axis order is (.., x, z): paper axis a -> numpy axis ndim-1-a
+    for a in range(ndim):
+        ax = ndim - 1 - a
+        rn = np.concatenate([np.take(r, range(1, r.shape[ax]), axis=ax),
+                             np.take(r, [r.shape[ax] - 1], axis=ax)], axis=ax)
+        bets.append(2.0 / (r + rn))
+    return kap, bets
+
+
+# ----------------------------------------------------------------------------- P1
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_fd_coefficients_solve_the_exactness_system(oracle, order):
+    """eq. (4): a_l make the staggered difference exact on polynomials of degree <= 2N-1;
+    the oracle's closed form must equal the solution of that linear system, and the stencil
+    must miss the first derivative of x^(2N+1) (order exactly 2N)."""
+    N = order // 2
+    a = oracle.fd_coef(order)
+    # sum_l a_l * 2 ((2l-1)/2)^(2k-1) = delta_{k,1}, k = 1..N  (odd monomials; even ones vanish)
+    A = [[2 * Fraction(2 * l - 1, 2) ** (2 * k - 1) for l in range(1, N + 1)] + [Fraction(k == 1)]
+         for k in range(1, N + 1)]
+    for c in range(N):  # exact Gauss-Jordan elimination over the rationals
+        piv = next(r for r in range(c, N) if A[r][c] != 0)
+        A[c], A[piv] = A[piv], A[c]
+        A[c] = [x / A[c][c] for x in A[c]]
+        for r in range(N):
+            if r != c and A[r][c] != 0:
+                A[r] = [x - A[r][c] * y for x, y in zip(A[r], A[c])]
+    np.testing.assert_allclose(a, [float(A[k][N]) for k in range(N)], rtol=1e-14, atol=0)
+    x0, h = 0.37, 1.0 / N  # f(x) = (x0 + h x)^k keeps every sample below 1
+    for k in range(0, 2 * N + 2):
+        f = lambda x: (x0 + h * x) ** k
+        approx = sum(a[l - 1] * (f((2 * l - 1) / 2.0) - f(-(2 * l - 1) / 2.0)) for l in range(1, N + 1))
+        exact = h * k * x0 ** (k - 1) if k > 0 else 0.0
+        if k <= 2 * N:
+            assert abs(approx - exact) < 1e-13, (k, approx, exact)
+        else:
+            assert abs(approx - exact) > 1e-13 * 1e3, (k, approx, exact)
+
+
+def test_fd_coefficients_known_rationals(oracle):
+    """Fornberg's staggered weights quoted in the literature the paper cites for eq. (4)
+    (fixture tests/golden/fd_coefficients.txt)."""
+    import os
+    known = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "fd_coefficients.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            o, l, num, den = map(int, line.split())
+            known.setdefault(o, []).append(Fraction(num, den))
+    assert sorted(known) == [4, 8]
+    for order, fr in known.items():
+        np.testing.assert_allclose(oracle.fd_coef(order), [float(x) for x in fr], rtol=1e-15)
+    assert abs(np.sum(np.abs(oracle.fd_coef(8))) - 1.2863095238095) < 1e-12
+
+
+# ----------------------------------------------------------------------------- P2
+
+@pytest.mark.parametrize("factor,stable", [(0.99, True), (1.01, False)])
+def test_cfl_bound_is_sharp(oracle, factor, stable):
+    """eq. (5) is the leap-frog stability limit: just below it a random field stays bounded,
+    just above it grows without bound (homogeneous medium, no absorption)."""
+    c, d, order = 2000.0, 10.0, 8
+    g = small_grid(order=order, n1=64, n2=64, nt=400, nb=4, d=d)
+    coef = np.sum(np.abs(oracle.fd_coef(order)))
+    g.dt = factor / (c * math.sqrt(2.0) / d * coef)
+    vp, rho = I.homogeneous(2, 64, d, c)
+    gr = oracle.og_grid(g, vmax=c, pml=0)
+    assert abs(oracle.cfl_number(g, c) - factor) < 1e-12
+    P = oracle.padded_size(gr)
+    rng = np.random.default_rng(7)
+    init = np.zeros((4, P))
+    init[0] = rng.standard_normal(P)
+    src = np.array([36, 36, 0], np.int32)
+    rec = np.array([[20, 20, 0], [36, 50, 0]], np.int32)
+    out = oracle.forward(gr, vp, rho, src, np.zeros(g.nt), rec, init=init)
+    amp = np.max(np.abs(out["dcal"][-50:]))
+    if stable:
+        assert amp < 10.0
+    else:
+        assert amp > 1e6
+
+
+# ----------------------------------------------------------------------------- P3
+
+def test_energy_is_conserved_without_absorption(oracle):
+    """Discrete energy E^n = 1/2 sum p^2/kappa + 1/2 sum_a v_a^{n+1/2} v_a^{n-1/2}/beta_a
+    is invariant for the staggered leap-frog with D- = -(D+)^T (PML off, no source)."""
+    g = small_grid(order=8, n1=40, n2=56, nt=800, nb=6)
+    vp, rho = smooth_random_model(g.n1, g.n2, 11)
+    gr = oracle.og_grid(g, vmax=float(vp.max()), pml=0)
+    kap, bets = padded_model(vp, rho, g.nb, 2)
+    M2, M1 = kap.shape
+    z = np.arange(M1)[None, :] - M1 / 2
+    x = np.arange(M2)[:, None] - M2 / 2
+    init = np.zeros((4, M1 * M2))
+    init[0] = np.exp(-(x * x + z * z) / 8.0).ravel()
+    out = oracle.forward(gr, vp, rho, np.array([20, 20, 0], np.int32), np.zeros(g.nt),
+                         np.array([[20, 30, 0]], np.int32), init=init, hist=True)
+    h = out["hist"]
+    E = []
+    for n in range(g.nt):
+        e = 0.5 * np.sum(h[n, 0] ** 2 / kap.ravel())
+        for a in range(2):
+            e += 0.5 * np.sum(h[n + 1, 1 + a] * h[n, 1 + a] / bets[a].ravel())
+        E.append(e)
+    E = np.array(E)
+    assert np.max(np.abs(E - E[0])) / E[0] < 1e-12
+    # the field really moved
+    assert np.max(np.abs(h[-1, 0] - h[0, 0])) > 0.1
+
+
+# ----------------------------------------------------------------------------- P4
+
+def _green_case(oracle, A, order, dt, window=0.6, n=241, nb=20, c=2000.0, fm=10.0):
+    nt = int(round(window / dt))
+    g = I.Grid(ndim=2, n1=n, n2=n, d1=10.0, d2=10.0, nb=nb, order=order, nt=nt, dt=dt, fm=fm)
+    vp, rho = I.homogeneous(2, n, 10.0, c)
+    gr = oracle.og_grid(g, vmax=c)
+    ctr = nb + n // 2
+    src = np.array([ctr, ctr, 0], np.int32)
+    rec = np.array([[ctr, ctr + 30, 0], [ctr, ctr + 60, 0]], np.int32)
+    out = oracle.forward(gr, vp, rho, src, I.ricker(nt, dt, fm), rec)
+    t = (np.arange(nt) + 1) * dt
+    errs = []
+    for k, r in enumerate([300.0, 600.0]):
+        ref = A.green2d_trace(r, c, t, fm, 1.2 / fm, dt, ntau=20000)
+        errs.append(np.linalg.norm(out["dcal"][:, k] - ref) / np.linalg.norm(ref))
+    return errs
+
+
+def test_green_function_2d_order4(oracle):
+    """Homogeneous 2D medium: seismograms match p = G2 * s' (amplitude, phase, the dt/2
+    source timing and the 1/dV source normalisation all enter)."""
+    from oracle import analytic as A
+    e300, e600 = _green_case(oracle, A, 4, 1e-3)
+    assert e300 <= 5e-3 and e600 <= 1e-2, (e300, e600)
+
+
+def test_green_function_2d_order8_converges_in_dt(oracle):
+    """At order 8 the time discretisation dominates: halving dt cuts the error ~4x."""
+    from oracle import analytic as A
+    e1 = _green_case(oracle, A, 8, 1e-3)[0]
+    e2 = _green_case(oracle, A, 8, 0.5e-3)[0]
+    assert e1 < 1e-2
+    assert 3.5 <= e1 / e2 <= 4.5, (e1, e2)
+
+
+def test_green_function_3d(oracle):
+    """Homogeneous 3D medium: p = s'(t - r/c) / (4 pi c^2 r)."""
+    from oracle import analytic as A
+    c, d, fm, dt, n, nb = 2000.0, 10.0, 15.0, 1e-3, 61, 10
+    nt = 260
+    g = I.Grid(ndim=3, n1=n, n2=n, n3=n, d1=d, d2=d, d3=d, nb=nb, order=8, nt=nt, dt=dt, fm=fm)
+    vp, rho = I.homogeneous(3, n, d, c)
+    gr = oracle.og_grid(g, vmax=c)
+    ctr = nb + n // 2
+    src = np.array([ctr, ctr, ctr], np.int32)
+    rec = np.array([[ctr, ctr + 15, ctr], [ctr + 12, ctr + 12, ctr]], np.int32)
+    out = oracle.forward(gr, vp, rho, src, I.ricker(nt, dt, fm), rec)
+    t = (np.arange(nt) + 1) * dt
+    for k in range(2):
+        r = d * math.sqrt(float(np.sum((rec[k] - src) ** 2)))
+        ref = A.green3d_trace(r, c, t, fm, 1.2 / fm, dt)
+        err = np.linalg.norm(out["dcal"][:, k] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-2, (k, err)
+
+
+# ----------------------------------------------------------------------------- P5
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_reciprocity(oracle, ndim):
+    """Swapping source and receiver: p(x_r; x_s) kappa(x_s) = p(x_s; x_r) kappa(x_r)
+    (heterogeneous medium, no absorption: exact to round-off)."""
+    if ndim == 2:
+        g = small_grid(order=8, n1=40, n2=50, nt=250, nb=6)
+        vp, rho = smooth_random_model(g.n1, g.n2, 5)
+        A_, B_ = np.array([14, 15, 0], np.int32), np.array([35, 44, 0], np.int32)
+    else:
+        g = small_grid(order=4, n1=20, n2=22, n3=24, nt=120, nb=4, ndim=3)
+        vp, rho = smooth_random_model(g.n1, g.n2, 6, n3=g.n3)
+        A_, B_ = np.array([8, 9, 10, 0], np.int32)[:3], np.array([18, 20, 22], np.int32)
+    gr = oracle.og_grid(g, vmax=float(vp.max()), pml=0)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    d_ab = oracle.forward(gr, vp, rho, A_, stf, B_[None])["dcal"][:, 0]
+    d_ba = oracle.forward(gr, vp, rho, B_, stf, A_[None])["dcal"][:, 0]
+    kap = lambda p: (rho.astype(np.float64) * vp.astype(np.float64) ** 2)[
+        tuple(int(p[a]) - g.nb for a in range(ndim))[::-1]]
+    lhs, rhs = d_ab * kap(A_), d_ba * kap(B_)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(lhs))
+    assert np.max(np.abs(lhs)) > 0
+
+
+# ----------------------------------------------------------------------------- P6
+
+def _dot_case(oracle, pml, ndim=2):
+    if ndim == 2:
+        g = small_grid(order=8, n1=40, n2=48, nt=220, nb=8)
+        vp, rho = smooth_random_model(g.n1, g.n2, 3)
+    else:
+        g = small_grid(order=4, n1=18, n2=20, n3=22, nt=90, nb=4, ndim=3)
+        vp, rho = smooth_random_model(g.n1, g.n2, 4, n3=g.n3)
+    gr = oracle.og_grid(g, vmax=float(vp.max()), pml=pml)
+    rng = np.random.default_rng(21)
+    src = np.array([g.nb + 3, g.nb + g.n2 // 3, g.nb + 5 if ndim == 3 else 0], np.int32)
+    rec = np.array([[g.nb + 2, g.nb + j, g.nb + 6 if ndim == 3 else 0] for j in range(1, g.n2 - 1, 3)],
+                   np.int32)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    dk = np.zeros(vp.shape)
+    core = tuple(slice(2, s - 2) for s in vp.shape)
+    dk[core] = rng.standard_normal(dk[core].shape)
+    dk *= float(np.mean(rho * vp.astype(np.float64) ** 2))
+    dd = oracle.born(gr, vp, rho, src, stf, rec, dk)
+    G = rng.standard_normal(dd.shape)
+    fw = oracle.forward(gr, vp, rho, src, stf, rec, hist=True)
+    gk = oracle.adjoint(gr, vp, rho, src, stf, rec, G, hist=fw["hist"], want=("gk",))["gk"]
+    lhs = float(np.sum(dd * G))
+    rhs = float(np.sum(dk.ravel() * gk))
+    return abs(lhs - rhs) / abs(lhs)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_dot_product_adjoint_exact_without_pml(oracle, ndim):
+    """<L dk, d> = <dk, L* d>: the same-solver adjoint (eq. 8) with the kappa gradient of
+    eq. (7) is the exact transpose of the tangent-linear map (no absorption)."""
+    assert _dot_case(oracle, 0, ndim) <= 1e-12
+
+
+def test_dot_product_with_cpml_is_close(oracle):
+    """With CPML the same-solver adjoint is not the exact transpose; the mismatch stays at
+    the level of the PML's residual reflections."""
+    assert _dot_case(oracle, 1) <= 1e-4
+
+
+def test_born_is_the_derivative_of_the_forward_map(oracle):
+    """Central finite differences of the forward map in a kappa direction match og_born."""
+    g = small_grid(order=8, n1=36, n2=44, nt=200, nb=8)
+    vp, rho = smooth_random_model(g.n1, g.n2, 8)
+    gr = oracle.og_grid(g, vmax=3000.0)
+    rng = np.random.default_rng(3)
+    src = np.array([g.nb + 3, g.nb + 20, 0], np.int32)
+    rec = np.array([[g.nb + 2, g.nb + j, 0] for j in range(2, 40, 4)], np.int32)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    kap = rho.astype(np.float64) * vp.astype(np.float64) ** 2
+    dk = np.zeros(vp.shape)
+    dk[3:-3, 3:-3] = rng.standard_normal((g.n2 - 6, g.n1 - 6)) * kap[3:-3, 3:-3]
+    eps = 1e-4
+    vpp = np.sqrt((kap + eps * dk) / rho)
+    vpm = np.sqrt((kap - eps * dk) / rho)
+    dp = oracle.forward(gr, vpp, rho, src, stf, rec)["dcal"]
+    dm = oracle.forward(gr, vpm, rho, src, stf, rec)["dcal"]
+    fd = (dp - dm) / (2 * eps)
+    born = oracle.born(gr, vp, rho, src, stf, rec, dk)
+    assert np.linalg.norm(fd - born) / np.linalg.norm(born) < 1e-6
+
+
+# ----------------------------------------------------------------------------- P7
+
+@pytest.mark.parametrize("box", [0, 1])
+def test_fwi_gradient_matches_finite_differences(oracle, box):
+    """eq. (6)-(8): dJ/dVp from the reverse loop (reconstruction from saved boundaries,
+    CPML on) against central differences of J on 20 random cells."""
+    g = small_grid(order=8, n1=50, n2=70, nt=420, nb=12, fm=15.0, box=box)
+    vp, rho = smooth_random_model(g.n1, g.n2, 9, vmin=1800.0, vmax=2500.0)
+    vtrue = vp.astype(np.float64).copy()
+    vtrue[20:40, 15:30] *= 1.08
+    sx = np.array([15.0, 35.0, 55.0]) * g.d2
+    acq = I._surface_line(sx, 3 * g.d1, np.arange(0, g.n2, 2) * g.d2, 2 * g.d1)
+    stf = np.repeat(I.ricker(g.nt, g.dt, g.fm)[None], 3, 0)
+    job = I.Job(g, vp, rho, acq, stf)
+    vmax = 2800.0
+    dobs = oracle.forward_job(job, vp=vtrue, vmax=vmax)
+    grad, J0 = oracle.fwi_grad(job, dobs, vmax=vmax)
+    grad_h, J1 = oracle.fwi_grad(job, dobs, vmax=vmax, use_history=True)
+    assert abs(J0 - J1) <= 1e-13 * J0
+    # plain definition (stored history) == method (boundary reconstruction)
+    assert np.max(np.abs(grad - grad_h)) <= 1e-10 * np.max(np.abs(grad_h))
+    rng = np.random.default_rng(1003)
+    N = g.order // 2
+    cand = [(ix, iz) for ix in range(2 * N, g.n2 - 2 * N) for iz in range(2 * N, g.n1 - 2 * N)
+            if abs(grad[ix, iz]) >= 0.01 * np.max(np.abs(grad))]
+    pick = rng.choice(len(cand), 20, replace=False)
+
+    def J(v):
+        d = oracle.forward_job(job, vp=v, vmax=vmax)
+        return sum(oracle.misfit(d[s], dobs[s], g.dt)[0] for s in range(3))
+
+    worst = 0.0
+    for k in pick:
+        ix, iz = cand[k]
+        eps = 1e-4 * float(vp[ix, iz])
+        vpl = vp.astype(np.float64).copy()
+        vpl[ix, iz] += eps
+        vmi = vp.astype(np.float64).copy()
+        vmi[ix, iz] -= eps
+        fd = (J(vpl) - J(vmi)) / (2 * eps)
+        worst = max(worst, abs(fd - grad[ix, iz]) / abs(grad[ix, iz]))
+    assert worst <= 1e-4, worst
+
+
+# ----------------------------------------------------------------------------- P8, P9, P10
+
+@pytest.mark.parametrize("ndim,box", [(2, 0), (2, 1), (3, 0), (3, 1)])
+def test_reconstruction_from_saved_boundaries_is_exact(oracle, ndim, box):
+    """Sec. 4.2 with dr = 1: running the step backwards on the interior with the saved
+    bands restored returns the forward wavefield at every level (to round-off)."""
+    if ndim == 2:
+        g = small_grid(order=8, n1=48, n2=60, nt=300, nb=10, box=box)
+        vp, rho = smooth_random_model(g.n1, g.n2, 13)
+        src = np.array([g.nb + 4, g.nb + 25, 0], np.int32)
+    else:
+        g = small_grid(order=8, n1=20, n2=24, n3=22, nt=100, nb=6, ndim=3, box=box)
+        vp, rho = smooth_random_model(g.n1, g.n2, 14, n3=g.n3)
+        src = np.array([g.nb + 3, g.nb + 10, g.nb + 11], np.int32)
+    gr = oracle.og_grid(g, vmax=float(vp.max()))
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    levels = list(range(0, g.nt + 1, 7)) + [g.nt]
+    fw = oracle.forward(gr, vp, rho, src, stf, src[None], bands=True, final=True, snaps=levels)
+    rc = oracle.reconstruct(gr, vp, rho, src, stf, fw["bands"], fw["final"], levels)
+    err = np.max(np.linalg.norm(rc - fw["snaps"], axis=1)) / np.max(np.linalg.norm(fw["snaps"], axis=1))
+    assert err <= 1e-13, err
+
+
+@pytest.mark.parametrize("bp_off,bv_off,exact", [(-1, 0, True), (0, -1, False)])
+def test_minimal_band_width(oracle, bp_off, bv_off, exact):
+    """N-1 planes of p and N of the face-normal v per face are the minimum for exact
+    reconstruction; dropping one v plane breaks it."""
+    g = small_grid(order=8, n1=40, n2=50, nt=250, nb=10)
+    vp, rho = smooth_random_model(g.n1, g.n2, 15)
+    N = g.order // 2
+    gr = oracle.og_grid(g, vmax=float(vp.max()), band_p=N + bp_off, band_v=N + bv_off)
+    src = np.array([g.nb + 4, g.nb + 20, 0], np.int32)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    levels = list(range(0, g.nt + 1, 10))
+    fw = oracle.forward(gr, vp, rho, src, stf, src[None], bands=True, final=True, snaps=levels)
+    rc = oracle.reconstruct(gr, vp, rho, src, stf, fw["bands"], fw["final"], levels)
+    err = np.max(np.linalg.norm(rc - fw["snaps"], axis=1)) / np.max(np.linalg.norm(fw["snaps"], axis=1))
+    if exact:
+        assert err <= 1e-13, err
+    else:
+        assert err >= 1e-6, err
+
+
+def test_computing_box_changes_nothing(oracle):
+    """Sec. 4.1: the evolving box (radius ceil(vmax (it+1) dt / d) + margin around the
+    source) reproduces the full-grid seismograms.  What the box cuts off is the leap-frog's
+    exponentially small numerical precursor: with the default margin 2N it is far below
+    FP32 resolution, with 4N at FP64 round-off, and with no margin it is visible."""
+    g = small_grid(order=8, n1=60, n2=90, nt=400, nb=10)
+    vp, rho = smooth_random_model(g.n1, g.n2, 16)
+    src = np.array([g.nb + 3, g.nb + 30, 0], np.int32)
+    rec = np.array([[g.nb + 2, g.nb + j, 0] for j in range(0, g.n2, 3)], np.int32)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    ref = oracle.forward(oracle.og_grid(g, vmax=float(vp.max()), box=0), vp, rho, src, stf, rec)["dcal"]
+    scale = np.max(np.abs(ref))
+    err = {}
+    for m in (0, g.order, 2 * g.order):
+        g.margin = m
+        on = oracle.forward(oracle.og_grid(g, vmax=float(vp.max()), box=1), vp, rho, src, stf, rec)["dcal"]
+        err[m] = np.max(np.abs(on - ref)) / scale
+    assert err[g.order] <= 1e-10, err
+    assert err[2 * g.order] <= 1e-14, err
+    assert err[0] > 1e3 * err[g.order], err
+    # the box really is smaller than the grid early on
+    lo, hi = oracle.fwd_box(oracle.og_grid(g, vmax=float(vp.max()), box=1), src, 10)
+    assert hi[1] - lo[1] + 1 < g.n2 + 2 * g.nb
+
+
+def test_box_schedule_grows_with_wavefront(oracle):
+    """Sec. 4.1 figure: the box half-width after it+1 steps is ceil(vmax (it+1) dt / d) + margin."""
+    g = small_grid(order=8, n1=200, n2=300, nt=1000, nb=20, box=1)
+    g.margin = 8
+    gr = oracle.og_grid(g, vmax=2000.0, box=1)
+    src = np.array([g.nb + 5, g.nb + 150, 0], np.int32)
+    for it, t in [(49, 0.05), (99, 0.1), (149, 0.15), (199, 0.2)]:
+        lo, hi = oracle.fwd_box(gr, src, it)
+        half = math.ceil(2000.0 * t / g.d2 - 1e-9) + 8
+        assert hi[1] - src[1] == half and src[1] - lo[1] == half
+        hz = math.ceil(2000.0 * t / g.d1 - 1e-9) + 8
+        assert lo[0] == max(0, src[0] - hz)  # clipped at the top of the padded grid
+        assert hi[0] == min(g.n1 + 2 * g.nb - 1, src[0] + hz)
+
+
+# ----------------------------------------------------------------------------- P11
+
+def test_cpml_absorbs(oracle):
+    """Sec. 2.1 (CPML, 20 layers): after two crossing times the energy left is < 1e-3 of
+    its maximum, and near-boundary traces match a much larger domain to 1e-2."""
+    c, n, nb, dt = 2000.0, 121, 20, 1e-3
+    g = I.Grid(ndim=2, n1=n, n2=n, d1=10.0, d2=10.0, nb=nb, order=4, nt=1300, dt=dt, fm=10.0)
+    vp, rho = I.homogeneous(2, n, 10.0, c)
+    gr = oracle.og_grid(g, vmax=c)
+    ctr = nb + n // 2
+    src = np.array([ctr, ctr, 0], np.int32)
+    rec = np.array([[ctr, nb + n - 3, 0], [nb + 2, ctr, 0], [nb + 5, nb + 5, 0]], np.int32)
+    levels = list(range(0, g.nt + 1, 50))
+    out = oracle.forward(gr, vp, rho, src, I.ricker(g.nt, dt, g.fm), rec, snaps=levels)
+    e = np.sum(out["snaps"] ** 2, axis=1)
+    assert e[-1] / e.max() < 1e-3
+    # large domain: same source, receivers at the same offsets, boundary far away
+    n2 = 3 * n
+    gb = I.Grid(ndim=2, n1=n2, n2=n2, d1=10.0, d2=10.0, nb=nb, order=4, nt=700, dt=dt, fm=10.0)
+    vpb, rhob = I.homogeneous(2, n2, 10.0, c)
+    cb = nb + n2 // 2
+    shift = cb - ctr
+    srcb = src + np.array([shift, shift, 0], np.int32)
+    recb = rec + np.array([shift, shift, 0], np.int32)
+    outb = oracle.forward(oracle.og_grid(gb, vmax=c), vpb, rhob, srcb, I.ricker(gb.nt, dt, g.fm), recb)
+    small = out["dcal"][:700]
+    big = outb["dcal"]
+    assert np.max(np.abs(small - big)) / np.max(np.abs(big)) < 1e-2
