@@ -1,0 +1,155 @@
+"""Throughput benchmark of the batched staggered-grid forward modelling on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2D batched forward modelling,
+500 x 1500 cells of 10 m, 10 dipping layers 1500-4500 m/s with a +-5% smoothed random
+perturbation (seeded), Gardner density, order 8, 30 CPML layers, Ricker 15 Hz, dt 0.8 ms,
+nt 4000, 16 shots spread along the surface in one launch, 1500 receivers each, evolving
+computing box on.  One bench "step" = one whole job: smi_forward over all 16 shots and all
+4000 time steps (model preparation, every time step of every shot, every seismogram sample).
+
+Reported: grid-point updates per second (a GPt = one cell of a shot's computing box advanced
+by one time step), p50/p99 of the step time, the plain one-shot-per-launch stepper on the same
+GPU, the fraction of the HBM roofline reached by the forward step kernels, and the FP64 oracle
+timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/s (GPts/s) and % HBM roofline, batched vs plain; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(job, steps: int):
+    """The FP64 oracle on the host cores: one shot, `steps` time steps at full spatial size,
+    computing box off (the plain definition); rate in GPts/s of the same cell-step count."""
+    from oracle import oracle as O
+    import copy
+    g = copy.copy(job.grid)
+    g.nt = steps
+    gr = O.og_grid(g, vmax=float(job.grid.vpmax), box=0)
+    src, rec = O.shot_nodes(g, job.acq, 0)
+    O.lib()
+    t0 = time.perf_counter()
+    O.forward(gr, job.vp, job.rho, src, job.stf[0][:steps], rec)
+    dt = time.perf_counter() - t0
+    cells = O.padded_size(gr) * steps
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": cells / dt / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 shot x {steps} of {job.grid.nt} steps, full padded grid "
+                      f"{g.n1 + 2 * g.nb}x{g.n2 + 2 * g.nb}, FP64, box off; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=4000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not provided "
+                                   "(shots would shard across GPUs with one gradient all-reduce)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2311_02293_amd import binding as B
+    from paper_2311_02293_amd import inputs as I
+
+    job = I.config2(nt=args.nt)
+    job.grid.vpmin = float(job.vp.min())
+    job.grid.vpmax = float(job.vp.max())
+    dev = "cuda:0"
+    vp = torch.from_numpy(job.vp).to(dev)
+    rho = torch.from_numpy(job.rho).to(dev)
+    stf = torch.from_numpy(job.stf).to(dev)
+    ctx = B.Context(0)
+    nrec = int(job.acq.rec_off[-1])
+    dcal = torch.empty(job.grid.nt * nrec, dtype=torch.float32, device=dev)
+    ws = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_FORWARD))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.forward(job.grid, job.acq, vp, rho, stf, dcal=dcal, ws=ws, stream=stream)
+
+    print(f"bench: warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.poll_status()
+    gpts = ctx.last_counts()[0]
+    alg_bytes = ctx.last_bytes()[0]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        step()
+        evs[k][1].record(stream)
+        print(f"bench: step {k} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in evs]
+    total_ms = sum(ms)
+    value = gpts * args.steps / (total_ms / 1e3) / 1e9
+    achieved = alg_bytes / (np.mean(ms) / 1e3) / 1e9
+
+    out = {"metric": METRIC, "value": value, "unit": "GPts/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": job.name, "nz": job.grid.n1, "nx": job.grid.n2,
+                      "nshot": job.acq.nshot, "nt": job.grid.nt, "order": job.grid.order,
+                      "nb": job.grid.nb, "box": job.grid.box,
+                      "gpts_per_step": gpts, "wall_s": wall},
+           "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "forward time step (v + p update, CPML, source, receivers)",
+                        "alg_bytes_per_step": alg_bytes}}
+
+    if not args.no_plain:
+        # plain stepper: one shot per launch, separate v and p kernels, box off
+        print("bench: plain stepper", file=sys.stderr, flush=True)
+        ctx.set_option(B.OPT_KERNEL, 1)
+        job.grid.box = 0
+        ws_p = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_FORWARD))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.forward(job.grid, job.acq, vp, rho, stf, dcal=dcal, ws=ws_p, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b)
+        pg = ctx.last_counts()[0]
+        ctx.set_option(B.OPT_KERNEL, 0)
+        job.grid.box = 1
+        out["plain"] = {"value": pg / (pms / 1e3) / 1e9, "unit": "GPts/s", "ms_per_step": pms,
+                        "gpts_per_step": pg,
+                        "what": "one shot per launch, separate v and p kernels, box off",
+                        "batched_speedup_wall": pms / (total_ms / args.steps)}
+
+    if not args.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(job, args.cpu_steps)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * smi.h -- C ABI of the MI355X staggered-grid acoustic modelling / RTM / FWI library.
+ *
+ * The library implements, for one GPU, the hot path of SMIwiz (Yang, "SMIwiz: An
+ * integrated toolbox for multidimensional seismic modelling and imaging"):
+ *
+ *   smi_forward              forward modelling (Sec. 2.1, eq. 1-5; Alg. 2 forward loop):
+ *                            seismograms, optional boundary saving (Sec. 4.2)
+ *   smi_adjoint_reconstruct  reverse loop of Alg. 2: source-field reconstruction from the
+ *                            saved boundaries (Sec. 4.2) while the adjoint field (eq. 8) is
+ *                            propagated; accumulates the Vp gradient (eq. 7), the
+ *                            cross-correlation image (eq. 10) and the source illumination
+ *   smi_rtm_image            forward + reverse with the observed data as adjoint source (Sec. 2.3)
+ *   smi_fwi_grad             forward + L2 misfit (eq. 6) + reverse: dJ/dVp with rho fixed
+ *
+ * Work is restricted to the evolving computing box of Sec. 4.1 when grid.box = 1.
+ *
+ * Conventions
+ *   - Every array is float32 unless stated.  Model arrays have n1*n2*n3 entries with
+ *     n1 = z fastest, then x (n2), then y (n3) -- the layout of the paper's binary files
+ *     (Sec. 3.5, 3.6).  In 2D set ndim = 2 and n3 = 1.
+ *   - Positions are (z, x, y) in metres from interior cell 0 and must fall on grid nodes
+ *     (within 1e-3 of a cell); off-grid (Kaiser-sinc) positions return SMI_E_UNSUPPORTED.
+ *   - "device" pointers are HIP device memory of the context's device; "host" pointers are
+ *     ordinary host memory, read during the call only.
+ *   - All device work is enqueued on the caller's HIP stream (hip_stream; NULL = the null
+ *     stream) and is asynchronous: results are ready once that stream is synchronised.
+ *   - The caller owns every device buffer, including the workspace `ws`, whose size is
+ *     given by smi_workspace_bytes.  The compute entry points never allocate device memory.
+ *   - Errors: argument, stability and capacity checks return synchronously (no work is
+ *     enqueued then).  Faults detected on the device (non-finite or out-of-range model
+ *     values, non-finite wavefields) are latched in a status word inside the workspace and
+ *     reported by smi_poll_status.  smi_last_error gives a human-readable reason.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef SMI_H
+#define SMI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMI_OK = 0,
+    SMI_E_ARG = -1,          /* invalid argument, shape, position or pointer */
+    SMI_E_CFL = -2,          /* eq. (5) violated: dt Vmax sqrt(sum 1/d^2) sum|a_l| > 1 */
+    SMI_E_DISPERSION = -3,   /* too few points per wavelength (Sec. 3.8) */
+    SMI_E_WORKSPACE = -4,    /* workspace missing or smaller than smi_workspace_bytes */
+    SMI_E_HIP = -5,          /* HIP runtime error */
+    SMI_E_UNSUPPORTED = -6,  /* free surface, off-grid positions, order not in {4, 8} */
+    SMI_E_STATE = -7,        /* state missing, consumed, or saved without boundaries */
+    SMI_E_NONFINITE = -8     /* device status: non-finite / non-positive model or field */
+} smi_status;
+
+/* What a workspace must hold (smi_workspace_bytes). */
+typedef enum {
+    SMI_JOB_FORWARD = 0,       /* smi_forward without state */
+    SMI_JOB_FORWARD_SAVE = 1,  /* smi_forward with state, then smi_adjoint_reconstruct */
+    SMI_JOB_RTM = 2,           /* smi_rtm_image */
+    SMI_JOB_GRAD = 3           /* smi_fwi_grad */
+} smi_job;
+
+typedef struct smi_ctx smi_ctx;      /* device, options, last error text */
+typedef struct smi_state smi_state;  /* host record of a saved forward pass (views into ws) */
+
+/* Simulation parameters; names follow the paper's keywords (Sec. 3.6, 3.8, 4.1, 4.2). */
+typedef struct {
+    int ndim;                /* 2 or 3 */
+    int n1, n2, n3;          /* interior cells along z, x, y (n3 = 1 in 2D) */
+    double d1, d2, d3;       /* spacing [m] */
+    int nb;                  /* absorbing (CPML) layers per side, >= order/2 */
+    int order;               /* spatial order 2N: 4 or 8 */
+    int freesurf;            /* must be 0 (free surface not provided) */
+    int nt;                  /* time steps */
+    double dt;               /* time step [s] */
+    double fm;               /* wavelet centre frequency [Hz]: CPML alpha, dispersion check */
+    int dr;                  /* boundary decimation ratio (Sec. 4.2), 1 = exact */
+    int box;                 /* 1: evolving computing box (Sec. 4.1) */
+    int box_margin;          /* box margin in cells; < 0: default 2N */
+    double vpmin, vpmax;     /* bounds of the model speed; 0, 0: reduced from the model
+                                on the device (one blocking read-back) */
+} smi_grid;
+
+/* Acquisition (Sec. 3.4): one source per shot; receivers of shot s are
+ * rec[rec_off[s] .. rec_off[s+1]).  All host arrays. */
+typedef struct {
+    int nshot;
+    const double *src;       /* [nshot][3] (z, x, y) metres */
+    const int *rec_off;      /* [nshot + 1], rec_off[0] = 0, non-decreasing */
+    const double *rec;       /* [rec_off[nshot]][3] (z, x, y) metres */
+} smi_acq;
+
+/* Options (smi_set_option). */
+typedef enum {
+    SMI_OPT_KERNEL = 0,      /* 0: batched kernels (default); 1: plain stepper -- one shot
+                                per launch, separate v and p kernels, no box */
+    SMI_OPT_GRAPH = 1        /* 1: replay the time loop from captured HIP graphs (default 0) */
+} smi_option;
+
+/* Create a context on HIP device `hip_device`. */
+smi_status smi_ctx_create(int hip_device, smi_ctx **out);
+void smi_ctx_destroy(smi_ctx *ctx);
+/* Text of the last error raised on this context (never NULL). */
+const char *smi_last_error(const smi_ctx *ctx);
+smi_status smi_set_option(smi_ctx *ctx, int option, int value);
+
+/* Host checks run by every entry point (Sec. 3.8): eq. (5) with Vmax = vp_max, and at least
+ * 5 (order 4) or 3 (order 8) points per wavelength at the highest frequency 2.5 fm:
+ * vp_min / (2.5 fm max(d)) >= ppw.  Returns SMI_OK, SMI_E_CFL, SMI_E_DISPERSION or SMI_E_ARG. */
+smi_status smi_check(const smi_ctx *ctx, const smi_grid *grid, double vp_min, double vp_max);
+
+/* Bytes of device workspace that `job` needs for this grid and acquisition. */
+smi_status smi_workspace_bytes(const smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                               smi_job job, size_t *bytes);
+
+/* Forward modelling, all shots batched (Sec. 2.1; Alg. 2 forward loop).
+ *   vp, rho  device [n1*n2*n3]       model (extended into the CPML layers by edge replication)
+ *   stf      device [nshot][nt]      source time function; p[src] += dt stf[it] / (d1 d2 [d3])
+ *                                    after the p update of step it
+ *   dcal     device                  shot s at dcal + nt*rec_off[s], layout [nt][nrec_s]:
+ *                                    dcal[it][r] = p^{it+1} at receiver r
+ *   state_out NULL: no boundary saving.  Otherwise the bands of Sec. 4.2 are saved every dr
+ *            steps and *state_out receives a host record of the final wavefield and the bands
+ *            (inside ws, which must be sized for SMI_JOB_FORWARD_SAVE); free it with
+ *            smi_state_destroy.  vp, rho, stf must stay valid until the state is consumed.
+ *   snap_it, nsnap, snaps   optional: host list of time levels (0..nt); snaps (device,
+ *            [nshot][nsnap][n1*n2*n3]) receives p at those levels (interior).  NULL/0 = none.
+ *   ws, ws_bytes  device workspace (>= smi_workspace_bytes). */
+smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                       const float *vp, const float *rho, const float *stf, float *dcal,
+                       smi_state **state_out, const int *snap_it, int nsnap, float *snaps,
+                       void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Reverse loop of Alg. 2 on a saved forward pass (consumes the state).
+ *   adj_src  device, layout of dcal: the adjoint source G injected as p~[rec] += kappa G[it]
+ *            before reverse step it (eq. 8 in the scaled variable p~ = kappa pbar).
+ *            G = dt (dcal - dobs) gives dJ/dVp of eq. (6)-(7); G = dL/d(dcal) gives the
+ *            vector-Jacobian product of any loss; G = dt dobs gives the RTM image (Sec. 2.3).
+ *   grad_vp  device [n1*n2*n3] or NULL: sum over shots of dL/dVp, rho held fixed:
+ *            -(2 dt / Vp) sum_it p~ div v^{it+1/2} (eq. 7 with kappa = rho Vp^2).  Overwritten.
+ *   image    device [n1*n2*n3] or NULL: sum_s sum_it dt p~^it p^it (eq. 10).  Overwritten.
+ *   illum    device [n1*n2*n3] or NULL: sum_s sum_it dt (p^it)^2.  Overwritten.
+ *   snap_it, nsnap, snaps   optional: reconstructed source-field p at the listed levels,
+ *            device [nshot][nsnap][n1*n2*n3].
+ * The state must come from smi_forward on the same context. */
+smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
+                                   float *grad_vp, float *image, float *illum,
+                                   const int *snap_it, int nsnap, float *snaps,
+                                   void *hip_stream);
+
+/* RTM (Sec. 2.3): forward with boundary saving, then the reverse loop with G = dt dobs.
+ * dobs has the layout of dcal.  image / illum as in smi_adjoint_reconstruct (any may be NULL). */
+smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                         const float *vp, const float *rho, const float *stf, const float *dobs,
+                         float *image, float *illum, void *ws, size_t ws_bytes,
+                         void *hip_stream);
+
+/* FWI gradient (Sec. 2.2): forward with boundary saving, residual r = dcal - dobs,
+ * misfit J = 1/2 dt sum r^2 (eq. 6, rectangle rule; device double, may be NULL), G = dt r,
+ * reverse loop -> grad_vp (device [n1*n2*n3]).  dcal_out (device, layout of dcal) receives
+ * the synthetic data when not NULL. */
+smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                        const float *vp, const float *rho, const float *stf, const float *dobs,
+                        float *grad_vp, double *misfit, float *dcal_out, void *ws,
+                        size_t ws_bytes, void *hip_stream);
+
+void smi_state_destroy(smi_state *state);
+
+/* Synchronise hip_stream and report the device status word of the last workspace used on
+ * this context (SMI_E_NONFINITE when a model value was non-finite or non-positive, or a
+ * wavefield became non-finite).  Clears the word. */
+smi_status smi_poll_status(smi_ctx *ctx, void *hip_stream);
+
+/* Algorithmic counts of the last compute call on this context (host, after the call):
+ * cell updates inside the computing boxes, summed over shots and steps, for the forward
+ * field (fwd), the adjoint field (adj) and the reconstructed field (rec). */
+smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double *rec);
+
+/* Algorithmic HBM bytes of the last forward loop and the last reverse loop on this context:
+ * the FP32 traffic the method itself requires (fields and CPML memory variables read and
+ * written once per cell-step inside the boxes, the model once per step, receivers, saved and
+ * restored boundary bands, image / gradient accumulators), independent of how the kernels
+ * move it.  Used to express throughput as a fraction of the HBM roofline. */
+smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMI_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of libsmi (include/smi.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the modelling path runs in
+the library's HIP kernels.  There is no CPU fallback: a missing library raises at load time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmi.so")
+
+SMI_OK = 0
+STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
+          -4: "SMI_E_WORKSPACE", -5: "SMI_E_HIP", -6: "SMI_E_UNSUPPORTED", -7: "SMI_E_STATE",
+          -8: "SMI_E_NONFINITE"}
+JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD = 0, 1, 2, 3
+OPT_KERNEL, OPT_GRAPH = 0, 1
+
+
+class SmiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SmiGrid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
+                ("d1", C.c_double), ("d2", C.c_double), ("d3", C.c_double),
+                ("nb", C.c_int), ("order", C.c_int), ("freesurf", C.c_int),
+                ("nt", C.c_int), ("dt", C.c_double), ("fm", C.c_double),
+                ("dr", C.c_int), ("box", C.c_int), ("box_margin", C.c_int),
+                ("vpmin", C.c_double), ("vpmax", C.c_double)]
+
+
+class SmiAcq(C.Structure):
+    _fields_ = [("nshot", C.c_int), ("src", C.POINTER(C.c_double)),
+                ("rec_off", C.POINTER(C.c_int)), ("rec", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmi.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2311_02293_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.smi_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.smi_ctx_destroy.argtypes = [vp]
+        L.smi_ctx_destroy.restype = None
+        L.smi_last_error.argtypes = [vp]
+        L.smi_last_error.restype = C.c_char_p
+        L.smi_set_option.argtypes = [vp, C.c_int, C.c_int]
+        L.smi_check.argtypes = [vp, C.POINTER(SmiGrid), C.c_double, C.c_double]
+        L.smi_workspace_bytes.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), C.c_int,
+                                          C.POINTER(C.c_size_t)]
+        L.smi_forward.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp,
+                                  C.POINTER(vp), C.POINTER(C.c_int), C.c_int, vp, vp, C.c_size_t, vp]
+        L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.c_int,
+                                              vp, vp]
+        L.smi_rtm_image.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
+                                    vp, vp, C.c_size_t, vp]
+        L.smi_fwi_grad.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
+                                   vp, vp, vp, C.c_size_t, vp]
+        L.smi_state_destroy.argtypes = [vp]
+        L.smi_state_destroy.restype = None
+        L.smi_poll_status.argtypes = [vp, vp]
+        L.smi_last_counts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+        L.smi_last_bytes.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def make_grid(g) -> SmiGrid:
+    """smi_grid from any object carrying the paper's keywords (see inputs.Grid)."""
+    return SmiGrid(int(g.ndim), int(g.n1), int(g.n2), int(g.n3 if g.ndim == 3 else 1),
+                   float(g.d1), float(g.d2), float(g.d3 if g.ndim == 3 else 1.0),
+                   int(g.nb), int(g.order), int(getattr(g, "freesurf", 0)), int(g.nt),
+                   float(g.dt), float(g.fm), int(getattr(g, "dr", 1)), int(getattr(g, "box", 0)),
+                   int(getattr(g, "margin", -1)), float(getattr(g, "vpmin", 0.0)),
+                   float(getattr(g, "vpmax", 0.0)))
+
+
+class _Acq:
+    """Keeps the host arrays of an smi_acq alive for the duration of a call."""
+
+    def __init__(self, acq):
+        self.src = np.ascontiguousarray(acq.src, np.float64).reshape(-1, 3)
+        self.off = np.ascontiguousarray(acq.rec_off, np.int32)
+        self.rec = np.ascontiguousarray(acq.rec, np.float64).reshape(-1, 3)
+        if self.rec.size == 0:
+            self.rec = np.zeros((1, 3))
+        self.c = SmiAcq(int(self.src.shape[0]), self.src.ctypes.data_as(C.POINTER(C.c_double)),
+                        self.off.ctypes.data_as(C.POINTER(C.c_int)),
+                        self.rec.ctypes.data_as(C.POINTER(C.c_double)))
+
+    @property
+    def nrec_total(self) -> int:
+        return int(self.off[-1])
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous(), "need a contiguous device tensor"
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class State:
+    """A saved forward pass (boundary bands + final wavefield inside its workspace)."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self.keep = keep            # tensors that must outlive the state (ws, vp, rho, stf)
+        self.consumed = False
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib().smi_state_destroy(self.handle)
+            self.handle = None
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        import torch
+        torch.cuda.init()
+        self.device = device
+        h = C.c_void_p()
+        rc = lib().smi_ctx_create(device, C.byref(h))
+        if rc != SMI_OK:
+            raise SmiError(rc, "smi_ctx_create failed")
+        self.h = h
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().smi_ctx_destroy(self.h)
+            self.h = None
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc: int):
+        if rc != SMI_OK:
+            raise SmiError(rc, lib().smi_last_error(self.h).decode())
+
+    def set_option(self, option: int, value: int):
+        self._check(lib().smi_set_option(self.h, option, value))
+
+    def check(self, grid, vpmin: float, vpmax: float) -> int:
+        g = make_grid(grid)
+        return lib().smi_check(self.h, C.byref(g), vpmin, vpmax)
+
+    def workspace_bytes(self, grid, acq, job: int) -> int:
+        g = make_grid(grid)
+        a = _Acq(acq)
+        n = C.c_size_t()
+        self._check(lib().smi_workspace_bytes(self.h, C.byref(g), C.byref(a.c), job, C.byref(n)))
+        return int(n.value)
+
+    def workspace(self, nbytes: int):
+        """A device workspace of at least nbytes (reused across calls when large enough)."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def last_counts(self):
+        f, a, r = C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().smi_last_counts(self.h, C.byref(f), C.byref(a), C.byref(r)))
+        return f.value, a.value, r.value
+
+    def last_bytes(self):
+        f, r = C.c_double(), C.c_double()
+        self._check(lib().smi_last_bytes(self.h, C.byref(f), C.byref(r)))
+        return f.value, r.value
+
+    def poll_status(self, stream=None):
+        self._check(lib().smi_poll_status(self.h, _stream(stream)))
+
+    # -------------------------------------------------------------- entry points
+    def forward(self, grid, acq, vp, rho, stf, *, save=False, snaps: Sequence[int] = (),
+                dcal=None, ws=None, stream=None):
+        """smi_forward.  Returns (dcal, snaps_tensor, state)."""
+        import torch
+        g = make_grid(grid)
+        a = _Acq(acq)
+        dev = vp.device
+        if dcal is None:
+            dcal = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=dev)
+        nb = self.workspace_bytes(grid, acq, JOB_FORWARD_SAVE if save else JOB_FORWARD)
+        if ws is None:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev) if save else self.workspace(nb)
+        snap_it = np.ascontiguousarray(list(snaps), np.int32)
+        out_snaps = None
+        if len(snap_it):
+            out_snaps = torch.empty((a.c.nshot, len(snap_it), grid.npts), dtype=torch.float32, device=dev)
+        st = C.c_void_p()
+        rc = lib().smi_forward(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho), _ptr(stf),
+                               _ptr(dcal), C.byref(st) if save else None,
+                               snap_it.ctypes.data_as(C.POINTER(C.c_int)) if len(snap_it) else None,
+                               len(snap_it), _ptr(out_snaps), _ptr(ws), ws.numel(), _stream(stream))
+        self._check(rc)
+        state = State(self, st, (ws, vp, rho, stf)) if save else None
+        return dcal, out_snaps, state
+
+    def adjoint_reconstruct(self, state: State, adj_src, *, grad=True, image=True, illum=True,
+                            snaps: Sequence[int] = (), nshot: Optional[int] = None, npts=None,
+                            stream=None):
+        """smi_adjoint_reconstruct.  Returns dict(grad, image, illum, snaps)."""
+        import torch
+        vp = state.keep[1]
+        dev = vp.device
+        n = vp.numel() if npts is None else npts
+        out = {k: (torch.empty(n, dtype=torch.float32, device=dev) if want else None)
+               for k, want in (("grad", grad), ("image", image), ("illum", illum))}
+        snap_it = np.ascontiguousarray(list(snaps), np.int32)
+        out["snaps"] = None
+        if len(snap_it):
+            out["snaps"] = torch.empty((nshot, len(snap_it), n), dtype=torch.float32, device=dev)
+        rc = lib().smi_adjoint_reconstruct(
+            self.h, state.handle, _ptr(adj_src), _ptr(out["grad"]), _ptr(out["image"]),
+            _ptr(out["illum"]), snap_it.ctypes.data_as(C.POINTER(C.c_int)) if len(snap_it) else None,
+            len(snap_it), _ptr(out["snaps"]), _stream(stream))
+        self._check(rc)
+        state.consumed = True
+        return out
+
+    def rtm_image(self, grid, acq, vp, rho, stf, dobs, *, illum=True, ws=None, stream=None):
+        import torch
+        g = make_grid(grid)
+        a = _Acq(acq)
+        nb = self.workspace_bytes(grid, acq, JOB_RTM)
+        ws = self.workspace(nb) if ws is None else ws
+        image = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
+        il = torch.empty_like(image) if illum else None
+        self._check(lib().smi_rtm_image(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
+                                        _ptr(stf), _ptr(dobs), _ptr(image), _ptr(il), _ptr(ws),
+                                        ws.numel(), _stream(stream)))
+        return image, il
+
+    def fwi_grad(self, grid, acq, vp, rho, stf, dobs, *, want_dcal=False, ws=None, stream=None):
+        import torch
+        g = make_grid(grid)
+        a = _Acq(acq)
+        nb = self.workspace_bytes(grid, acq, JOB_GRAD)
+        ws = self.workspace(nb) if ws is None else ws
+        grad = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
+        mis = torch.zeros(1, dtype=torch.float64, device=vp.device)
+        dcal = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=vp.device) if want_dcal else None
+        self._check(lib().smi_fwi_grad(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
+                                       _ptr(stf), _ptr(dobs), _ptr(grad), _ptr(mis), _ptr(dcal),
+                                       _ptr(ws), ws.numel(), _stream(stream)))
+        return grad, mis, dcal
+
+
+_default = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def split_dcal(dcal, acq, nt: int):
+    """View the flat dcal buffer as a list of [nt, nrec_s] per shot."""
+    off = np.asarray(acq.rec_off)
+    return [dcal[nt * int(off[s]): nt * int(off[s + 1])].view(nt, int(off[s + 1] - off[s]))
+            for s in range(len(off) - 1)]

@@ -1,0 +1,404 @@
+// abi.cpp -- the extern "C" entry points of libsmi (declared in include/smi.h).
+//
+// Each entry point validates on the host (synchronous error codes), builds a plan, uploads
+// the plan's small tables into the caller's workspace and enqueues the time loop on the
+// caller's stream.  No device memory is allocated here.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "smi_internal.hpp"
+
+using smi::Plan;
+using smi::Views;
+
+struct smi_ctx {
+    int device = 0;
+    std::string err;
+    int opt_kernel = 0;
+    int opt_graph = 0;
+    void *last_ws = nullptr;
+    size_t last_status_off = 0;
+    double cnt[3] = {0, 0, 0};
+    double bytes[2] = {0, 0};
+};
+
+struct smi_state {
+    smi_ctx *ctx = nullptr;
+    Plan plan;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    const float *vp = nullptr, *rho = nullptr, *stf = nullptr;
+    bool consumed = false;
+};
+
+namespace {
+
+smi_status fail(smi_ctx *c, smi_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+smi_status hip_fail(smi_ctx *c, hipError_t e, const char *where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(c, SMI_E_HIP, m);
+}
+
+#define HIPCHK(expr, where)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+// Model speed range: the grid's stated bounds, or a device reduction read back once.
+smi_status speeds(smi_ctx *ctx, const smi_grid *g, const float *vp, void *ws, size_t ws_bytes,
+                  hipStream_t st, double &vmin, double &vmax) {
+    if (g->vpmin > 0 && g->vpmax > 0) {
+        vmin = g->vpmin;
+        vmax = g->vpmax;
+        return SMI_OK;
+    }
+    if (!vp || !ws || ws_bytes < 64) return fail(ctx, SMI_E_ARG, "vp / workspace missing");
+    unsigned init[2] = {0x7f7fffffu, 0u}, out[2];
+    unsigned *d = (unsigned *)((char *)ws + 16);
+    long long n = (long long)g->n1 * g->n2 * (g->ndim == 3 ? g->n3 : 1);
+    HIPCHK(hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, st), "minmax init");
+    HIPCHK(smi::launch_minmax(vp, n, d, st), "minmax");
+    HIPCHK(hipMemcpyAsync(out, d, sizeof out, hipMemcpyDeviceToHost, st), "minmax read");
+    HIPCHK(hipStreamSynchronize(st), "minmax sync");
+    float lo, hi;
+    std::memcpy(&lo, &out[0], 4);
+    std::memcpy(&hi, &out[1], 4);
+    if (out[0] == 0u || !(hi > 0)) return fail(ctx, SMI_E_NONFINITE, "vp has non-finite or non-positive values");
+    vmin = lo;
+    vmax = hi;
+    return SMI_OK;
+}
+
+// Upload CPML profiles, box tables, receivers and sources; clear the status word.
+smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) {
+    HIPCHK(hipMemsetAsync(w.status, 0, 64, st), "status clear");
+    for (int a = 0; a < pl.nd; ++a) {
+        std::vector<float> ai, bi, ah, bh;
+        smi::cpml_profiles(pl, a, ai, bi, ah, bh);
+        size_t M = pl.M[a] * sizeof(float);
+        HIPCHK(hipMemcpyAsync(w.cpml.a_i[a], ai.data(), M, hipMemcpyHostToDevice, st), "cpml");
+        HIPCHK(hipMemcpyAsync(w.cpml.b_i[a], bi.data(), M, hipMemcpyHostToDevice, st), "cpml");
+        HIPCHK(hipMemcpyAsync(w.cpml.a_h[a], ah.data(), M, hipMemcpyHostToDevice, st), "cpml");
+        HIPCHK(hipMemcpyAsync(w.cpml.b_h[a], bh.data(), M, hipMemcpyHostToDevice, st), "cpml");
+    }
+    size_t nb = pl.fbox.size() * sizeof(int);
+    HIPCHK(hipMemcpyAsync(w.fbox, pl.fbox.data(), nb, hipMemcpyHostToDevice, st), "fbox");
+    if (pl.adjoint) {
+        HIPCHK(hipMemcpyAsync(w.abox, pl.abox.data(), nb, hipMemcpyHostToDevice, st), "abox");
+        HIPCHK(hipMemcpyAsync(w.rbox, pl.rbox.data(), nb, hipMemcpyHostToDevice, st), "rbox");
+    }
+    int R = pl.rec_off[pl.nshot];
+    if (R > 0) {
+        std::vector<long long> cell(R), obase(R);
+        std::vector<int> shot(R), stride(R);
+        for (int s = 0; s < pl.nshot; ++s)
+            for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
+                const int *q = &pl.rec[3 * (size_t)r];
+                cell[r] = q[0] + (long long)pl.ld1 * (q[1] + (long long)pl.M[1] * q[2]);
+                obase[r] = (long long)pl.g.nt * pl.rec_off[s] + (r - pl.rec_off[s]);
+                shot[r] = s;
+                stride[r] = pl.rec_off[s + 1] - pl.rec_off[s];
+            }
+        HIPCHK(hipMemcpyAsync(w.recv.cell, cell.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.obase, obase.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.shot, shot.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.stride, stride.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rec");
+    }
+    HIPCHK(hipMemcpyAsync(w.src_cell, pl.src_cell.data(), pl.nshot * sizeof(long long),
+                          hipMemcpyHostToDevice, st), "src");
+    return SMI_OK;
+}
+
+smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipStream_t st) {
+    size_t ns = pl.nshot;
+    size_t bytes = sizeof(float) * ns * ((size_t)pl.P * (1 + pl.nd) +
+                   2 * (size_t)(pl.geom.psz[0] + pl.geom.psz[1] + pl.geom.psz[2]));
+    HIPCHK(hipMemsetAsync(f.p, 0, bytes, st), "field clear");
+    return SMI_OK;
+}
+
+smi_status check_snaps(smi_ctx *ctx, const smi_grid *g, const int *snap_it, int nsnap, float *snaps) {
+    if (nsnap < 0) return fail(ctx, SMI_E_ARG, "nsnap < 0");
+    if (nsnap > 0) {
+        if (!snap_it || !snaps) return fail(ctx, SMI_E_ARG, "snapshot list or buffer missing");
+        for (int k = 0; k < nsnap; ++k)
+            if (snap_it[k] < 0 || snap_it[k] > g->nt) return fail(ctx, SMI_E_ARG, "snapshot level outside 0..nt");
+    }
+    return SMI_OK;
+}
+
+// Alg. 2, forward loop: [save bands] -> v, p update with source -> record.
+smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float *vp,
+                       const float *rho, const float *stf, float *dcal, const int *snap_it,
+                       int nsnap, float *snaps, hipStream_t st) {
+    smi_status s = upload(ctx, pl, w, st);
+    if (s != SMI_OK) return s;
+    HIPCHK(smi::launch_model_prep(pl, w, vp, rho, st), "model prep");
+    s = zero_fields(ctx, pl, w.f, st);
+    if (s != SMI_OK) return s;
+    smi::StepCtx c{&pl, &w, stf, st, ctx->opt_kernel == 1};
+    for (int k = 0; k < nsnap; ++k)
+        if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    for (int it = 0; it < pl.g.nt; ++it) {
+        if (pl.save && it % pl.g.dr == 0) HIPCHK(smi::band_save(c, it / pl.g.dr), "band save");
+        HIPCHK(smi::fwd_step(c, it), "forward step");
+        HIPCHK(smi::extract(c, it, dcal), "extract");
+        for (int k = 0; k < nsnap; ++k)
+            if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    }
+    if (pl.save) HIPCHK(smi::band_save(c, pl.nsave), "band save (final level)");
+    ctx->cnt[0] = pl.cnt_fwd;
+    ctx->cnt[1] = ctx->cnt[2] = 0;
+    ctx->bytes[0] = pl.bytes_fwd;
+    ctx->bytes[1] = 0;
+    ctx->last_ws = (void *)w.status;
+    return SMI_OK;
+}
+
+// Alg. 2, reverse loop: adjoint source -> reconstruction (+gradient) -> adjoint step (+image).
+smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad, float *image,
+                       float *illum, const int *snap_it, int nsnap, float *snaps, hipStream_t st) {
+    const Plan &pl = stt->plan;
+    Views w = smi::views(pl, stt->ws);
+    bool adj = G != nullptr;
+    bool want_g = adj && grad, want_i = adj && (image || illum);
+    smi_status s = zero_fields(ctx, pl, w.q, st);
+    if (s != SMI_OK) return s;
+    HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
+    smi::StepCtx c{&pl, &w, stt->stf, st, ctx->opt_kernel == 1};
+    for (int k = 0; k < nsnap; ++k)
+        if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    for (int it = pl.g.nt - 1; it >= 0; --it) {
+        if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
+        HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+        for (int k = 0; k < nsnap; ++k)
+            if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    }
+    HIPCHK(smi::finalize(c, stt->vp, want_g ? grad : nullptr, want_i ? image : nullptr,
+                         want_i ? illum : nullptr), "finalize");
+    if (!adj) {
+        size_t I = sizeof(float) * pl.I;
+        if (grad) HIPCHK(hipMemsetAsync(grad, 0, I, st), "grad clear");
+        if (image) HIPCHK(hipMemsetAsync(image, 0, I, st), "image clear");
+        if (illum) HIPCHK(hipMemsetAsync(illum, 0, I, st), "illum clear");
+    }
+    ctx->cnt[1] = adj ? pl.cnt_adj : 0;
+    ctx->cnt[2] = pl.cnt_rec;
+    ctx->bytes[1] = pl.bytes_rev;
+    return SMI_OK;
+}
+
+smi_status forward_common(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                          smi_job job, const float *vp, const float *rho, const float *stf,
+                          float *dcal, const int *snap_it, int nsnap, float *snaps, void *ws,
+                          size_t ws_bytes, hipStream_t st, std::unique_ptr<smi_state> &out) {
+    if (!grid || !acq) return fail(ctx, SMI_E_ARG, "grid / acq is NULL");
+    if (!vp || !rho || !stf || !dcal) return fail(ctx, SMI_E_ARG, "vp, rho, stf and dcal are required");
+    if (!ws) return fail(ctx, SMI_E_WORKSPACE, "workspace is NULL");
+    smi_status s = check_snaps(ctx, grid, snap_it, nsnap, snaps);
+    if (s != SMI_OK) return s;
+    double vmin = 0, vmax = 0;
+    s = speeds(ctx, grid, vp, ws, ws_bytes, st, vmin, vmax);
+    if (s != SMI_OK) return s;
+    auto stt = std::make_unique<smi_state>();
+    s = smi::make_plan(grid, acq, job, vmin, vmax, stt->plan, ctx->err);
+    if (s != SMI_OK) return s;
+    if (ws_bytes < stt->plan.bytes) {
+        char b[200];
+        snprintf(b, sizeof b, "workspace has %zu bytes, %zu needed", ws_bytes, stt->plan.bytes);
+        return fail(ctx, SMI_E_WORKSPACE, b);
+    }
+    Views w = smi::views(stt->plan, ws);
+    s = run_forward(ctx, stt->plan, w, vp, rho, stf, dcal, snap_it, nsnap, snaps, st);
+    if (s != SMI_OK) return s;
+    stt->ctx = ctx;
+    stt->ws = ws;
+    stt->ws_bytes = ws_bytes;
+    stt->vp = vp;
+    stt->rho = rho;
+    stt->stf = stf;
+    out = std::move(stt);
+    return SMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+smi_status smi_ctx_create(int hip_device, smi_ctx **out) {
+    if (!out) return SMI_E_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SMI_E_HIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return SMI_E_HIP;
+    smi_ctx *c = new smi_ctx();
+    c->device = hip_device;
+    *out = c;
+    return SMI_OK;
+}
+
+void smi_ctx_destroy(smi_ctx *ctx) { delete ctx; }
+
+const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
+    if (!ctx) return SMI_E_ARG;
+    if (option == SMI_OPT_KERNEL && (value == 0 || value == 1)) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
+    return fail(ctx, SMI_E_ARG, "unknown option or value");
+}
+
+smi_status smi_check(const smi_ctx *ctx, const smi_grid *grid, double vp_min, double vp_max) {
+    std::string err;
+    smi_status s = smi::check_grid(grid, vp_min, vp_max, err);
+    if (ctx) const_cast<smi_ctx *>(ctx)->err = err;
+    return s;
+}
+
+smi_status smi_workspace_bytes(const smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                               smi_job job, size_t *bytes) {
+    smi_ctx *c = const_cast<smi_ctx *>(ctx);
+    if (!grid || !acq || !bytes) return fail(c, SMI_E_ARG, "NULL argument");
+    if (job < SMI_JOB_FORWARD || job > SMI_JOB_GRAD) return fail(c, SMI_E_ARG, "bad job");
+    // the layout does not depend on the speeds; use a range that passes the checks
+    smi_grid g = *grid;
+    double vmin = grid->vpmin > 0 ? grid->vpmin : 0, vmax = grid->vpmax > 0 ? grid->vpmax : 0;
+    Plan pl;
+    std::string err;
+    if (!(vmin > 0 && vmax > 0)) {
+        vmax = 1e-3 / g.dt;   // tiny CFL number
+        vmin = vmax;
+        g.fm = 1e-9;          // no dispersion limit
+    }
+    smi_status s = smi::make_plan(&g, acq, job, vmin, vmax, pl, err);
+    if (c) c->err = err;
+    if (s != SMI_OK) return s;
+    *bytes = pl.bytes;
+    return SMI_OK;
+}
+
+smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
+                       const float *rho, const float *stf, float *dcal, smi_state **state_out,
+                       const int *snap_it, int nsnap, float *snaps, void *ws, size_t ws_bytes,
+                       void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    std::unique_ptr<smi_state> stt;
+    smi_status s = forward_common(ctx, grid, acq, state_out ? SMI_JOB_FORWARD_SAVE : SMI_JOB_FORWARD,
+                                  vp, rho, stf, dcal, snap_it, nsnap, snaps, ws, ws_bytes,
+                                  (hipStream_t)hip_stream, stt);
+    if (s != SMI_OK) return s;
+    if (state_out) *state_out = stt.release();
+    return SMI_OK;
+}
+
+smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
+                                   float *grad_vp, float *image, float *illum, const int *snap_it,
+                                   int nsnap, float *snaps, void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!state || state->consumed || !state->plan.save)
+        return fail(ctx, SMI_E_STATE, "state missing, already consumed, or saved without boundaries");
+    if (state->ctx != ctx) return fail(ctx, SMI_E_STATE, "state belongs to another context");
+    smi_status s = check_snaps(ctx, &state->plan.g, snap_it, nsnap, snaps);
+    if (s != SMI_OK) return s;
+    s = run_reverse(ctx, state, adj_src, grad_vp, image, illum, snap_it, nsnap, snaps,
+                    (hipStream_t)hip_stream);
+    if (s != SMI_OK) return s;
+    state->consumed = true;
+    return SMI_OK;
+}
+
+smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
+                         const float *rho, const float *stf, const float *dobs, float *image,
+                         float *illum, void *ws, size_t ws_bytes, void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!dobs) return fail(ctx, SMI_E_ARG, "dobs is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the internal dcal buffer sits inside ws; plan once to find it
+    double vmin = 0, vmax = 0;
+    smi_status s = speeds(ctx, grid, vp, ws, ws_bytes, st, vmin, vmax);
+    if (s != SMI_OK) return s;
+    smi_grid g = *grid;
+    g.vpmin = vmin;
+    g.vpmax = vmax;
+    Plan pl;
+    s = smi::make_plan(&g, acq, SMI_JOB_RTM, vmin, vmax, pl, ctx->err);
+    if (s != SMI_OK) return s;
+    if (!ws || ws_bytes < pl.bytes) return fail(ctx, SMI_E_WORKSPACE, "workspace too small");
+    Views w = smi::views(pl, ws);
+    std::unique_ptr<smi_state> stt;
+    s = forward_common(ctx, &g, acq, SMI_JOB_RTM, vp, rho, stf, w.dcal, nullptr, 0, nullptr, ws,
+                       ws_bytes, st, stt);
+    if (s != SMI_OK) return s;
+    smi::StepCtx c{&stt->plan, &w, stf, st, false};
+    HIPCHK(smi::scale_copy(c, dobs, w.G, (float)g.dt), "rtm source");
+    return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, nullptr, 0, nullptr, st);
+}
+
+smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
+                        const float *rho, const float *stf, const float *dobs, float *grad_vp,
+                        double *misfit, float *dcal_out, void *ws, size_t ws_bytes,
+                        void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!dobs || !grad_vp) return fail(ctx, SMI_E_ARG, "dobs and grad_vp are required");
+    hipStream_t st = (hipStream_t)hip_stream;
+    double vmin = 0, vmax = 0;
+    smi_status s = speeds(ctx, grid, vp, ws, ws_bytes, st, vmin, vmax);
+    if (s != SMI_OK) return s;
+    smi_grid g = *grid;
+    g.vpmin = vmin;
+    g.vpmax = vmax;
+    Plan pl;
+    s = smi::make_plan(&g, acq, SMI_JOB_GRAD, vmin, vmax, pl, ctx->err);
+    if (s != SMI_OK) return s;
+    if (!ws || ws_bytes < pl.bytes) return fail(ctx, SMI_E_WORKSPACE, "workspace too small");
+    Views w = smi::views(pl, ws);
+    float *dcal = dcal_out ? dcal_out : w.dcal;
+    std::unique_ptr<smi_state> stt;
+    s = forward_common(ctx, &g, acq, SMI_JOB_GRAD, vp, rho, stf, dcal, nullptr, 0, nullptr, ws,
+                       ws_bytes, st, stt);
+    if (s != SMI_OK) return s;
+    smi::StepCtx c{&stt->plan, &w, stf, st, false};
+    HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
+    return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, 0, nullptr, st);
+}
+
+void smi_state_destroy(smi_state *state) { delete state; }
+
+smi_status smi_poll_status(smi_ctx *ctx, void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    if (!ctx->last_ws) return SMI_OK;
+    unsigned word = 0;
+    HIPCHK(hipMemcpy(&word, ctx->last_ws, sizeof word, hipMemcpyDeviceToHost), "status read");
+    unsigned zero = 0;
+    HIPCHK(hipMemcpy(ctx->last_ws, &zero, sizeof zero, hipMemcpyHostToDevice), "status clear");
+    if (word & 1u) return fail(ctx, SMI_E_NONFINITE, "model has non-finite, non-positive or out-of-range values");
+    if (word & 2u) return fail(ctx, SMI_E_NONFINITE, "wavefield became non-finite");
+    return SMI_OK;
+}
+
+smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double *rec) {
+    if (!ctx) return SMI_E_ARG;
+    if (fwd) *fwd = ctx->cnt[0];
+    if (adj) *adj = ctx->cnt[1];
+    if (rec) *rec = ctx->cnt[2];
+    return SMI_OK;
+}
+
+smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_bytes) {
+    if (!ctx) return SMI_E_ARG;
+    if (fwd_bytes) *fwd_bytes = ctx->bytes[0];
+    if (rev_bytes) *rev_bytes = ctx->bytes[1];
+    return SMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,610 @@
+// kernels.hip -- gfx950 kernels of the staggered-grid acoustic stepper (Sec. 2.1, eq. 3-4),
+// CPML (Sec. 2.1), source injection / receiver sampling (Alg. 2), boundary save/restore and
+// reconstruction (Sec. 4.2), adjoint propagation and gradient / image accumulation (eq. 7,
+// 8, 10), misfit (eq. 6) and the shot reduction.
+//
+// These are the sweep kernels: one lane per cell, 64 consecutive z cells per wavefront (a
+// 256-byte coalesced row), 4 x-columns per 256-lane workgroup; neighbours come from the
+// L1/L2 caches.  Each launch covers one time step of every shot of the batch, restricted to
+// that shot's computing box (grid z-dimension = shot x y-plane).
+#include "smi_internal.hpp"
+
+namespace smi {
+
+namespace {
+
+constexpr int BZ = 64, BX = 4;
+
+__device__ __forceinline__ int slab_index(int i, int M, int nb) {
+    return i < nb ? i : (i >= M - nb - 1 ? i - (M - nb - 1) + nb : -1);
+}
+
+// f[k + off*stride] if the shifted index stays inside [0, M), else 0 (the padded grid is
+// surrounded by zeros).  The address is clamped so that no lane ever reads out of bounds.
+__device__ __forceinline__ float ldz(const float *__restrict__ f, long long k, int i, int off,
+                                     long long stride, int M) {
+    bool ok = (unsigned)(i + off) < (unsigned)M;
+    float v = f[k + (ok ? (long long)off * stride : 0)];
+    return ok ? v : 0.f;
+}
+
+struct Cell {
+    int s, z, x, y;
+    long long k;
+    bool ok;
+};
+
+__device__ __forceinline__ Cell cell_of(const Geom &g, const int *__restrict__ box, int shot0,
+                                        int ey) {
+    Cell c;
+    c.s = shot0 + blockIdx.z / ey;
+    int yo = blockIdx.z % ey;
+    const int *b = box + 6 * c.s;
+    c.z = b[0] + blockIdx.x * BZ + threadIdx.x;
+    c.x = b[2] + blockIdx.y * BX + threadIdx.y;
+    c.y = b[4] + yo;
+    c.ok = c.z < b[1] && c.x < b[3] && c.y < b[5];
+    c.k = c.z + (long long)g.ld1 * (c.x + (long long)g.M[1] * c.y);
+    return c;
+}
+
+__device__ __forceinline__ long long stride_of(const Geom &g, int a) {
+    return a == 0 ? 1 : (a == 1 ? (long long)g.ld1 : (long long)g.ld1 * g.M[1]);
+}
+
+__device__ __forceinline__ int coord(const Cell &c, int a) { return a == 0 ? c.z : (a == 1 ? c.x : c.y); }
+
+// slab offset of the memory variable of axis a at cell c (or -1 outside the slabs)
+__device__ __forceinline__ long long slab_off(const Geom &g, const Cell &c, int a) {
+    if (a == 0) {
+        int zc = slab_index(c.z, g.M[0], g.nb);
+        return zc < 0 ? -1 : zc + (long long)g.W * (c.x + (long long)g.M[1] * c.y);
+    } else if (a == 1) {
+        int xc = slab_index(c.x, g.M[1], g.nb);
+        return xc < 0 ? -1 : c.z + (long long)g.ld1 * (xc + (long long)g.W * c.y);
+    } else {
+        int yc = slab_index(c.y, g.M[2], g.nb);
+        return yc < 0 ? -1 : c.z + (long long)g.ld1 * (c.x + (long long)g.M[1] * yc);
+    }
+}
+
+// (D+_a p)(i + 1/2) * d_a = sum_l a_l (p[i+l] - p[i-l+1])          eq. (4), second row
+template <int N>
+__device__ __forceinline__ float dplus(const Geom &g, const float *__restrict__ p, const Cell &c, int a) {
+    long long st = stride_of(g, a);
+    int i = coord(c, a), M = g.M[a];
+    float e = 0.f;
+#pragma unroll
+    for (int l = 1; l <= N; ++l)
+        e += g.c[a][l - 1] * (ldz(p, c.k, i, l, st, M) - ldz(p, c.k, i, -(l - 1), st, M));
+    return e;
+}
+
+// (D-_a v)(i) * d_a = sum_l a_l (v[i+l-1] - v[i-l])                  eq. (4), first row
+template <int N>
+__device__ __forceinline__ float dminus(const Geom &g, const float *__restrict__ v, const Cell &c, int a) {
+    long long st = stride_of(g, a);
+    int i = coord(c, a), M = g.M[a];
+    float e = 0.f;
+#pragma unroll
+    for (int l = 1; l <= N; ++l)
+        e += g.c[a][l - 1] * (ldz(v, c.k, i, l - 1, st, M) - ldz(v, c.k, i, -l, st, M));
+    return e;
+}
+
+// ---------------------------------------------------------------- model preparation
+
+// Extend vp, rho into the absorbing layers by edge replication; kdt = dt rho vp^2 (eq. 1),
+// bdt_a = 2 dt / (rho_i + rho_{i+1}) along a (rho beyond the last node repeats it).
+__global__ __launch_bounds__(256) void k_model_prep(Geom g, Model m, const float *__restrict__ vp,
+                                                     const float *__restrict__ rho,
+                                                     unsigned *status, float vlo, float vhi) {
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    long long tot = (long long)g.ld1 * g.M[1] * g.M[2];
+    if (t >= tot) return;
+    int z = (int)(t % g.ld1);
+    long long r = t / g.ld1;
+    int x = (int)(r % g.M[1]);
+    int y = (int)(r / g.M[1]);
+    if (z >= g.M[0]) {
+        m.kdt[t] = 0.f;
+        for (int a = 0; a < g.nd; ++a) m.bdt[a][t] = 0.f;
+        return;
+    }
+    int i[3] = {z - g.nb, x - g.nb, g.nd == 3 ? y - g.nb : 0};
+    int j[3];
+    for (int a = 0; a < 3; ++a) j[a] = min(max(i[a], 0), g.n[a] - 1);
+    long long s = j[0] + (long long)g.n[0] * (j[1] + (long long)g.n[1] * j[2]);
+    float v = vp[s], rh = rho[s];
+    bool own = i[0] == j[0] && i[1] == j[1] && i[2] == j[2];
+    if (own && (!(v > 0.f) || !(rh > 0.f) || !isfinite(v) || !isfinite(rh) ||
+                v < vlo || v > vhi))
+        atomicOr(status, 1u);
+    m.kdt[t] = g.dt * rh * v * v;
+    for (int a = 0; a < g.nd; ++a) {
+        int jn[3] = {j[0], j[1], j[2]};
+        jn[a] = min(max(i[a] + 1, 0), g.n[a] - 1);
+        long long sn = jn[0] + (long long)g.n[0] * (jn[1] + (long long)g.n[1] * jn[2]);
+        m.bdt[a][t] = 2.f * g.dt / (rh + rho[sn]);
+    }
+}
+
+// positive finite floats order like their bit patterns
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ v, long long n, unsigned *out) {
+    unsigned lo = 0x7f7fffffu, hi = 0u;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        float x = v[t];
+        unsigned u = x > 0.f && isfinite(x) ? __float_as_uint(x) : 0u;
+        if (u) { lo = min(lo, u); hi = max(hi, u); } else { lo = 0u; }
+    }
+    atomicMin(out, lo);
+    atomicMax(out + 1, hi);
+}
+
+// ---------------------------------------------------------------- leap-frog step (eq. 3 + CPML)
+
+template <int ND, int N>
+__global__ __launch_bounds__(256) void k_step_v(Geom g, Fields f, Model m, Cpml cp,
+                                                const int *__restrict__ box, int shot0, int ey) {
+    Cell c = cell_of(g, box, shot0, ey);
+    if (!c.ok) return;
+    const float *p = f.p + c.s * g.P;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        float e = dplus<N>(g, p, c, a);
+        long long so = slab_off(g, c, a);
+        if (so >= 0) {
+            int i = coord(c, a);
+            float *ps = f.psp[a] + c.s * g.psz[a] + so;
+            float psi = cp.b_h[a][i] * *ps + cp.a_h[a][i] * e;
+            *ps = psi;
+            e += psi;
+        }
+        f.v[a][c.s * g.P + c.k] -= m.bdt[a][c.k] * e;
+    }
+}
+
+// p update; SRC: add dt stf[it]/dV at the shot's source; IMG: accumulate the image of the
+// interior with the (already reconstructed) source field pf.
+template <int ND, int N, bool SRC, bool IMG>
+__global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml cp,
+                                                const int *__restrict__ box, int shot0, int ey,
+                                                const long long *__restrict__ src_cell,
+                                                const float *__restrict__ stf, int nt, int it,
+                                                const float *__restrict__ pf, float *acc_i) {
+    Cell c = cell_of(g, box, shot0, ey);
+    if (!c.ok) return;
+    float sdiv = 0.f;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        float e = dminus<N>(g, f.v[a] + c.s * g.P, c, a);
+        long long so = slab_off(g, c, a);
+        if (so >= 0) {
+            int i = coord(c, a);
+            float *ps = f.psv[a] + c.s * g.psz[a] + so;
+            float psi = cp.b_i[a][i] * *ps + cp.a_i[a][i] * e;
+            *ps = psi;
+            e += psi;
+        }
+        sdiv += e;
+    }
+    float *pp = f.p + c.s * g.P + c.k;
+    float pn = *pp - m.kdt[c.k] * sdiv;
+    if (SRC && c.k == src_cell[c.s]) pn += g.src_scale * stf[(long long)c.s * nt + it];
+    *pp = pn;
+    if (IMG) {
+        int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
+        if ((unsigned)iz < (unsigned)g.n[0] && (unsigned)ix < (unsigned)g.n[1] &&
+            (unsigned)iy < (unsigned)g.n[2]) {
+            long long ii = c.s * g.I + iz + (long long)g.n[0] * (ix + (long long)g.n[1] * iy);
+            acc_i[ii] += g.dt * pn * pf[c.s * g.P + c.k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reconstruction (Sec. 4.2)
+
+// p^it = p^{it+1} - dt stf[it]/dV [at the source] + dt kappa div v^{it+1/2}  on the interior;
+// GRAD: acc_g += p~ div v^{it+1/2}  (p~: adjoint pressure after this step's injection);
+// ILL:  acc_l += dt (p^it)^2  (source illumination).
+template <int ND, int N, bool GRAD, bool ILL>
+__global__ __launch_bounds__(256) void k_recon_p(Geom g, Fields f, Model m,
+                                                 const int *__restrict__ rbox, int shot0, int ey,
+                                                 const long long *__restrict__ src_cell,
+                                                 const float *__restrict__ stf, int nt, int it,
+                                                 const float *__restrict__ qp, float *acc_g,
+                                                 float *acc_l) {
+    Cell c = cell_of(g, rbox, shot0, ey);
+    if (!c.ok) return;
+    float div = 0.f;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) div += dminus<N>(g, f.v[a] + c.s * g.P, c, a);
+    float *pp = f.p + c.s * g.P + c.k;
+    float pv = *pp;
+    if (c.k == src_cell[c.s]) pv -= g.src_scale * stf[(long long)c.s * nt + it];
+    float pn = pv + m.kdt[c.k] * div;
+    *pp = pn;
+    long long ii = c.s * g.I + (c.z - g.nb) +
+                   (long long)g.n[0] * ((c.x - g.nb) + (long long)g.n[1] * (ND == 3 ? c.y - g.nb : 0));
+    if (GRAD) acc_g[ii] += qp[c.s * g.P + c.k] * div;
+    if (ILL) acc_l[ii] += g.dt * pn * pn;
+}
+
+// v_a^{it-1/2} = v_a^{it+1/2} + dt beta_a D+_a p^it  at v_a points strictly between interior
+// p nodes along a (interior along the other axes).
+template <int ND, int N>
+__global__ __launch_bounds__(256) void k_recon_v(Geom g, Fields f, Model m,
+                                                 const int *__restrict__ rbox, int shot0, int ey) {
+    Cell c = cell_of(g, rbox, shot0, ey);
+    if (!c.ok) return;
+    const float *p = f.p + c.s * g.P;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        if (coord(c, a) >= g.nb + g.n[a] - 1) continue;
+        float e = dplus<N>(g, p, c, a);
+        f.v[a][c.s * g.P + c.k] += m.bdt[a][c.k] * e;
+    }
+}
+
+// ---------------------------------------------------------------- saved boundaries (Sec. 4.2)
+
+// dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt) buf + wt buf2.
+// which: 0 p blocks, 1 v blocks, 2 all.  One lane per band cell; blockIdx.y = shot.
+__global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, float *buf,
+                                              const float *buf2, long long shot_stride, int shot0,
+                                              int dir, int which, float wt) {
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= bd.B) return;
+    int s = shot0 + blockIdx.y;
+    int b = 0;
+#pragma unroll 1
+    while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
+    const BandBlock &bl = bd.blk[b];
+    if (which != 2 && bl.field != which) return;
+    long long r = q - bl.off;
+    int z = bl.org[0] + (int)(r % bl.ext[0]);
+    r /= bl.ext[0];
+    int x = bl.org[1] + (int)(r % bl.ext[1]);
+    int y = bl.org[2] + (int)(r / bl.ext[1]);
+    long long k = z + (long long)g.ld1 * (x + (long long)g.M[1] * y);
+    float *fld = (bl.field == 0 ? f.p : f.v[bl.axis]) + s * g.P + k;
+    long long bo = s * shot_stride + q;
+    if (dir == 0) buf[bo] = *fld;
+    else if (dir == 1) *fld = buf[bo];
+    else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
+}
+
+// ---------------------------------------------------------------- receivers
+
+// dcal[it][r] = p^{it+1}[rec_r]  (Alg. 2 extract_wavefield)
+__global__ __launch_bounds__(256) void k_extract(Geom g, const float *__restrict__ p, Recv rv,
+                                                 float *dcal, int it, unsigned *status) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rv.R) return;
+    float v = p[rv.shot[r] * g.P + rv.cell[r]];
+    dcal[rv.obase[r] + (long long)it * rv.stride[r]] = v;
+    if (!isfinite(v)) atomicOr(status, 2u);
+}
+
+__global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, float *out, long long n,
+                                               float a) {
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < n) out[t] = a * in[t];
+}
+
+// p~[rec_r] += kappa(rec_r) G[it][r]  (eq. 8 source in the scaled adjoint variable)
+__global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *__restrict__ kdt,
+                                                Recv rv, const float *__restrict__ G, int it,
+                                                float inv_dt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rv.R) return;
+    long long c = rv.cell[r];
+    qp[rv.shot[r] * g.P + c] += kdt[c] * inv_dt * G[rv.obase[r] + (long long)it * rv.stride[r]];
+}
+
+// ---------------------------------------------------------------- misfit (eq. 6)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// r = dcal - dobs, G = dt r, partial[b] = sum over this block's grid-stride share of r^2
+__global__ __launch_bounds__(256) void k_residual(const float *__restrict__ dcal,
+                                                  const float *__restrict__ dobs, float *G,
+                                                  long long n, float dt, double *partial) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        float r = dcal[t] - dobs[t];
+        G[t] = dt * r;
+        acc += (double)r * (double)r;
+    }
+    acc = wave_sum(acc);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// out = scale * sum(partial[0..n)) in a fixed order (one workgroup)
+__global__ __launch_bounds__(256) void k_sum_partial(const double *__restrict__ partial, int n,
+                                                     double *out, double scale) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) acc += partial[t];
+    acc = wave_sum(acc);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = scale * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------- shot reduction + chain rule
+
+// grad = -(2 dt / vp) sum_s acc_g[s]  (dJ/dVp = 2 rho Vp dJ/dkappa, dJ/dkappa = -(dt/kappa) sum p~ div v)
+__global__ __launch_bounds__(256) void k_finalize_grad(const float *__restrict__ acc, int nshot,
+                                                       long long I, const float *__restrict__ vp,
+                                                       float dt, float *grad) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= I) return;
+    float s = 0.f;
+    for (int k = 0; k < nshot; ++k) s += acc[k * I + i];
+    grad[i] = -2.f * dt / vp[i] * s;
+}
+
+__global__ __launch_bounds__(256) void k_finalize_sum(const float *__restrict__ acc, int nshot,
+                                                      long long I, float *out) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= I) return;
+    float s = 0.f;
+    for (int k = 0; k < nshot; ++k) s += acc[k * I + i];
+    out[i] = s;
+}
+
+// interior p of every shot -> snaps[s][k][...]
+__global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
+                                              int k, int nsnap) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= g.I) return;
+    int s = blockIdx.y;
+    int iz = (int)(i % g.n[0]);
+    long long r = i / g.n[0];
+    int ix = (int)(r % g.n[1]);
+    int iy = (int)(r / g.n[1]);
+    long long c = (iz + g.nb) + (long long)g.ld1 * ((ix + g.nb) + (long long)g.M[1] * (g.nd == 3 ? iy + g.nb : 0));
+    snaps[((long long)s * nsnap + k) * g.I + i] = p[s * g.P + c];
+}
+
+unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// launch geometry of one step over a box table row: max extents over the shots [s0, s1)
+struct Launch {
+    dim3 grid, block;
+    int ey;
+    bool empty;
+};
+
+Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1) {
+    int ez = 0, ex = 0, ey = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
+        ez = std::max(ez, b[1] - b[0]);
+        ex = std::max(ex, b[3] - b[2]);
+        ey = std::max(ey, b[5] - b[4]);
+    }
+    Launch L;
+    L.empty = ez <= 0 || ex <= 0 || ey <= 0;
+    L.ey = std::max(ey, 1);
+    L.block = dim3(BZ, BX, 1);
+    L.grid = dim3((unsigned)std::max(1, (ez + BZ - 1) / BZ), (unsigned)std::max(1, (ex + BX - 1) / BX),
+                  (unsigned)((s1 - s0) * L.ey));
+    return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host launchers
+
+hipError_t launch_model_prep(const Plan &pl, const Views &w, const float *vp, const float *rho,
+                             hipStream_t st) {
+    long long tot = (long long)pl.ld1 * pl.M[1] * pl.M[2];
+    float lo = (float)(pl.vmin * (1.0 - 1e-6)), hi = (float)(pl.vmax * (1.0 + 1e-6));
+    hipLaunchKernelGGL(k_model_prep, dim3(blocks(tot)), dim3(256), 0, st, pl.geom, w.model, vp,
+                       rho, w.status, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const float *vp, long long n, unsigned *out2, hipStream_t st) {
+    unsigned nb = std::min<unsigned>(blocks(n), 2048u);
+    hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(256), 0, st, vp, n, out2);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int ND, int N>
+hipError_t fwd_step_t(const StepCtx &c, int it) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *box = w.fbox + (size_t)it * pl.nshot * 6;
+    int step = c.plain ? 1 : pl.nshot;
+    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
+        int s1 = std::min(pl.nshot, s0 + step);
+        Launch L = box_launch(pl, pl.fbox, it, s0, s1);
+        if (L.empty) continue;
+        hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
+                           w.cpml, box, s0, L.ey);
+        hipLaunchKernelGGL((k_step_p<ND, N, true, false>), L.grid, L.block, 0, c.st, pl.geom,
+                           w.f, w.model, w.cpml, box, s0, L.ey, (const long long *)w.src_cell,
+                           c.stf, pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
+    }
+    return hipGetLastError();
+}
+
+template <int ND, int N>
+hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
+    const int *ab = w.abox + (size_t)it * pl.nshot * 6;
+    int step = c.plain ? 1 : pl.nshot;
+    // source field: p^{it} (with the gradient read of p~ before the adjoint step)
+    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
+        int s1 = std::min(pl.nshot, s0 + step);
+        Launch L = box_launch(pl, pl.rbox, it, s0, s1);
+        if (L.empty) continue;
+#define SMI_RECON_P(G_, L_)                                                                    \
+    hipLaunchKernelGGL((k_recon_p<ND, N, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, w.f,      \
+                       w.model, rb, s0, L.ey, (const long long *)w.src_cell, c.stf, pl.g.nt, it, \
+                       (const float *)w.q.p, w.acc_g, w.acc_l)
+        if (grad && image) SMI_RECON_P(true, true);
+        else if (grad) SMI_RECON_P(true, false);
+        else if (image) SMI_RECON_P(false, true);
+        else SMI_RECON_P(false, false);
+#undef SMI_RECON_P
+    }
+    hipError_t e = band_restore(c, it, 0);
+    if (e != hipSuccess) return e;
+    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
+        int s1 = std::min(pl.nshot, s0 + step);
+        Launch L = box_launch(pl, pl.rbox, it, s0, s1);
+        if (L.empty) continue;
+        hipLaunchKernelGGL((k_recon_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
+                           rb, s0, L.ey);
+    }
+    e = band_restore(c, it, 1);
+    if (e != hipSuccess) return e;
+    // adjoint field: one step of the same solver (eq. 8), image with p^{it}
+    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
+        int s1 = std::min(pl.nshot, s0 + step);
+        Launch L = box_launch(pl, pl.abox, it, s0, s1);
+        if (L.empty) continue;
+        hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
+                           w.cpml, ab, s0, L.ey);
+        if (image)
+            hipLaunchKernelGGL((k_step_p<ND, N, false, true>), L.grid, L.block, 0, c.st, pl.geom,
+                               w.q, w.model, w.cpml, ab, s0, L.ey, (const long long *)w.src_cell,
+                               c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
+        else
+            hipLaunchKernelGGL((k_step_p<ND, N, false, false>), L.grid, L.block, 0, c.st,
+                               pl.geom, w.q, w.model, w.cpml, ab, s0, L.ey,
+                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                               (const float *)w.f.p, w.acc_i);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define SMI_DISPATCH(fn, ...)                                                    \
+    do {                                                                         \
+        const Plan &pl_ = *c.pl;                                                 \
+        if (pl_.nd == 2 && pl_.N == 2) return fn<2, 2>(__VA_ARGS__);             \
+        if (pl_.nd == 2 && pl_.N == 4) return fn<2, 4>(__VA_ARGS__);             \
+        if (pl_.nd == 3 && pl_.N == 2) return fn<3, 2>(__VA_ARGS__);             \
+        if (pl_.nd == 3 && pl_.N == 4) return fn<3, 4>(__VA_ARGS__);             \
+        return hipErrorInvalidValue;                                             \
+    } while (0)
+
+hipError_t fwd_step(const StepCtx &c, int it) { SMI_DISPATCH(fwd_step_t, c, it); }
+
+hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {
+    SMI_DISPATCH(rev_step_t, c, it, grad, image);
+}
+
+hipError_t extract(const StepCtx &c, int it, float *dcal) {
+    const Views &w = *c.w;
+    if (w.recv.R == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom,
+                       (const float *)w.f.p, w.recv, dcal, it, w.status);
+    return hipGetLastError();
+}
+
+hipError_t band_save(const StepCtx &c, int slot) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    long long ss = (long long)(pl.nsave + 1) * pl.band.B;
+    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
+                       w.f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
+                       ss, 0, 0, 2, 0.f);
+    return hipGetLastError();
+}
+
+// bands at level it: saved level (copy) or linear interpolation between the saved levels
+// t0 = floor(it/dr) dr and t1 = min(t0 + dr, nt) (slot nsave holds level nt).
+hipError_t band_restore(const StepCtx &c, int it, int which) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    long long ss = (long long)(pl.nsave + 1) * pl.band.B;
+    int dr = pl.g.dr, nt = pl.g.nt;
+    int k0 = it / dr, t0 = k0 * dr;
+    float *b0 = w.bands + (size_t)k0 * pl.band.B;
+    if (t0 == it) {
+        hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
+                           pl.geom, w.f, pl.band, b0, (const float *)nullptr, ss, 0, 1, which, 0.f);
+    } else {
+        int t1 = std::min(t0 + dr, nt);
+        int k1 = t1 == nt ? pl.nsave : k0 + 1;
+        float wt = (float)((double)(it - t0) / (double)(t1 - t0));
+        hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
+                           pl.geom, w.f, pl.band, b0,
+                           (const float *)(w.bands + (size_t)k1 * pl.band.B), ss, 0, 2, which, wt);
+    }
+    return hipGetLastError();
+}
+
+hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a) {
+    const Plan &pl = *c.pl;
+    long long n = (long long)pl.g.nt * pl.rec_off[pl.nshot];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(blocks(n)), dim3(256), 0, c.st, in, out, n, a);
+    return hipGetLastError();
+}
+
+hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap) {
+    const Plan &pl = *c.pl;
+    hipLaunchKernelGGL(k_snap, dim3(blocks(pl.I), pl.nshot), dim3(256), 0, c.st, pl.geom,
+                       (const float *)f.p, snaps, k, nsnap);
+    return hipGetLastError();
+}
+
+hipError_t adj_inject(const StepCtx &c, int it, const float *G) {
+    const Views &w = *c.w;
+    if (w.recv.R == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inject, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom, w.q.p,
+                       (const float *)w.model.kdt, w.recv, G, it, (float)(1.0 / c.pl->g.dt));
+    return hipGetLastError();
+}
+
+hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
+                    double *misfit) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    long long n = (long long)pl.g.nt * pl.rec_off[pl.nshot];
+    hipLaunchKernelGGL(k_residual, dim3(pl.npartial), dim3(256), 0, c.st, dcal, dobs, G, n,
+                       (float)pl.g.dt, w.partial);
+    hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, c.st, (const double *)w.partial,
+                       pl.npartial, misfit ? misfit : w.misfit_tmp, 0.5 * pl.g.dt);
+    return hipGetLastError();
+}
+
+hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    if (grad)
+        hipLaunchKernelGGL(k_finalize_grad, dim3(blocks(pl.I)), dim3(256), 0, c.st,
+                           (const float *)w.acc_g, pl.nshot, pl.I, vp, (float)pl.g.dt, grad);
+    if (image)
+        hipLaunchKernelGGL(k_finalize_sum, dim3(blocks(pl.I)), dim3(256), 0, c.st,
+                           (const float *)w.acc_i, pl.nshot, pl.I, image);
+    if (illum)
+        hipLaunchKernelGGL(k_finalize_sum, dim3(blocks(pl.I)), dim3(256), 0, c.st,
+                           (const float *)w.acc_l, pl.nshot, pl.I, illum);
+    return hipGetLastError();
+}
+
+}  // namespace smi

@@ -1,0 +1,424 @@
+// plan.cpp -- host planning: validation (Sec. 3.8, eq. 5), acquisition to grid nodes,
+// CPML profiles (Sec. 2.1), computing-box schedules (Sec. 4.1), boundary-band layout
+// (Sec. 4.2) and the workspace layout.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+#include "smi_internal.hpp"
+
+namespace smi {
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Staggered first-derivative weights of eq. (4): the a_l that make the 2N-point
+// staggered difference exact on polynomials up to degree 2N-1, from Lagrange
+// differentiation at the nodes +-(2m-1)/2.
+void fd_weights(int N, double *a) {
+    // The weight of node +x_l (x_m = (2m-1)/2) is the derivative at 0 of its Lagrange basis
+    // polynomial over the nodes {+-x_m}:
+    //   L_l(x) = (x + x_l)/(2 x_l) * prod_{m!=l} (x^2 - x_m^2)/(x_l^2 - x_m^2)
+    //   a_l = L_l'(0) = 1/(2 x_l) * prod_{m!=l} (-x_m^2)/(x_l^2 - x_m^2)
+    for (int l = 1; l <= N; ++l) {
+        double xl = (2.0 * l - 1.0) / 2.0;
+        double r = 1.0 / (2.0 * xl);
+        for (int m = 1; m <= N; ++m) {
+            if (m == l) continue;
+            double xm = (2.0 * m - 1.0) / 2.0;
+            r *= -xm * xm / (xl * xl - xm * xm);
+        }
+        a[l - 1] = r;
+    }
+}
+
+int slab_width(int nb) { return 2 * nb + 1; }
+
+}  // namespace
+
+smi_status check_grid(const smi_grid *g, double vmin, double vmax, std::string &err) {
+    if (!g) { err = "grid is NULL"; return SMI_E_ARG; }
+    if (g->ndim != 2 && g->ndim != 3) { err = "ndim must be 2 or 3"; return SMI_E_ARG; }
+    if (g->order != 4 && g->order != 8) {
+        err = "order must be 4 or 8";
+        return SMI_E_UNSUPPORTED;
+    }
+    if (g->freesurf) { err = "free surface is not provided"; return SMI_E_UNSUPPORTED; }
+    if (g->n1 < 1 || g->n2 < 1 || (g->ndim == 3 ? g->n3 < 1 : g->n3 != 1)) {
+        err = "bad n1/n2/n3";
+        return SMI_E_ARG;
+    }
+    if (!(g->d1 > 0) || !(g->d2 > 0) || (g->ndim == 3 && !(g->d3 > 0))) {
+        err = "spacing must be positive";
+        return SMI_E_ARG;
+    }
+    if (g->nb < g->order / 2 || g->nb > 1000) { err = "nb must be >= order/2"; return SMI_E_ARG; }
+    if (g->nt < 1 || !(g->dt > 0) || !(g->fm > 0)) { err = "bad nt/dt/fm"; return SMI_E_ARG; }
+    if (g->dr < 1) { err = "dr must be >= 1"; return SMI_E_ARG; }
+    if (g->box != 0 && g->box != 1) { err = "box must be 0 or 1"; return SMI_E_ARG; }
+    if (!(vmin > 0) || !(vmax >= vmin) || !std::isfinite(vmax)) {
+        err = "model speeds must be finite and positive";
+        return SMI_E_ARG;
+    }
+    int N = g->order / 2;
+    double a[kMaxN];
+    fd_weights(N, a);
+    double sa = 0;
+    for (int l = 0; l < N; ++l) sa += std::fabs(a[l]);
+    double inv = 1.0 / (g->d1 * g->d1) + 1.0 / (g->d2 * g->d2) +
+                 (g->ndim == 3 ? 1.0 / (g->d3 * g->d3) : 0.0);
+    double cfl = g->dt * vmax * std::sqrt(inv) * sa;
+    if (cfl > 1.0) {
+        char b[160];
+        snprintf(b, sizeof b, "CFL violated: dt*Vmax*sqrt(sum 1/d^2)*sum|a| = %.4f > 1", cfl);
+        err = b;
+        return SMI_E_CFL;
+    }
+    double dmax = std::max(g->d1, std::max(g->d2, g->ndim == 3 ? g->d3 : 0.0));
+    double ppw = vmin / (2.5 * g->fm * dmax);
+    double need = g->order == 4 ? 5.0 : 3.0;
+    if (ppw < need) {
+        char b[160];
+        snprintf(b, sizeof b, "dispersion: %.2f points per wavelength < %.0f", ppw, need);
+        err = b;
+        return SMI_E_DISPERSION;
+    }
+    return SMI_OK;
+}
+
+void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vector<float> &b_i,
+                   std::vector<float> &a_h, std::vector<float> &b_h) {
+    // Komatitsch & Martin CPML with kappa_pml = 1: b = exp(-(d + alpha) dt),
+    // a = d (b - 1)/(d + alpha); d = d0 l^2 (l: normalised depth into the layer at the
+    // node), d0 = -3 Vmax ln(R) / (2 nb h), Collino-Tsogka R, alpha = pi fm (1 - l).
+    const smi_grid &g = pl.g;
+    int nb = g.nb, n = pl.n[axis], M = pl.M[axis];
+    double h = axis == 0 ? g.d1 : axis == 1 ? g.d2 : g.d3;
+    double R = std::pow(10.0, -((std::log10((double)nb) - 1.0) / std::log10(2.0) + 3.0));
+    double d0 = -3.0 * pl.vmax * std::log(R) / (2.0 * nb * h);
+    a_i.assign(M, 0.f); b_i.assign(M, 1.f); a_h.assign(M, 0.f); b_h.assign(M, 1.f);
+    for (int half = 0; half < 2; ++half)
+        for (int i = 0; i < M; ++i) {
+            double x = i + 0.5 * half;
+            double dist = x < nb ? nb - x : (x > nb + n - 1 ? x - (nb + n - 1) : 0.0);
+            double l = dist / nb;
+            double dd = d0 * l * l, al = M_PI * g.fm * (1.0 - l);
+            double b = std::exp(-(dd + al) * g.dt);
+            double a = dist > 0 ? dd * (b - 1.0) / (dd + al) : 0.0;
+            (half ? a_h : a_i)[i] = (float)a;
+            (half ? b_h : b_i)[i] = (float)b;
+        }
+}
+
+static bool to_node(double pos, double h, int n, int nb, int &node) {
+    double q = pos / h;
+    double r = std::nearbyint(q);
+    if (std::fabs(q - r) > 1e-3) return false;
+    if (r < 0 || r > n - 1) return false;
+    node = nb + (int)r;
+    return true;
+}
+
+// Algorithmic HBM bytes of the forward and reverse loops (what the method must move at
+// FP32, independent of how the kernels move it):
+//   per cell-step of a box: fields p and v_a read + written, 8 (nd + 1) B; CPML memory
+//   variables read + written, 16 B per axis whose slab contains the cell;
+//   per step: the model (dt kappa, dt beta_a) once per distinct cell of the union of the
+//   shots' boxes, 4 (nd + 1) B (approximated by the largest box); receivers 8 B each
+//   (read p, write dcal); saved bands 8 B per band cell (read field, write buffer).
+//   Reverse: the adjoint step as above over the adjoint box; the reconstruction reads and
+//   writes p and v_a on its region (8 (nd + 1) B) plus the accumulators touched (gradient:
+//   read p~ + read/write acc = 12 B; image: read p + read/write acc = 12 B; illumination
+//   8 B), the model again, the restored bands 8 B per band cell, adjoint sources 8 B each.
+static double box_slab_cells(const Plan &pl, const int *b) {
+    double tot = 0;
+    for (int a = 0; a < pl.nd; ++a) {
+        int nb = pl.g.nb, M = pl.M[a];
+        int lo = b[2 * a], hi = b[2 * a + 1];
+        // slab planes along a: [0, nb) and [M - nb - 1, M)
+        int in = std::max(0, std::min(hi, nb) - lo) + std::max(0, hi - std::max(lo, M - nb - 1));
+        double other = 1;
+        for (int q = 0; q < 3; ++q)
+            if (q != a) other *= b[2 * q + 1] - b[2 * q];
+        tot += in * other;
+    }
+    return tot;
+}
+
+void algorithmic_bytes(Plan &pl) {
+    const int nt = pl.g.nt, ns = pl.nshot, nd = pl.nd;
+    double R = pl.rec_off[ns];
+    double bf = 0, br = 0;
+    for (int it = 0; it < nt; ++it) {
+        double maxf = 0, maxa = 0;
+        for (int s = 0; s < ns; ++s) {
+            const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
+            double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
+            bf += 8.0 * (nd + 1) * vf + 16.0 * box_slab_cells(pl, fb);
+            maxf = std::max(maxf, vf);
+            if (pl.adjoint) {
+                const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
+                const int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
+                double va = (double)std::max(0, ab[1] - ab[0]) * std::max(0, ab[3] - ab[2]) *
+                            std::max(0, ab[5] - ab[4]);
+                double vr = (double)(rb[1] - rb[0]) * (rb[3] - rb[2]) * (rb[5] - rb[4]);
+                br += 8.0 * (nd + 1) * va + 16.0 * box_slab_cells(pl, ab);
+                br += 8.0 * (nd + 1) * vr + (12.0 + 8.0) * vr;      // p~ read, gradient, illumination
+                br += 12.0 * va;                                    // image
+                maxa = std::max(maxa, std::max(va, vr));
+            }
+        }
+        bf += 4.0 * (nd + 1) * maxf + 8.0 * R;
+        if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
+        if (pl.adjoint) br += 4.0 * (nd + 1) * maxa + 8.0 * R + 8.0 * (double)ns * pl.band.B;
+    }
+    pl.bytes_fwd = bf;
+    pl.bytes_rev = pl.adjoint ? br : 0;
+}
+
+smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double vmin,
+                     double vmax, Plan &pl, std::string &err) {
+    smi_status st = check_grid(g, vmin, vmax, err);
+    if (st != SMI_OK) return st;
+    if (!acq || acq->nshot < 1 || !acq->src || !acq->rec_off) {
+        err = "acquisition must have at least one shot";
+        return SMI_E_ARG;
+    }
+    pl = Plan();
+    pl.g = *g;
+    pl.nd = g->ndim;
+    pl.N = g->order / 2;
+    pl.vmin = vmin;
+    pl.vmax = vmax;
+    pl.margin = g->box_margin >= 0 ? g->box_margin : 2 * pl.N;
+    pl.n[0] = g->n1; pl.n[1] = g->n2; pl.n[2] = g->ndim == 3 ? g->n3 : 1;
+    for (int a = 0; a < 3; ++a) pl.M[a] = a < pl.nd ? pl.n[a] + 2 * g->nb : 1;
+    pl.ld1 = (int)align_up((size_t)pl.M[0], 32);
+    pl.P = (long long)pl.ld1 * pl.M[1] * pl.M[2];
+    pl.I = (long long)pl.n[0] * pl.n[1] * pl.n[2];
+    pl.nshot = acq->nshot;
+    if (acq->rec_off[0] != 0) { err = "rec_off[0] must be 0"; return SMI_E_ARG; }
+    for (int s = 0; s < pl.nshot; ++s)
+        if (acq->rec_off[s + 1] < acq->rec_off[s]) { err = "rec_off must not decrease"; return SMI_E_ARG; }
+    int R = acq->rec_off[pl.nshot];
+    if (R > 0 && !acq->rec) { err = "rec is NULL"; return SMI_E_ARG; }
+    pl.rec_off.assign(acq->rec_off, acq->rec_off + pl.nshot + 1);
+    double hs[3] = {g->d1, g->d2, g->ndim == 3 ? g->d3 : 1.0};
+    pl.src.assign(3 * pl.nshot, 0);
+    pl.src_cell.resize(pl.nshot);
+    for (int s = 0; s < pl.nshot; ++s) {
+        for (int a = 0; a < pl.nd; ++a)
+            if (!to_node(acq->src[3 * s + a], hs[a], pl.n[a], g->nb, pl.src[3 * s + a])) {
+                err = "source " + std::to_string(s) + " is off-grid or outside the model";
+                return std::fabs(acq->src[3 * s + a] / hs[a] - std::nearbyint(acq->src[3 * s + a] / hs[a])) > 1e-3
+                           ? SMI_E_UNSUPPORTED : SMI_E_ARG;
+            }
+        pl.src_cell[s] = pl.src[3 * s] + (long long)pl.ld1 * (pl.src[3 * s + 1] + (long long)pl.M[1] * pl.src[3 * s + 2]);
+    }
+    pl.rec.assign(3 * (size_t)R, 0);
+    for (int s = 0; s < pl.nshot; ++s) {
+        std::set<long long> seen;
+        for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
+            for (int a = 0; a < pl.nd; ++a)
+                if (!to_node(acq->rec[3 * (size_t)r + a], hs[a], pl.n[a], g->nb, pl.rec[3 * (size_t)r + a])) {
+                    err = "receiver " + std::to_string(r) + " is off-grid or outside the model";
+                    double q = acq->rec[3 * (size_t)r + a] / hs[a];
+                    return std::fabs(q - std::nearbyint(q)) > 1e-3 ? SMI_E_UNSUPPORTED : SMI_E_ARG;
+                }
+            long long c = pl.rec[3 * (size_t)r] + (long long)pl.ld1 * (pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2]);
+            if (!seen.insert(c).second) {
+                err = "two receivers of shot " + std::to_string(s) + " share a grid node";
+                return SMI_E_ARG;
+            }
+        }
+    }
+
+    pl.save = job != SMI_JOB_FORWARD;
+    pl.adjoint = pl.save;
+    pl.need_G = job == SMI_JOB_GRAD || job == SMI_JOB_RTM;
+    pl.need_dcal = pl.need_G;
+
+    // computing boxes (Sec. 4.1)
+    const int nt = g->nt, ns = pl.nshot;
+    pl.fbox.assign((size_t)nt * ns * 6, 0);
+    pl.abox.assign(pl.adjoint ? (size_t)nt * ns * 6 : 0, 0);
+    pl.rbox.assign(pl.adjoint ? (size_t)nt * ns * 6 : 0, 0);
+    pl.cnt_fwd = pl.cnt_adj = pl.cnt_rec = 0;
+    for (int it = 0; it < nt; ++it)
+        for (int s = 0; s < ns; ++s) {
+            int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
+            double vf = 1, va = 1, vr = 1;
+            for (int a = 0; a < 3; ++a) {
+                int lo = 0, hi = pl.M[a];
+                if (a < pl.nd && g->box) {
+                    int r = (int)std::ceil(vmax * (it + 1) * g->dt / hs[a]) + pl.margin;
+                    lo = std::max(0, pl.src[3 * s + a] - r);
+                    hi = std::min(pl.M[a] - 1, pl.src[3 * s + a] + r) + 1;
+                }
+                fb[2 * a] = lo; fb[2 * a + 1] = hi;
+                vf *= hi - lo;
+                if (pl.adjoint) {
+                    int *ab = &pl.abox[((size_t)it * ns + s) * 6];
+                    int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
+                    int alo = 0, ahi = pl.M[a];
+                    int nr = pl.rec_off[s + 1] - pl.rec_off[s];
+                    if (a < pl.nd && nr == 0) { alo = 0; ahi = 0; }
+                    else if (a < pl.nd && g->box) {
+                        int rmin = 1 << 30, rmax = -1;
+                        for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
+                            rmin = std::min(rmin, pl.rec[3 * (size_t)r + a]);
+                            rmax = std::max(rmax, pl.rec[3 * (size_t)r + a]);
+                        }
+                        int w = (int)std::ceil(vmax * (nt - it) * g->dt / hs[a]) + pl.margin;
+                        alo = std::max(0, rmin - w);
+                        ahi = std::min(pl.M[a] - 1, rmax + w) + 1;
+                    }
+                    ab[2 * a] = alo; ab[2 * a + 1] = ahi;
+                    va *= std::max(0, ahi - alo);
+                    int rlo = lo, rhi = hi;
+                    if (a < pl.nd) {
+                        rlo = std::max(lo, g->nb);
+                        rhi = std::min(hi, g->nb + pl.n[a]);
+                    }
+                    if (rhi < rlo) rhi = rlo;
+                    rb[2 * a] = rlo; rb[2 * a + 1] = rhi;
+                    vr *= rhi - rlo;
+                }
+            }
+            pl.cnt_fwd += vf;
+            if (pl.adjoint) { pl.cnt_adj += va; pl.cnt_rec += vr; }
+        }
+    algorithmic_bytes(pl);
+
+    // boundary bands (Sec. 4.2): N planes of p and N of the face-normal v per face
+    BandDesc &bd = pl.band;
+    bd = BandDesc();
+    long long off = 0;
+    for (int a = 0; a < pl.nd; ++a) {
+        int N = pl.N, nb = g->nb, na = pl.n[a];
+        int starts[4] = {nb - N, nb + na, nb - N, nb + na - 1};
+        for (int k = 0; k < 4; ++k) {
+            BandBlock &b = bd.blk[bd.nblk++];
+            b.field = k < 2 ? 0 : 1;
+            b.axis = a;
+            b.start = starts[k];
+            b.w = N;
+            long long cnt = 1;
+            for (int q = 0; q < 3; ++q) {
+                if (q >= pl.nd) { b.ext[q] = 1; b.org[q] = 0; }
+                else if (q == a) { b.ext[q] = N; b.org[q] = b.start; }
+                else { b.ext[q] = pl.n[q]; b.org[q] = nb; }
+                cnt *= b.ext[q];
+            }
+            b.off = off;
+            b.cnt = cnt;
+            off += cnt;
+        }
+    }
+    bd.B = off;
+    pl.nsave = pl.save ? (nt + g->dr - 1) / g->dr : 0;
+
+    // device geometry
+    Geom &G = pl.geom;
+    G.nd = pl.nd; G.N = pl.N; G.nb = g->nb; G.ld1 = pl.ld1; G.P = pl.P; G.I = pl.I;
+    for (int a = 0; a < 3; ++a) { G.n[a] = pl.n[a]; G.M[a] = pl.M[a]; }
+    G.W = slab_width(g->nb);
+    G.psz[0] = (long long)G.W * pl.M[1] * pl.M[2];
+    G.psz[1] = pl.nd >= 2 ? (long long)pl.ld1 * G.W * pl.M[2] : 0;
+    G.psz[2] = pl.nd == 3 ? (long long)pl.ld1 * pl.M[1] * G.W : 0;
+    double aw[kMaxN];
+    fd_weights(pl.N, aw);
+    for (int a = 0; a < 3; ++a)
+        for (int l = 0; l < kMaxN; ++l) G.c[a][l] = l < pl.N ? (float)(aw[l] / hs[a]) : 0.f;
+    G.dt = (float)g->dt;
+    G.src_scale = (float)(g->dt / (hs[0] * hs[1] * (pl.nd == 3 ? hs[2] : 1.0)));
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+    pl.off_status = take(64);
+    pl.off_misfit = take(16);
+    pl.npartial = 1024;
+    pl.off_partial = take(sizeof(double) * pl.npartial);
+    pl.off_model = take(sizeof(float) * (size_t)pl.P * (1 + pl.nd));
+    size_t cp = 0;
+    for (int a = 0; a < pl.nd; ++a) cp += 4 * (size_t)pl.M[a];
+    pl.off_cpml = take(sizeof(float) * cp);
+    size_t nbox = (size_t)nt * ns * 6;
+    pl.off_tables = take(sizeof(int) * nbox * (pl.adjoint ? 3 : 1));
+    pl.off_recv = take((size_t)R * (sizeof(int) * 2 + sizeof(long long) * 2) +
+                       sizeof(long long) * (size_t)ns + 64);
+    size_t fld = sizeof(float) * (size_t)ns * ((size_t)pl.P * (1 + pl.nd) +
+                 2 * (size_t)(G.psz[0] + G.psz[1] + G.psz[2]));
+    pl.off_fields = take(fld);
+    pl.off_adj = pl.adjoint ? take(fld) : 0;
+    pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * (pl.nsave + 1) * (size_t)bd.B) : 0;
+    pl.off_acc = pl.adjoint ? take(sizeof(float) * 3 * (size_t)ns * (size_t)pl.I) : 0;
+    pl.off_G = pl.need_G ? take(sizeof(float) * (size_t)nt * R) : 0;
+    pl.off_dcal = pl.need_dcal ? take(sizeof(float) * (size_t)nt * R) : 0;
+    pl.bytes = o;
+    return SMI_OK;
+}
+
+Views views(const Plan &pl, void *ws) {
+    char *b = (char *)ws;
+    Views w{};
+    w.status = (unsigned *)(b + pl.off_status);
+    w.misfit_tmp = (double *)(b + pl.off_misfit);
+    w.partial = (double *)(b + pl.off_partial);
+    float *m = (float *)(b + pl.off_model);
+    w.model.kdt = m;
+    for (int a = 0; a < 3; ++a) w.model.bdt[a] = a < pl.nd ? m + (size_t)pl.P * (1 + a) : nullptr;
+    float *c = (float *)(b + pl.off_cpml);
+    for (int a = 0; a < 3; ++a) {
+        if (a >= pl.nd) { w.cpml.a_i[a] = w.cpml.b_i[a] = w.cpml.a_h[a] = w.cpml.b_h[a] = nullptr; continue; }
+        int M = pl.M[a];
+        w.cpml.a_i[a] = c; w.cpml.b_i[a] = c + M; w.cpml.a_h[a] = c + 2 * M; w.cpml.b_h[a] = c + 3 * M;
+        c += 4 * M;
+    }
+    size_t nbox = (size_t)pl.g.nt * pl.nshot * 6;
+    int *t = (int *)(b + pl.off_tables);
+    w.fbox = t;
+    w.abox = pl.adjoint ? t + nbox : nullptr;
+    w.rbox = pl.adjoint ? t + 2 * nbox : nullptr;
+    int R = pl.rec_off[pl.nshot];
+    char *r = b + pl.off_recv;
+    w.recv.R = R;
+    w.recv.cell = (long long *)r;
+    w.recv.obase = (long long *)(r + sizeof(long long) * R);
+    w.recv.shot = (int *)(r + 2 * sizeof(long long) * R);
+    w.recv.stride = (int *)(r + 2 * sizeof(long long) * R + sizeof(int) * R);
+    w.src_cell = (long long *)(r + align_up(2 * (sizeof(long long) + sizeof(int)) * (size_t)R, 8));
+    auto fields = [&](size_t off) {
+        Fields f{};
+        float *p = (float *)(b + off);
+        size_t ns = pl.nshot;
+        f.p = p; p += ns * pl.P;
+        for (int a = 0; a < 3; ++a) {
+            if (a < pl.nd) { f.v[a] = p; p += ns * pl.P; } else f.v[a] = nullptr;
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (a < pl.nd) {
+                f.psp[a] = p; p += ns * pl.geom.psz[a];
+                f.psv[a] = p; p += ns * pl.geom.psz[a];
+            } else f.psp[a] = f.psv[a] = nullptr;
+        }
+        return f;
+    };
+    w.f = fields(pl.off_fields);
+    w.q = pl.adjoint ? fields(pl.off_adj) : Fields{};
+    w.bands = pl.save ? (float *)(b + pl.off_bands) : nullptr;
+    if (pl.adjoint) {
+        float *a = (float *)(b + pl.off_acc);
+        w.acc_g = a;
+        w.acc_i = a + (size_t)pl.nshot * pl.I;
+        w.acc_l = a + 2 * (size_t)pl.nshot * pl.I;
+    }
+    w.G = pl.need_G ? (float *)(b + pl.off_G) : nullptr;
+    w.dcal = pl.need_dcal ? (float *)(b + pl.off_dcal) : nullptr;
+    return w;
+}
+
+}  // namespace smi

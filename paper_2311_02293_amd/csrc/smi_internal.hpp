@@ -1,0 +1,168 @@
+// smi_internal.hpp -- plan, workspace layout and kernel launch interface of libsmi.
+//
+// Layout of one wavefield in HBM (per shot): z (n1) is the contiguous axis, padded to a
+// leading dimension ld1 that is a multiple of 32 floats (128 B) so every column starts on a
+// cache-line boundary; then x (M2), then y (M3).  M_a = n_a + 2 nb.  Shots are stacked with
+// a stride of P = ld1 * M2 * M3 floats.  CPML memory variables exist only in the absorbing
+// slabs: along axis a the compact index keeps planes [0, nb) and [M_a - nb - 1, M_a).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/smi.h"
+
+namespace smi {
+
+constexpr int kMaxN = 4;       // half order (orders 4 and 8)
+constexpr int kMaxBlocks = 12; // band blocks per save level: 3 axes x {p, v} x {left, right}
+
+// ---------------------------------------------------------------- device-side views
+
+struct Geom {
+    int nd, N;
+    int n[3];           // interior extents (1 for inactive axes)
+    int M[3];           // padded extents (1 for inactive axes)
+    int nb;
+    int ld1;            // leading dimension along z
+    long long P;        // floats per field per shot
+    int W;              // slab width 2 nb + 1
+    long long psz[3];   // floats per slab array per shot, per axis
+    long long I;        // interior cells per shot
+    float c[3][kMaxN];  // a_l / d_a
+    float dt;
+    float src_scale;    // dt / (d1 d2 [d3])
+};
+
+struct Model {
+    float *kdt;         // dt * kappa, padded
+    float *bdt[3];      // dt * beta_a at v_a points, padded
+};
+
+struct Cpml {           // per axis, indexed by the padded node index along that axis
+    float *a_i[3], *b_i[3];   // integer nodes (p points)
+    float *a_h[3], *b_h[3];   // half nodes (v points)
+};
+
+struct Fields {
+    float *p, *v[3];
+    float *psp[3];      // memory variables of d_a p (at v_a points), slab layout
+    float *psv[3];      // memory variables of d_a v_a (at p points), slab layout
+};
+
+struct BandBlock {      // one block of a saved level: planes [start, start+w) along `axis`
+    int field;          // 0: p, 1: v_axis
+    int axis;
+    int start, w;
+    long long off;      // offset of the block inside one level
+    long long cnt;      // cells in the block
+    int ext[3];         // box extents (z, x, y) of the block
+    int org[3];         // box origin (z, x, y) of the block
+};
+
+struct BandDesc {
+    int nblk;
+    long long B;        // floats per level per shot
+    BandBlock blk[kMaxBlocks];
+};
+
+struct Recv {           // flattened receivers of all shots
+    int R;
+    int *shot;          // [R]
+    long long *cell;    // [R] cell offset inside one shot's field
+    long long *obase;   // [R] offset of sample 0 in dcal
+    int *stride;        // [R] nrec of its shot
+};
+
+// ---------------------------------------------------------------- host plan
+
+struct Plan {
+    smi_grid g{};
+    int nd = 2, N = 2;
+    int n[3] = {1, 1, 1}, M[3] = {1, 1, 1};
+    int ld1 = 0;
+    long long P = 0, I = 0;
+    double vmin = 0, vmax = 0;
+    int margin = 0;
+    int nshot = 0;
+    std::vector<int> src;          // [nshot][3] padded nodes
+    std::vector<long long> src_cell;
+    std::vector<int> rec_off;      // [nshot + 1]
+    std::vector<int> rec;          // [R][3]
+    std::vector<int> fbox;         // [nt][nshot][6] forward box (lo, hi exclusive per axis)
+    std::vector<int> abox;         // [nt][nshot][6] adjoint box
+    std::vector<int> rbox;         // [nt][nshot][6] reconstruction region (interior clip)
+    BandDesc band{};
+    int nsave = 0;      // saved levels 0, dr, 2 dr, ...; slot nsave holds level nt
+    Geom geom{};
+    // workspace layout (byte offsets)
+    size_t off_status = 0, off_misfit = 0, off_partial = 0;
+    size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
+    size_t off_fields = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
+    size_t off_vrange = 0;
+    size_t bytes = 0;
+    int npartial = 0;
+    bool save = false, adjoint = false, need_G = false, need_dcal = false;
+    double cnt_fwd = 0, cnt_adj = 0, cnt_rec = 0;
+    double bytes_fwd = 0, bytes_rev = 0;   // algorithmic HBM bytes (see plan.cpp)
+};
+
+// Build and validate a plan.  Returns SMI_OK or an error with `err` filled.
+smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double vmin,
+                     double vmax, Plan &pl, std::string &err);
+smi_status check_grid(const smi_grid *g, double vmin, double vmax, std::string &err);
+void algorithmic_bytes(Plan &pl);
+void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vector<float> &b_i,
+                   std::vector<float> &a_h, std::vector<float> &b_h);
+
+// ---------------------------------------------------------------- device views of a workspace
+
+struct Views {
+    unsigned *status;
+    double *misfit_tmp;
+    double *partial;
+    Model model;
+    Cpml cpml;
+    int *fbox, *abox, *rbox;
+    Recv recv;
+    long long *src_cell;  // [nshot] source cell offset inside one shot's field
+    Fields f, q;        // source field, adjoint field
+    float *bands;       // [nshot][nsave][B]
+    float *acc_g, *acc_i, *acc_l;   // [nshot][I] gradient / image / illumination
+    float *G;           // [nt * R] adjoint source (when computed internally)
+    float *dcal;        // internal dcal when the caller gave none
+};
+
+Views views(const Plan &pl, void *ws);
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+
+hipError_t launch_model_prep(const Plan &pl, const Views &w, const float *vp, const float *rho,
+                             hipStream_t st);
+hipError_t launch_minmax(const float *vp, long long n, unsigned *out2, hipStream_t st);
+
+struct StepCtx {
+    const Plan *pl;
+    const Views *w;
+    const float *stf;       // device [nshot][nt]
+    hipStream_t st;
+    bool plain;
+};
+
+hipError_t fwd_step(const StepCtx &c, int it);
+hipError_t extract(const StepCtx &c, int it, float *dcal);
+hipError_t band_save(const StepCtx &c, int slot);
+hipError_t band_restore(const StepCtx &c, int it, int which);
+hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
+hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a);
+hipError_t adj_inject(const StepCtx &c, int it, const float *G);
+hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image);
+hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
+                    double *misfit);
+hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum);
+
+}  // namespace smi

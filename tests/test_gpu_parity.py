@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Tolerances: seismogram relative L2 <= 1e-4, reconstructed wavefield (globally
+normalised) <= 1e-5, gradient / image relative L2 <= 1e-4 (FP32 fields, FP32 accumulation
+over nt steps, against FP64)."""
+import numpy as np
+import pytest
+
+from paper_2311_02293_amd import inputs as I
+from helpers import dev, rel_l2, oracle_dcal, say, with_bounds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_02293_amd import binding as B
+    return B.Context(0)
+
+
+def split(dcal, job):
+    from paper_2311_02293_amd import binding as B
+    return [d.cpu().numpy() for d in B.split_dcal(dcal, job.acq, job.grid.nt)]
+
+
+@pytest.mark.parametrize("box", [0, 1])
+def test_forward_config1_matches_oracle(ctx, box):
+    """2D, order 4, 201x201, 3 layers, one shot, nt = 1000: seismogram 1000 x 201."""
+    job = with_bounds(I.config1())
+    job.grid.box = box
+    say("config1 forward, box", box)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    ctx.poll_status()
+    got = split(dcal, job)[0]
+    ref = oracle_dcal(job, box=0)[0]
+    assert got.shape == (1000, 201)
+    err = rel_l2(got, ref)
+    say("config1 rel L2", err)
+    assert err <= 1e-4
+
+
+def test_forward_order8_batched_matches_oracle_and_alone(ctx):
+    """Config-2 model family (dipping layers, Gardner density, order 8, 30 CPML layers),
+    reduced grid: 4 shots in one launch == each shot alone (bitwise), and == oracle."""
+    job = with_bounds(I.config2(n1=96, n2=260, nt=700, nshot=4))
+    say("order-8 batched forward", job.grid)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    got = split(dcal, job)
+    for s in range(job.acq.nshot):
+        sub = job.acq.shot(s)
+        one, _, _ = ctx.forward(job.grid, sub, vp, rho, stf[s:s + 1].contiguous())
+        np.testing.assert_array_equal(one.cpu().numpy().reshape(got[s].shape), got[s])
+    ref = oracle_dcal(job, shots=[0, 3], box=0)
+    for k, s in enumerate([0, 3]):
+        err = rel_l2(got[s], ref[k])
+        say("shot", s, "rel L2", err)
+        assert err <= 1e-4
+
+
+def test_plain_stepper_equals_batched(ctx):
+    """The plain stepper (one shot per launch) computes the same numbers as the batched one."""
+    from paper_2311_02293_amd import binding as B
+    job = with_bounds(I.config2(n1=64, n2=200, nt=300, nshot=3, box=0))
+    vp, rho, stf = dev(job)
+    a, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    a = a.cpu().numpy()
+    ctx.set_option(B.OPT_KERNEL, 1)
+    try:
+        b, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+
+
+def test_forward_is_deterministic(ctx):
+    job = with_bounds(I.config2(n1=64, n2=200, nt=300, nshot=3))
+    vp, rho, stf = dev(job)
+    a, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    a = a.cpu().numpy()
+    b, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    np.testing.assert_array_equal(a, b.cpu().numpy())
+
+
+@pytest.mark.parametrize("box", [0, 1])
+def test_reconstruction_from_saved_boundaries(ctx, box):
+    """Sec. 4.2, dr = 1: the source field rebuilt backwards from the saved bands equals the
+    forward field: max_n ||p_rec - p||_I / max_n ||p||_I <= 1e-5 (FP32)."""
+    job = with_bounds(I.config2(n1=80, n2=200, nt=800, nshot=2, box=box))
+    vp, rho, stf = dev(job)
+    levels = list(range(0, job.grid.nt + 1, 50))
+    dcal, fw, state = ctx.forward(job.grid, job.acq, vp, rho, stf, save=True, snaps=levels)
+    out = ctx.adjoint_reconstruct(state, None, grad=False, image=False, illum=False,
+                                  snaps=levels, nshot=job.acq.nshot)
+    fw = fw.cpu().numpy().astype(np.float64)
+    rc = out["snaps"].cpu().numpy().astype(np.float64)
+    for s in range(job.acq.nshot):
+        num = np.max(np.linalg.norm(rc[s] - fw[s], axis=1))
+        den = np.max(np.linalg.norm(fw[s], axis=1))
+        say("shot", s, "reconstruction error", num / den)
+        assert num / den <= 1e-5
+
+
+def _grad_job(nt=700, nshot=3):
+    job = I.config3(n1=70, n2=160, nt=nt, nshot=nshot)
+    return with_bounds(job, [job.extra["vp_true"]])
+
+
+def test_fwi_gradient_matches_oracle(ctx):
+    """eq. (6)-(8): misfit and dJ/dVp (rho fixed) against the oracle's reverse loop."""
+    from oracle import oracle as O
+    import torch
+    job = _grad_job()
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    ref_g, ref_J = O.fwi_grad(job, dobs, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs_t)
+    ctx.poll_status()
+    g = g.cpu().numpy().reshape(job.vp.shape)
+    J = float(J.cpu().numpy()[0])
+    say("misfit", J, ref_J, "grad rel L2", rel_l2(g, ref_g))
+    assert abs(J - ref_J) <= 1e-4 * ref_J
+    assert rel_l2(g, ref_g) <= 1e-4
+
+
+def test_rtm_image_matches_oracle(ctx):
+    """eq. (10): image and illumination against the oracle (G = dt dobs)."""
+    from oracle import oracle as O
+    import torch
+    job = _grad_job(nt=600, nshot=2)
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    ref_i, ref_l = O.rtm_image(job, dobs, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    im = im.cpu().numpy().reshape(job.vp.shape)
+    il = il.cpu().numpy().reshape(job.vp.shape)
+    say("image rel L2", rel_l2(im, ref_i), "illum rel L2", rel_l2(il, ref_l))
+    assert rel_l2(im, ref_i) <= 1e-4
+    assert rel_l2(il, ref_l) <= 1e-4
+
+
+def test_forward_3d_matches_oracle(ctx):
+    """3D order 8, layered cube with a salt body, 2 shots, surface receiver grid."""
+    job = with_bounds(I.config4(n=36, nt=220, nshot=2, dr=1, rec_step=4))
+    say("3d forward", job.grid)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    got = split(dcal, job)
+    ref = oracle_dcal(job, box=0)
+    for s in range(2):
+        err = rel_l2(got[s], ref[s])
+        say("3d shot", s, "rel L2", err)
+        assert err <= 1e-4
+
+
+def test_rtm_3d_matches_oracle(ctx):
+    from oracle import oracle as O
+    import torch
+    job = with_bounds(I.config4(n=32, nt=200, nshot=1, dr=1, rec_step=4), )
+    job.grid.vpmax = float(max(job.grid.vpmax, np.max(job.extra["vp_true"])))
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    ref_i, _ = O.rtm_image(job, dobs, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    im, _ = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    err = rel_l2(im.cpu().numpy().reshape(job.vp.shape), ref_i)
+    say("3d image rel L2", err)
+    assert err <= 1e-4
+
+
+def test_errors_are_synchronous(ctx):
+    """Validation errors return before any work: CFL (eq. 5), workspace too small."""
+    from paper_2311_02293_amd import binding as B
+    job = with_bounds(I.config1(nt=50))
+    vp, rho, stf = dev(job)
+    job.grid.dt = 0.004
+    with pytest.raises(B.SmiError) as e:
+        ctx.forward(job.grid, job.acq, vp, rho, stf)
+    assert e.value.code == -2
+    job.grid.dt = 1e-3
+    import torch
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.SmiError) as e:
+        ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws)
+    assert e.value.code == -4

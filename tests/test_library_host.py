@@ -1,0 +1,83 @@
+"""Host-side checks of libsmi that need no GPU: the library loads, exports every entry
+point declared in include/smi.h, and its synchronous validation (eq. 5 CFL, Sec. 3.8
+dispersion, argument checks, workspace sizing) answers as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2311_02293_amd import binding as B
+from paper_2311_02293_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "smi.h")).read()
+    return sorted(set(re.findall(r"\b(smi_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_check_cfl_and_dispersion():
+    L = B.lib()
+    job = I.config1()
+    g = B.make_grid(job.grid)
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == 0
+    # eq. (5): CFL number 0.412 at 2500 m/s; 2.5x the speed violates it
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0 * 2.5) == -2
+    # Sec. 3.8: 1500 / (2.5 * 10 * 10) = 6 points per wavelength; fm = 14 gives 4.3 < 5
+    g.fm = 14.0
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -3
+    g.fm = 10.0
+    g.order = 6
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -6
+    g.order = 4
+    g.freesurf = 1
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -6
+
+
+@pytest.mark.parametrize("cfg", ["config2", "config3"])
+def test_baseline_configs_pass_the_checks(cfg):
+    job = getattr(I, cfg)(nt=10) if cfg != "config3" else I.config3(nt=10)
+    g = B.make_grid(job.grid)
+    vmin = float(np.min(job.vp))
+    vmax = float(max(np.max(job.vp), np.max(job.extra.get("vp_true", job.vp))))
+    assert B.lib().smi_check(None, C.byref(g), vmin, vmax) == 0
+
+
+def test_workspace_bytes_and_argument_errors():
+    L = B.lib()
+    job = I.config2(n1=40, n2=120, nt=50, nshot=4)
+    g = B.make_grid(job.grid)
+    a = B._Acq(job.acq)
+    n0, n1 = C.c_size_t(), C.c_size_t()
+    assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a.c), B.JOB_FORWARD, C.byref(n0)) == 0
+    assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a.c), B.JOB_GRAD, C.byref(n1)) == 0
+    M1, M2 = 40 + 60, 120 + 60
+    ld1 = (M1 + 31) // 32 * 32
+    # fields p, vz, vx of 4 shots at least
+    assert n0.value >= 4 * 3 * ld1 * M2 * 4
+    # the gradient job adds bands for every step: 4 shots x 50 levels x 4N (n1 + n2) floats
+    assert n1.value - n0.value >= 4 * 50 * 16 * (40 + 120) * 4
+    # off-grid receiver -> unsupported; receiver outside the model -> argument error
+    acq = I.Acquisition(job.acq.src.copy(), job.acq.rec_off.copy(), job.acq.rec.copy())
+    acq.rec[3, 1] += 3.0
+    a2 = B._Acq(acq)
+    assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a2.c), 0, C.byref(n0)) == -6
+    acq.rec[3, 1] = 1e6
+    a3 = B._Acq(acq)
+    assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a3.c), 0, C.byref(n0)) == -1
+    # duplicate receiver node within one shot
+    acq = I.Acquisition(job.acq.src.copy(), job.acq.rec_off.copy(), job.acq.rec.copy())
+    acq.rec[5] = acq.rec[6]
+    a4 = B._Acq(acq)
+    assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a4.c), 0, C.byref(n0)) == -1
