@@ -94,9 +94,14 @@ typedef struct {
 
 /* Options (smi_set_option). */
 typedef enum {
-    SMI_OPT_KERNEL = 0,      /* 0: batched kernels (default); 1: plain stepper -- one shot
-                                per launch, separate v and p kernels, no box */
-    SMI_OPT_GRAPH = 1        /* 1: replay the time loop from captured HIP graphs (default 0) */
+    SMI_OPT_KERNEL = 0,      /* 0: batched sweep kernels (default): every shot of the batch in
+                                one launch per half step; 1: plain stepper -- one shot per
+                                launch, separate v and p sweep kernels; 2: fused 2D step
+                                (v and p in one marching kernel, double-buffered levels) */
+    SMI_OPT_GRAPH = 1,       /* 1: replay the time loop from captured HIP graphs (default 0) */
+    SMI_OPT_CHUNK = 2        /* tuning of the fused 2D step: 1000 (2 order + t2) + L, with L the
+                                columns marched by one wavefront, t2 = 1 for 2-column chunks and
+                                order 0/1/2 the workgroup order (0: default 16) */
 } smi_option;
 
 /* Create a context on HIP device `hip_device`. */

@@ -20,6 +20,7 @@ struct smi_ctx {
     std::string err;
     int opt_kernel = 0;
     int opt_graph = 0;
+    int opt_chunk = 0;
     void *last_ws = nullptr;
     size_t last_status_off = 0;
     double cnt[3] = {0, 0, 0};
@@ -103,7 +104,7 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
         for (int s = 0; s < pl.nshot; ++s)
             for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
                 const int *q = &pl.rec[3 * (size_t)r];
-                cell[r] = q[0] + (long long)pl.ld1 * (q[1] + (long long)pl.M[1] * q[2]);
+                cell[r] = pl.cell(q[0], q[1], q[2]);
                 obase[r] = (long long)pl.g.nt * pl.rec_off[s] + (r - pl.rec_off[s]);
                 shot[r] = s;
                 stride[r] = pl.rec_off[s + 1] - pl.rec_off[s];
@@ -115,14 +116,23 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
     }
     HIPCHK(hipMemcpyAsync(w.src_cell, pl.src_cell.data(), pl.nshot * sizeof(long long),
                           hipMemcpyHostToDevice, st), "src");
+    HIPCHK(hipMemcpyAsync(w.rcol_off, pl.rcol_off.data(), pl.rcol_off.size() * sizeof(int),
+                          hipMemcpyHostToDevice, st), "rcol");
+    if (R > 0) {
+        HIPCHK(hipMemcpyAsync(w.rcol_z, pl.rcol_z.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rcol");
+        HIPCHK(hipMemcpyAsync(w.rcol_out, pl.rcol_out.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rcol");
+        HIPCHK(hipMemcpyAsync(w.rcol_stride, pl.rcol_stride.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rcol");
+    }
     return SMI_OK;
 }
 
+size_t field_bytes(const Plan &pl) {
+    return sizeof(float) * (size_t)pl.nshot * ((size_t)pl.P * (1 + pl.nd) +
+           2 * (size_t)(pl.geom.psz[0] + pl.geom.psz[1] + pl.geom.psz[2]));
+}
+
 smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipStream_t st) {
-    size_t ns = pl.nshot;
-    size_t bytes = sizeof(float) * ns * ((size_t)pl.P * (1 + pl.nd) +
-                   2 * (size_t)(pl.geom.psz[0] + pl.geom.psz[1] + pl.geom.psz[2]));
-    HIPCHK(hipMemsetAsync(f.p, 0, bytes, st), "field clear");
+    HIPCHK(hipMemsetAsync(f.p, 0, field_bytes(pl), st), "field clear");
     return SMI_OK;
 }
 
@@ -148,14 +158,35 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     smi::StepCtx c{&pl, &w, stf, st, ctx->opt_kernel == 1};
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
-    for (int it = 0; it < pl.g.nt; ++it) {
-        if (pl.save && it % pl.g.dr == 0) HIPCHK(smi::band_save(c, it / pl.g.dr), "band save");
-        HIPCHK(smi::fwd_step(c, it), "forward step");
-        HIPCHK(smi::extract(c, it, dcal), "extract");
-        for (int k = 0; k < nsnap; ++k)
-            if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    bool fused = ctx->opt_kernel == 2 && pl.dbuf && smi::fused_fwd_available(pl);
+    if (fused) {
+        s = zero_fields(ctx, pl, w.f2, st);
+        if (s != SMI_OK) return s;
+        // the fused step writes the samples of receivers inside the box; the field outside
+        // the box is still zero, so every other sample is zero
+        HIPCHK(hipMemsetAsync(dcal, 0, sizeof(float) * (size_t)pl.g.nt * pl.rec_off[pl.nshot], st),
+               "dcal clear");
     }
-    if (pl.save) HIPCHK(smi::band_save(c, pl.nsave), "band save (final level)");
+    for (int it = 0; it < pl.g.nt; ++it) {
+        // fused steps alternate between the two buffers: level it lives in cur
+        const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
+        const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
+        if (pl.save && it % pl.g.dr == 0) HIPCHK(smi::band_save(c, cur, it / pl.g.dr), "band save");
+        if (fused) {
+            HIPCHK(smi::fwd_step_fused(c, cur, nxt, it, dcal), "forward step");
+        } else {
+            HIPCHK(smi::fwd_step(c, it), "forward step");
+            HIPCHK(smi::extract(c, it, dcal), "extract");
+        }
+        for (int k = 0; k < nsnap; ++k)
+            if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
+    }
+    if (fused && (pl.g.nt & 1)) {
+        // the final level is in the second buffer; the reverse pass works on the first
+        HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, st),
+               "final state copy");
+    }
+    if (pl.save) HIPCHK(smi::band_save(c, w.f, pl.nsave), "band save (final level)");
     ctx->cnt[0] = pl.cnt_fwd;
     ctx->cnt[1] = ctx->cnt[2] = 0;
     ctx->bytes[0] = pl.bytes_fwd;
@@ -217,6 +248,7 @@ smi_status forward_common(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq
         snprintf(b, sizeof b, "workspace has %zu bytes, %zu needed", ws_bytes, stt->plan.bytes);
         return fail(ctx, SMI_E_WORKSPACE, b);
     }
+    stt->plan.chunk = ctx->opt_chunk;
     Views w = smi::views(stt->plan, ws);
     s = run_forward(ctx, stt->plan, w, vp, rho, stf, dcal, snap_it, nsnap, snaps, st);
     if (s != SMI_OK) return s;
@@ -251,8 +283,9 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && (value == 0 || value == 1)) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 2) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
+    if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     return fail(ctx, SMI_E_ARG, "unknown option or value");
 }
 

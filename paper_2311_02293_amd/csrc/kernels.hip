@@ -8,6 +8,7 @@
 // L1/L2 caches.  Each launch covers one time step of every shot of the batch, restricted to
 // that shot's computing box (grid z-dimension = shot x y-plane).
 #include "smi_internal.hpp"
+#include "device.hpp"
 
 namespace smi {
 
@@ -15,41 +16,40 @@ namespace {
 
 constexpr int BZ = 64, BX = 4;
 
-__device__ __forceinline__ int slab_index(int i, int M, int nb) {
-    return i < nb ? i : (i >= M - nb - 1 ? i - (M - nb - 1) + nb : -1);
-}
-
-// f[k + off*stride] if the shifted index stays inside [0, M), else 0 (the padded grid is
-// surrounded by zeros).  The address is clamped so that no lane ever reads out of bounds.
-__device__ __forceinline__ float ldz(const float *__restrict__ f, long long k, int i, int off,
-                                     long long stride, int M) {
-    bool ok = (unsigned)(i + off) < (unsigned)M;
-    float v = f[k + (ok ? (long long)off * stride : 0)];
-    return ok ? v : 0.f;
-}
-
 struct Cell {
     int s, z, x, y;
     long long k;
     bool ok;
 };
 
+// 1D grid over (shot, z-block, x-block, y-plane) with the shot fastest, remapped so that
+// each XCD runs a contiguous range: the shots of one tile run together on one XCD and share
+// the model coefficients in its L2.
+struct LG {
+    int nsh, nzb, nxb;  // shots, z-blocks, x-blocks of the launch
+};
+
 __device__ __forceinline__ Cell cell_of(const Geom &g, const int *__restrict__ box, int shot0,
-                                        int ey) {
+                                        LG lg) {
     Cell c;
-    c.s = shot0 + blockIdx.z / ey;
-    int yo = blockIdx.z % ey;
+    const int nzb = lg.nzb, nxb = lg.nxb, nsh = lg.nsh;
+    int t = xcd_remap(blockIdx.x, gridDim.x);
+    c.s = shot0 + t % nsh;
+    t /= nsh;
+    const int zb = t % nzb;
+    t /= nzb;
+    const int xb = t % nxb, yo = t / nxb;
     const int *b = box + 6 * c.s;
-    c.z = b[0] + blockIdx.x * BZ + threadIdx.x;
-    c.x = b[2] + blockIdx.y * BX + threadIdx.y;
+    c.z = b[0] + zb * BZ + threadIdx.x;
+    c.x = b[2] + xb * BX + threadIdx.y;
     c.y = b[4] + yo;
     c.ok = c.z < b[1] && c.x < b[3] && c.y < b[5];
-    c.k = c.z + (long long)g.ld1 * (c.x + (long long)g.M[1] * c.y);
+    c.k = g.org + c.z + (long long)g.ld1 * c.x + g.ld2 * c.y;
     return c;
 }
 
 __device__ __forceinline__ long long stride_of(const Geom &g, int a) {
-    return a == 0 ? 1 : (a == 1 ? (long long)g.ld1 : (long long)g.ld1 * g.M[1]);
+    return a == 0 ? 1 : (a == 1 ? (long long)g.ld1 : g.ld2);
 }
 
 __device__ __forceinline__ int coord(const Cell &c, int a) { return a == 0 ? c.z : (a == 1 ? c.x : c.y); }
@@ -72,11 +72,9 @@ __device__ __forceinline__ long long slab_off(const Geom &g, const Cell &c, int 
 template <int N>
 __device__ __forceinline__ float dplus(const Geom &g, const float *__restrict__ p, const Cell &c, int a) {
     long long st = stride_of(g, a);
-    int i = coord(c, a), M = g.M[a];
     float e = 0.f;
 #pragma unroll
-    for (int l = 1; l <= N; ++l)
-        e += g.c[a][l - 1] * (ldz(p, c.k, i, l, st, M) - ldz(p, c.k, i, -(l - 1), st, M));
+    for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (p[c.k + l * st] - p[c.k - (l - 1) * st]);
     return e;
 }
 
@@ -84,11 +82,9 @@ __device__ __forceinline__ float dplus(const Geom &g, const float *__restrict__ 
 template <int N>
 __device__ __forceinline__ float dminus(const Geom &g, const float *__restrict__ v, const Cell &c, int a) {
     long long st = stride_of(g, a);
-    int i = coord(c, a), M = g.M[a];
     float e = 0.f;
 #pragma unroll
-    for (int l = 1; l <= N; ++l)
-        e += g.c[a][l - 1] * (ldz(v, c.k, i, l - 1, st, M) - ldz(v, c.k, i, -l, st, M));
+    for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (v[c.k + (l - 1) * st] - v[c.k - l * st]);
     return e;
 }
 
@@ -100,13 +96,14 @@ __global__ __launch_bounds__(256) void k_model_prep(Geom g, Model m, const float
                                                      const float *__restrict__ rho,
                                                      unsigned *status, float vlo, float vhi) {
     long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    long long tot = (long long)g.ld1 * g.M[1] * g.M[2];
-    if (t >= tot) return;
-    int z = (int)(t % g.ld1);
+    if (t >= g.P) return;
+    // storage index -> node of the padded grid (ghost nodes get zeros)
+    int z = (int)(t % g.ld1) - GH;
     long long r = t / g.ld1;
-    int x = (int)(r % g.M[1]);
-    int y = (int)(r / g.M[1]);
-    if (z >= g.M[0]) {
+    const int ex = g.M[1] + 2 * GH;
+    int x = (int)(r % ex) - GH;
+    int y = g.nd == 3 ? (int)(r / ex) - GH : 0;
+    if (z < 0 || z >= g.M[0] || x < 0 || x >= g.M[1] || y < 0 || y >= g.M[2]) {
         m.kdt[t] = 0.f;
         for (int a = 0; a < g.nd; ++a) m.bdt[a][t] = 0.f;
         return;
@@ -146,8 +143,8 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ v, lon
 
 template <int ND, int N>
 __global__ __launch_bounds__(256) void k_step_v(Geom g, Fields f, Model m, Cpml cp,
-                                                const int *__restrict__ box, int shot0, int ey) {
-    Cell c = cell_of(g, box, shot0, ey);
+                                                const int *__restrict__ box, int shot0, LG lg) {
+    Cell c = cell_of(g, box, shot0, lg);
     if (!c.ok) return;
     const float *p = f.p + c.s * g.P;
 #pragma unroll
@@ -169,11 +166,11 @@ __global__ __launch_bounds__(256) void k_step_v(Geom g, Fields f, Model m, Cpml 
 // interior with the (already reconstructed) source field pf.
 template <int ND, int N, bool SRC, bool IMG>
 __global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml cp,
-                                                const int *__restrict__ box, int shot0, int ey,
+                                                const int *__restrict__ box, int shot0, LG lg,
                                                 const long long *__restrict__ src_cell,
                                                 const float *__restrict__ stf, int nt, int it,
                                                 const float *__restrict__ pf, float *acc_i) {
-    Cell c = cell_of(g, box, shot0, ey);
+    Cell c = cell_of(g, box, shot0, lg);
     if (!c.ok) return;
     float sdiv = 0.f;
 #pragma unroll
@@ -210,12 +207,12 @@ __global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml 
 // ILL:  acc_l += dt (p^it)^2  (source illumination).
 template <int ND, int N, bool GRAD, bool ILL>
 __global__ __launch_bounds__(256) void k_recon_p(Geom g, Fields f, Model m,
-                                                 const int *__restrict__ rbox, int shot0, int ey,
+                                                 const int *__restrict__ rbox, int shot0, LG lg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
                                                  const float *__restrict__ qp, float *acc_g,
                                                  float *acc_l) {
-    Cell c = cell_of(g, rbox, shot0, ey);
+    Cell c = cell_of(g, rbox, shot0, lg);
     if (!c.ok) return;
     float div = 0.f;
 #pragma unroll
@@ -235,8 +232,8 @@ __global__ __launch_bounds__(256) void k_recon_p(Geom g, Fields f, Model m,
 // p nodes along a (interior along the other axes).
 template <int ND, int N>
 __global__ __launch_bounds__(256) void k_recon_v(Geom g, Fields f, Model m,
-                                                 const int *__restrict__ rbox, int shot0, int ey) {
-    Cell c = cell_of(g, rbox, shot0, ey);
+                                                 const int *__restrict__ rbox, int shot0, LG lg) {
+    Cell c = cell_of(g, rbox, shot0, lg);
     if (!c.ok) return;
     const float *p = f.p + c.s * g.P;
 #pragma unroll
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, flo
     r /= bl.ext[0];
     int x = bl.org[1] + (int)(r % bl.ext[1]);
     int y = bl.org[2] + (int)(r / bl.ext[1]);
-    long long k = z + (long long)g.ld1 * (x + (long long)g.M[1] * y);
+    long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
     float *fld = (bl.field == 0 ? f.p : f.v[bl.axis]) + s * g.P + k;
     long long bo = s * shot_stride + q;
     if (dir == 0) buf[bo] = *fld;
@@ -375,7 +372,7 @@ __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ 
     long long r = i / g.n[0];
     int ix = (int)(r % g.n[1]);
     int iy = (int)(r / g.n[1]);
-    long long c = (iz + g.nb) + (long long)g.ld1 * ((ix + g.nb) + (long long)g.M[1] * (g.nd == 3 ? iy + g.nb : 0));
+    long long c = g.org + (iz + g.nb) + (long long)g.ld1 * (ix + g.nb) + g.ld2 * (g.nd == 3 ? iy + g.nb : 0);
     snaps[((long long)s * nsnap + k) * g.I + i] = p[s * g.P + c];
 }
 
@@ -384,7 +381,7 @@ unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); 
 // launch geometry of one step over a box table row: max extents over the shots [s0, s1)
 struct Launch {
     dim3 grid, block;
-    int ey;
+    LG ey;
     bool empty;
 };
 
@@ -398,10 +395,10 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
     }
     Launch L;
     L.empty = ez <= 0 || ex <= 0 || ey <= 0;
-    L.ey = std::max(ey, 1);
+    const int nzb = std::max(1, (ez + BZ - 1) / BZ), nxb = std::max(1, (ex + BX - 1) / BX);
+    L.ey = LG{s1 - s0, nzb, nxb};
     L.block = dim3(BZ, BX, 1);
-    L.grid = dim3((unsigned)std::max(1, (ez + BZ - 1) / BZ), (unsigned)std::max(1, (ex + BX - 1) / BX),
-                  (unsigned)((s1 - s0) * L.ey));
+    L.grid = dim3((unsigned)((long long)(s1 - s0) * nzb * nxb * std::max(ey, 1)), 1, 1);
     return L;
 }
 
@@ -411,7 +408,7 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
 
 hipError_t launch_model_prep(const Plan &pl, const Views &w, const float *vp, const float *rho,
                              hipStream_t st) {
-    long long tot = (long long)pl.ld1 * pl.M[1] * pl.M[2];
+    long long tot = pl.P;
     float lo = (float)(pl.vmin * (1.0 - 1e-6)), hi = (float)(pl.vmax * (1.0 + 1e-6));
     hipLaunchKernelGGL(k_model_prep, dim3(blocks(tot)), dim3(256), 0, st, pl.geom, w.model, vp,
                        rho, w.status, lo, hi);
@@ -524,12 +521,12 @@ hipError_t extract(const StepCtx &c, int it, float *dcal) {
     return hipGetLastError();
 }
 
-hipError_t band_save(const StepCtx &c, int slot) {
+hipError_t band_save(const StepCtx &c, const Fields &f, int slot) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     long long ss = (long long)(pl.nsave + 1) * pl.band.B;
     hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
-                       w.f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
+                       f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
                        ss, 0, 0, 2, 0.f);
     return hipGetLastError();
 }

@@ -195,8 +195,14 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.margin = g->box_margin >= 0 ? g->box_margin : 2 * pl.N;
     pl.n[0] = g->n1; pl.n[1] = g->n2; pl.n[2] = g->ndim == 3 ? g->n3 : 1;
     for (int a = 0; a < 3; ++a) pl.M[a] = a < pl.nd ? pl.n[a] + 2 * g->nb : 1;
-    pl.ld1 = (int)align_up((size_t)pl.M[0], 32);
-    pl.P = (long long)pl.ld1 * pl.M[1] * pl.M[2];
+    if ((long long)((pl.M[1] + 3) / 4) * pl.M[2] > 65535 || (pl.M[0] + 63) / 64 > 65535) {
+        err = "grid too large for the sweep-kernel launch geometry";
+        return SMI_E_UNSUPPORTED;
+    }
+    pl.ld1 = (int)align_up((size_t)pl.M[0] + 2 * GH, 32);
+    pl.ld2 = (long long)pl.ld1 * (pl.M[1] + 2 * GH);
+    pl.org = GH + (long long)pl.ld1 * GH + (pl.nd == 3 ? pl.ld2 * GH : 0);
+    pl.P = pl.ld2 * (pl.nd == 3 ? pl.M[2] + 2 * GH : 1);
     pl.I = (long long)pl.n[0] * pl.n[1] * pl.n[2];
     pl.nshot = acq->nshot;
     if (acq->rec_off[0] != 0) { err = "rec_off[0] must be 0"; return SMI_E_ARG; }
@@ -215,7 +221,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                 return std::fabs(acq->src[3 * s + a] / hs[a] - std::nearbyint(acq->src[3 * s + a] / hs[a])) > 1e-3
                            ? SMI_E_UNSUPPORTED : SMI_E_ARG;
             }
-        pl.src_cell[s] = pl.src[3 * s] + (long long)pl.ld1 * (pl.src[3 * s + 1] + (long long)pl.M[1] * pl.src[3 * s + 2]);
+        pl.src_cell[s] = pl.cell(pl.src[3 * s], pl.src[3 * s + 1], pl.src[3 * s + 2]);
     }
     pl.rec.assign(3 * (size_t)R, 0);
     for (int s = 0; s < pl.nshot; ++s) {
@@ -227,10 +233,36 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                     double q = acq->rec[3 * (size_t)r + a] / hs[a];
                     return std::fabs(q - std::nearbyint(q)) > 1e-3 ? SMI_E_UNSUPPORTED : SMI_E_ARG;
                 }
-            long long c = pl.rec[3 * (size_t)r] + (long long)pl.ld1 * (pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2]);
+            long long c = pl.cell(pl.rec[3 * (size_t)r], pl.rec[3 * (size_t)r + 1], pl.rec[3 * (size_t)r + 2]);
             if (!seen.insert(c).second) {
                 err = "two receivers of shot " + std::to_string(s) + " share a grid node";
                 return SMI_E_ARG;
+            }
+        }
+    }
+
+    // receivers grouped by column (x + M2 y), stable within a column
+    {
+        long long ncol = (long long)pl.M[1] * pl.M[2];
+        pl.rcol_off.assign((size_t)pl.nshot * (ncol + 1), 0);
+        pl.rcol_z.resize(R);
+        pl.rcol_out.resize(R);
+        pl.rcol_stride.resize(R);
+        for (int s = 0; s < pl.nshot; ++s) {
+            int *off = &pl.rcol_off[(size_t)s * (ncol + 1)];
+            int base = pl.rec_off[s], nr = pl.rec_off[s + 1] - base;
+            std::vector<int> cnt(ncol + 1, 0);
+            for (int r = base; r < base + nr; ++r)
+                cnt[pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2] + 1]++;
+            for (long long q = 0; q < ncol; ++q) cnt[q + 1] += cnt[q];
+            for (long long q = 0; q <= ncol; ++q) off[q] = base + cnt[q];
+            std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+            for (int r = base; r < base + nr; ++r) {
+                long long col = pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2];
+                int dst = base + fill[col]++;
+                pl.rcol_z[dst] = pl.rec[3 * (size_t)r];
+                pl.rcol_out[dst] = (long long)g->nt * base + (r - base);
+                pl.rcol_stride[dst] = nr;
             }
         }
     }
@@ -322,7 +354,8 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
 
     // device geometry
     Geom &G = pl.geom;
-    G.nd = pl.nd; G.N = pl.N; G.nb = g->nb; G.ld1 = pl.ld1; G.P = pl.P; G.I = pl.I;
+    G.nd = pl.nd; G.N = pl.N; G.nb = g->nb; G.ld1 = pl.ld1; G.ld2 = pl.ld2; G.org = pl.org;
+    G.P = pl.P; G.I = pl.I;
     for (int a = 0; a < 3; ++a) { G.n[a] = pl.n[a]; G.M[a] = pl.M[a]; }
     G.W = slab_width(g->nb);
     G.psz[0] = (long long)G.W * pl.M[1] * pl.M[2];
@@ -350,9 +383,12 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.off_tables = take(sizeof(int) * nbox * (pl.adjoint ? 3 : 1));
     pl.off_recv = take((size_t)R * (sizeof(int) * 2 + sizeof(long long) * 2) +
                        sizeof(long long) * (size_t)ns + 64);
+    pl.off_rcol = take(sizeof(int) * pl.rcol_off.size() + (size_t)R * (2 * sizeof(int) + sizeof(long long)) + 64);
     size_t fld = sizeof(float) * (size_t)ns * ((size_t)pl.P * (1 + pl.nd) +
                  2 * (size_t)(G.psz[0] + G.psz[1] + G.psz[2]));
     pl.off_fields = take(fld);
+    pl.dbuf = pl.nd == 2;
+    pl.off_fields2 = pl.dbuf ? take(fld) : 0;
     pl.off_adj = pl.adjoint ? take(fld) : 0;
     pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * (pl.nsave + 1) * (size_t)bd.B) : 0;
     pl.off_acc = pl.adjoint ? take(sizeof(float) * 3 * (size_t)ns * (size_t)pl.I) : 0;
@@ -391,6 +427,16 @@ Views views(const Plan &pl, void *ws) {
     w.recv.shot = (int *)(r + 2 * sizeof(long long) * R);
     w.recv.stride = (int *)(r + 2 * sizeof(long long) * R + sizeof(int) * R);
     w.src_cell = (long long *)(r + align_up(2 * (sizeof(long long) + sizeof(int)) * (size_t)R, 8));
+    {
+        char *q = b + pl.off_rcol;
+        w.rcol_out = (long long *)q;
+        q += sizeof(long long) * (size_t)R;
+        w.rcol_off = (int *)q;
+        q += sizeof(int) * pl.rcol_off.size();
+        w.rcol_z = (int *)q;
+        q += sizeof(int) * (size_t)R;
+        w.rcol_stride = (int *)q;
+    }
     auto fields = [&](size_t off) {
         Fields f{};
         float *p = (float *)(b + off);
@@ -408,6 +454,7 @@ Views views(const Plan &pl, void *ws) {
         return f;
     };
     w.f = fields(pl.off_fields);
+    w.f2 = pl.dbuf ? fields(pl.off_fields2) : Fields{};
     w.q = pl.adjoint ? fields(pl.off_adj) : Fields{};
     w.bands = pl.save ? (float *)(b + pl.off_bands) : nullptr;
     if (pl.adjoint) {

@@ -1,10 +1,13 @@
 // smi_internal.hpp -- plan, workspace layout and kernel launch interface of libsmi.
 //
-// Layout of one wavefield in HBM (per shot): z (n1) is the contiguous axis, padded to a
-// leading dimension ld1 that is a multiple of 32 floats (128 B) so every column starts on a
-// cache-line boundary; then x (M2), then y (M3).  M_a = n_a + 2 nb.  Shots are stacked with
-// a stride of P = ld1 * M2 * M3 floats.  CPML memory variables exist only in the absorbing
-// slabs: along axis a the compact index keeps planes [0, nb) and [M_a - nb - 1, M_a).
+// Layout of one wavefield in HBM (per shot): z (n1) is the contiguous axis, then x, then y.
+// The padded grid (M_a = n_a + 2 nb nodes per axis) is surrounded by GH ghost nodes per side
+// and axis that are zero and never written, so stencil reads need no bounds checks.  Node
+// (z, x, y) of the padded grid lives at org + z + ld1 x + ld2 y, with ld1 a multiple of 32
+// floats (128 B); shots are stacked with a stride of P floats.  The model arrays use the same
+// layout, so one offset addresses a field and its coefficients.  CPML memory variables exist
+// only in the absorbing slabs: along axis a the compact index keeps planes [0, nb) and
+// [M_a - nb - 1, M_a).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,6 +23,7 @@ namespace smi {
 
 constexpr int kMaxN = 4;       // half order (orders 4 and 8)
 constexpr int kMaxBlocks = 12; // band blocks per save level: 3 axes x {p, v} x {left, right}
+constexpr int GH = 2 * kMaxN;  // ghost nodes per side and axis (>= the 2N-1 halo of a fused step)
 
 // ---------------------------------------------------------------- device-side views
 
@@ -28,7 +32,9 @@ struct Geom {
     int n[3];           // interior extents (1 for inactive axes)
     int M[3];           // padded extents (1 for inactive axes)
     int nb;
-    int ld1;            // leading dimension along z
+    int ld1;            // stride of x (floats)
+    long long ld2;      // stride of y (floats)
+    long long org;      // offset of node (0, 0, 0)
     long long P;        // floats per field per shot
     int W;              // slab width 2 nb + 1
     long long psz[3];   // floats per slab array per shot, per axis
@@ -85,7 +91,9 @@ struct Plan {
     int nd = 2, N = 2;
     int n[3] = {1, 1, 1}, M[3] = {1, 1, 1};
     int ld1 = 0;
+    long long ld2 = 0, org = 0;
     long long P = 0, I = 0;
+    long long cell(int z, int x, int y) const { return org + z + (long long)ld1 * x + ld2 * y; }
     double vmin = 0, vmax = 0;
     int margin = 0;
     int nshot = 0;
@@ -96,17 +104,24 @@ struct Plan {
     std::vector<int> fbox;         // [nt][nshot][6] forward box (lo, hi exclusive per axis)
     std::vector<int> abox;         // [nt][nshot][6] adjoint box
     std::vector<int> rbox;         // [nt][nshot][6] reconstruction region (interior clip)
+    // receivers grouped by grid column (x, and y in 3D): CSR per shot over the M2*M3 columns
+    std::vector<int> rcol_off;     // [nshot][M2*M3 + 1]
+    std::vector<int> rcol_z;       // [R] padded z node
+    std::vector<long long> rcol_out;   // [R] dcal offset of sample 0
+    std::vector<int> rcol_stride;  // [R] samples per time step of that shot
     BandDesc band{};
     int nsave = 0;      // saved levels 0, dr, 2 dr, ...; slot nsave holds level nt
     Geom geom{};
     // workspace layout (byte offsets)
     size_t off_status = 0, off_misfit = 0, off_partial = 0;
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
-    size_t off_fields = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
-    size_t off_vrange = 0;
+    size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
+    size_t off_rcol = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
+    bool dbuf = false;  // second source-field buffer for the fused steps
+    int chunk = 0;      // columns per workgroup of the fused 2D step (0: default)
     double cnt_fwd = 0, cnt_adj = 0, cnt_rec = 0;
     double bytes_fwd = 0, bytes_rev = 0;   // algorithmic HBM bytes (see plan.cpp)
 };
@@ -130,7 +145,10 @@ struct Views {
     int *fbox, *abox, *rbox;
     Recv recv;
     long long *src_cell;  // [nshot] source cell offset inside one shot's field
+    int *rcol_off, *rcol_z, *rcol_stride;   // receivers by column (see Plan)
+    long long *rcol_out;
     Fields f, q;        // source field, adjoint field
+    Fields f2;          // second buffer of the source field (fused, double-buffered steps)
     float *bands;       // [nshot][nsave][B]
     float *acc_g, *acc_i, *acc_l;   // [nshot][I] gradient / image / illumination
     float *G;           // [nt * R] adjoint source (when computed internally)
@@ -154,8 +172,12 @@ struct StepCtx {
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);
+// fused forward step (v, p, CPML, source, receivers in one kernel); false if not provided
+bool fused_fwd_available(const Plan &pl);
+hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it,
+                          float *dcal);
 hipError_t extract(const StepCtx &c, int it, float *dcal);
-hipError_t band_save(const StepCtx &c, int slot);
+hipError_t band_save(const StepCtx &c, const Fields &f, int slot);
 hipError_t band_restore(const StepCtx &c, int it, int which);
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
 hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a);
