@@ -22,23 +22,32 @@ struct Cell {
     bool ok;
 };
 
-// 1D grid over (shot, z-block, x-block, y-plane) with the shot fastest, remapped so that
-// each XCD runs a contiguous range: the shots of one tile run together on one XCD and share
-// the model coefficients in its L2.
+// 1D grid over (z-block, x-block, y-plane, shot).  order 0 (default): z-block fastest and the
+// shot slowest -- neighbouring tiles of one shot run together and share halos in L2;
+// order 1: shot fastest (the shots of one box-relative tile run together); order 2: as 1 with
+// an XCD-contiguous remap.  With computing boxes the shots' tiles sit at different absolute
+// positions, so order 0 measures fastest there.
 struct LG {
-    int nsh, nzb, nxb;  // shots, z-blocks, x-blocks of the launch
+    int nsh, nzb, nxb, ny;  // shots, z-blocks, x-blocks, y-planes of the launch
+    int order;
 };
 
 __device__ __forceinline__ Cell cell_of(const Geom &g, const int *__restrict__ box, int shot0,
                                         LG lg) {
     Cell c;
-    const int nzb = lg.nzb, nxb = lg.nxb, nsh = lg.nsh;
-    int t = xcd_remap(blockIdx.x, gridDim.x);
-    c.s = shot0 + t % nsh;
-    t /= nsh;
-    const int zb = t % nzb;
-    t /= nzb;
-    const int xb = t % nxb, yo = t / nxb;
+    int t = lg.order == 2 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int zb, xb, yo;
+    if (lg.order == 0) {
+        zb = t % lg.nzb; t /= lg.nzb;
+        xb = t % lg.nxb; t /= lg.nxb;
+        yo = t % lg.ny;
+        c.s = shot0 + t / lg.ny;
+    } else {
+        c.s = shot0 + t % lg.nsh; t /= lg.nsh;
+        zb = t % lg.nzb; t /= lg.nzb;
+        xb = t % lg.nxb;
+        yo = t / lg.nxb;
+    }
     const int *b = box + 6 * c.s;
     c.z = b[0] + zb * BZ + threadIdx.x;
     c.x = b[2] + xb * BX + threadIdx.y;
@@ -396,7 +405,7 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
     Launch L;
     L.empty = ez <= 0 || ex <= 0 || ey <= 0;
     const int nzb = std::max(1, (ez + BZ - 1) / BZ), nxb = std::max(1, (ex + BX - 1) / BX);
-    L.ey = LG{s1 - s0, nzb, nxb};
+    L.ey = LG{s1 - s0, nzb, nxb, std::max(ey, 1), pl.chunk == 1 || pl.chunk == 2 ? pl.chunk : 0};
     L.block = dim3(BZ, BX, 1);
     L.grid = dim3((unsigned)((long long)(s1 - s0) * nzb * nxb * std::max(ey, 1)), 1, 1);
     return L;
