@@ -16,43 +16,34 @@ namespace {
 
 constexpr int BZ = 64, BX = 4;
 
+// first z of the 32-float-aligned storage line that contains node z
+__host__ __device__ __forceinline__ int zalign(int z) { return ((z + GH) & ~31) - GH; }
+
 struct Cell {
     int s, z, x, y;
     long long k;
     bool ok;
 };
 
-// 1D grid over (z-block, x-block, y-plane, shot).  order 0 (default): z-block fastest and the
-// shot slowest -- neighbouring tiles of one shot run together and share halos in L2;
-// order 1: shot fastest (the shots of one box-relative tile run together); order 2: as 1 with
-// an XCD-contiguous remap.  With computing boxes the shots' tiles sit at different absolute
-// positions, so order 0 measures fastest there.
+// Grid: x = z-block, y = x-block, z = y-plane + ny * shot (shot slowest: neighbouring tiles
+// of one shot run together and share halos in L2).
 struct LG {
-    int nsh, nzb, nxb, ny;  // shots, z-blocks, x-blocks, y-planes of the launch
-    int order;
+    int ny;             // y-planes of the launch (1 in 2D)
 };
 
 __device__ __forceinline__ Cell cell_of(const Geom &g, const int *__restrict__ box, int shot0,
                                         LG lg) {
     Cell c;
-    int t = lg.order == 2 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    int zb, xb, yo;
-    if (lg.order == 0) {
-        zb = t % lg.nzb; t /= lg.nzb;
-        xb = t % lg.nxb; t /= lg.nxb;
-        yo = t % lg.ny;
-        c.s = shot0 + t / lg.ny;
-    } else {
-        c.s = shot0 + t % lg.nsh; t /= lg.nsh;
-        zb = t % lg.nzb; t /= lg.nzb;
-        xb = t % lg.nxb;
-        yo = t / lg.nxb;
-    }
+    const int zb = blockIdx.x, xb = blockIdx.y;
+    const int sy = lg.ny == 1 ? 0 : (int)blockIdx.z / lg.ny;
+    const int yo = lg.ny == 1 ? 0 : (int)blockIdx.z - sy * lg.ny;
+    c.s = shot0 + (lg.ny == 1 ? (int)blockIdx.z : sy);
     const int *b = box + 6 * c.s;
-    c.z = b[0] + zb * BZ + threadIdx.x;
+    // z tiles start on a 128-byte boundary of the storage (the ghost frame shifts z = 0)
+    c.z = zalign(b[0]) + zb * BZ + threadIdx.x;
     c.x = b[2] + xb * BX + threadIdx.y;
     c.y = b[4] + yo;
-    c.ok = c.z < b[1] && c.x < b[3] && c.y < b[5];
+    c.ok = c.z >= b[0] && c.z < b[1] && c.x < b[3] && c.y < b[5];
     c.k = g.org + c.z + (long long)g.ld1 * c.x + g.ld2 * c.y;
     return c;
 }
@@ -398,16 +389,16 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
     int ez = 0, ex = 0, ey = 0;
     for (int s = s0; s < s1; ++s) {
         const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
-        ez = std::max(ez, b[1] - b[0]);
+        ez = std::max(ez, b[1] - zalign(b[0]));
         ex = std::max(ex, b[3] - b[2]);
         ey = std::max(ey, b[5] - b[4]);
     }
     Launch L;
     L.empty = ez <= 0 || ex <= 0 || ey <= 0;
     const int nzb = std::max(1, (ez + BZ - 1) / BZ), nxb = std::max(1, (ex + BX - 1) / BX);
-    L.ey = LG{s1 - s0, nzb, nxb, std::max(ey, 1), pl.chunk == 1 || pl.chunk == 2 ? pl.chunk : 0};
+    L.ey = LG{std::max(ey, 1)};
     L.block = dim3(BZ, BX, 1);
-    L.grid = dim3((unsigned)((long long)(s1 - s0) * nzb * nxb * std::max(ey, 1)), 1, 1);
+    L.grid = dim3((unsigned)nzb, (unsigned)nxb, (unsigned)((s1 - s0) * std::max(ey, 1)));
     return L;
 }
 

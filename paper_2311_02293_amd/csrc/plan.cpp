@@ -195,7 +195,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.margin = g->box_margin >= 0 ? g->box_margin : 2 * pl.N;
     pl.n[0] = g->n1; pl.n[1] = g->n2; pl.n[2] = g->ndim == 3 ? g->n3 : 1;
     for (int a = 0; a < 3; ++a) pl.M[a] = a < pl.nd ? pl.n[a] + 2 * g->nb : 1;
-    if ((long long)((pl.M[1] + 3) / 4) * pl.M[2] > 65535 || (pl.M[0] + 63) / 64 > 65535) {
+    if ((pl.M[1] + 3) / 4 > 65535 || (long long)pl.M[2] * acq->nshot > 65535) {
         err = "grid too large for the sweep-kernel launch geometry";
         return SMI_E_UNSUPPORTED;
     }

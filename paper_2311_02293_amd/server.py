@@ -1,0 +1,304 @@
+"""Shot server: continuous batching of modelling / gradient / RTM requests on one GPU.
+
+Requests (forward, FWI gradient or RTM jobs on their own grids and models) arrive over time.
+The server keeps a FIFO queue; at every scheduling pass it
+
+  * merges queued requests that share a grid and a model (same `model_key`) and a job kind
+    into one multi-shot call (the library runs all shots of a call in one launch per step);
+  * admits calls while their HBM footprint (workspace from smi_workspace_bytes + model, data
+    and result buffers) fits the remaining budget and a stream is free -- later, smaller calls
+    may pass a call that does not fit yet (backfill);
+  * launches each admitted call on its own HIP stream, so calls admitted while others run
+    overlap on the device;
+  * polls completion events, frees the call's memory and records per-request latency
+    (completion - arrival).
+
+A failing request (validation error) fails alone; the rest of the stream continues.  The
+scheduling logic is independent of the device: `HipBackend` runs calls through the C ABI,
+`FakeBackend` simulates durations on a virtual clock for CPU tests.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+from typing import Any, Dict, List, Optional
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclasses.dataclass(eq=False)
+class Request:
+    kind: str                     # "forward" | "grad" | "rtm"
+    job: I.Job                    # grid, model, acquisition, wavelet (host arrays)
+    arrival: float = 0.0          # seconds after the stream start
+    dobs: Optional[np.ndarray] = None   # flat observed data (grad, rtm)
+    model_key: Optional[str] = None     # requests with equal keys share grid + model
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class Outcome:
+    rid: int
+    kind: str
+    ok: bool
+    latency: float = float("nan")
+    result: Any = None
+    error: str = ""
+    gpts: float = 0.0
+    batch: int = 1
+
+
+def _grid_sig(g) -> tuple:
+    return (g.ndim, g.n1, g.n2, g.n3, g.d1, g.d2, g.d3, g.nb, g.order, g.nt, g.dt, g.fm, g.dr,
+            g.box, g.margin)
+
+
+def merge_requests(reqs: List[Request]) -> I.Job:
+    """One multi-shot job from requests that share grid and model."""
+    base = reqs[0].job
+    src = np.concatenate([r.job.acq.src for r in reqs])
+    recs = [r.job.acq.rec for r in reqs]
+    off = np.zeros(len(src) + 1, np.int32)
+    k = 0
+    for r in reqs:
+        for s in range(r.job.acq.nshot):
+            off[k + 1] = off[k] + r.job.acq.nrec(s)
+            k += 1
+    acq = I.Acquisition(src, off, np.concatenate(recs) if recs else np.zeros((0, 3)))
+    stf = np.concatenate([r.job.stf for r in reqs])
+    return I.Job(base.grid, base.vp, base.rho, acq, stf, name="+".join(r.job.name for r in reqs))
+
+
+class HipBackend:
+    """Runs calls through libsmi on one device, one HIP stream per in-flight call."""
+
+    def __init__(self, device: int = 0, nstreams: int = 4):
+        import torch
+        from . import binding as B
+        self.torch = torch
+        self.B = B
+        self.ctx = B.Context(device)
+        self.dev = f"cuda:{device}"
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(nstreams)]
+
+    def budget(self, frac: float = 0.85) -> int:
+        free, _ = self.torch.cuda.mem_get_info(self.dev)
+        return int(frac * free)
+
+    def footprint(self, job: I.Job, kind: str) -> int:
+        B = self.B
+        jobtype = {"forward": B.JOB_FORWARD, "grad": B.JOB_GRAD, "rtm": B.JOB_RTM}[kind]
+        ws = self.ctx.workspace_bytes(job.grid, job.acq, jobtype)
+        nrec = int(job.acq.rec_off[-1])
+        data = 4 * job.grid.nt * nrec * (2 if kind != "forward" else 1)
+        model = 4 * job.grid.npts * (2 + (2 if kind != "forward" else 0))
+        return ws + data + model + 4 * job.stf.size
+
+    def launch(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
+        torch = self.torch
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(self.dev, non_blocking=False)
+            rho = torch.from_numpy(np.ascontiguousarray(job.rho)).to(self.dev)
+            stf = torch.from_numpy(np.ascontiguousarray(job.stf)).to(self.dev)
+            jt = {"forward": self.B.JOB_FORWARD, "grad": self.B.JOB_GRAD, "rtm": self.B.JOB_RTM}[kind]
+            ws = torch.empty(self.ctx.workspace_bytes(job.grid, job.acq, jt), dtype=torch.uint8,
+                             device=self.dev)
+            if kind == "forward":
+                out, _, _ = self.ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=st)
+                keep = (vp, rho, stf, ws, out)
+            else:
+                d = torch.from_numpy(np.ascontiguousarray(dobs, np.float32)).to(self.dev)
+                if kind == "grad":
+                    g, J, _ = self.ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                    out = (g, J)
+                else:
+                    out = self.ctx.rtm_image(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                keep = (vp, rho, stf, ws, d, out)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        counts = self.ctx.last_counts()
+        return {"ev": ev, "out": out, "keep": keep, "gpts": sum(counts)}
+
+    def done(self, h) -> bool:
+        return h["ev"].query()
+
+    def result(self, h):
+        out = h["out"]
+        if isinstance(out, tuple):
+            return tuple(None if o is None else o.cpu().numpy() for o in out)
+        return out.cpu().numpy()
+
+    def gpts(self, h) -> float:
+        return h["gpts"]
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def idle(self):
+        time.sleep(2e-4)
+
+
+class FakeBackend:
+    """Virtual-clock backend for CPU tests: a call takes `cost(job)` seconds once launched,
+    calls on different slots overlap; `fail(job)` makes a launch raise."""
+
+    def __init__(self, cost=None, fail=None, footprint=None):
+        self.t = 0.0
+        self.cost = cost or (lambda job, kind: 1e-3 * job.acq.nshot)
+        self.fail = fail or (lambda job, kind: False)
+        self.fp = footprint or (lambda job, kind: 1)
+        self.running = []
+        self.launched = []
+
+    def budget(self, frac: float = 0.85) -> int:
+        return 1 << 60
+
+    def footprint(self, job, kind) -> int:
+        return self.fp(job, kind)
+
+    def launch(self, job, kind, dobs, slot):
+        if self.fail(job, kind):
+            raise RuntimeError("SMI_E_ARG: injected failure")
+        h = {"end": self.t + self.cost(job, kind), "job": job, "slot": slot}
+        self.launched.append((self.t, job.name, slot))
+        return h
+
+    def done(self, h) -> bool:
+        return self.t >= h["end"] - 1e-15
+
+    def result(self, h):
+        return h["job"].name
+
+    def gpts(self, h) -> float:
+        return 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def idle(self, pending_arrivals: Optional[float] = None, ends: Optional[List[float]] = None):
+        cands = [e for e in (ends or []) if e > self.t]
+        if pending_arrivals is not None and pending_arrivals > self.t:
+            cands.append(pending_arrivals)
+        self.t = min(cands) if cands else self.t + 1e-3
+
+
+class ShotServer:
+    def __init__(self, backend, budget_bytes: Optional[int] = None, max_inflight: int = 4,
+                 max_batch_shots: int = 64, batch: bool = True):
+        self.be = backend
+        self.budget = budget_bytes if budget_bytes is not None else backend.budget()
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch_shots
+        self.batch = batch
+        self.log: List[str] = []
+
+    def _batches(self, queue: deque) -> List[List[Request]]:
+        """Group queued requests (FIFO order of first member) into compatible calls."""
+        groups: Dict[tuple, List[Request]] = {}
+        order = []
+        for r in queue:
+            if self.batch and r.model_key is not None and r.kind in ("forward", "rtm", "grad"):
+                key = (r.kind, r.model_key, _grid_sig(r.job.grid))
+            else:
+                key = ("solo", r.rid)
+            if key not in groups:
+                groups[key] = []
+                order.append(key)
+            g = groups[key]
+            if sum(x.job.acq.nshot for x in g) + r.job.acq.nshot <= self.max_batch or not g:
+                g.append(r)
+        return [groups[k] for k in order]
+
+    def run(self, requests: List[Request]) -> Dict[str, Any]:
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for i, r in enumerate(reqs):
+            if r.rid < 0:
+                r.rid = i
+        be = self.be
+        t0 = be.now()
+        pending = deque(reqs)
+        queue: deque = deque()
+        inflight = []                 # (handle, [requests], footprint, slot)
+        free_slots = list(range(self.max_inflight))
+        used = 0
+        outcomes: Dict[int, Outcome] = {}
+        total_gpts = 0.0
+        while pending or queue or inflight:
+            now = be.now() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            # completions
+            still = []
+            for h, rs, fp, slot in inflight:
+                if be.done(h):
+                    tdone = be.now() - t0
+                    res = be.result(h)
+                    for k, r in enumerate(rs):
+                        outcomes[r.rid] = Outcome(r.rid, r.kind, True, tdone - r.arrival,
+                                                  res if len(rs) == 1 else (k, res),
+                                                  gpts=be.gpts(h) / len(rs), batch=len(rs))
+                    total_gpts += be.gpts(h)
+                    used -= fp
+                    free_slots.append(slot)
+                else:
+                    still.append((h, rs, fp, slot))
+            inflight = still
+            # admissions (FIFO with backfill)
+            launched_any = False
+            if queue and free_slots:
+                for grp in self._batches(queue):
+                    if not free_slots:
+                        break
+                    job = merge_requests(grp) if len(grp) > 1 else grp[0].job
+                    kind = grp[0].kind
+                    try:
+                        fp = be.footprint(job, kind)
+                    except Exception as e:      # validation error: this request fails alone
+                        for r in grp:
+                            outcomes[r.rid] = Outcome(r.rid, r.kind, False, error=str(e))
+                            queue.remove(r)
+                        continue
+                    if fp > self.budget:
+                        for r in grp:
+                            outcomes[r.rid] = Outcome(r.rid, r.kind, False,
+                                                      error=f"footprint {fp} B exceeds the budget")
+                            queue.remove(r)
+                        continue
+                    if used + fp > self.budget:
+                        continue                 # waits for memory; smaller calls may pass
+                    dobs = None
+                    if kind != "forward":
+                        dobs = np.concatenate([np.ravel(r.dobs) for r in grp])
+                    slot = free_slots.pop()
+                    try:
+                        h = be.launch(job, kind, dobs, slot)
+                    except Exception as e:
+                        free_slots.append(slot)
+                        for r in grp:
+                            outcomes[r.rid] = Outcome(r.rid, r.kind, False, error=str(e))
+                            queue.remove(r)
+                        continue
+                    used += fp
+                    for r in grp:
+                        queue.remove(r)
+                    inflight.append((h, grp, fp, slot))
+                    launched_any = True
+            if not launched_any:
+                if isinstance(be, FakeBackend):
+                    be.idle(pending[0].arrival + t0 if pending else None,
+                            [h["end"] for h, _, _, _ in inflight])
+                else:
+                    be.idle()
+        makespan = be.now() - t0
+        lat = np.array([o.latency for o in outcomes.values() if o.ok])
+        return {"outcomes": [outcomes[r.rid] for r in reqs],
+                "p50": float(np.percentile(lat, 50)) if lat.size else math.nan,
+                "p99": float(np.percentile(lat, 99)) if lat.size else math.nan,
+                "makespan": makespan, "gpts": total_gpts,
+                "gpts_per_s": total_gpts / makespan if makespan > 0 else math.nan,
+                "failed": sum(1 for o in outcomes.values() if not o.ok)}

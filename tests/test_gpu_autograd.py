@@ -1,0 +1,116 @@
+"""Differentiation: the autograd wrapper's hand-written backward (the adjoint reverse pass with
+boundary-saving reconstruction) against smi_fwi_grad, the FP64 oracle gradient, and central
+finite differences of the GPU forward map on 20 random cells."""
+import numpy as np
+import pytest
+
+from paper_2311_02293_amd import inputs as I
+from helpers import dev, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def grad_job(n1=80, n2=200, nt=800, nshot=2, box=1):
+    job = I.config3(n1=n1, n2=n2, nt=nt, nshot=nshot)
+    job.grid.box = box
+    vt = job.extra["vp_true"]
+    job.grid.vpmin = float(min(job.vp.min(), vt.min()))
+    job.grid.vpmax = float(1.05 * max(job.vp.max(), vt.max()))
+    return job
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_02293_amd import binding as B
+    return B.Context(0)
+
+
+def test_autograd_backward_equals_fwi_grad(ctx):
+    import torch
+    from paper_2311_02293_amd.autograd import forward_modelling, l2_misfit
+    job = grad_job()
+    vp, rho, stf = dev(job)
+    vt = torch.from_numpy(job.extra["vp_true"]).cuda()
+    dobs, _, _ = ctx.forward(job.grid, job.acq, vt, rho, stf)
+    v = vp.clone().requires_grad_(True)
+    dcal = forward_modelling(v, rho, stf, job.grid, job.acq, ctx)
+    J = l2_misfit(dcal, dobs, job.grid.dt)
+    J.backward()
+    g_auto = v.grad.cpu().numpy()
+    g_ref, J_ref, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+    say("J", float(J), float(J_ref.cpu()[0]), "grad rel", rel_l2(g_auto.ravel(), g_ref.cpu().numpy()))
+    assert abs(float(J) - float(J_ref.cpu()[0])) <= 1e-6 * float(J)
+    assert rel_l2(g_auto.ravel(), g_ref.cpu().numpy()) <= 1e-6
+
+
+def test_autograd_matches_oracle_gradient(ctx):
+    import torch
+    from oracle import oracle as O
+    from paper_2311_02293_amd.autograd import forward_modelling, l2_misfit
+    job = grad_job(n1=60, n2=150, nt=600)
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    g_ref, J_ref = O.fwi_grad(job, dobs, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    d_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    v = vp.clone().requires_grad_(True)
+    J = l2_misfit(forward_modelling(v, rho, stf, job.grid, job.acq, ctx), d_t, job.grid.dt)
+    J.backward()
+    err = rel_l2(v.grad.cpu().numpy(), g_ref)
+    say("autograd vs oracle gradient", err, "J", float(J), J_ref)
+    assert err <= 1e-4
+    assert abs(float(J) - J_ref) <= 1e-4 * J_ref
+
+
+def test_gradient_matches_finite_differences(ctx):
+    """dJ/dVp per cell against central differences of J computed with the GPU forward
+    (FP32 fields, FP64 misfit sum), 20 cells drawn with seed 1003 at least 2N cells inside
+    the interior edge and with |g| >= 1% of max|g|: relative error <= 1e-3."""
+    import torch
+    from paper_2311_02293_amd.autograd import forward_modelling, l2_misfit
+    job = grad_job(n1=70, n2=160, nt=700, nshot=2)
+    vp, rho, stf = dev(job)
+    vt = torch.from_numpy(job.extra["vp_true"]).cuda()
+    dobs, _, _ = ctx.forward(job.grid, job.acq, vt, rho, stf)
+    v = vp.clone().requires_grad_(True)
+    J = l2_misfit(forward_modelling(v, rho, stf, job.grid, job.acq, ctx), dobs, job.grid.dt)
+    J.backward()
+    g = v.grad.cpu().numpy()
+    N = job.grid.order // 2
+    n2, n1 = job.vp.shape
+    gmax = np.max(np.abs(g))
+    cand = [(ix, iz) for ix in range(2 * N, n2 - 2 * N) for iz in range(2 * N, n1 - 2 * N)
+            if abs(g[ix, iz]) >= 0.01 * gmax]
+    rng = np.random.default_rng(1003)
+    pick = rng.choice(len(cand), 20, replace=False)
+
+    def Jof(vv):
+        d, _, _ = ctx.forward(job.grid, job.acq, vv, rho, stf)
+        return float(l2_misfit(d, dobs, job.grid.dt))
+
+    worst = 0.0
+    for k in pick:
+        ix, iz = cand[k]
+        eps = 5e-3 * float(job.vp[ix, iz])
+        vpl = vp.clone()
+        vpl[ix, iz] += eps
+        vmi = vp.clone()
+        vmi[ix, iz] -= eps
+        fd = (Jof(vpl) - Jof(vmi)) / (2 * eps)
+        err = abs(fd - g[ix, iz]) / abs(g[ix, iz])
+        worst = max(worst, err)
+    say("worst FD relative error over 20 cells", worst)
+    assert worst <= 1e-3
+
+
+def test_backward_twice_raises(ctx):
+    import torch
+    from paper_2311_02293_amd.autograd import forward_modelling
+    job = grad_job(n1=40, n2=80, nt=100, nshot=1)
+    vp, rho, stf = dev(job)
+    v = vp.clone().requires_grad_(True)
+    d = forward_modelling(v, rho, stf, job.grid, job.acq, ctx)
+    s = (d * d).sum()
+    s.backward(retain_graph=True)
+    with pytest.raises(RuntimeError):
+        s.backward()
