@@ -64,6 +64,8 @@ def lib():
         L.og_fwd_box.argtypes = [gp, ip, C.c_int, ip, ip]
         L.og_band_size.argtypes = [gp]
         L.og_band_size.restype = C.c_size_t
+        L.og_band_levels.argtypes = [gp]
+        L.og_band_levels.restype = C.c_size_t
         L.og_forward.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, C.c_int,
                                  ip, dp]
         L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp]
@@ -178,7 +180,7 @@ def forward(gr: OgGrid, vp, rho, src, stf, rec, *, init=None, hist=False, bands=
     P = padded_size(gr)
     out = {"dcal": np.zeros((gr.nt, nrec))}
     out["hist"] = np.zeros((gr.nt + 1, 4, P)) if hist else None
-    out["bands"] = np.zeros(((gr.nt + gr.dr - 1) // gr.dr, band_size(gr))) if bands else None
+    out["bands"] = np.zeros((int(lib().og_band_levels(C.byref(gr))), band_size(gr))) if bands else None
     out["final"] = np.zeros((4, P)) if final else None
     snap_it = np.ascontiguousarray(np.asarray(list(snaps), np.int32))
     out["snaps"] = np.zeros((len(snap_it), interior_size(gr)))

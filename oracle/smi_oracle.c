@@ -354,6 +354,39 @@ size_t og_band_size(const og_grid *g)
     return s;
 }
 
+/* Saved band levels.  dr = 1: every level 0..nt-1.  dr > 1: the levels k dr for
+ * k = 0 .. (nt-1)/dr + OG_TAPS, so that the time interpolator below finds all of its taps for
+ * every level 0..nt-1 (the forward pass continues past nt, source off, to save the last
+ * ones).                                                                               */
+#define OG_TAPS 4          /* half-width, in saved levels, of the band interpolator */
+#define OG_KAISER_BETA 6.31
+
+size_t og_band_levels(const og_grid *g)
+{
+    return g->dr == 1 ? (size_t)g->nt : (size_t)((g->nt - 1) / g->dr + OG_TAPS + 1);
+}
+
+static double og_bessel_i0(double x)
+{
+    double s = 1.0, t = 1.0;
+    for (int k = 1; k < 60; k++) {
+        t *= (x / (2.0 * k)) * (x / (2.0 * k));
+        s += t;
+        if (t < 1e-17 * s) break;
+    }
+    return s;
+}
+
+/* Kaiser-windowed sinc weight of a sample at distance u (in saved levels), half-width R */
+static double og_ksinc(double u)
+{
+    if (fabs(u) >= OG_TAPS) return 0.0;
+    double x = u / OG_TAPS;
+    double win = og_bessel_i0(OG_KAISER_BETA * sqrt(1.0 - x * x)) / og_bessel_i0(OG_KAISER_BETA);
+    double sc = u == 0.0 ? 1.0 : sin(M_PI * u) / (M_PI * u);
+    return sc * win;
+}
+
 /* copy planes [start, start+w) along axis a (interior extent elsewhere) between the field
  * and buf; dir = 0: field -> buf, 1: buf -> field, 2: field <- (1-wt)*buf + wt*buf2   */
 static size_t og_block(const og_model *m, double *fld, int a, int start, int w, double *buf,
@@ -439,7 +472,7 @@ static void og_take_snaps(const og_model *m, const double *p, int level, int nsn
  * with CPML, p[src] += dt stf[it] / dV (the explosive source f_p of eq. 1 as a cell
  * average), dcal[it][r] = p^{it+1}[rec_r].
  * Optional: init (4P: p, v1, v2, v3 at level 0), hist ((nt+1) x 4P: every (p^n, v^{n-1/2})),
- * bands (ceil(nt/dr) x og_band_size), final (4P at level nt), snaps of interior p. */
+ * bands (og_band_levels x og_band_size), final (4P at level nt), snaps of interior p. */
 int og_forward(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, double *dcal, const double *init,
                double *hist, double *bands, double *final_state, int nsnap, const int *snap_it,
@@ -452,20 +485,27 @@ int og_forward(const og_grid *g, const double *vp, const double *rho, const int 
     if (init) og_state_set(&m, &f, init);
     size_t B = og_band_size(g);
     size_t sidx = IDX(&m, src[0], src[1], src[2]);
+    /* with decimated bands the loop continues (source off, nothing recorded) until the last
+     * saved level the interpolator needs */
+    int last = g->nt;
+    if (bands && g->dr > 1) last = (int)(og_band_levels(g) - 1) * g->dr;
     og_take_snaps(&m, f.p, 0, nsnap, snap_it, snaps);
-    for (int it = 0; it < g->nt; it++) {
-        if (hist) og_state_get(&m, &f, hist + (size_t)it * 4 * m.P);
-        if (bands && it % g->dr == 0) og_bands(&m, &f, bands + (size_t)(it / g->dr) * B, NULL, 0.0, 0, 2);
+    for (int it = 0; it <= last; it++) {
+        if (hist && it <= g->nt) og_state_get(&m, &f, hist + (size_t)it * 4 * m.P);
+        if (it == g->nt && final_state) og_state_get(&m, &f, final_state);
+        if (bands && it % g->dr == 0 && (size_t)(it / g->dr) < og_band_levels(g))
+            og_bands(&m, &f, bands + (size_t)(it / g->dr) * B, NULL, 0.0, 0, 2);
+        if (it == last) break;
         int lo[3], hi[3];
         og_fwd_box_m(&m, src, it, lo, hi);
         og_step(&m, &f, lo, hi);
-        f.p[sidx] += g->dt * stf[it] / m.dV;
-        for (int r = 0; r < nrec; r++)
-            dcal[(size_t)it * nrec + r] = f.p[IDX(&m, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
-        og_take_snaps(&m, f.p, it + 1, nsnap, snap_it, snaps);
+        if (it < g->nt) {
+            f.p[sidx] += g->dt * stf[it] / m.dV;
+            for (int r = 0; r < nrec; r++)
+                dcal[(size_t)it * nrec + r] = f.p[IDX(&m, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+            og_take_snaps(&m, f.p, it + 1, nsnap, snap_it, snaps);
+        }
     }
-    if (hist) og_state_get(&m, &f, hist + (size_t)g->nt * 4 * m.P);
-    if (final_state) og_state_get(&m, &f, final_state);
     og_field_free(&f);
     og_free_model(&m);
     return 0;
@@ -473,20 +513,28 @@ int og_forward(const og_grid *g, const double *vp, const double *rho, const int 
 
 /* ------------------------------------------------------------------ reconstruction (Sec. 4.2) */
 
-/* Restore bands at level `it` (p^it and v^{it-1/2}).  dr = 1: a copy.  dr > 1: linear
- * interpolation in time between the saved levels t0 = floor(it/dr) dr and
- * t1 = min(t0 + dr, nt); level nt is taken from the final state (fin_bands).         */
-static void og_restore(const og_model *m, og_field *f, const double *bands, const double *fin_bands,
-                       int it, int which)
+/* Restore bands at level `it` (p^it and v^{it-1/2}).  dr = 1: a copy of the saved level.
+ * dr > 1 (Sec. 4.2 interpolates decimated boundaries without naming the kernel): a
+ * Kaiser-windowed sinc in time over the 2 OG_TAPS saved levels around `it`, weights
+ * normalised to sum 1; levels before 0 are exactly zero (the field starts at rest).      */
+static void og_restore(const og_model *m, og_field *f, const double *bands, int it, int which)
 {
     size_t B = og_band_size(&m->g);
-    int dr = m->g.dr, nt = m->g.nt;
-    int k0 = it / dr, t0 = k0 * dr;
-    if (t0 == it) { og_bands(m, f, (double *)(bands + (size_t)k0 * B), NULL, 0.0, 1, which); return; }
-    int t1 = t0 + dr < nt ? t0 + dr : nt;
-    const double *b1 = t1 == nt ? fin_bands : bands + (size_t)(k0 + 1) * B;
-    double wt = (double)(it - t0) / (double)(t1 - t0);
-    og_bands(m, f, (double *)(bands + (size_t)k0 * B), b1, wt, 2, which);
+    int dr = m->g.dr;
+    int k0 = it / dr;
+    if (it % dr == 0) { og_bands(m, f, (double *)(bands + (size_t)k0 * B), NULL, 0.0, 1, which); return; }
+    double u = (double)it / dr, wsum = 0.0;
+    double *tmp = calloc(B, sizeof(double));
+    for (int k = k0 - OG_TAPS + 1; k <= k0 + OG_TAPS; k++) {
+        double w = og_ksinc(u - k);
+        wsum += w;
+        if (k < 0) continue;
+        const double *b = bands + (size_t)k * B;
+        for (size_t q = 0; q < B; q++) tmp[q] += w * b[q];
+    }
+    for (size_t q = 0; q < B; q++) tmp[q] /= wsum;
+    og_bands(m, f, tmp, NULL, 0.0, 1, which);
+    free(tmp);
 }
 
 /* One reverse iteration (Alg. 2 reverse loop, source-field part), from (p^{it+1}, v^{it+1/2})
@@ -494,7 +542,7 @@ static void og_restore(const og_model *m, og_field *f, const double *bands, cons
  *   p[src] -= dt stf[it]/dV;  p^it = p^{it+1} + dt kappa div v^{it+1/2};  restore p band;
  *   v_a^{it-1/2} = v_a^{it+1/2} + dt beta_a d_a p^it;                      restore v bands. */
 static void og_recon_iter(const og_model *m, og_field *f, const int *src, const double *stf,
-                          const double *bands, const double *fin_bands, int it)
+                          const double *bands, int it)
 {
     const double dt = m->g.dt;
     int nb = m->g.nb;
@@ -514,7 +562,7 @@ static void og_recon_iter(const og_model *m, og_field *f, const int *src, const 
                 size_t k = IDX(m, i1, i2, i3);
                 f->p[k] += dt * m->kap[k] * divv(m, f, i1, i2, i3);
             }
-    og_restore(m, f, bands, fin_bands, it, 0);
+    og_restore(m, f, bands, it, 0);
     for (int a = 0; a < m->nd; a++) {
         int vhi[3] = {hi[0], hi[1], hi[2]};
         if (vhi[a] > nb + m->n[a] - 2) vhi[a] = nb + m->n[a] - 2;
@@ -526,17 +574,7 @@ static void og_recon_iter(const og_model *m, og_field *f, const int *src, const 
                     f->v[a][k] += dt * m->bet[a][k] * dplus(m, f->p, i1, i2, i3, a);
                 }
     }
-    og_restore(m, f, bands, fin_bands, it, 1);
-}
-
-static double *og_final_bands(const og_model *m, const double *final_state)
-{
-    og_field t;
-    t.p = (double *)final_state;
-    for (int a = 0; a < 3; a++) t.v[a] = (double *)final_state + (a + 1) * m->P;
-    double *fb = malloc(og_band_size(&m->g) * sizeof(double));
-    og_bands(m, &t, fb, NULL, 0.0, 0, 2);
-    return fb;
+    og_restore(m, f, bands, it, 1);
 }
 
 /* Rebuild the source field backwards in time from the final state and the saved bands;
@@ -550,13 +588,11 @@ int og_reconstruct(const og_grid *g, const double *vp, const double *rho, const 
     og_field f;
     og_field_alloc(&f, m.P);
     og_state_set(&m, &f, final_state);
-    double *fb = og_final_bands(&m, final_state);
     og_take_snaps(&m, f.p, g->nt, nsnap, snap_it, snaps);
     for (int it = g->nt - 1; it >= 0; it--) {
-        og_recon_iter(&m, &f, src, stf, bands, fb, it);
+        og_recon_iter(&m, &f, src, stf, bands, it);
         og_take_snaps(&m, f.p, it, nsnap, snap_it, snaps);
     }
-    free(fb);
     og_field_free(&f);
     og_free_model(&m);
     return 0;
@@ -587,11 +623,9 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
     og_field f, q;
     og_field_alloc(&f, m.P);
     og_field_alloc(&q, m.P);
-    double *fb = NULL;
     if (!hist) {
         if (!bands || !final_state) { og_field_free(&f); og_field_free(&q); og_free_model(&m); return -2; }
         og_state_set(&m, &f, final_state);
-        fb = og_final_bands(&m, final_state);
     }
     int nb = m.g.nb;
     for (int it = g->nt - 1; it >= 0; it--) {
@@ -615,7 +649,7 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
         og_adj_box_m(&m, nrec, rec, it, lo, hi);
         og_step(&m, &q, lo, hi);
         if (hist) og_state_set(&m, &f, hist + (size_t)it * 4 * m.P);
-        else og_recon_iter(&m, &f, src, stf, bands, fb, it);
+        else og_recon_iter(&m, &f, src, stf, bands, it);
         if (image || illum) {
 #pragma omp parallel for collapse(2) schedule(static)
             for (int i3 = 0; i3 < m.n[2]; i3++)
@@ -628,7 +662,6 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
                     }
         }
     }
-    free(fb);
     og_field_free(&f);
     og_field_free(&q);
     og_free_model(&m);

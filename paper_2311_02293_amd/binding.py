@@ -132,8 +132,8 @@ class State:
         self.consumed = False
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            lib().smi_state_destroy(self.handle)
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.smi_state_destroy(self.handle)
             self.handle = None
 
 
@@ -150,8 +150,8 @@ class Context:
         self._ws = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().smi_ctx_destroy(self.h)
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.smi_ctx_destroy(self.h)
             self.h = None
 
     # -------------------------------------------------------------- helpers

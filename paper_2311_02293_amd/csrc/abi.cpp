@@ -91,11 +91,13 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
         HIPCHK(hipMemcpyAsync(w.cpml.a_h[a], ah.data(), M, hipMemcpyHostToDevice, st), "cpml");
         HIPCHK(hipMemcpyAsync(w.cpml.b_h[a], bh.data(), M, hipMemcpyHostToDevice, st), "cpml");
     }
-    size_t nb = pl.fbox.size() * sizeof(int);
-    HIPCHK(hipMemcpyAsync(w.fbox, pl.fbox.data(), nb, hipMemcpyHostToDevice, st), "fbox");
+    HIPCHK(hipMemcpyAsync(w.fbox, pl.fbox.data(), pl.fbox.size() * sizeof(int),
+                          hipMemcpyHostToDevice, st), "fbox");
     if (pl.adjoint) {
-        HIPCHK(hipMemcpyAsync(w.abox, pl.abox.data(), nb, hipMemcpyHostToDevice, st), "abox");
-        HIPCHK(hipMemcpyAsync(w.rbox, pl.rbox.data(), nb, hipMemcpyHostToDevice, st), "rbox");
+        HIPCHK(hipMemcpyAsync(w.abox, pl.abox.data(), pl.abox.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st), "abox");
+        HIPCHK(hipMemcpyAsync(w.rbox, pl.rbox.data(), pl.rbox.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st), "rbox");
     }
     int R = pl.rec_off[pl.nshot];
     if (R > 0) {
@@ -158,7 +160,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     smi::StepCtx c{&pl, &w, stf, st, ctx->opt_kernel == 1};
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
-    bool fused = ctx->opt_kernel == 2 && pl.dbuf && smi::fused_fwd_available(pl);
+    bool fused = ctx->opt_kernel == 2 && pl.dbuf && pl.g.dr == 1 && smi::fused_fwd_available(pl);
     if (fused) {
         s = zero_fields(ctx, pl, w.f2, st);
         if (s != SMI_OK) return s;
@@ -167,26 +169,33 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         HIPCHK(hipMemsetAsync(dcal, 0, sizeof(float) * (size_t)pl.g.nt * pl.rec_off[pl.nshot], st),
                "dcal clear");
     }
-    for (int it = 0; it < pl.g.nt; ++it) {
+    const int nt = pl.g.nt, dr = pl.g.dr;
+    const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
+    for (int it = 0; it < pl.nrun; ++it) {
         // fused steps alternate between the two buffers: level it lives in cur
         const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
         const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
-        if (pl.save && it % pl.g.dr == 0) HIPCHK(smi::band_save(c, cur, it / pl.g.dr), "band save");
+        if (pl.save && it % dr == 0) HIPCHK(smi::band_save(c, cur, it / dr), "band save");
         if (fused) {
             HIPCHK(smi::fwd_step_fused(c, cur, nxt, it, dcal), "forward step");
         } else {
             HIPCHK(smi::fwd_step(c, it), "forward step");
-            HIPCHK(smi::extract(c, it, dcal), "extract");
+            if (it < nt) HIPCHK(smi::extract(c, it, dcal), "extract");
         }
         for (int k = 0; k < nsnap; ++k)
             if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
+        if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
+            HIPCHK(hipMemcpyAsync(w.fin, w.f.p, state_bytes, hipMemcpyDeviceToDevice, st), "final copy");
     }
-    if (fused && (pl.g.nt & 1)) {
+    if (fused && (pl.nrun & 1)) {
         // the final level is in the second buffer; the reverse pass works on the first
         HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, st),
                "final state copy");
     }
-    if (pl.save) HIPCHK(smi::band_save(c, w.f, pl.nsave), "band save (final level)");
+    if (pl.save && dr > 1) {
+        HIPCHK(smi::band_save(c, w.f, pl.nsave - 1), "band save (last level)");
+        HIPCHK(hipMemcpyAsync(w.f.p, w.fin, state_bytes, hipMemcpyDeviceToDevice, st), "final restore");
+    }
     ctx->cnt[0] = pl.cnt_fwd;
     ctx->cnt[1] = ctx->cnt[2] = 0;
     ctx->bytes[0] = pl.bytes_fwd;

@@ -7,6 +7,8 @@
 // 256-byte coalesced row), 4 x-columns per 256-lane workgroup; neighbours come from the
 // L1/L2 caches.  Each launch covers one time step of every shot of the batch, restricted to
 // that shot's computing box (grid z-dimension = shot x y-plane).
+#include <cmath>
+
 #include "smi_internal.hpp"
 #include "device.hpp"
 
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml 
     }
     float *pp = f.p + c.s * g.P + c.k;
     float pn = *pp - m.kdt[c.k] * sdiv;
-    if (SRC && c.k == src_cell[c.s]) pn += g.src_scale * stf[(long long)c.s * nt + it];
+    if (SRC && it < nt && c.k == src_cell[c.s]) pn += g.src_scale * stf[(long long)c.s * nt + it];
     *pp = pn;
     if (IMG) {
         int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
@@ -270,6 +272,34 @@ __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, flo
     if (dir == 0) buf[bo] = *fld;
     else if (dir == 1) *fld = buf[bo];
     else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
+}
+
+// Band cells at level it = sum_j w[j] * saved level slot[j] (decimated bands, dr > 1).
+struct Taps {
+    int n;
+    int slot[2 * kTaps];
+    float w[2 * kTaps];
+};
+
+__global__ __launch_bounds__(256) void k_band_mix(Geom g, Fields f, BandDesc bd, const float *buf,
+                                                  long long shot_stride, Taps tp, int which) {
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= bd.B) return;
+    int s = blockIdx.y;
+    int b = 0;
+#pragma unroll 1
+    while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
+    const BandBlock &bl = bd.blk[b];
+    if (which != 2 && bl.field != which) return;
+    long long r = q - bl.off;
+    int z = bl.org[0] + (int)(r % bl.ext[0]);
+    r /= bl.ext[0];
+    int x = bl.org[1] + (int)(r % bl.ext[1]);
+    int y = bl.org[2] + (int)(r / bl.ext[1]);
+    long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
+    float acc = 0.f;
+    for (int j = 0; j < tp.n; ++j) acc += tp.w[j] * buf[s * shot_stride + (long long)tp.slot[j] * bd.B + q];
+    (bl.field == 0 ? f.p : f.v[bl.axis])[s * g.P + k] = acc;
 }
 
 // ---------------------------------------------------------------- receivers
@@ -524,33 +554,60 @@ hipError_t extract(const StepCtx &c, int it, float *dcal) {
 hipError_t band_save(const StepCtx &c, const Fields &f, int slot) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    long long ss = (long long)(pl.nsave + 1) * pl.band.B;
+    long long ss = (long long)pl.nsave * pl.band.B;
     hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
                        f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
                        ss, 0, 0, 2, 0.f);
     return hipGetLastError();
 }
 
-// bands at level it: saved level (copy) or linear interpolation between the saved levels
-// t0 = floor(it/dr) dr and t1 = min(t0 + dr, nt) (slot nsave holds level nt).
+// Kaiser-windowed sinc of half-width kTaps levels (u in saved levels)
+static double ksinc(double u) {
+    if (std::fabs(u) >= kTaps) return 0.0;
+    auto i0 = [](double x) {
+        double s = 1.0, t = 1.0;
+        for (int k = 1; k < 60; ++k) {
+            t *= (x / (2.0 * k)) * (x / (2.0 * k));
+            s += t;
+            if (t < 1e-17 * s) break;
+        }
+        return s;
+    };
+    double x = u / kTaps;
+    double win = i0(kKaiserBeta * std::sqrt(1.0 - x * x)) / i0(kKaiserBeta);
+    return (u == 0.0 ? 1.0 : std::sin(M_PI * u) / (M_PI * u)) * win;
+}
+
+// Bands at level it (p^it and v^{it-1/2}): the saved level itself when it is one (dr = 1 or
+// it % dr == 0); otherwise a Kaiser-windowed sinc in time over the 2 kTaps saved levels
+// around it, weights normalised to sum 1, levels before 0 being zero (field at rest).
 hipError_t band_restore(const StepCtx &c, int it, int which) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    long long ss = (long long)(pl.nsave + 1) * pl.band.B;
-    int dr = pl.g.dr, nt = pl.g.nt;
-    int k0 = it / dr, t0 = k0 * dr;
-    float *b0 = w.bands + (size_t)k0 * pl.band.B;
-    if (t0 == it) {
+    long long ss = (long long)pl.nsave * pl.band.B;
+    const int dr = pl.g.dr;
+    const int k0 = it / dr;
+    if (it % dr == 0) {
         hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
-                           pl.geom, w.f, pl.band, b0, (const float *)nullptr, ss, 0, 1, which, 0.f);
-    } else {
-        int t1 = std::min(t0 + dr, nt);
-        int k1 = t1 == nt ? pl.nsave : k0 + 1;
-        float wt = (float)((double)(it - t0) / (double)(t1 - t0));
-        hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
-                           pl.geom, w.f, pl.band, b0,
-                           (const float *)(w.bands + (size_t)k1 * pl.band.B), ss, 0, 2, which, wt);
+                           pl.geom, w.f, pl.band, w.bands + (size_t)k0 * pl.band.B,
+                           (const float *)nullptr, ss, 0, 1, which, 0.f);
+        return hipGetLastError();
     }
+    Taps tp{};
+    const double u = (double)it / dr;
+    double ws = 0.0, wk[2 * kTaps];
+    int sl[2 * kTaps], n = 0;
+    for (int k = k0 - kTaps + 1; k <= k0 + kTaps; ++k) {
+        const double wt = ksinc(u - k);
+        ws += wt;
+        if (k < 0) continue;
+        sl[n] = k;
+        wk[n++] = wt;
+    }
+    tp.n = n;
+    for (int j = 0; j < n; ++j) { tp.slot[j] = sl[j]; tp.w[j] = (float)(wk[j] / ws); }
+    hipLaunchKernelGGL(k_band_mix, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
+                       pl.geom, w.f, pl.band, (const float *)w.bands, ss, tp, which);
     return hipGetLastError();
 }
 

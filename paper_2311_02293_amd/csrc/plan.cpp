@@ -151,14 +151,15 @@ void algorithmic_bytes(Plan &pl) {
     const int nt = pl.g.nt, ns = pl.nshot, nd = pl.nd;
     double R = pl.rec_off[ns];
     double bf = 0, br = 0;
-    for (int it = 0; it < nt; ++it) {
+    for (int it = 0; it < pl.nrun; ++it) {
         double maxf = 0, maxa = 0;
+        const bool adj_it = pl.adjoint && it < nt;
         for (int s = 0; s < ns; ++s) {
             const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
             double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
             bf += 8.0 * (nd + 1) * vf + 16.0 * box_slab_cells(pl, fb);
             maxf = std::max(maxf, vf);
-            if (pl.adjoint) {
+            if (adj_it) {
                 const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
                 const int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
                 double va = (double)std::max(0, ab[1] - ab[0]) * std::max(0, ab[3] - ab[2]) *
@@ -170,9 +171,10 @@ void algorithmic_bytes(Plan &pl) {
                 maxa = std::max(maxa, std::max(va, vr));
             }
         }
-        bf += 4.0 * (nd + 1) * maxf + 8.0 * R;
+        bf += 4.0 * (nd + 1) * maxf + (it < nt ? 8.0 * R : 0.0);
         if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
-        if (pl.adjoint) br += 4.0 * (nd + 1) * maxa + 8.0 * R + 8.0 * (double)ns * pl.band.B;
+        const double restore = pl.g.dr == 1 || it % pl.g.dr == 0 ? 8.0 : 4.0 * (2 * kTaps + 1);
+        if (adj_it) br += 4.0 * (nd + 1) * maxa + 8.0 * R + restore * (double)ns * pl.band.B;
     }
     pl.bytes_fwd = bf;
     pl.bytes_rev = pl.adjoint ? br : 0;
@@ -274,12 +276,18 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
 
     // computing boxes (Sec. 4.1)
     const int nt = g->nt, ns = pl.nshot;
-    pl.fbox.assign((size_t)nt * ns * 6, 0);
+    // decimated bands (dr > 1): the interpolator needs saved levels up to (nt-1)/dr + kTaps,
+    // so the forward pass continues past nt (source off, nothing recorded) to that level
+    pl.nsave = !pl.save ? 0 : (g->dr == 1 ? nt : (nt - 1) / g->dr + kTaps + 1);
+    pl.nrun = pl.save && g->dr > 1 ? (pl.nsave - 1) * g->dr : nt;
+    const int nrun = pl.nrun;
+    pl.fbox.assign((size_t)nrun * ns * 6, 0);
     pl.abox.assign(pl.adjoint ? (size_t)nt * ns * 6 : 0, 0);
     pl.rbox.assign(pl.adjoint ? (size_t)nt * ns * 6 : 0, 0);
     pl.cnt_fwd = pl.cnt_adj = pl.cnt_rec = 0;
-    for (int it = 0; it < nt; ++it)
+    for (int it = 0; it < nrun; ++it)
         for (int s = 0; s < ns; ++s) {
+            const bool adj_it = pl.adjoint && it < nt;
             int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
             double vf = 1, va = 1, vr = 1;
             for (int a = 0; a < 3; ++a) {
@@ -291,7 +299,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                 }
                 fb[2 * a] = lo; fb[2 * a + 1] = hi;
                 vf *= hi - lo;
-                if (pl.adjoint) {
+                if (adj_it) {
                     int *ab = &pl.abox[((size_t)it * ns + s) * 6];
                     int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
                     int alo = 0, ahi = pl.M[a];
@@ -320,7 +328,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                 }
             }
             pl.cnt_fwd += vf;
-            if (pl.adjoint) { pl.cnt_adj += va; pl.cnt_rec += vr; }
+            if (adj_it) { pl.cnt_adj += va; pl.cnt_rec += vr; }
         }
     algorithmic_bytes(pl);
 
@@ -350,7 +358,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
         }
     }
     bd.B = off;
-    pl.nsave = pl.save ? (nt + g->dr - 1) / g->dr : 0;
+
 
     // device geometry
     Geom &G = pl.geom;
@@ -379,8 +387,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     size_t cp = 0;
     for (int a = 0; a < pl.nd; ++a) cp += 4 * (size_t)pl.M[a];
     pl.off_cpml = take(sizeof(float) * cp);
-    size_t nbox = (size_t)nt * ns * 6;
-    pl.off_tables = take(sizeof(int) * nbox * (pl.adjoint ? 3 : 1));
+    pl.off_tables = take(sizeof(int) * (pl.fbox.size() + pl.abox.size() + pl.rbox.size()));
     pl.off_recv = take((size_t)R * (sizeof(int) * 2 + sizeof(long long) * 2) +
                        sizeof(long long) * (size_t)ns + 64);
     pl.off_rcol = take(sizeof(int) * pl.rcol_off.size() + (size_t)R * (2 * sizeof(int) + sizeof(long long)) + 64);
@@ -390,7 +397,8 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.dbuf = pl.nd == 2;
     pl.off_fields2 = pl.dbuf ? take(fld) : 0;
     pl.off_adj = pl.adjoint ? take(fld) : 0;
-    pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * (pl.nsave + 1) * (size_t)bd.B) : 0;
+    pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * pl.nsave * (size_t)bd.B) : 0;
+    pl.off_fin = pl.save && g->dr > 1 ? take(sizeof(float) * (size_t)ns * (size_t)pl.P * (1 + pl.nd)) : 0;
     pl.off_acc = pl.adjoint ? take(sizeof(float) * 3 * (size_t)ns * (size_t)pl.I) : 0;
     pl.off_G = pl.need_G ? take(sizeof(float) * (size_t)nt * R) : 0;
     pl.off_dcal = pl.need_dcal ? take(sizeof(float) * (size_t)nt * R) : 0;
@@ -414,11 +422,10 @@ Views views(const Plan &pl, void *ws) {
         w.cpml.a_i[a] = c; w.cpml.b_i[a] = c + M; w.cpml.a_h[a] = c + 2 * M; w.cpml.b_h[a] = c + 3 * M;
         c += 4 * M;
     }
-    size_t nbox = (size_t)pl.g.nt * pl.nshot * 6;
     int *t = (int *)(b + pl.off_tables);
     w.fbox = t;
-    w.abox = pl.adjoint ? t + nbox : nullptr;
-    w.rbox = pl.adjoint ? t + 2 * nbox : nullptr;
+    w.abox = pl.adjoint ? t + pl.fbox.size() : nullptr;
+    w.rbox = pl.adjoint ? t + pl.fbox.size() + pl.abox.size() : nullptr;
     int R = pl.rec_off[pl.nshot];
     char *r = b + pl.off_recv;
     w.recv.R = R;
@@ -465,6 +472,7 @@ Views views(const Plan &pl, void *ws) {
     }
     w.G = pl.need_G ? (float *)(b + pl.off_G) : nullptr;
     w.dcal = pl.need_dcal ? (float *)(b + pl.off_dcal) : nullptr;
+    w.fin = pl.off_fin ? (float *)(b + pl.off_fin) : nullptr;
     return w;
 }
 

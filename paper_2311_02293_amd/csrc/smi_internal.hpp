@@ -24,6 +24,8 @@ namespace smi {
 constexpr int kMaxN = 4;       // half order (orders 4 and 8)
 constexpr int kMaxBlocks = 12; // band blocks per save level: 3 axes x {p, v} x {left, right}
 constexpr int GH = 2 * kMaxN;  // ghost nodes per side and axis (>= the 2N-1 halo of a fused step)
+constexpr int kTaps = 4;       // half-width (saved levels) of the decimated-band interpolator
+constexpr double kKaiserBeta = 6.31;
 
 // ---------------------------------------------------------------- device-side views
 
@@ -110,13 +112,14 @@ struct Plan {
     std::vector<long long> rcol_out;   // [R] dcal offset of sample 0
     std::vector<int> rcol_stride;  // [R] samples per time step of that shot
     BandDesc band{};
-    int nsave = 0;      // saved levels 0, dr, 2 dr, ...; slot nsave holds level nt
+    int nsave = 0;      // saved band levels k dr, k = 0 .. nsave-1
+    int nrun = 0;       // forward steps: nt, or past nt until the last saved level (dr > 1)
     Geom geom{};
     // workspace layout (byte offsets)
     size_t off_status = 0, off_misfit = 0, off_partial = 0;
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
-    size_t off_rcol = 0;
+    size_t off_rcol = 0, off_fin = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
@@ -153,6 +156,7 @@ struct Views {
     float *acc_g, *acc_i, *acc_l;   // [nshot][I] gradient / image / illumination
     float *G;           // [nt * R] adjoint source (when computed internally)
     float *dcal;        // internal dcal when the caller gave none
+    float *fin;         // level-nt copy of p and v while the forward runs past nt (dr > 1)
 };
 
 Views views(const Plan &pl, void *ws);
