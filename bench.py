@@ -53,6 +53,49 @@ def cpu_baseline(job, steps: int):
                       f"{g.n1 + 2 * g.nb}x{g.n2 + 2 * g.nb}, FP64, box off; {dt:.1f} s"}
 
 
+def probe_copy(torch, gib: float = 1.0, reps: int = 20):
+    """A plain device-to-device copy of known size: the reference the HBM counters of the
+    step kernels are scaled by (bytes read = bytes written = `gib` GiB per copy)."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"probe": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "ms": ms, "GBps": 8 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
+# HBM traffic of the step kernels from rocprofv3 counter runs, kept with the profiles: valid
+# only while the kernel source is the one the counters were taken on.
+COUNTERS = os.path.join(ROOT, "profiles", "step_kernels_2d_order8_16shots_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_02293_amd", "csrc", "kernels.hip")
+
+
+def counter_traffic():
+    import hashlib
+    try:
+        kv = {}
+        with open(COUNTERS) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(KERNEL_SRC, "rb") as f:
+            src = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("kernel_source_sha256") != src:
+            return None
+        return float(kv["traffic_bytes_per_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +105,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4000)
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="device-stamp the step kernels of every k-th time step (0: off)")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not provided "
@@ -69,6 +116,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.probe_copy:
+        probe_copy(torch)
+        return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
 
@@ -97,6 +147,7 @@ def main():
     alg_bytes = ctx.last_bytes()[0]
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
+    ctx.set_option(B.OPT_TIMING, args.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -109,7 +160,20 @@ def main():
     ms = [a.elapsed_time(b) for a, b in evs]
     total_ms = sum(ms)
     value = gpts * args.steps / (total_ms / 1e3) / 1e9
-    achieved = alg_bytes / (np.mean(ms) / 1e3) / 1e9
+    # the dominant kernel: the forward time step (v kernel + p kernel, every shot of the batch
+    # in one launch each), timed on the device at every k-th step of the timed region
+    kt = {}
+    for which, name in ((0, "step_span"), (1, "k_step_v"), (2, "k_step_p")):
+        kms, kby, kn = ctx.kernel_timing(which)
+        kt[name] = {"avg_us": kms * 1e3, "alg_bytes": kby, "samples": kn,
+                    "GBps": kby / (kms / 1e3) / 1e9 if kms > 0 else None}
+    ctx.set_option(B.OPT_TIMING, 0)
+    # duration of the step = the two kernels' own durations (the span from the start of the v
+    # kernel to the end of the p kernel also holds the launch gap between them)
+    step_us = kt["k_step_v"]["avg_us"] + kt["k_step_p"]["avg_us"]
+    step_bytes = kt["step_span"]["alg_bytes"]
+    achieved = step_bytes / (step_us / 1e6) / 1e9 if step_us > 0 else None
+    whole_job_GBps = alg_bytes / (np.mean(ms) / 1e3) / 1e9
 
     out = {"metric": METRIC, "value": value, "unit": "GPts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
@@ -120,9 +184,12 @@ def main():
                       "gpts_per_step": gpts, "wall_s": wall},
            "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "forward time step (v + p update, CPML, source, receivers)",
-                        "alg_bytes_per_step": alg_bytes}}
+                        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                        "traffic": counter_traffic(),
+                        "kernel": "forward time step: k_step_v + k_step_p over 16 shots",
+                        "alg_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
+                        "kernels": kt, "whole_job_alg_GBps": whole_job_GBps,
+                        "whole_job_alg_bytes": alg_bytes}}
 
     if not args.no_plain:
         # plain stepper: one shot per launch, separate v and p kernels, box off

@@ -99,9 +99,16 @@ typedef enum {
                                 launch, separate v and p sweep kernels; 2: fused 2D step
                                 (v and p in one marching kernel, double-buffered levels) */
     SMI_OPT_GRAPH = 1,       /* 1: replay the time loop from captured HIP graphs (default 0) */
-    SMI_OPT_CHUNK = 2        /* tuning of the fused 2D step: 1000 (2 order + t2) + L, with L the
+    SMI_OPT_CHUNK = 2,       /* tuning of the fused 2D step: 1000 (2 order + t2) + L, with L the
                                 columns marched by one wavefront, t2 = 1 for 2-column chunks and
                                 order 0/1/2 the workgroup order (0: default 16) */
+    SMI_OPT_TIMING = 3,      /* S > 0: every S-th forward time step of the batched sweep kernels
+                                is launched with device-stamped start / stop events (read with
+                                smi_kernel_timing); 0: off (default).  Setting it clears the
+                                samples collected so far. */
+    SMI_OPT_TILEMAP = 4      /* order in which the sweep kernels' tiles are dispatched: 0 plain
+                                (z-block fastest, then x-block); 1 each of the 8 XCDs takes a
+                                contiguous range of x-blocks, so tiles sharing halos share an L2 */
 } smi_option;
 
 /* Create a context on HIP device `hip_device`. */
@@ -189,6 +196,23 @@ smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double 
  * restored boundary bands, image / gradient accumulators), independent of how the kernels
  * move it.  Used to express throughput as a fraction of the HBM roofline. */
 smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_bytes);
+
+/* Durations of the forward time-step kernels sampled (SMI_OPT_TIMING) since the option was
+ * last set, over every forward pass run on this context meanwhile.  Waits for the sampled
+ * kernels to finish.
+ *   which 0: the whole step (start of the v kernel to the end of the p kernel), with the
+ *            algorithmic bytes of the step as the method defines it (fields read and written
+ *            once, CPML memory variables, the model once per step for the batch);
+ *         1: the v kernel (eq. 3, first row) and its own algorithmic bytes (reads p, reads and
+ *            writes v_a, CPML variables of p, dt beta_a);
+ *         2: the p kernel (eq. 3, second row, source injection) and its bytes (reads v_a, reads
+ *            and writes p, CPML variables of v, dt kappa).
+ *   avg_ms     mean kernel duration over the samples (ms);
+ *   avg_bytes  mean algorithmic bytes of the sampled launches;
+ *   nsamples   number of samples (0: nothing timed; both means are then 0).
+ * Any output pointer may be NULL.  SMI_E_ARG for another `which`. */
+smi_status smi_kernel_timing(smi_ctx *ctx, int which, double *avg_ms, double *avg_bytes,
+                             int *nsamples);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
           -4: "SMI_E_WORKSPACE", -5: "SMI_E_HIP", -6: "SMI_E_UNSUPPORTED", -7: "SMI_E_STATE",
           -8: "SMI_E_NONFINITE"}
 JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD = 0, 1, 2, 3
-OPT_KERNEL, OPT_GRAPH, OPT_CHUNK = 0, 1, 2
+OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP = 0, 1, 2, 3, 4
 
 
 class SmiError(RuntimeError):
@@ -76,6 +76,8 @@ def lib():
         L.smi_last_counts.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
         L.smi_last_bytes.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.smi_kernel_timing.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -190,6 +192,13 @@ class Context:
         f, r = C.c_double(), C.c_double()
         self._check(lib().smi_last_bytes(self.h, C.byref(f), C.byref(r)))
         return f.value, r.value
+
+    def kernel_timing(self, which: int = 0):
+        """smi_kernel_timing: (mean ms, mean algorithmic bytes, samples) of the sampled forward
+        step kernels -- which 0: v + p step, 1: v kernel, 2: p kernel."""
+        ms, by, n = C.c_double(), C.c_double(), C.c_int()
+        self._check(lib().smi_kernel_timing(self.h, which, C.byref(ms), C.byref(by), C.byref(n)))
+        return ms.value, by.value, n.value
 
     def poll_status(self, stream=None):
         self._check(lib().smi_poll_status(self.h, _stream(stream)))

@@ -21,10 +21,20 @@ struct smi_ctx {
     int opt_kernel = 0;
     int opt_graph = 0;
     int opt_chunk = 0;
+    int opt_xcd = 0;
     void *last_ws = nullptr;
     size_t last_status_off = 0;
     double cnt[3] = {0, 0, 0};
     double bytes[2] = {0, 0};
+    // kernel timing (SMI_OPT_TIMING): every opt_timing-th forward step of the batched sweep
+    // is launched with device-stamped events; events[4 k .. 4 k + 4) belong to sample k
+    int opt_timing = 0;
+    std::vector<hipEvent_t> events;
+    std::vector<double> sample_bytes;   // [samples][3], as Plan::step_bytes
+    size_t nsample = 0;
+    ~smi_ctx() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
 };
 
 struct smi_state {
@@ -158,6 +168,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     s = zero_fields(ctx, pl, w.f, st);
     if (s != SMI_OK) return s;
     smi::StepCtx c{&pl, &w, stf, st, ctx->opt_kernel == 1};
+    c.xcd = ctx->opt_xcd != 0;
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     bool fused = ctx->opt_kernel == 2 && pl.dbuf && pl.g.dr == 1 && smi::fused_fwd_available(pl);
@@ -170,6 +181,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
                "dcal clear");
     }
     const int nt = pl.g.nt, dr = pl.g.dr;
+    const bool timed = ctx->opt_timing > 0 && !fused && ctx->opt_kernel == 0;
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
     for (int it = 0; it < pl.nrun; ++it) {
         // fused steps alternate between the two buffers: level it lives in cur
@@ -179,7 +191,20 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         if (fused) {
             HIPCHK(smi::fwd_step_fused(c, cur, nxt, it, dcal), "forward step");
         } else {
+            if (timed && it % ctx->opt_timing == 0) {
+                const size_t k = ctx->nsample;
+                while (ctx->events.size() < 4 * (k + 1)) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e), "timing event");
+                    ctx->events.push_back(e);
+                }
+                ctx->sample_bytes.insert(ctx->sample_bytes.end(), &pl.step_bytes[3 * (size_t)it],
+                                         &pl.step_bytes[3 * (size_t)it] + 3);
+                ctx->nsample = k + 1;
+                c.ev = &ctx->events[4 * k];
+            }
             HIPCHK(smi::fwd_step(c, it), "forward step");
+            c.ev = nullptr;
             if (it < nt) HIPCHK(smi::extract(c, it, dcal), "extract");
         }
         for (int k = 0; k < nsnap; ++k)
@@ -215,6 +240,7 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     if (s != SMI_OK) return s;
     HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
     smi::StepCtx c{&pl, &w, stt->stf, st, ctx->opt_kernel == 1};
+    c.xcd = ctx->opt_xcd != 0;
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     for (int it = pl.g.nt - 1; it >= 0; --it) {
@@ -295,6 +321,13 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_KERNEL && value >= 0 && value <= 2) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
+    if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }
+    if (option == SMI_OPT_TIMING && value >= 0) {
+        ctx->opt_timing = value;
+        ctx->nsample = 0;
+        ctx->sample_bytes.clear();
+        return SMI_OK;
+    }
     return fail(ctx, SMI_E_ARG, "unknown option or value");
 }
 
@@ -380,6 +413,7 @@ smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                        ws_bytes, st, stt);
     if (s != SMI_OK) return s;
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
+    c.xcd = ctx->opt_xcd != 0;
     HIPCHK(smi::scale_copy(c, dobs, w.G, (float)g.dt), "rtm source");
     return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, nullptr, 0, nullptr, st);
 }
@@ -408,6 +442,7 @@ smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, 
                        ws_bytes, st, stt);
     if (s != SMI_OK) return s;
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
+    c.xcd = ctx->opt_xcd != 0;
     HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
     return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, 0, nullptr, st);
 }
@@ -433,6 +468,27 @@ smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double 
     if (fwd) *fwd = ctx->cnt[0];
     if (adj) *adj = ctx->cnt[1];
     if (rec) *rec = ctx->cnt[2];
+    return SMI_OK;
+}
+
+smi_status smi_kernel_timing(smi_ctx *ctx, int which, double *avg_ms, double *avg_bytes,
+                             int *nsamples) {
+    if (!ctx || which < 0 || which > 2) return fail(ctx, SMI_E_ARG, "which must be 0, 1 or 2");
+    double ms = 0, by = 0;
+    for (size_t k = 0; k < ctx->nsample; ++k) {
+        hipEvent_t a = ctx->events[4 * k + (which == 2 ? 2 : 0)];
+        hipEvent_t b = ctx->events[4 * k + (which == 1 ? 1 : 3)];
+        hipError_t e = hipEventSynchronize(b);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "kernel timing");
+        ms += t;
+        by += ctx->sample_bytes[3 * k + which];
+    }
+    const double n = (double)ctx->nsample;
+    if (avg_ms) *avg_ms = n > 0 ? ms / n : 0.0;
+    if (avg_bytes) *avg_bytes = n > 0 ? by / n : 0.0;
+    if (nsamples) *nsamples = (int)ctx->nsample;
     return SMI_OK;
 }
 

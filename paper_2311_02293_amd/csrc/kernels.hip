@@ -9,6 +9,8 @@
 // that shot's computing box (grid z-dimension = shot x y-plane).
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "smi_internal.hpp"
 #include "device.hpp"
 
@@ -29,14 +31,19 @@ struct Cell {
 
 // Grid: x = z-block, y = x-block, z = y-plane + ny * shot (shot slowest: neighbouring tiles
 // of one shot run together and share halos in L2).
+// With nxc > 0 the tiles are handed to the 8 XCDs in contiguous x ranges: workgroups are
+// dispatched round-robin over the XCDs in launch order, so blockIdx.x & 7 names the XCD and
+// XCD k takes x-blocks [k nxc, (k + 1) nxc) (tiles that share x halos share one L2).
 struct LG {
     int ny;             // y-planes of the launch (1 in 2D)
+    int nxc;            // x-blocks per XCD (0: plain order, blockIdx.y = x-block)
 };
 
 __device__ __forceinline__ Cell cell_of(const Geom &g, const int *__restrict__ box, int shot0,
                                         LG lg) {
     Cell c;
-    const int zb = blockIdx.x, xb = blockIdx.y;
+    const int zb = lg.nxc ? (int)blockIdx.x >> 3 : (int)blockIdx.x;
+    const int xb = lg.nxc ? ((int)blockIdx.x & 7) * lg.nxc + (int)blockIdx.y : (int)blockIdx.y;
     const int sy = lg.ny == 1 ? 0 : (int)blockIdx.z / lg.ny;
     const int yo = lg.ny == 1 ? 0 : (int)blockIdx.z - sy * lg.ny;
     c.s = shot0 + (lg.ny == 1 ? (int)blockIdx.z : sy);
@@ -415,7 +422,8 @@ struct Launch {
     bool empty;
 };
 
-Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1) {
+Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1,
+                  bool xcd) {
     int ez = 0, ex = 0, ey = 0;
     for (int s = s0; s < s1; ++s) {
         const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
@@ -426,9 +434,11 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
     Launch L;
     L.empty = ez <= 0 || ex <= 0 || ey <= 0;
     const int nzb = std::max(1, (ez + BZ - 1) / BZ), nxb = std::max(1, (ex + BX - 1) / BX);
-    L.ey = LG{std::max(ey, 1)};
+    const int nxc = xcd ? (nxb + 7) / 8 : 0;
+    L.ey = LG{std::max(ey, 1), nxc};
     L.block = dim3(BZ, BX, 1);
-    L.grid = dim3((unsigned)nzb, (unsigned)nxb, (unsigned)((s1 - s0) * std::max(ey, 1)));
+    L.grid = dim3((unsigned)(xcd ? 8 * nzb : nzb), (unsigned)(xcd ? nxc : nxb),
+                  (unsigned)((s1 - s0) * std::max(ey, 1)));
     return L;
 }
 
@@ -461,8 +471,18 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
     int step = c.plain ? 1 : pl.nshot;
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
-        Launch L = box_launch(pl, pl.fbox, it, s0, s1);
+        Launch L = box_launch(pl, pl.fbox, it, s0, s1, c.xcd);
         if (L.empty) continue;
+        if (c.ev && step == pl.nshot) {
+            // timed step: the device stamps the events at each kernel's start and end
+            hipExtLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
+                                  0, pl.geom, w.f, w.model, w.cpml, box, s0, L.ey);
+            hipExtLaunchKernelGGL((k_step_p<ND, N, true, false>), L.grid, L.block, 0, c.st,
+                                  c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, s0,
+                                  L.ey, (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                                  (const float *)nullptr, (float *)nullptr);
+            continue;
+        }
         hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
                            w.cpml, box, s0, L.ey);
         hipLaunchKernelGGL((k_step_p<ND, N, true, false>), L.grid, L.block, 0, c.st, pl.geom,
@@ -482,7 +502,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     // source field: p^{it} (with the gradient read of p~ before the adjoint step)
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
-        Launch L = box_launch(pl, pl.rbox, it, s0, s1);
+        Launch L = box_launch(pl, pl.rbox, it, s0, s1, c.xcd);
         if (L.empty) continue;
 #define SMI_RECON_P(G_, L_)                                                                    \
     hipLaunchKernelGGL((k_recon_p<ND, N, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, w.f,      \
@@ -498,7 +518,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     if (e != hipSuccess) return e;
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
-        Launch L = box_launch(pl, pl.rbox, it, s0, s1);
+        Launch L = box_launch(pl, pl.rbox, it, s0, s1, c.xcd);
         if (L.empty) continue;
         hipLaunchKernelGGL((k_recon_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
                            rb, s0, L.ey);
@@ -508,7 +528,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     // adjoint field: one step of the same solver (eq. 8), image with p^{it}
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
-        Launch L = box_launch(pl, pl.abox, it, s0, s1);
+        Launch L = box_launch(pl, pl.abox, it, s0, s1, c.xcd);
         if (L.empty) continue;
         hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                            w.cpml, ab, s0, L.ey);

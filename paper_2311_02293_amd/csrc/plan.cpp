@@ -151,13 +151,17 @@ void algorithmic_bytes(Plan &pl) {
     const int nt = pl.g.nt, ns = pl.nshot, nd = pl.nd;
     double R = pl.rec_off[ns];
     double bf = 0, br = 0;
+    pl.step_bytes.assign((size_t)pl.nrun * 3, 0.0);
     for (int it = 0; it < pl.nrun; ++it) {
-        double maxf = 0, maxa = 0;
+        double maxf = 0, maxa = 0, sb = 0, sv = 0, sp = 0;
         const bool adj_it = pl.adjoint && it < nt;
         for (int s = 0; s < ns; ++s) {
             const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
             double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
-            bf += 8.0 * (nd + 1) * vf + 16.0 * box_slab_cells(pl, fb);
+            const double slab = box_slab_cells(pl, fb);
+            sb += 8.0 * (nd + 1) * vf + 16.0 * slab;
+            sv += (4.0 + 8.0 * nd) * vf + 8.0 * slab;
+            sp += (4.0 * nd + 8.0) * vf + 8.0 * slab;
             maxf = std::max(maxf, vf);
             if (adj_it) {
                 const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
@@ -171,7 +175,11 @@ void algorithmic_bytes(Plan &pl) {
                 maxa = std::max(maxa, std::max(va, vr));
             }
         }
-        bf += 4.0 * (nd + 1) * maxf + (it < nt ? 8.0 * R : 0.0);
+        sb += 4.0 * (nd + 1) * maxf;
+        pl.step_bytes[3 * (size_t)it] = sb;
+        pl.step_bytes[3 * (size_t)it + 1] = sv + 4.0 * nd * maxf;
+        pl.step_bytes[3 * (size_t)it + 2] = sp + 4.0 * maxf;
+        bf += sb + (it < nt ? 8.0 * R : 0.0);
         if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
         const double restore = pl.g.dr == 1 || it % pl.g.dr == 0 ? 8.0 : 4.0 * (2 * kTaps + 1);
         if (adj_it) br += 4.0 * (nd + 1) * maxa + 8.0 * R + restore * (double)ns * pl.band.B;

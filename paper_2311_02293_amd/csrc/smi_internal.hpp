@@ -127,6 +127,10 @@ struct Plan {
     int chunk = 0;      // columns per workgroup of the fused 2D step (0: default)
     double cnt_fwd = 0, cnt_adj = 0, cnt_rec = 0;
     double bytes_fwd = 0, bytes_rev = 0;   // algorithmic HBM bytes (see plan.cpp)
+    // [nrun][3] algorithmic bytes of forward step it: the step as the method defines it
+    // (fields read and written once), then the v and the p kernel as launched separately
+    // (each reads the other field)
+    std::vector<double> step_bytes;
 };
 
 // Build and validate a plan.  Returns SMI_OK or an error with `err` filled.
@@ -173,6 +177,10 @@ struct StepCtx {
     const float *stf;       // device [nshot][nt]
     hipStream_t st;
     bool plain;
+    // when set (batched sweep only): start / stop events of the v launch (ev[0], ev[1]) and of
+    // the p launch (ev[2], ev[3]) of this step, taken by the device around each kernel
+    const hipEvent_t *ev = nullptr;
+    bool xcd = false;       // XCD-contiguous tile order of the sweep kernels
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);

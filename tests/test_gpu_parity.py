@@ -96,6 +96,58 @@ def test_fused_step_matches_sweep_kernels(ctx):
         ctx.set_option(B.OPT_CHUNK, 0)
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_xcd_tile_order_is_bitwise_identical(ctx, ndim):
+    """The XCD-contiguous tile order changes only which workgroup computes a cell: forward
+    data and the FWI gradient are bitwise equal to those of the plain order."""
+    from paper_2311_02293_amd import binding as B
+    if ndim == 2:
+        job = with_bounds(I.config2(n1=70, n2=230, nt=300, nshot=3, box=1))
+    else:
+        job = with_bounds(I.config4(n=40, nt=160, dr=1, nshot=2, rec_step=4))
+    say("xcd tile order", ndim, job.grid)
+    vp, rho, stf = dev(job)
+    dobs = None
+    outs = []
+    for tm in (0, 1):
+        ctx.set_option(B.OPT_TILEMAP, tm)
+        try:
+            d, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+            if dobs is None:
+                dobs = (0.9 * d).contiguous()
+            g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+            outs.append((d.cpu().numpy(), g.cpu().numpy()))
+        finally:
+            ctx.set_option(B.OPT_TILEMAP, 0)
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    assert np.abs(outs[0][1]).max() > 0
+
+
+def test_kernel_timing_samples_the_step_kernels(ctx):
+    """SMI_OPT_TIMING = 4 on nt = 200: 50 sampled steps; the step spans both kernels and
+    carries the method's bytes (fields once), each kernel its own bytes."""
+    from paper_2311_02293_amd import binding as B
+    job = with_bounds(I.config2(n1=64, n2=200, nt=200, nshot=2, box=0))
+    vp, rho, stf = dev(job)
+    ctx.set_option(B.OPT_TIMING, 4)
+    try:
+        ctx.forward(job.grid, job.acq, vp, rho, stf)
+        step = ctx.kernel_timing(0)
+        kv = ctx.kernel_timing(1)
+        kp = ctx.kernel_timing(2)
+    finally:
+        ctx.set_option(B.OPT_TIMING, 0)
+    say("timing", step, kv, kp)
+    assert step[2] == kv[2] == kp[2] == 50
+    assert step[0] > 0 and kv[0] > 0 and kp[0] > 0
+    assert step[0] >= kv[0] + kp[0] - 1e-3
+    P = (64 + 60) * (200 + 60)
+    assert step[1] >= 2 * 24 * P and kv[1] + kp[1] > step[1]
+    ctx.set_option(B.OPT_TIMING, 0)
+    assert ctx.kernel_timing(0)[2] == 0
+
+
 def test_forward_is_deterministic(ctx):
     job = with_bounds(I.config2(n1=64, n2=200, nt=300, nshot=3))
     vp, rho, stf = dev(job)
