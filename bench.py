@@ -163,14 +163,14 @@ def main():
     # the dominant kernel: the forward time step (v kernel + p kernel, every shot of the batch
     # in one launch each), timed on the device at every k-th step of the timed region
     kt = {}
-    for which, name in ((0, "step_span"), (1, "k_step_v"), (2, "k_step_p")):
+    for which, name in ((0, "step_span"), (1, "v_kernel"), (2, "p_kernel")):
         kms, kby, kn = ctx.kernel_timing(which)
         kt[name] = {"avg_us": kms * 1e3, "alg_bytes": kby, "samples": kn,
                     "GBps": kby / (kms / 1e3) / 1e9 if kms > 0 else None}
     ctx.set_option(B.OPT_TIMING, 0)
     # duration of the step = the two kernels' own durations (the span from the start of the v
     # kernel to the end of the p kernel also holds the launch gap between them)
-    step_us = kt["k_step_v"]["avg_us"] + kt["k_step_p"]["avg_us"]
+    step_us = kt["v_kernel"]["avg_us"] + kt["p_kernel"]["avg_us"]
     step_bytes = kt["step_span"]["alg_bytes"]
     achieved = step_bytes / (step_us / 1e6) / 1e9 if step_us > 0 else None
     whole_job_GBps = alg_bytes / (np.mean(ms) / 1e3) / 1e9
@@ -186,7 +186,8 @@ def main():
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS if achieved else None,
                         "traffic": counter_traffic(),
-                        "kernel": "forward time step: k_step_v + k_step_p over 16 shots",
+                        "kernel": "forward time step: v kernel + p kernel (k_march_v, k_march_p) "
+                                  "over 16 shots",
                         "alg_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
                         "kernels": kt, "whole_job_alg_GBps": whole_job_GBps,
                         "whole_job_alg_bytes": alg_bytes}}

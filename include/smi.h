@@ -94,21 +94,27 @@ typedef struct {
 
 /* Options (smi_set_option). */
 typedef enum {
-    SMI_OPT_KERNEL = 0,      /* 0: batched sweep kernels (default): every shot of the batch in
-                                one launch per half step; 1: plain stepper -- one shot per
-                                launch, separate v and p sweep kernels; 2: fused 2D step
-                                (v and p in one marching kernel, double-buffered levels) */
+    SMI_OPT_KERNEL = 0,      /* 0 (default): register-blocked half-step kernels, every shot of
+                                the batch in one launch per half step, 4 cells per lane and
+                                the XCD-contiguous order in 2D, 2 cells per lane in 3D;
+                                1: plain stepper -- one shot per launch, one cell per lane;
+                                2: fused 2D step (v and p in one marching kernel,
+                                double-buffered levels); 3: register-blocked kernels with
+                                SMI_OPT_CHUNK = 2, 4 or 8 cells per lane along the slowest
+                                axis and the order of SMI_OPT_TILEMAP; 4: batched one-cell-per-
+                                lane sweep kernels in the order of SMI_OPT_TILEMAP */
     SMI_OPT_GRAPH = 1,       /* 1: replay the time loop from captured HIP graphs (default 0) */
-    SMI_OPT_CHUNK = 2,       /* tuning of the fused 2D step: 1000 (2 order + t2) + L, with L the
-                                columns marched by one wavefront, t2 = 1 for 2-column chunks and
-                                order 0/1/2 the workgroup order (0: default 16) */
-    SMI_OPT_TIMING = 3,      /* S > 0: every S-th forward time step of the batched sweep kernels
+    SMI_OPT_CHUNK = 2,       /* tuning.  SMI_OPT_KERNEL 3: cells per lane (2, 4, 8; else 4).
+                                SMI_OPT_KERNEL 2: 1000 (2 order + t2) + L, with L the columns
+                                marched by one wavefront, t2 = 1 for 2-column chunks and order
+                                0/1/2 the workgroup order (0: default 16) */
+    SMI_OPT_TIMING = 3,      /* S > 0: every S-th forward time step of the batched kernels
                                 is launched with device-stamped start / stop events (read with
                                 smi_kernel_timing); 0: off (default).  Setting it clears the
                                 samples collected so far. */
-    SMI_OPT_TILEMAP = 4      /* order in which the sweep kernels' tiles are dispatched: 0 plain
-                                (z-block fastest, then x-block); 1 each of the 8 XCDs takes a
-                                contiguous range of x-blocks, so tiles sharing halos share an L2 */
+    SMI_OPT_TILEMAP = 4      /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
+                                then x-block); 1 each of the 8 XCDs takes a contiguous range of
+                                x-blocks, so tiles that share halos share an L2 */
 } smi_option;
 
 /* Create a context on HIP device `hip_device`. */

@@ -48,6 +48,24 @@ struct smi_state {
 
 namespace {
 
+// Kernel choice of a step context from the context options.  Default: register-blocked half
+// steps, 4 cells per lane with the XCD-contiguous order in 2D, 2 cells per lane in the plain
+// order in 3D (the fastest measured on the configurations the library targets).
+void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
+    c.plain = ctx->opt_kernel == 1;
+    c.march = 0;
+    c.xcd = false;
+    if (ctx->opt_kernel == 0) {
+        c.march = pl.nd == 2 ? 4 : 2;
+        c.xcd = pl.nd == 2;
+    } else if (ctx->opt_kernel == 3) {
+        c.march = ctx->opt_chunk == 2 || ctx->opt_chunk == 8 ? ctx->opt_chunk : 4;
+        c.xcd = ctx->opt_xcd != 0;
+    } else if (ctx->opt_kernel == 4) {
+        c.xcd = ctx->opt_xcd != 0;
+    }
+}
+
 smi_status fail(smi_ctx *c, smi_status st, const std::string &msg) {
     if (c) c->err = msg;
     return st;
@@ -167,8 +185,8 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     HIPCHK(smi::launch_model_prep(pl, w, vp, rho, st), "model prep");
     s = zero_fields(ctx, pl, w.f, st);
     if (s != SMI_OK) return s;
-    smi::StepCtx c{&pl, &w, stf, st, ctx->opt_kernel == 1};
-    c.xcd = ctx->opt_xcd != 0;
+    smi::StepCtx c{&pl, &w, stf, st, false};
+    configure(c, ctx, pl);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     bool fused = ctx->opt_kernel == 2 && pl.dbuf && pl.g.dr == 1 && smi::fused_fwd_available(pl);
@@ -181,7 +199,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
                "dcal clear");
     }
     const int nt = pl.g.nt, dr = pl.g.dr;
-    const bool timed = ctx->opt_timing > 0 && !fused && ctx->opt_kernel == 0;
+    const bool timed = ctx->opt_timing > 0 && !fused && !c.plain;
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
     for (int it = 0; it < pl.nrun; ++it) {
         // fused steps alternate between the two buffers: level it lives in cur
@@ -239,8 +257,8 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     smi_status s = zero_fields(ctx, pl, w.q, st);
     if (s != SMI_OK) return s;
     HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
-    smi::StepCtx c{&pl, &w, stt->stf, st, ctx->opt_kernel == 1};
-    c.xcd = ctx->opt_xcd != 0;
+    smi::StepCtx c{&pl, &w, stt->stf, st, false};
+    configure(c, ctx, pl);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     for (int it = pl.g.nt - 1; it >= 0; --it) {
@@ -318,7 +336,7 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 2) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 4) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }
@@ -413,7 +431,7 @@ smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                        ws_bytes, st, stt);
     if (s != SMI_OK) return s;
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
-    c.xcd = ctx->opt_xcd != 0;
+    configure(c, ctx, stt->plan);
     HIPCHK(smi::scale_copy(c, dobs, w.G, (float)g.dt), "rtm source");
     return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, nullptr, 0, nullptr, st);
 }
@@ -442,7 +460,7 @@ smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, 
                        ws_bytes, st, stt);
     if (s != SMI_OK) return s;
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
-    c.xcd = ctx->opt_xcd != 0;
+    configure(c, ctx, stt->plan);
     HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
     return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, 0, nullptr, st);
 }

@@ -209,6 +209,219 @@ __global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml 
     }
 }
 
+// ---------------------------------------------------------------- marching sweep kernels
+//
+// The same two half steps, with each lane marching along the slowest axis (x in 2D, y in 3D)
+// over CM consecutive cells.  The values of the differentiated field along the march axis
+// stay in a register window that slides by one cell per step, so each is loaded once per
+// march instead of 2N times, and the halo of the tile along that axis shrinks to 2N - 1 cells
+// per CM.  Lanes run along z (one 256-byte row per wavefront, rows aligned to 128 bytes of
+// storage); in 2D the four wavefronts of a workgroup take four consecutive z tiles, in 3D
+// four consecutive x columns (whose x-stencil reads then share the L1).  Every lane updates
+// only its own cells, so the updates stay in place.
+
+struct MG {
+    int nmarch;         // march strips per shot along the march axis (3D: grid z = strip + nmarch shot)
+    int nxc;            // > 0: XCD-contiguous order, blockIdx.x & 7 = XCD, which takes nxc
+                        // consecutive blocks of x (2D: march strips, 3D: 4-column groups)
+};
+
+struct MCell {
+    int s, z, x, y;     // y unused in 2D
+    int lo, hi;         // march range [lo, hi) along the march axis
+    long long k;        // storage offset of the first cell
+    bool ok;
+};
+
+template <int ND, int CM>
+__device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0, MG mg) {
+    MCell c;
+    const int wv = threadIdx.y, lane = threadIdx.x;
+    const int bz = mg.nxc ? (int)blockIdx.x >> 3 : (int)blockIdx.x;
+    const int bx = mg.nxc ? ((int)blockIdx.x & 7) * mg.nxc + (int)blockIdx.y : (int)blockIdx.y;
+    if (ND == 2) {
+        c.s = shot0 + (int)blockIdx.z;
+        const int *b = box + 6 * c.s;
+        c.z = zalign(b[0]) + (bz * 4 + wv) * 64 + lane;
+        c.lo = b[2] + bx * CM;
+        c.hi = min(c.lo + CM, b[3]);
+        c.x = c.lo;
+        c.y = 0;
+        c.ok = c.z >= b[0] && c.z < b[1];
+    } else {
+        const int strip = (int)blockIdx.z % mg.nmarch;
+        c.s = shot0 + (int)blockIdx.z / mg.nmarch;
+        const int *b = box + 6 * c.s;
+        c.z = zalign(b[0]) + bz * 64 + lane;
+        c.x = b[2] + bx * 4 + wv;
+        c.lo = b[4] + strip * CM;
+        c.hi = min(c.lo + CM, b[5]);
+        c.y = c.lo;
+        c.ok = c.z >= b[0] && c.z < b[1] && c.x < b[3];
+    }
+    return c;
+}
+
+template <int ND>
+__device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
+    Cell c;
+    c.s = m.s;
+    c.z = m.z;
+    c.x = ND == 2 ? t : m.x;
+    c.y = ND == 2 ? 0 : t;
+    c.k = g.org + c.z + (long long)g.ld1 * c.x + g.ld2 * c.y;
+    c.ok = true;
+    return c;
+}
+
+// v_a -= dt beta_a (D+_a p + psi_a), psi updated in the slabs (eq. 3 first row, CPML).
+// All loads of the lane's CM cells are issued before any arithmetic (the loads are
+// independent, so a wavefront keeps CM times more requests in flight); cells past the end of
+// the march range re-read the last cell and store nothing.
+template <int ND, int N, int CM>
+__global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
+                                                 const int *__restrict__ box, int shot0, MG mg) {
+    constexpr int MA = ND - 1;              // march axis
+    constexpr int NW = CM + 2 * N - 1;      // window: march offsets -(N-1) .. CM-1+N
+    MCell mc = mcell_of<ND, CM>(box, shot0, mg);
+    if (!mc.ok || mc.lo >= mc.hi) return;
+    const int cnt = mc.hi - mc.lo;
+    const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
+    const float *__restrict__ p = f.p + mc.s * g.P;
+    const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
+    float w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) w[j] = p[k0 + min(j - (N - 1), cnt - 1 + N) * ms];
+    // other axes: p at offsets d = -(N-1) .. N, d != 0, per cell; v_a and dt beta_a per cell
+    float st[CM][ND - 1][2 * N - 1];
+    float vo[CM][ND], bd[CM][ND];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const long long k = k0 + min(t, cnt - 1) * ms;
+#pragma unroll
+        for (int a = 0; a < ND - 1; ++a) {
+            const long long sa = stride_of(g, a);
+#pragma unroll
+            for (int j = 0; j < 2 * N - 1; ++j) {
+                const int d = j < N - 1 ? j - (N - 1) : j - (N - 1) + 1;
+                st[t][a][j] = p[k + d * sa];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            vo[t][a] = f.v[a][mc.s * g.P + k];
+            bd[t][a] = m.bdt[a][k];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        if (t >= cnt) break;
+        Cell c = as_cell<ND>(g, mc, mc.lo + t);
+        const float pc = w[t + N - 1];
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            float e = 0.f;
+            if (a == MA) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N - 1 + l] - w[t + N - l]);
+            } else {
+                // st index of offset d: d < 0 -> d + N - 1, d > 0 -> d + N - 2
+#pragma unroll
+                for (int l = 1; l <= N; ++l) {
+                    const float hi = st[t][a][l + N - 2];
+                    const float lo = l == 1 ? pc : st[t][a][-(l - 1) + N - 1];
+                    e += g.c[a][l - 1] * (hi - lo);
+                }
+            }
+            long long so = slab_off(g, c, a);
+            if (so >= 0) {
+                int i = coord(c, a);
+                float *ps = f.psp[a] + c.s * g.psz[a] + so;
+                float psi = cp.b_h[a][i] * *ps + cp.a_h[a][i] * e;
+                *ps = psi;
+                e += psi;
+            }
+            f.v[a][c.s * g.P + c.k] = vo[t][a] - bd[t][a] * e;
+        }
+    }
+}
+
+// p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
+// first, as in k_march_v.
+template <int ND, int N, int CM, bool SRC, bool IMG>
+__global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml cp,
+                                                 const int *__restrict__ box, int shot0, MG mg,
+                                                 const long long *__restrict__ src_cell,
+                                                 const float *__restrict__ stf, int nt, int it,
+                                                 const float *__restrict__ pf, float *acc_i) {
+    constexpr int MA = ND - 1;
+    constexpr int NW = CM + 2 * N - 1;      // window: march offsets -N .. CM-1+N-1
+    MCell mc = mcell_of<ND, CM>(box, shot0, mg);
+    if (!mc.ok || mc.lo >= mc.hi) return;
+    const int cnt = mc.hi - mc.lo;
+    const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
+    const long long so0 = mc.s * g.P;
+    const float *__restrict__ vm = f.v[MA] + so0;
+    const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
+    float w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) w[j] = vm[k0 + min(j - N, cnt - 1 + N - 1) * ms];
+    // other axes: v_a at offsets -N .. N-1 per cell; p and dt kappa per cell
+    float st[CM][ND - 1][2 * N];
+    float po[CM], kd[CM];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const long long k = k0 + min(t, cnt - 1) * ms;
+#pragma unroll
+        for (int a = 0; a < ND - 1; ++a) {
+            const long long sa = stride_of(g, a);
+            const float *__restrict__ va = f.v[a] + so0;
+#pragma unroll
+            for (int j = 0; j < 2 * N; ++j) st[t][a][j] = va[k + (j - N) * sa];
+        }
+        po[t] = f.p[so0 + k];
+        kd[t] = m.kdt[k];
+    }
+    const long long sc = SRC ? src_cell[mc.s] : -1;
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        if (t >= cnt) break;
+        Cell c = as_cell<ND>(g, mc, mc.lo + t);
+        float sdiv = 0.f;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            float e = 0.f;
+            if (a == MA) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N + l - 1] - w[t + N - l]);
+            } else {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (st[t][a][N + l - 1] - st[t][a][N - l]);
+            }
+            long long so = slab_off(g, c, a);
+            if (so >= 0) {
+                int i = coord(c, a);
+                float *ps = f.psv[a] + c.s * g.psz[a] + so;
+                float psi = cp.b_i[a][i] * *ps + cp.a_i[a][i] * e;
+                *ps = psi;
+                e += psi;
+            }
+            sdiv += e;
+        }
+        float pn = po[t] - kd[t] * sdiv;
+        if (SRC && it < nt && c.k == sc) pn += g.src_scale * stf[(long long)c.s * nt + it];
+        f.p[so0 + c.k] = pn;
+        if (IMG) {
+            int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
+            if ((unsigned)iz < (unsigned)g.n[0] && (unsigned)ix < (unsigned)g.n[1] &&
+                (unsigned)iy < (unsigned)g.n[2]) {
+                long long ii = c.s * g.I + iz + (long long)g.n[0] * (ix + (long long)g.n[1] * iy);
+                acc_i[ii] += g.dt * pn * pf[so0 + c.k];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- reconstruction (Sec. 4.2)
 
 // p^it = p^{it+1} - dt stf[it]/dV [at the source] + dt kappa div v^{it+1/2}  on the interior;
@@ -442,6 +655,40 @@ Launch box_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, i
     return L;
 }
 
+// launch geometry of a marching half step over a box table row (max extents over the shots)
+struct MLaunch {
+    dim3 grid, block;
+    MG mg;
+    bool empty;
+};
+
+MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1,
+                     int cm, bool xcd) {
+    int ez = 0, ex = 0, ey = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
+        ez = std::max(ez, b[1] - zalign(b[0]));
+        ex = std::max(ex, b[3] - b[2]);
+        ey = std::max(ey, b[5] - b[4]);
+    }
+    MLaunch L;
+    L.empty = ez <= 0 || ex <= 0 || ey <= 0;
+    L.block = dim3(64, 4, 1);
+    int gz, gx, nm = 1;
+    if (pl.nd == 2) {
+        gz = std::max(1, (ez + 255) / 256);
+        gx = std::max(1, (ex + cm - 1) / cm);
+    } else {
+        nm = std::max(1, (ey + cm - 1) / cm);
+        gz = std::max(1, (ez + 63) / 64);
+        gx = std::max(1, (ex + 3) / 4);
+    }
+    const int nxc = xcd ? (gx + 7) / 8 : 0;
+    L.mg = MG{nm, nxc};
+    L.grid = dim3((unsigned)(xcd ? 8 * gz : gz), (unsigned)(xcd ? nxc : gx), (unsigned)((s1 - s0) * nm));
+    return L;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host launchers
@@ -463,10 +710,59 @@ hipError_t launch_minmax(const float *vp, long long n, unsigned *out2, hipStream
 
 namespace {
 
+template <int ND, int N, int CM>
+hipError_t fwd_march_t(const StepCtx &c, int it) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *box = w.fbox + (size_t)it * pl.nshot * 6;
+    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd);
+    if (L.empty) return hipSuccess;
+    if (c.ev) {
+        hipExtLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
+                              0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg);
+        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, true, false>), L.grid, L.block, 0, c.st,
+                              c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
+                              (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                              (const float *)nullptr, (float *)nullptr);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
+                       w.cpml, box, 0, L.mg);
+    hipLaunchKernelGGL((k_march_p<ND, N, CM, true, false>), L.grid, L.block, 0, c.st, pl.geom,
+                       w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
+                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
+    return hipGetLastError();
+}
+
+// adjoint half steps with the marching kernels (image with the source field when asked)
+template <int ND, int N, int CM>
+hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *ab = w.abox + (size_t)it * pl.nshot * 6;
+    MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
+    if (L.empty) return hipSuccess;
+    hipLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
+                       w.cpml, ab, 0, L.mg);
+    if (image)
+        hipLaunchKernelGGL((k_march_p<ND, N, CM, false, true>), L.grid, L.block, 0, c.st, pl.geom,
+                           w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
+                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
+    else
+        hipLaunchKernelGGL((k_march_p<ND, N, CM, false, false>), L.grid, L.block, 0, c.st,
+                           pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
+                           (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                           (const float *)w.f.p, w.acc_i);
+    return hipGetLastError();
+}
+
 template <int ND, int N>
 hipError_t fwd_step_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    if (!c.plain && c.march == 2) return fwd_march_t<ND, N, 2>(c, it);
+    if (!c.plain && c.march == 4) return fwd_march_t<ND, N, 4>(c, it);
+    if (!c.plain && c.march == 8) return fwd_march_t<ND, N, 8>(c, it);
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     int step = c.plain ? 1 : pl.nshot;
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
@@ -526,6 +822,9 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     e = band_restore(c, it, 1);
     if (e != hipSuccess) return e;
     // adjoint field: one step of the same solver (eq. 8), image with p^{it}
+    if (!c.plain && c.march == 2) return adj_march_t<ND, N, 2>(c, it, image);
+    if (!c.plain && c.march == 4) return adj_march_t<ND, N, 4>(c, it, image);
+    if (!c.plain && c.march == 8) return adj_march_t<ND, N, 8>(c, it, image);
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
         Launch L = box_launch(pl, pl.abox, it, s0, s1, c.xcd);

@@ -181,6 +181,7 @@ struct StepCtx {
     // the p launch (ev[2], ev[3]) of this step, taken by the device around each kernel
     const hipEvent_t *ev = nullptr;
     bool xcd = false;       // XCD-contiguous tile order of the sweep kernels
+    int march = 0;          // > 0: marching half-step kernels with this march length (8, 16, 32)
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);

@@ -96,8 +96,8 @@ def test_fused_step_matches_sweep_kernels(ctx):
         ctx.set_option(B.OPT_CHUNK, 0)
 
 
-@pytest.mark.parametrize("ndim", [2, 3])
-def test_xcd_tile_order_is_bitwise_identical(ctx, ndim):
+@pytest.mark.parametrize("ndim,kernel", [(2, 4), (3, 4), (2, 3), (3, 3)])
+def test_xcd_tile_order_is_bitwise_identical(ctx, ndim, kernel):
     """The XCD-contiguous tile order changes only which workgroup computes a cell: forward
     data and the FWI gradient are bitwise equal to those of the plain order."""
     from paper_2311_02293_amd import binding as B
@@ -109,6 +109,7 @@ def test_xcd_tile_order_is_bitwise_identical(ctx, ndim):
     vp, rho, stf = dev(job)
     dobs = None
     outs = []
+    ctx.set_option(B.OPT_KERNEL, kernel)
     for tm in (0, 1):
         ctx.set_option(B.OPT_TILEMAP, tm)
         try:
@@ -119,9 +120,50 @@ def test_xcd_tile_order_is_bitwise_identical(ctx, ndim):
             outs.append((d.cpu().numpy(), g.cpu().numpy()))
         finally:
             ctx.set_option(B.OPT_TILEMAP, 0)
+    ctx.set_option(B.OPT_KERNEL, 0)
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     assert np.abs(outs[0][1]).max() > 0
+
+
+@pytest.mark.parametrize("ndim,cm", [(2, 2), (2, 4), (2, 8), (3, 2), (3, 4)])
+def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm):
+    """The register-blocked half steps (cm cells per lane along the slowest axis) compute the
+    one-cell-per-lane sweep kernels' update: forward data and FWI gradient agree to rounding,
+    and the data also match the oracle."""
+    from paper_2311_02293_amd import binding as B
+    if ndim == 2:
+        job = with_bounds(I.config2(n1=70, n2=230, nt=300, nshot=3, box=1))
+    else:
+        job = with_bounds(I.config4(n=40, nt=160, dr=1, nshot=2, rec_step=4))
+    say("marching kernels", ndim, cm, job.grid)
+    vp, rho, stf = dev(job)
+    ctx.set_option(B.OPT_KERNEL, 4)
+    try:
+        ref, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+        dobs = (0.9 * ref).contiguous()
+        gref, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+    ctx.set_option(B.OPT_KERNEL, 3)
+    ctx.set_option(B.OPT_CHUNK, cm)
+    try:
+        got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+        g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+        ctx.set_option(B.OPT_CHUNK, 0)
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-6
+    assert rel_l2(g.cpu().numpy(), gref.cpu().numpy()) <= 1e-5
+    if ndim == 2:
+        o = oracle_dcal(job, shots=[1], box=0)[0]
+        assert rel_l2(split(dcal_t(got), job)[1], o) <= 1e-4
+
+
+def dcal_t(a):
+    import torch
+    return torch.from_numpy(a)
 
 
 def test_kernel_timing_samples_the_step_kernels(ctx):
