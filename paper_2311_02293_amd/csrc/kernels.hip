@@ -466,6 +466,141 @@ __global__ __launch_bounds__(256) void k_recon_v(Geom g, Fields f, Model m,
     }
 }
 
+// Register-blocked forms of the two reconstruction kernels (cells per lane along the slowest
+// axis, loads first, as k_march_v / k_march_p).
+template <int ND, int N, int CM, bool GRAD, bool ILL>
+__global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m,
+                                                       const int *__restrict__ rbox, int shot0,
+                                                       MG mg, const long long *__restrict__ src_cell,
+                                                       const float *__restrict__ stf, int nt, int it,
+                                                       const float *__restrict__ qp, float *acc_g,
+                                                       float *acc_l) {
+    constexpr int MA = ND - 1;
+    constexpr int NW = CM + 2 * N - 1;
+    MCell mc = mcell_of<ND, CM>(rbox, shot0, mg);
+    if (!mc.ok || mc.lo >= mc.hi) return;
+    const int cnt = mc.hi - mc.lo;
+    const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
+    const long long so0 = mc.s * g.P;
+    const float *__restrict__ vm = f.v[MA] + so0;
+    const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
+    // interior index of the first cell and its step along the march axis
+    const long long ii0 = mc.s * g.I + (mc.z - g.nb) +
+                          (long long)g.n[0] * ((ND == 2 ? mc.lo : mc.x) - g.nb +
+                                               (long long)g.n[1] * (ND == 3 ? mc.lo - g.nb : 0));
+    const long long iis = ND == 2 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1];
+    float w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) w[j] = vm[k0 + min(j - N, cnt - 1 + N - 1) * ms];
+    float st[CM][ND - 1][2 * N];
+    float po[CM], kd[CM], qv[CM], ag[CM], al[CM];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const int tc = min(t, cnt - 1);
+        const long long k = k0 + tc * ms;
+#pragma unroll
+        for (int a = 0; a < ND - 1; ++a) {
+            const long long sa = stride_of(g, a);
+            const float *__restrict__ va = f.v[a] + so0;
+#pragma unroll
+            for (int j = 0; j < 2 * N; ++j) st[t][a][j] = va[k + (j - N) * sa];
+        }
+        po[t] = f.p[so0 + k];
+        kd[t] = m.kdt[k];
+        if (GRAD) { qv[t] = qp[so0 + k]; ag[t] = acc_g[ii0 + tc * iis]; }
+        if (ILL) al[t] = acc_l[ii0 + tc * iis];
+    }
+    const long long sc = src_cell[mc.s];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        if (t >= cnt) break;
+        const long long k = k0 + t * ms;
+        float div = 0.f;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            float e = 0.f;
+            if (a == MA) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N + l - 1] - w[t + N - l]);
+            } else {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (st[t][a][N + l - 1] - st[t][a][N - l]);
+            }
+            div += e;
+        }
+        float pv = po[t];
+        if (k == sc) pv -= g.src_scale * stf[(long long)mc.s * nt + it];
+        const float pn = pv + kd[t] * div;
+        f.p[so0 + k] = pn;
+        if (GRAD) acc_g[ii0 + t * iis] = ag[t] + qv[t] * div;
+        if (ILL) acc_l[ii0 + t * iis] = al[t] + g.dt * pn * pn;
+    }
+}
+
+template <int ND, int N, int CM>
+__global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m,
+                                                       const int *__restrict__ rbox, int shot0,
+                                                       MG mg) {
+    constexpr int MA = ND - 1;
+    constexpr int NW = CM + 2 * N - 1;
+    MCell mc = mcell_of<ND, CM>(rbox, shot0, mg);
+    if (!mc.ok || mc.lo >= mc.hi) return;
+    const int cnt = mc.hi - mc.lo;
+    const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
+    const float *__restrict__ p = f.p + mc.s * g.P;
+    const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
+    float w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) w[j] = p[k0 + min(j - (N - 1), cnt - 1 + N) * ms];
+    float st[CM][ND - 1][2 * N - 1];
+    float vo[CM][ND], bd[CM][ND];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const long long k = k0 + min(t, cnt - 1) * ms;
+#pragma unroll
+        for (int a = 0; a < ND - 1; ++a) {
+            const long long sa = stride_of(g, a);
+#pragma unroll
+            for (int j = 0; j < 2 * N - 1; ++j) {
+                const int d = j < N - 1 ? j - (N - 1) : j - (N - 1) + 1;
+                st[t][a][j] = p[k + d * sa];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            vo[t][a] = f.v[a][mc.s * g.P + k];
+            bd[t][a] = m.bdt[a][k];
+        }
+    }
+    // v_a points strictly between interior p nodes along a
+    const int lastz = g.nb + g.n[0] - 1, lastx = g.nb + g.n[1] - 1, lasty = g.nb + g.n[2] - 1;
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        if (t >= cnt) break;
+        const int tt = mc.lo + t;
+        const long long k = k0 + t * ms;
+        const float pc = w[t + N - 1];
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            const int ca = a == 0 ? mc.z : (a == MA ? tt : mc.x);
+            if (ca >= (a == 0 ? lastz : (a == 1 ? lastx : lasty))) continue;
+            float e = 0.f;
+            if (a == MA) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N - 1 + l] - w[t + N - l]);
+            } else {
+#pragma unroll
+                for (int l = 1; l <= N; ++l) {
+                    const float hi = st[t][a][l + N - 2];
+                    const float lo = l == 1 ? pc : st[t][a][-(l - 1) + N - 1];
+                    e += g.c[a][l - 1] * (hi - lo);
+                }
+            }
+            f.v[a][mc.s * g.P + k] = vo[t][a] + bd[t][a] * e;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- saved boundaries (Sec. 4.2)
 
 // dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt) buf + wt buf2.
@@ -788,10 +923,45 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
     return hipGetLastError();
 }
 
+// reconstruction half steps with the register-blocked kernels (region: rbox row it)
+template <int ND, int N, int CM>
+hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
+    MLaunch L = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
+    if (!L.empty) {
+#define SMI_MRECON_P(G_, L_)                                                                   \
+    hipLaunchKernelGGL((k_march_recon_p<ND, N, CM, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, \
+                       w.f, w.model, rb, 0, L.mg, (const long long *)w.src_cell, c.stf,         \
+                       pl.g.nt, it, (const float *)w.q.p, w.acc_g, w.acc_l)
+        if (grad && image) SMI_MRECON_P(true, true);
+        else if (grad) SMI_MRECON_P(true, false);
+        else if (image) SMI_MRECON_P(false, true);
+        else SMI_MRECON_P(false, false);
+#undef SMI_MRECON_P
+    }
+    hipError_t e = band_restore(c, it, 0);
+    if (e != hipSuccess) return e;
+    if (!L.empty)
+        hipLaunchKernelGGL((k_march_recon_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.f,
+                           w.model, rb, 0, L.mg);
+    return band_restore(c, it, 1);
+}
+
 template <int ND, int N>
 hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    if (!c.plain && c.march) {
+        hipError_t e = c.march == 2 ? recon_march_t<ND, N, 2>(c, it, grad, image)
+                     : c.march == 8 ? recon_march_t<ND, N, 8>(c, it, grad, image)
+                                    : recon_march_t<ND, N, 4>(c, it, grad, image);
+        if (e != hipSuccess) return e;
+        if (c.march == 2) return adj_march_t<ND, N, 2>(c, it, image);
+        if (c.march == 4) return adj_march_t<ND, N, 4>(c, it, image);
+        return adj_march_t<ND, N, 8>(c, it, image);
+    }
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
     int step = c.plain ? 1 : pl.nshot;
@@ -822,9 +992,6 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     e = band_restore(c, it, 1);
     if (e != hipSuccess) return e;
     // adjoint field: one step of the same solver (eq. 8), image with p^{it}
-    if (!c.plain && c.march == 2) return adj_march_t<ND, N, 2>(c, it, image);
-    if (!c.plain && c.march == 4) return adj_march_t<ND, N, 4>(c, it, image);
-    if (!c.plain && c.march == 8) return adj_march_t<ND, N, 8>(c, it, image);
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
         int s1 = std::min(pl.nshot, s0 + step);
         Launch L = box_launch(pl, pl.abox, it, s0, s1, c.xcd);
