@@ -104,7 +104,8 @@ typedef enum {
                                 axis and the order of SMI_OPT_TILEMAP; 4: batched one-cell-per-
                                 lane sweep kernels in the order of SMI_OPT_TILEMAP */
     SMI_OPT_GRAPH = 1,       /* 1: replay the time loop from captured HIP graphs (default 0) */
-    SMI_OPT_CHUNK = 2,       /* tuning.  SMI_OPT_KERNEL 3: cells per lane (2, 4, 8; else 4).
+    SMI_OPT_CHUNK = 2,       /* tuning.  SMI_OPT_KERNEL 3: cells per lane (2, 4, 8; else 4),
+                                plus 100 to take the z-neighbours from LDS.
                                 SMI_OPT_KERNEL 2: 1000 (2 order + t2) + L, with L the columns
                                 marched by one wavefront, t2 = 1 for 2-column chunks and order
                                 0/1/2 the workgroup order (0: default 16) */
@@ -213,6 +214,8 @@ smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_byt
  *            writes v_a, CPML variables of p, dt beta_a);
  *         2: the p kernel (eq. 3, second row, source injection) and its bytes (reads v_a, reads
  *            and writes p, CPML variables of v, dt kappa).
+ *   With the fused 2D step (SMI_OPT_KERNEL 2) the step is one kernel: which 0 and 1 both
+ *   report it, with the step's bytes, and which 2 reports nothing (0 ms, 0 bytes).
  *   avg_ms     mean kernel duration over the samples (ms);
  *   avg_bytes  mean algorithmic bytes of the sampled launches;
  *   nsamples   number of samples (0: nothing timed; both means are then 0).

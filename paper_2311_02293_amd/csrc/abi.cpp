@@ -31,6 +31,7 @@ struct smi_ctx {
     int opt_timing = 0;
     std::vector<hipEvent_t> events;
     std::vector<double> sample_bytes;   // [samples][3], as Plan::step_bytes
+    std::vector<int> sample_nk;         // kernels of the sampled step (2, or 1 for the fused step)
     size_t nsample = 0;
     ~smi_ctx() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -58,8 +59,12 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
+    } else if (ctx->opt_kernel == 2) {
+        c.march = ctx->opt_chunk == 8 ? 8 : 4;
     } else if (ctx->opt_kernel == 3) {
-        c.march = ctx->opt_chunk == 2 || ctx->opt_chunk == 8 ? ctx->opt_chunk : 4;
+        const int cm = ctx->opt_chunk % 100;
+        c.march = cm == 2 || cm == 8 ? cm : 4;
+        c.zl = ctx->opt_chunk >= 100;
         c.xcd = ctx->opt_xcd != 0;
     } else if (ctx->opt_kernel == 4) {
         c.xcd = ctx->opt_xcd != 0;
@@ -193,34 +198,35 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     if (fused) {
         s = zero_fields(ctx, pl, w.f2, st);
         if (s != SMI_OK) return s;
-        // the fused step writes the samples of receivers inside the box; the field outside
-        // the box is still zero, so every other sample is zero
-        HIPCHK(hipMemsetAsync(dcal, 0, sizeof(float) * (size_t)pl.g.nt * pl.rec_off[pl.nshot], st),
-               "dcal clear");
     }
     const int nt = pl.g.nt, dr = pl.g.dr;
-    const bool timed = ctx->opt_timing > 0 && !fused && !c.plain;
+    const bool timed = ctx->opt_timing > 0 && !c.plain;
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
     for (int it = 0; it < pl.nrun; ++it) {
         // fused steps alternate between the two buffers: level it lives in cur
         const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
         const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
         if (pl.save && it % dr == 0) HIPCHK(smi::band_save(c, cur, it / dr), "band save");
-        if (fused) {
-            HIPCHK(smi::fwd_step_fused(c, cur, nxt, it, dcal), "forward step");
-        } else {
-            if (timed && it % ctx->opt_timing == 0) {
-                const size_t k = ctx->nsample;
-                while (ctx->events.size() < 4 * (k + 1)) {
-                    hipEvent_t e;
-                    HIPCHK(hipEventCreate(&e), "timing event");
-                    ctx->events.push_back(e);
-                }
-                ctx->sample_bytes.insert(ctx->sample_bytes.end(), &pl.step_bytes[3 * (size_t)it],
-                                         &pl.step_bytes[3 * (size_t)it] + 3);
-                ctx->nsample = k + 1;
-                c.ev = &ctx->events[4 * k];
+        if (timed && it % ctx->opt_timing == 0) {
+            const size_t k = ctx->nsample;
+            while (ctx->events.size() < 4 * (k + 1)) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e), "timing event");
+                ctx->events.push_back(e);
             }
+            const double *sb = &pl.step_bytes[3 * (size_t)it];
+            // the fused step is one kernel: it carries the step's bytes as its "first" kernel
+            const double row[3] = {sb[0], fused ? sb[0] : sb[1], fused ? 0.0 : sb[2]};
+            ctx->sample_bytes.insert(ctx->sample_bytes.end(), row, row + 3);
+            ctx->sample_nk.push_back(fused ? 1 : 2);
+            ctx->nsample = k + 1;
+            c.ev = &ctx->events[4 * k];
+        }
+        if (fused) {
+            HIPCHK(smi::fwd_step_fused(c, cur, nxt, it), "forward step");
+            c.ev = nullptr;
+            if (it < nt) HIPCHK(smi::extract(c, it, dcal, nxt.p), "extract");
+        } else {
             HIPCHK(smi::fwd_step(c, it), "forward step");
             c.ev = nullptr;
             if (it < nt) HIPCHK(smi::extract(c, it, dcal), "extract");
@@ -344,6 +350,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
         ctx->opt_timing = value;
         ctx->nsample = 0;
         ctx->sample_bytes.clear();
+        ctx->sample_nk.clear();
         return SMI_OK;
     }
     return fail(ctx, SMI_E_ARG, "unknown option or value");
@@ -494,8 +501,10 @@ smi_status smi_kernel_timing(smi_ctx *ctx, int which, double *avg_ms, double *av
     if (!ctx || which < 0 || which > 2) return fail(ctx, SMI_E_ARG, "which must be 0, 1 or 2");
     double ms = 0, by = 0;
     for (size_t k = 0; k < ctx->nsample; ++k) {
+        const bool one = ctx->sample_nk[k] == 1;
+        if (one && which == 2) continue;          // a fused step has no second kernel
         hipEvent_t a = ctx->events[4 * k + (which == 2 ? 2 : 0)];
-        hipEvent_t b = ctx->events[4 * k + (which == 1 ? 1 : 3)];
+        hipEvent_t b = ctx->events[4 * k + (which == 1 || one ? 1 : 3)];
         hipError_t e = hipEventSynchronize(b);
         float t = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);

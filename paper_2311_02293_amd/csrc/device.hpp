@@ -5,6 +5,10 @@
 
 namespace smi {
 
+// first z of the 32-float-aligned (128-byte) storage line that contains node z, with the
+// ghost frame of 8 nodes in front of node 0
+__host__ __device__ __forceinline__ int zalign(int z) { return ((z + 8) & ~31) - 8; }
+
 // Compact index of node i inside the CPML slabs of an axis with M nodes: [0, nb) and
 // [M - nb - 1, M) map to [0, 2 nb + 1); interior nodes return -1.
 __device__ __forceinline__ int slab_index(int i, int M, int nb) {

@@ -1,21 +1,22 @@
-// fused2d.hip -- one kernel per 2D time step: v update, p update, CPML, source injection and
-// receiver sampling (eq. 3-4, Sec. 2.1, Alg. 2 forward loop), for every shot of the batch.
+// fused2d.hip -- one kernel per 2D time step: v update, p update, CPML and source injection
+// (eq. 3-4, Sec. 2.1, Alg. 2 forward loop) for every shot of the batch, reading level n from
+// one buffer and writing level n + 1 to the other.
 //
-// Work decomposition.  A workgroup owns a z-strip of one shot's computing box (lanes along
-// z, one coalesced row per wavefront, 2N-1 halo lanes at each end) and a range of L columns
-// along x, which it marches through in chunks of T columns.  Per lane, registers hold a
-// window of p^n over the columns [xc - (2N-1), xc + T + 2N - 1) and of v_x^{n+1/2} over
-// [xc - N, xc + T + N - 1); both windows slide by T per chunk, so every p and v_x value is
-// loaded once per march and the x-derivatives never leave registers.  Per chunk: all global
-// loads of the chunk are issued together, v_x of the T new columns is formed in registers,
-// p of the chunk goes to LDS (barrier), v_z is formed from its z-neighbours and goes to LDS
-// (barrier), and p^{n+1} is formed from v_z (LDS) and v_x (registers).
-// Level n is read from one buffer and level n+1 written to the other, so values a workgroup
-// reads in its halo are never overwritten by a neighbour during the step.  The zero ghost
-// nodes around the padded grid make every stencil read valid without per-lane checks; the
-// CPML memory variables are touched only on (uniform) branches for slab columns and on the
-// lanes of slab rows.  Workgroups are ordered chunk-major with the shot fastest and remapped
-// so that each XCD takes a contiguous range: the shots of one region share the model in L2.
+// Work decomposition (as the register-blocked half-step kernels): a lane owns one z row of a
+// run of CM consecutive columns [lo, hi); the four wavefronts of a workgroup take four
+// consecutive 64-row tiles; the 8 XCDs take contiguous ranges of column runs.  One step needs
+//   * v_x^{n+1/2} on the lane's row at columns lo-N .. hi+N-2 (the p stencil along x): formed
+//     in registers from a window of p^n over lo-2N+1 .. hi+2N-2;
+//   * v_z^{n+1/2} at rows z-N .. z+N-1 of each owned column: formed from p^n staged in the
+//     wavefront's LDS slice (rows z0-2N+1 .. z0+64+2N-2), for the 64 own rows and, by lanes
+//     0 .. 2N-2, for the 2N-1 rows just outside; staged again in LDS for the p update.
+// Values computed for neighbours' cells (halo columns and rows) are used and not stored, so
+// every cell is written by exactly one lane, and every read is of level n: the two levels
+// live in different buffers.  Cells outside the shot's computing box keep their old value
+// (they are zero), as in the half-step kernels.  All global loads of a lane are issued before
+// its arithmetic.
+#include <hip/hip_ext.h>
+
 #include "smi_internal.hpp"
 #include "device.hpp"
 
@@ -23,285 +24,209 @@ namespace smi {
 
 namespace {
 
-struct Recv2 {
-    const int *off;          // [nshot][M2 + 1]
-    const int *z;
-    const long long *out;
-    const int *stride;
-};
+constexpr int kRows = 64 + 2 * (2 * kMaxN - 1);   // staged p rows per column (own + halo)
 
-struct March2 {
-    const float *src;        // field section at level n (p of shot 0)
-    float *dst;              // field section at level n + 1
-    int o_vz, o_vx;          // offsets of the v_z, v_x arrays in a section (floats)
-    int o_pzp, o_pzv, o_pxp, o_pxv;   // offsets of the CPML memory variables
-    int P, psz0, psz1;       // per-shot strides
-    const float *model;      // dt kappa; dt beta_z at +P, dt beta_x at +2P
-    const float *cpz, *cpx;  // CPML profiles per axis: a_i | b_i | a_h | b_h
-    int M1, M2, nb, ld1, org, W;
-    float cz[kMaxN], cx[kMaxN];
-    float src_scale;
-};
+template <int N, int CM>
+__global__ __launch_bounds__(256) void k_fused2d(Geom g, Fields src, Fields dst, Model m, Cpml cp,
+                                                 const int *__restrict__ box, int nxc,
+                                                 const long long *__restrict__ src_cell,
+                                                 const float *__restrict__ stf, int nt, int it) {
+    constexpr int H = 2 * N - 1;           // p halo of the fused step
+    constexpr int NP = CM + 2 * H;         // p window along x: columns lo-H .. hi-1+H
+    constexpr int NV = CM + 2 * N - 1;     // v_x window: columns lo-N .. hi-1+N-1
+    __shared__ float sp[4][CM][kRows];     // p^n, rows z0-H .. z0+63+H
+    __shared__ float sv[4][CM][64 + 2 * N]; // v_z^{n+1/2}, rows z0-N .. z0+63+N
 
-// One wavefront = one z-strip of 64 lanes (TZ = 64 - 2(2N-1) owned rows plus the halo rows
-// each side) marching through L columns in chunks of T; the four wavefronts of a workgroup
-// are independent (no workgroup barrier), each with its own LDS slice for the z-neighbour
-// exchange.  The march is software-pipelined: the loads of chunk c+1 are issued before the
-// arithmetic and the stores of chunk c, so the wait for a chunk's data never includes the
-// completion of the previous chunk's stores (vector-memory counters retire in order).
-template <int N, int T>
-struct Chunk {
-    float p[T], vo[T], bx[T], vz[T], bz[T], kd[T];
-};
-
-template <int N, int T>
-__global__ __launch_bounds__(256) void k_fwd2d(March2 a, const int *__restrict__ box, int nshot,
-                                               int ngrp, int L, int order,
-                                               const long long *__restrict__ src_cell,
-                                               const float *__restrict__ stf, int nt, int it,
-                                               Recv2 rv, float *__restrict__ dcal) {
-    constexpr int H = 2 * N - 1, TZ = 64 - 2 * H;
-    constexpr int PW = T + 2 * H, VW = T + 2 * N - 1;
-    __shared__ float lds[4][2][T][64];
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // order 0: shot fastest, XCD-contiguous; 1: shot slowest, XCD-contiguous; 2: shot slowest
-    const int logical = order == 2 ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-    int s, grp, cxk;
-    if (order == 0) {
-        s = logical % nshot;
-        const int rest = logical / nshot;
-        grp = rest % ngrp;
-        cxk = rest / ngrp;
-    } else {
-        const int per = (int)gridDim.x / nshot;
-        s = logical / per;
-        const int rest = logical % per;
-        grp = rest % ngrp;
-        cxk = rest / ngrp;
-    }
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int xcd = (int)blockIdx.x & 7;
+    const int bz = (int)blockIdx.x >> 3;
+    const int s = (int)blockIdx.z;
     const int *b = box + 6 * s;
-    const int bz0 = b[0], bz1 = b[1], bx0 = b[2], bx1 = b[3];
-    const int zs = bz0 + (grp * 4 + wave) * TZ, ze = min(zs + TZ, bz1);
-    const int xs = bx0 + cxk * L, xe = min(xs + L, bx1);
-    if (zs >= ze || xs >= xe) return;            // per wavefront: no workgroup barrier follows
-    float(*sp)[64] = lds[wave][0];
-    float(*svz)[64] = lds[wave][1];
+    const int z0 = zalign(b[0]) + (bz * 4 + wv) * 64;
+    const int z = z0 + lane;
+    const int lo = b[2] + (xcd * nxc + (int)blockIdx.y) * CM;
+    const int hi = min(lo + CM, b[3]);
+    if (lo >= hi || z0 >= b[1]) return;                 // uniform over the wavefront
+    const int cnt = hi - lo;
+    const bool ok = z >= b[0] && z < b[1];              // owns cells
+    const bool needp = z >= b[0] - H && z < b[1] + H;  // p row read by some owned cell's stencil
+    const bool needv = z >= b[0] - N && z < b[1] + N;  // v_z row read by some owned cell
+    const long long so = (long long)s * g.P;
+    const long long kz = g.org + z;                     // offset of (z, 0)
+    const int ld1 = g.ld1;
+    const float *__restrict__ P0 = src.p + so;
+    const float *__restrict__ VZ0 = src.v[0] + so;
+    const float *__restrict__ VX0 = src.v[1] + so;
 
-    const int M2 = a.M2, nb = a.nb, ld1 = a.ld1;
-    const int XM = M2 + GH - 1;                 // last column inside the ghost frame
-    const int z = zs - H + lane;
-    const int zl = min(z, ze + H - 1);          // lanes past the halo read a valid node
-    const bool zbox = z >= bz0 && z < bz1;
-    const bool own = z >= zs && z < ze;
-    const bool vzc = zbox && lane >= N - 1 && lane + N < 64;
-    const int zsl = zbox ? slab_index(z, a.M1, nb) : -1;
-    const int k0 = a.org + zl;                  // offset of (zl, x = 0)
-
-    const float *__restrict__ Ps = a.src + s * a.P;
-    const float *__restrict__ VZs = a.src + a.o_vz + s * a.P;
-    const float *__restrict__ VXs = a.src + a.o_vx + s * a.P;
-    float *__restrict__ Pd = a.dst + s * a.P;
-    float *__restrict__ VZd = a.dst + a.o_vz + s * a.P;
-    float *__restrict__ VXd = a.dst + a.o_vx + s * a.P;
-    const float *__restrict__ KD = a.model;
-    const float *__restrict__ BZ = a.model + a.P;
-    const float *__restrict__ BX = a.model + 2 * a.P;
-    float cz[N], cx[N];
+    // ---- loads (level n, and the model)
+    float pw[NP];
 #pragma unroll
-    for (int l = 0; l < N; ++l) { cz[l] = a.cz[l]; cx[l] = a.cx[l]; }
-    const int srck = (int)src_cell[s];
+    for (int j = 0; j < NP; ++j) {
+        const int x = lo - H + min(j, cnt - 1 + 2 * H);
+        pw[j] = (ok || (needp && j >= H && j < H + CM)) ? P0[kz + (long long)ld1 * x] : 0.f;
+    }
+    float vxo[NV], bx[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int x = lo - N + min(j, cnt - 1 + 2 * N - 1);
+        vxo[j] = ok ? VX0[kz + (long long)ld1 * x] : 0.f;
+        bx[j] = ok ? m.bdt[1][kz + (long long)ld1 * x] : 0.f;
+    }
+    float vzo[CM], bzz[CM], kd[CM];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const long long k = kz + (long long)ld1 * (lo + min(t, cnt - 1));
+        vzo[t] = needv ? VZ0[k] : 0.f;
+        bzz[t] = needv ? m.bdt[0][k] : 0.f;
+        kd[t] = ok ? m.kdt[k] : 0.f;
+    }
+    // halo rows of the p staging: lanes 0 .. 2H-1 load rows z0-H+lane (lane < H) and
+    // z0+64+lane-H (lane >= H)
+    const int hr = lane < H ? z0 - H + lane : z0 + 64 + lane - H;
+    const bool hp = lane < 2 * H && hr >= b[0] - H && hr < b[1] + H;
+    float hpv[CM];
+#pragma unroll
+    for (int t = 0; t < CM; ++t)
+        hpv[t] = hp ? P0[g.org + hr + (long long)ld1 * (lo + min(t, cnt - 1))] : 0.f;
+    // v_z rows just outside the wavefront that lanes 0 .. 2N-2 form: z0-N+lane (lane < N) and
+    // z0+64+lane-N (lane >= N)
+    const int vr = lane < N ? z0 - N + lane : z0 + 64 + lane - N;
+    const bool hv = lane < 2 * N - 1 && vr >= b[0] - N && vr < b[1] + N;
+    float hvz[CM], hbz[CM];
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        const long long k = g.org + vr + (long long)ld1 * (lo + min(t, cnt - 1));
+        hvz[t] = hv ? VZ0[k] : 0.f;
+        hbz[t] = hv ? m.bdt[0][k] : 0.f;
+    }
 
-    // v_x at column j from the p window (p(j - N + 1 + q) = pw[o + q]); only owned rows need it
-    auto vx_at = [&](int j, const float *pw, int o, float vold, float bb) -> float {
-        if (!(own && j >= bx0 && j < bx1)) return vold;
+    // ---- p^n of the owned columns to LDS
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+        sp[wv][t][H + lane] = pw[H + t];
+        if (lane < 2 * H) sp[wv][t][lane < H ? lane : 64 + lane] = hpv[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- v_z^{n+1/2} at this lane's row (and one outside row for lanes 0 .. 2N-2)
+    auto vz_new = [&](int r, int t, float vold, float bdz) -> float {
+        if (r < b[0] || r >= b[1]) return vold;         // outside the box: unchanged
+        const int i = r - z0 + H;                        // LDS row index
         float e = 0.f;
 #pragma unroll
-        for (int l = 1; l <= N; ++l) e += cx[l - 1] * (pw[o + N - 1 + l] - pw[o + N - l]);
-        const int xsl = slab_index(j, M2, nb);
-        const bool wr = j >= xs && j < xe;
-        if (xsl >= 0) {
-            const int q = s * a.psz1 + z + ld1 * xsl;
-            const float psi = a.cpx[3 * M2 + j] * a.src[a.o_pxp + q] + a.cpx[2 * M2 + j] * e;
-            if (wr) a.dst[a.o_pxp + q] = psi;
+        for (int l = 1; l <= N; ++l) e += g.c[0][l - 1] * (sp[wv][t][i + l] - sp[wv][t][i - l + 1]);
+        const int zc = slab_index(r, g.M[0], g.nb);
+        if (zc >= 0) {
+            const int x = lo + t;
+            const float *ps = src.psp[0] + (long long)s * g.psz[0] + zc + (long long)g.W * x;
+            const float psi = cp.b_h[0][r] * *ps + cp.a_h[0][r] * e;
+            if (r == z && x < hi)
+                dst.psp[0][(long long)s * g.psz[0] + zc + (long long)g.W * x] = psi;
             e += psi;
         }
-        const float v = vold - bb * e;
-        if (wr) VXd[k0 + ld1 * j] = v;
-        return v;
+        return vold - bdz * e;
     };
-    auto load = [&](int xc, Chunk<N, T> &d) {
+    float vzn[CM];
 #pragma unroll
-        for (int c = 0; c < T; ++c) {
-            const int kp = k0 + ld1 * min(xc + H + c, XM);
-            const int kv = k0 + ld1 * min(xc + N - 1 + c, XM);
-            const int kc = k0 + ld1 * min(xc + c, XM);
-            d.p[c] = Ps[kp];
-            d.vo[c] = VXs[kv];
-            d.bx[c] = BX[kv];
-            d.vz[c] = VZs[kc];
-            d.bz[c] = BZ[kc];
-            d.kd[c] = KD[kc];
+    for (int t = 0; t < CM; ++t) {
+        vzn[t] = needv && t < cnt ? vz_new(z, t, vzo[t], bzz[t]) : 0.f;
+        sv[wv][t][N + lane] = vzn[t];
+        if (lane < 2 * N - 1) {
+            const float o = hv && t < cnt ? vz_new(vr, t, hvz[t], hbz[t]) : 0.f;
+            sv[wv][t][lane < N ? lane : 64 + lane] = o;
         }
-    };
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (!ok) return;
 
-    float pw[PW], vw[VW];
+    // ---- v_x^{n+1/2} at columns lo-N+j on this row
+    float vxn[NV];
 #pragma unroll
-    for (int q = 0; q < 2 * H; ++q) pw[q] = Ps[k0 + ld1 * (xs - H + q)];
-    {
-        float vo[2 * N - 1], bb[2 * N - 1];
+    for (int j = 0; j < NV; ++j) {
+        const int x = lo - N + j;
+        if (x < b[2] || x >= b[3] || j >= cnt + 2 * N - 1) { vxn[j] = vxo[j]; continue; }
+        float e = 0.f;
 #pragma unroll
-        for (int q = 0; q < 2 * N - 1; ++q) {
-            const int kk = k0 + ld1 * (xs - N + q);
-            vo[q] = VXs[kk];
-            bb[q] = BX[kk];
+        for (int l = 1; l <= N; ++l) e += g.c[1][l - 1] * (pw[j + N + l - 1] - pw[j + N - l]);
+        const int xc = slab_index(x, g.M[1], g.nb);
+        if (xc >= 0) {
+            const long long q = (long long)s * g.psz[1] + z + (long long)ld1 * xc;
+            const float psi = cp.b_h[1][x] * src.psp[1][q] + cp.a_h[1][x] * e;
+            if (j >= N && j < N + cnt) dst.psp[1][q] = psi;
+            e += psi;
         }
-#pragma unroll
-        for (int q = 0; q < 2 * N - 1; ++q) vw[q] = vx_at(xs - N + q, pw, q, vo[q], bb[q]);
+        vxn[j] = vxo[j] - bx[j] * e;
     }
 
-    auto compute = [&](int xc, const Chunk<N, T> &d) {
+    // ---- p^{n+1} on the owned cells; store the owned v
+    const long long sc = src_cell[s];
+    const int zc = slab_index(z, g.M[0], g.nb);
 #pragma unroll
-        for (int c = 0; c < T; ++c) pw[2 * H + c] = d.p[c];
+    for (int t = 0; t < CM; ++t) {
+        if (t >= cnt) break;
+        const int x = lo + t;
+        const long long k = kz + (long long)ld1 * x;
+        const int i = lane + N;
+        float ez = 0.f;
 #pragma unroll
-        for (int c = 0; c < T; ++c) vw[2 * N - 1 + c] = vx_at(xc + N - 1 + c, pw, c + H, d.vo[c], d.bx[c]);
-        // v_z from p of the chunk: z-neighbours through this wavefront's LDS slice
-#pragma unroll
-        for (int c = 0; c < T; ++c) sp[c][lane] = pw[H + c];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int c = 0; c < T; ++c) {
-            const int x = xc + c;
-            float v = d.vz[c];
-            if (vzc && x < xe) {
-                float e = 0.f;
-#pragma unroll
-                for (int l = 1; l <= N; ++l) e += cz[l - 1] * (sp[c][lane + l] - sp[c][lane + 1 - l]);
-                if (zsl >= 0) {
-                    const int q = s * a.psz0 + zsl + a.W * x;
-                    const float psi = a.cpz[3 * a.M1 + z] * a.src[a.o_pzp + q] + a.cpz[2 * a.M1 + z] * e;
-                    if (own) a.dst[a.o_pzp + q] = psi;
-                    e += psi;
-                }
-                v = v - d.bz[c] * e;
-                if (own) VZd[k0 + ld1 * x] = v;
-            }
-            svz[c][lane] = v;
+        for (int l = 1; l <= N; ++l) ez += g.c[0][l - 1] * (sv[wv][t][i + l - 1] - sv[wv][t][i - l]);
+        if (zc >= 0) {
+            const long long q = (long long)s * g.psz[0] + zc + (long long)g.W * x;
+            const float psi = cp.b_i[0][z] * src.psv[0][q] + cp.a_i[0][z] * ez;
+            dst.psv[0][q] = psi;
+            ez += psi;
         }
-        __builtin_amdgcn_wave_barrier();
-        if (own) {
+        float ex = 0.f;
 #pragma unroll
-            for (int c = 0; c < T; ++c) {
-                const int x = xc + c;
-                if (x >= xe) break;
-                float ez = 0.f, ex = 0.f;
-#pragma unroll
-                for (int l = 1; l <= N; ++l) ez += cz[l - 1] * (svz[c][lane + l - 1] - svz[c][lane - l]);
-                if (zsl >= 0) {
-                    const int q = s * a.psz0 + zsl + a.W * x;
-                    const float psi = a.cpz[a.M1 + z] * a.src[a.o_pzv + q] + a.cpz[z] * ez;
-                    a.dst[a.o_pzv + q] = psi;
-                    ez += psi;
-                }
-#pragma unroll
-                for (int l = 1; l <= N; ++l) ex += cx[l - 1] * (vw[c + N + l - 1] - vw[c + N - l]);
-                const int xsl = slab_index(x, M2, nb);
-                if (xsl >= 0) {
-                    const int q = s * a.psz1 + z + ld1 * xsl;
-                    const float psi = a.cpx[M2 + x] * a.src[a.o_pxv + q] + a.cpx[x] * ex;
-                    a.dst[a.o_pxv + q] = psi;
-                    ex += psi;
-                }
-                const int k = k0 + ld1 * x;
-                float pn = pw[H + c] - d.kd[c] * (ez + ex);
-                if (k == srck) pn += a.src_scale * stf[(long long)s * nt + it];
-                Pd[k] = pn;
-                const int r0 = rv.off[s * (M2 + 1) + x];
-                const int r1 = rv.off[s * (M2 + 1) + x + 1];
-                for (int r = r0; r < r1; ++r)
-                    if (rv.z[r] == z) dcal[rv.out[r] + (long long)it * rv.stride[r]] = pn;
-            }
+        for (int l = 1; l <= N; ++l) ex += g.c[1][l - 1] * (vxn[t + N + l - 1] - vxn[t + N - l]);
+        const int xc = slab_index(x, g.M[1], g.nb);
+        if (xc >= 0) {
+            const long long q = (long long)s * g.psz[1] + z + (long long)ld1 * xc;
+            const float psi = cp.b_i[1][x] * src.psv[1][q] + cp.a_i[1][x] * ex;
+            dst.psv[1][q] = psi;
+            ex += psi;
         }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < 2 * H; ++q) pw[q] = pw[q + T];
-#pragma unroll
-        for (int q = 0; q < 2 * N - 1; ++q) vw[q] = vw[q + T];
-    };
-
-    Chunk<N, T> A, Bc;
-    load(xs, A);
-    for (int xc = xs; xc < xe; xc += 2 * T) {
-        load(xc + T, Bc);              // prefetch (clamped; unused past the end)
-        compute(xc, A);
-        if (xc + T >= xe) break;
-        load(xc + 2 * T, A);
-        compute(xc + T, Bc);
+        float pn = pw[H + t] - kd[t] * (ez + ex);
+        if (it < nt && k == sc) pn += g.src_scale * stf[(long long)s * nt + it];
+        dst.p[so + k] = pn;
+        dst.v[0][so + k] = vzn[t];
+        dst.v[1][so + k] = vxn[N + t];
     }
 }
 
 }  // namespace
 
-bool fused_fwd_available(const Plan &pl) {
-    // 32-bit offsets inside one field section
-    double sec = (double)pl.nshot * ((double)pl.P * 3 + 2.0 * (pl.geom.psz[0] + pl.geom.psz[1]));
-    return pl.nd == 2 && sec < 2.0e9;
-}
+bool fused_fwd_available(const Plan &pl) { return pl.nd == 2 && pl.dbuf; }
 
-hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it,
-                          float *dcal) {
+hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    const int H = 2 * pl.N - 1;
+    const int cm = c.march == 8 ? 8 : 4;
     int ez = 0, ex = 0;
     for (int s = 0; s < pl.nshot; ++s) {
         const int *b = &pl.fbox[((size_t)it * pl.nshot + s) * 6];
-        ez = std::max(ez, b[1] - b[0]);
+        ez = std::max(ez, b[1] - zalign(b[0]));
         ex = std::max(ex, b[3] - b[2]);
     }
     if (ez <= 0 || ex <= 0) return hipSuccess;
-    const int TZ = 64 - 2 * H;
-    int nstripw = (ez + TZ - 1) / TZ;         // wavefront strips
-    int ngrp = (nstripw + 3) / 4;             // 4 strips per workgroup
-    // chunk option (tuning): v = 1000 * (2 order + t2) + L
-    const int opt = pl.chunk > 0 ? pl.chunk : 16;
-    const int order = (opt / 1000) / 2;
-    const bool t2 = (opt / 1000) % 2 == 1;
-    int L = opt % 1000;
-    int nchunk = (ex + L - 1) / L;
-    unsigned G = (unsigned)(pl.nshot * ngrp * nchunk);
-
-    March2 a{};
-    a.src = src.p;
-    a.dst = dst.p;
-    a.o_vz = (int)(src.v[0] - src.p);
-    a.o_vx = (int)(src.v[1] - src.p);
-    a.o_pzp = (int)(src.psp[0] - src.p);
-    a.o_pzv = (int)(src.psv[0] - src.p);
-    a.o_pxp = (int)(src.psp[1] - src.p);
-    a.o_pxv = (int)(src.psv[1] - src.p);
-    a.P = (int)pl.P;
-    a.psz0 = (int)pl.geom.psz[0];
-    a.psz1 = (int)pl.geom.psz[1];
-    a.model = w.model.kdt;
-    a.cpz = w.cpml.a_i[0];
-    a.cpx = w.cpml.a_i[1];
-    a.M1 = pl.M[0];
-    a.M2 = pl.M[1];
-    a.nb = pl.g.nb;
-    a.ld1 = pl.ld1;
-    a.org = (int)pl.org;
-    a.W = pl.geom.W;
-    for (int l = 0; l < kMaxN; ++l) { a.cz[l] = pl.geom.c[0][l]; a.cx[l] = pl.geom.c[1][l]; }
-    a.src_scale = pl.geom.src_scale;
+    const int gz = (ez + 255) / 256, gx = (ex + cm - 1) / cm;
+    const int nxc = (gx + 7) / 8;
+    dim3 grid((unsigned)(8 * gz), (unsigned)nxc, (unsigned)pl.nshot), block(64, 4, 1);
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
-    Recv2 rv{w.rcol_off, w.rcol_z, w.rcol_out, w.rcol_stride};
-#define SMI_MARCH(N_, T_)                                                                        \
-    hipLaunchKernelGGL((k_fwd2d<N_, T_>), dim3(G), dim3(256), 0, c.st, a, box, pl.nshot, ngrp, L, order, \
-                       (const long long *)w.src_cell, c.stf, pl.g.nt, it, rv, dcal)
-    if (pl.N == 2) { if (t2) SMI_MARCH(2, 2); else SMI_MARCH(2, 4); }
-    else { if (t2) SMI_MARCH(4, 2); else SMI_MARCH(4, 4); }
-#undef SMI_MARCH
+#define SMI_FUSED(N_, CM_)                                                                     \
+    do {                                                                                       \
+        if (c.ev)                                                                              \
+            hipExtLaunchKernelGGL((k_fused2d<N_, CM_>), grid, block, 0, c.st, c.ev[0], c.ev[1], 0, \
+                                  pl.geom, src, dst, w.model, w.cpml, box, nxc,                \
+                                  (const long long *)w.src_cell, c.stf, pl.g.nt, it);          \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_fused2d<N_, CM_>), grid, block, 0, c.st, pl.geom, src, dst,   \
+                               w.model, w.cpml, box, nxc, (const long long *)w.src_cell, c.stf, \
+                               pl.g.nt, it);                                                   \
+    } while (0)
+    if (pl.N == 2) { if (cm == 8) SMI_FUSED(2, 8); else SMI_FUSED(2, 4); }
+    else { if (cm == 8) SMI_FUSED(4, 8); else SMI_FUSED(4, 4); }
+#undef SMI_FUSED
     return hipGetLastError();
 }
 

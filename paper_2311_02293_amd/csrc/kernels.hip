@@ -20,8 +20,6 @@ namespace {
 
 constexpr int BZ = 64, BX = 4;
 
-// first z of the 32-float-aligned storage line that contains node z
-__host__ __device__ __forceinline__ int zalign(int z) { return ((z + GH) & ~31) - GH; }
 
 struct Cell {
     int s, z, x, y;
@@ -229,8 +227,11 @@ struct MG {
 struct MCell {
     int s, z, x, y;     // y unused in 2D
     int lo, hi;         // march range [lo, hi) along the march axis
+    int zb0, zb1;       // the box along z
     long long k;        // storage offset of the first cell
-    bool ok;
+    bool ok;            // this lane updates cells
+    bool run;           // the wavefront has work (uniform over the wavefront)
+    bool need;          // this lane's row is within 4 of the box along z (z-neighbour of a cell)
 };
 
 template <int ND, int CM>
@@ -247,7 +248,9 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.hi = min(c.lo + CM, b[3]);
         c.x = c.lo;
         c.y = 0;
-        c.ok = c.z >= b[0] && c.z < b[1];
+        c.zb0 = b[0];
+        c.zb1 = b[1];
+        c.run = c.lo < c.hi && c.z - lane < b[1];
     } else {
         const int strip = (int)blockIdx.z % mg.nmarch;
         c.s = shot0 + (int)blockIdx.z / mg.nmarch;
@@ -257,9 +260,41 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.lo = b[4] + strip * CM;
         c.hi = min(c.lo + CM, b[5]);
         c.y = c.lo;
-        c.ok = c.z >= b[0] && c.z < b[1] && c.x < b[3];
+        c.zb0 = b[0];
+        c.zb1 = b[1];
+        c.run = c.lo < c.hi && c.x < b[3] && c.z - lane < b[1];
     }
+    c.ok = c.run && c.z >= c.zb0 && c.z < c.zb1;
+    c.need = c.run && c.z >= c.zb0 - 4 && c.z < c.zb1 + 4;
     return c;
+}
+
+// z-neighbours through LDS: each wavefront stages, per cell of its lanes' runs, the 64 rows it
+// owns plus 4 rows each side in its own slice (rows z0 - 4 .. z0 + 67 at index 0 .. 71);
+// lanes 0-7 load the 8 outside rows.  Rows more than 4 away from the box are never read and
+// are staged as 0.  No workgroup barrier: a wavefront reads only its own slice.
+constexpr int ZS = 72;
+
+template <int CM>
+__device__ __forceinline__ void zstage(float (*zs)[ZS], const float (&cv)[CM], const float (&hv)[CM]) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < CM; ++t) zs[t][4 + lane] = cv[t];
+    if (lane < 8) {
+#pragma unroll
+        for (int t = 0; t < CM; ++t) zs[t][lane < 4 ? lane : 64 + lane] = hv[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// the outside row lane (< 8) stages: z0 - 4 + lane (lane < 4) or z0 + 60 + lane (lane >= 4),
+// as an offset from the lane's own row z0 + lane; `ok` when that row is within 4 of the box
+__device__ __forceinline__ int zhalo(const MCell &mc, bool &ok) {
+    const int lane = threadIdx.x;
+    const int z0 = mc.z - lane;
+    const int r = lane < 4 ? z0 - 4 + lane : z0 + 60 + lane;
+    ok = mc.run && lane < 8 && r >= mc.zb0 - 4 && r < mc.zb1 + 4;
+    return r - mc.z;
 }
 
 template <int ND>
@@ -277,42 +312,57 @@ __device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
 // v_a -= dt beta_a (D+_a p + psi_a), psi updated in the slabs (eq. 3 first row, CPML).
 // All loads of the lane's CM cells are issued before any arithmetic (the loads are
 // independent, so a wavefront keeps CM times more requests in flight); cells past the end of
-// the march range re-read the last cell and store nothing.
-template <int ND, int N, int CM>
+// the march range re-read the last cell and store nothing.  ZL: the z-neighbours come from
+// the wavefront's LDS slice instead of seven unaligned global loads per cell.
+template <int ND, int N, int CM, bool ZL>
 __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg) {
     constexpr int MA = ND - 1;              // march axis
     constexpr int NW = CM + 2 * N - 1;      // window: march offsets -(N-1) .. CM-1+N
+    constexpr int A0 = ZL ? 1 : 0;          // first axis read through global stencil loads
+    __shared__ float zsh[ZL ? 4 : 1][ZL ? CM : 1][ZS];
     MCell mc = mcell_of<ND, CM>(box, shot0, mg);
-    if (!mc.ok || mc.lo >= mc.hi) return;
+    if (ZL ? !mc.run : !mc.ok) return;
+    const bool ld = ZL ? mc.need : true;
     const int cnt = mc.hi - mc.lo;
     const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
     const float *__restrict__ p = f.p + mc.s * g.P;
     const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
     float w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) w[j] = p[k0 + min(j - (N - 1), cnt - 1 + N) * ms];
-    // other axes: p at offsets d = -(N-1) .. N, d != 0, per cell; v_a and dt beta_a per cell
-    float st[CM][ND - 1][2 * N - 1];
-    float vo[CM][ND], bd[CM][ND];
+    for (int j = 0; j < NW; ++j) w[j] = ld ? p[k0 + min(j - (N - 1), cnt - 1 + N) * ms] : 0.f;
+    // axes other than the march axis (and z when ZL): p at offsets d = -(N-1) .. N, d != 0
+    float st[CM][ND - 1 > A0 ? ND - 1 - A0 : 1][2 * N - 1];
+    float vo[CM][ND], bd[CM][ND], hv[CM];
+    bool hok = false;
+    const int hoff = ZL ? zhalo(mc, hok) : 0;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
         const long long k = k0 + min(t, cnt - 1) * ms;
 #pragma unroll
-        for (int a = 0; a < ND - 1; ++a) {
+        for (int a = A0; a < ND - 1; ++a) {
             const long long sa = stride_of(g, a);
 #pragma unroll
             for (int j = 0; j < 2 * N - 1; ++j) {
                 const int d = j < N - 1 ? j - (N - 1) : j - (N - 1) + 1;
-                st[t][a][j] = p[k + d * sa];
+                st[t][a - A0][j] = mc.ok ? p[k + d * sa] : 0.f;
             }
         }
 #pragma unroll
         for (int a = 0; a < ND; ++a) {
-            vo[t][a] = f.v[a][mc.s * g.P + k];
-            bd[t][a] = m.bdt[a][k];
+            vo[t][a] = mc.ok ? f.v[a][mc.s * g.P + k] : 0.f;
+            bd[t][a] = mc.ok ? m.bdt[a][k] : 0.f;
         }
+        if (ZL) hv[t] = hok ? p[k + hoff] : 0.f;
     }
+    if (ZL) {
+        float cv[CM];
+#pragma unroll
+        for (int t = 0; t < CM; ++t) cv[t] = w[t + N - 1];
+        zstage<CM>(zsh[threadIdx.y], cv, hv);
+    }
+    if (!mc.ok) return;
+    const int zl = 4 + (int)threadIdx.x;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
         if (t >= cnt) break;
@@ -324,12 +374,16 @@ __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml
             if (a == MA) {
 #pragma unroll
                 for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N - 1 + l] - w[t + N - l]);
+            } else if (ZL && a == 0) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[0][l - 1] * (zsh[threadIdx.y][t][zl + l] - zsh[threadIdx.y][t][zl - l + 1]);
             } else {
                 // st index of offset d: d < 0 -> d + N - 1, d > 0 -> d + N - 2
 #pragma unroll
                 for (int l = 1; l <= N; ++l) {
-                    const float hi = st[t][a][l + N - 2];
-                    const float lo = l == 1 ? pc : st[t][a][-(l - 1) + N - 1];
+                    const float hi = st[t][a - A0][l + N - 2];
+                    const float lo = l == 1 ? pc : st[t][a - A0][-(l - 1) + N - 1];
                     e += g.c[a][l - 1] * (hi - lo);
                 }
             }
@@ -348,7 +402,7 @@ __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml
 
 // p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
 // first, as in k_march_v.
-template <int ND, int N, int CM, bool SRC, bool IMG>
+template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG>
 __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
@@ -356,8 +410,10 @@ __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml
                                                  const float *__restrict__ pf, float *acc_i) {
     constexpr int MA = ND - 1;
     constexpr int NW = CM + 2 * N - 1;      // window: march offsets -N .. CM-1+N-1
+    constexpr int A0 = ZL ? 1 : 0;
+    __shared__ float zsh[ZL ? 4 : 1][ZL ? CM : 1][ZS];
     MCell mc = mcell_of<ND, CM>(box, shot0, mg);
-    if (!mc.ok || mc.lo >= mc.hi) return;
+    if (ZL ? !mc.run : !mc.ok) return;
     const int cnt = mc.hi - mc.lo;
     const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
     const long long so0 = mc.s * g.P;
@@ -365,23 +421,33 @@ __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml
     const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
     float w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) w[j] = vm[k0 + min(j - N, cnt - 1 + N - 1) * ms];
-    // other axes: v_a at offsets -N .. N-1 per cell; p and dt kappa per cell
-    float st[CM][ND - 1][2 * N];
-    float po[CM], kd[CM];
+    for (int j = 0; j < NW; ++j) w[j] = mc.ok ? vm[k0 + min(j - N, cnt - 1 + N - 1) * ms] : 0.f;
+    // other axes (x in 3D, and z unless ZL): v_a at offsets -N .. N-1 per cell
+    float st[CM][ND - 1 > A0 ? ND - 1 - A0 : 1][2 * N];
+    float po[CM], kd[CM], zc[CM], hv[CM];
+    bool hok = false;
+    const int hoff = ZL ? zhalo(mc, hok) : 0;
+    const float *__restrict__ vz = f.v[0] + so0;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
         const long long k = k0 + min(t, cnt - 1) * ms;
 #pragma unroll
-        for (int a = 0; a < ND - 1; ++a) {
+        for (int a = A0; a < ND - 1; ++a) {
             const long long sa = stride_of(g, a);
             const float *__restrict__ va = f.v[a] + so0;
 #pragma unroll
-            for (int j = 0; j < 2 * N; ++j) st[t][a][j] = va[k + (j - N) * sa];
+            for (int j = 0; j < 2 * N; ++j) st[t][a - A0][j] = mc.ok ? va[k + (j - N) * sa] : 0.f;
         }
-        po[t] = f.p[so0 + k];
-        kd[t] = m.kdt[k];
+        po[t] = mc.ok ? f.p[so0 + k] : 0.f;
+        kd[t] = mc.ok ? m.kdt[k] : 0.f;
+        if (ZL) {
+            zc[t] = mc.need ? vz[k] : 0.f;
+            hv[t] = hok ? vz[k + hoff] : 0.f;
+        }
     }
+    if (ZL) zstage<CM>(zsh[threadIdx.y], zc, hv);
+    if (!mc.ok) return;
+    const int zl = 4 + (int)threadIdx.x;
     const long long sc = SRC ? src_cell[mc.s] : -1;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
@@ -394,9 +460,14 @@ __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml
             if (a == MA) {
 #pragma unroll
                 for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N + l - 1] - w[t + N - l]);
+            } else if (ZL && a == 0) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[0][l - 1] * (zsh[threadIdx.y][t][zl + l - 1] - zsh[threadIdx.y][t][zl - l]);
             } else {
 #pragma unroll
-                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (st[t][a][N + l - 1] - st[t][a][N - l]);
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[a][l - 1] * (st[t][a - A0][N + l - 1] - st[t][a - A0][N - l]);
             }
             long long so = slab_off(g, c, a);
             if (so >= 0) {
@@ -467,8 +538,8 @@ __global__ __launch_bounds__(256) void k_recon_v(Geom g, Fields f, Model m,
 }
 
 // Register-blocked forms of the two reconstruction kernels (cells per lane along the slowest
-// axis, loads first, as k_march_v / k_march_p).
-template <int ND, int N, int CM, bool GRAD, bool ILL>
+// axis, loads first, z-neighbours through LDS when ZL), as k_march_v / k_march_p.
+template <int ND, int N, int CM, bool ZL, bool GRAD, bool ILL>
 __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m,
                                                        const int *__restrict__ rbox, int shot0,
                                                        MG mg, const long long *__restrict__ src_cell,
@@ -477,8 +548,10 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
                                                        float *acc_l) {
     constexpr int MA = ND - 1;
     constexpr int NW = CM + 2 * N - 1;
+    constexpr int A0 = ZL ? 1 : 0;
+    __shared__ float zsh[ZL ? 4 : 1][ZL ? CM : 1][ZS];
     MCell mc = mcell_of<ND, CM>(rbox, shot0, mg);
-    if (!mc.ok || mc.lo >= mc.hi) return;
+    if (ZL ? !mc.run : !mc.ok) return;
     const int cnt = mc.hi - mc.lo;
     const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
     const long long so0 = mc.s * g.P;
@@ -489,27 +562,41 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
                           (long long)g.n[0] * ((ND == 2 ? mc.lo : mc.x) - g.nb +
                                                (long long)g.n[1] * (ND == 3 ? mc.lo - g.nb : 0));
     const long long iis = ND == 2 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1];
+    const bool ok = mc.ok;
     float w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) w[j] = vm[k0 + min(j - N, cnt - 1 + N - 1) * ms];
-    float st[CM][ND - 1][2 * N];
-    float po[CM], kd[CM], qv[CM], ag[CM], al[CM];
+    for (int j = 0; j < NW; ++j) w[j] = ok ? vm[k0 + min(j - N, cnt - 1 + N - 1) * ms] : 0.f;
+    float st[CM][ND - 1 > A0 ? ND - 1 - A0 : 1][2 * N];
+    float po[CM], kd[CM], qv[CM], ag[CM], al[CM], zc[CM], hv[CM];
+    bool hok = false;
+    const int hoff = ZL ? zhalo(mc, hok) : 0;
+    const float *__restrict__ vz = f.v[0] + so0;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
         const int tc = min(t, cnt - 1);
         const long long k = k0 + tc * ms;
 #pragma unroll
-        for (int a = 0; a < ND - 1; ++a) {
+        for (int a = A0; a < ND - 1; ++a) {
             const long long sa = stride_of(g, a);
             const float *__restrict__ va = f.v[a] + so0;
 #pragma unroll
-            for (int j = 0; j < 2 * N; ++j) st[t][a][j] = va[k + (j - N) * sa];
+            for (int j = 0; j < 2 * N; ++j) st[t][a - A0][j] = ok ? va[k + (j - N) * sa] : 0.f;
         }
-        po[t] = f.p[so0 + k];
-        kd[t] = m.kdt[k];
-        if (GRAD) { qv[t] = qp[so0 + k]; ag[t] = acc_g[ii0 + tc * iis]; }
-        if (ILL) al[t] = acc_l[ii0 + tc * iis];
+        po[t] = ok ? f.p[so0 + k] : 0.f;
+        kd[t] = ok ? m.kdt[k] : 0.f;
+        if (GRAD) {
+            qv[t] = ok ? qp[so0 + k] : 0.f;
+            ag[t] = ok ? acc_g[ii0 + tc * iis] : 0.f;
+        }
+        if (ILL) al[t] = ok ? acc_l[ii0 + tc * iis] : 0.f;
+        if (ZL) {
+            zc[t] = mc.need ? vz[k] : 0.f;
+            hv[t] = hok ? vz[k + hoff] : 0.f;
+        }
     }
+    if (ZL) zstage<CM>(zsh[threadIdx.y], zc, hv);
+    if (!ok) return;
+    const int zl = 4 + (int)threadIdx.x;
     const long long sc = src_cell[mc.s];
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
@@ -522,9 +609,14 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
             if (a == MA) {
 #pragma unroll
                 for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N + l - 1] - w[t + N - l]);
+            } else if (ZL && a == 0) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[0][l - 1] * (zsh[threadIdx.y][t][zl + l - 1] - zsh[threadIdx.y][t][zl - l]);
             } else {
 #pragma unroll
-                for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (st[t][a][N + l - 1] - st[t][a][N - l]);
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[a][l - 1] * (st[t][a - A0][N + l - 1] - st[t][a - A0][N - l]);
             }
             div += e;
         }
@@ -537,41 +629,56 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
     }
 }
 
-template <int ND, int N, int CM>
+template <int ND, int N, int CM, bool ZL>
 __global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m,
                                                        const int *__restrict__ rbox, int shot0,
                                                        MG mg) {
     constexpr int MA = ND - 1;
     constexpr int NW = CM + 2 * N - 1;
+    constexpr int A0 = ZL ? 1 : 0;
+    __shared__ float zsh[ZL ? 4 : 1][ZL ? CM : 1][ZS];
     MCell mc = mcell_of<ND, CM>(rbox, shot0, mg);
-    if (!mc.ok || mc.lo >= mc.hi) return;
+    if (ZL ? !mc.run : !mc.ok) return;
+    const bool ld = ZL ? mc.need : true;
+    const bool ok = mc.ok;
     const int cnt = mc.hi - mc.lo;
     const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
     const float *__restrict__ p = f.p + mc.s * g.P;
     const long long k0 = as_cell<ND>(g, mc, mc.lo).k;
     float w[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) w[j] = p[k0 + min(j - (N - 1), cnt - 1 + N) * ms];
-    float st[CM][ND - 1][2 * N - 1];
-    float vo[CM][ND], bd[CM][ND];
+    for (int j = 0; j < NW; ++j) w[j] = ld ? p[k0 + min(j - (N - 1), cnt - 1 + N) * ms] : 0.f;
+    float st[CM][ND - 1 > A0 ? ND - 1 - A0 : 1][2 * N - 1];
+    float vo[CM][ND], bd[CM][ND], hv[CM];
+    bool hok = false;
+    const int hoff = ZL ? zhalo(mc, hok) : 0;
 #pragma unroll
     for (int t = 0; t < CM; ++t) {
         const long long k = k0 + min(t, cnt - 1) * ms;
 #pragma unroll
-        for (int a = 0; a < ND - 1; ++a) {
+        for (int a = A0; a < ND - 1; ++a) {
             const long long sa = stride_of(g, a);
 #pragma unroll
             for (int j = 0; j < 2 * N - 1; ++j) {
                 const int d = j < N - 1 ? j - (N - 1) : j - (N - 1) + 1;
-                st[t][a][j] = p[k + d * sa];
+                st[t][a - A0][j] = ok ? p[k + d * sa] : 0.f;
             }
         }
 #pragma unroll
         for (int a = 0; a < ND; ++a) {
-            vo[t][a] = f.v[a][mc.s * g.P + k];
-            bd[t][a] = m.bdt[a][k];
+            vo[t][a] = ok ? f.v[a][mc.s * g.P + k] : 0.f;
+            bd[t][a] = ok ? m.bdt[a][k] : 0.f;
         }
+        if (ZL) hv[t] = hok ? p[k + hoff] : 0.f;
     }
+    if (ZL) {
+        float cv[CM];
+#pragma unroll
+        for (int t = 0; t < CM; ++t) cv[t] = w[t + N - 1];
+        zstage<CM>(zsh[threadIdx.y], cv, hv);
+    }
+    if (!ok) return;
+    const int zl = 4 + (int)threadIdx.x;
     // v_a points strictly between interior p nodes along a
     const int lastz = g.nb + g.n[0] - 1, lastx = g.nb + g.n[1] - 1, lasty = g.nb + g.n[2] - 1;
 #pragma unroll
@@ -588,11 +695,15 @@ __global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m
             if (a == MA) {
 #pragma unroll
                 for (int l = 1; l <= N; ++l) e += g.c[a][l - 1] * (w[t + N - 1 + l] - w[t + N - l]);
+            } else if (ZL && a == 0) {
+#pragma unroll
+                for (int l = 1; l <= N; ++l)
+                    e += g.c[0][l - 1] * (zsh[threadIdx.y][t][zl + l] - zsh[threadIdx.y][t][zl - l + 1]);
             } else {
 #pragma unroll
                 for (int l = 1; l <= N; ++l) {
-                    const float hi = st[t][a][l + N - 2];
-                    const float lo = l == 1 ? pc : st[t][a][-(l - 1) + N - 1];
+                    const float hi = st[t][a - A0][l + N - 2];
+                    const float lo = l == 1 ? pc : st[t][a - A0][-(l - 1) + N - 1];
                     e += g.c[a][l - 1] * (hi - lo);
                 }
             }
@@ -845,7 +956,7 @@ hipError_t launch_minmax(const float *vp, long long n, unsigned *out2, hipStream
 
 namespace {
 
-template <int ND, int N, int CM>
+template <int ND, int N, int CM, bool ZL>
 hipError_t fwd_march_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
@@ -853,38 +964,38 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd);
     if (L.empty) return hipSuccess;
     if (c.ev) {
-        hipExtLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
+        hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
                               0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg);
-        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, true, false>), L.grid, L.block, 0, c.st,
+        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                               (const float *)nullptr, (float *)nullptr);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
+    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
                        w.cpml, box, 0, L.mg);
-    hipLaunchKernelGGL((k_march_p<ND, N, CM, true, false>), L.grid, L.block, 0, c.st, pl.geom,
+    hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
                        pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
     return hipGetLastError();
 }
 
 // adjoint half steps with the marching kernels (image with the source field when asked)
-template <int ND, int N, int CM>
+template <int ND, int N, int CM, bool ZL>
 hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
     MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
     if (L.empty) return hipSuccess;
-    hipLaunchKernelGGL((k_march_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
+    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, ab, 0, L.mg);
     if (image)
-        hipLaunchKernelGGL((k_march_p<ND, N, CM, false, true>), L.grid, L.block, 0, c.st, pl.geom,
+        hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                            w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
                            c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
     else
-        hipLaunchKernelGGL((k_march_p<ND, N, CM, false, false>), L.grid, L.block, 0, c.st,
+        hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, false>), L.grid, L.block, 0, c.st,
                            pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
                            (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                            (const float *)w.f.p, w.acc_i);
@@ -895,9 +1006,13 @@ template <int ND, int N>
 hipError_t fwd_step_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    if (!c.plain && c.march == 2) return fwd_march_t<ND, N, 2>(c, it);
-    if (!c.plain && c.march == 4) return fwd_march_t<ND, N, 4>(c, it);
-    if (!c.plain && c.march == 8) return fwd_march_t<ND, N, 8>(c, it);
+#define SMI_MARCH(fn, ...)                                                                      \
+    do {                                                                                        \
+        if (c.march == 2) return c.zl ? fn<ND, N, 2, true>(__VA_ARGS__) : fn<ND, N, 2, false>(__VA_ARGS__); \
+        if (c.march == 8) return c.zl ? fn<ND, N, 8, true>(__VA_ARGS__) : fn<ND, N, 8, false>(__VA_ARGS__); \
+        return c.zl ? fn<ND, N, 4, true>(__VA_ARGS__) : fn<ND, N, 4, false>(__VA_ARGS__);          \
+    } while (0)
+    if (!c.plain && c.march) SMI_MARCH(fwd_march_t, c, it);
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     int step = c.plain ? 1 : pl.nshot;
     for (int s0 = 0; s0 < pl.nshot; s0 += step) {
@@ -924,7 +1039,7 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
 }
 
 // reconstruction half steps with the register-blocked kernels (region: rbox row it)
-template <int ND, int N, int CM>
+template <int ND, int N, int CM, bool ZL>
 hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
@@ -932,7 +1047,7 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     MLaunch L = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
     if (!L.empty) {
 #define SMI_MRECON_P(G_, L_)                                                                   \
-    hipLaunchKernelGGL((k_march_recon_p<ND, N, CM, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, \
+    hipLaunchKernelGGL((k_march_recon_p<ND, N, CM, ZL, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, \
                        w.f, w.model, rb, 0, L.mg, (const long long *)w.src_cell, c.stf,         \
                        pl.g.nt, it, (const float *)w.q.p, w.acc_g, w.acc_l)
         if (grad && image) SMI_MRECON_P(true, true);
@@ -944,7 +1059,7 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     hipError_t e = band_restore(c, it, 0);
     if (e != hipSuccess) return e;
     if (!L.empty)
-        hipLaunchKernelGGL((k_march_recon_v<ND, N, CM>), L.grid, L.block, 0, c.st, pl.geom, w.f,
+        hipLaunchKernelGGL((k_march_recon_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.f,
                            w.model, rb, 0, L.mg);
     return band_restore(c, it, 1);
 }
@@ -954,13 +1069,10 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     if (!c.plain && c.march) {
-        hipError_t e = c.march == 2 ? recon_march_t<ND, N, 2>(c, it, grad, image)
-                     : c.march == 8 ? recon_march_t<ND, N, 8>(c, it, grad, image)
-                                    : recon_march_t<ND, N, 4>(c, it, grad, image);
+        auto recon = [&]() -> hipError_t { SMI_MARCH(recon_march_t, c, it, grad, image); };
+        hipError_t e = recon();
         if (e != hipSuccess) return e;
-        if (c.march == 2) return adj_march_t<ND, N, 2>(c, it, image);
-        if (c.march == 4) return adj_march_t<ND, N, 4>(c, it, image);
-        return adj_march_t<ND, N, 8>(c, it, image);
+        SMI_MARCH(adj_march_t, c, it, image);
     }
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
@@ -1029,11 +1141,11 @@ hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {
     SMI_DISPATCH(rev_step_t, c, it, grad, image);
 }
 
-hipError_t extract(const StepCtx &c, int it, float *dcal) {
+hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p) {
     const Views &w = *c.w;
     if (w.recv.R == 0) return hipSuccess;
     hipLaunchKernelGGL(k_extract, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom,
-                       (const float *)w.f.p, w.recv, dcal, it, w.status);
+                       p ? p : (const float *)w.f.p, w.recv, dcal, it, w.status);
     return hipGetLastError();
 }
 

@@ -181,15 +181,16 @@ struct StepCtx {
     // the p launch (ev[2], ev[3]) of this step, taken by the device around each kernel
     const hipEvent_t *ev = nullptr;
     bool xcd = false;       // XCD-contiguous tile order of the sweep kernels
-    int march = 0;          // > 0: marching half-step kernels with this march length (8, 16, 32)
+    int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
+    bool zl = false;        // register-blocked kernels take z-neighbours from LDS
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);
-// fused forward step (v, p, CPML, source, receivers in one kernel); false if not provided
+// fused 2D forward step (v, p, CPML, source in one kernel, level n from src, level n + 1 to
+// dst); false if not provided for this plan
 bool fused_fwd_available(const Plan &pl);
-hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it,
-                          float *dcal);
-hipError_t extract(const StepCtx &c, int it, float *dcal);
+hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it);
+hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p = nullptr);
 hipError_t band_save(const StepCtx &c, const Fields &f, int slot);
 hipError_t band_restore(const StepCtx &c, int it, int which);
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
