@@ -161,19 +161,31 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
  *            -(2 dt / Vp) sum_it p~ div v^{it+1/2} (eq. 7 with kappa = rho Vp^2).  Overwritten.
  *   image    device [n1*n2*n3] or NULL: sum_s sum_it dt p~^it p^it (eq. 10).  Overwritten.
  *   illum    device [n1*n2*n3] or NULL: sum_s sum_it dt (p^it)^2.  Overwritten.
+ *   image_norm device [n1*n2*n3] or NULL: the normalised imaging condition of Sec. 2.3, each
+ *            shot's image divided by its own source illumination, summed over shots:
+ *            sum_s image_s / (illum_s + 1e-3 max(illum_s)) (the stabiliser is not given by the
+ *            paper).  Overwritten.
  *   snap_it, nsnap, snaps   optional: reconstructed source-field p at the listed levels,
  *            device [nshot][nsnap][n1*n2*n3].
  * The state must come from smi_forward on the same context. */
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
-                                   float *grad_vp, float *image, float *illum,
+                                   float *grad_vp, float *image, float *illum, float *image_norm,
                                    const int *snap_it, int nsnap, float *snaps,
                                    void *hip_stream);
 
 /* RTM (Sec. 2.3): forward with boundary saving, then the reverse loop with G = dt dobs.
- * dobs has the layout of dcal.  image / illum as in smi_adjoint_reconstruct (any may be NULL). */
+ * dobs has the layout of dcal.  image / illum / image_norm as in smi_adjoint_reconstruct (any
+ * may be NULL). */
 smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                          const float *vp, const float *rho, const float *stf, const float *dobs,
-                         float *image, float *illum, void *ws, size_t ws_bytes,
+                         float *image, float *illum, float *image_norm, void *ws, size_t ws_bytes,
+                         void *hip_stream);
+
+/* Laplace filter of an image (Sec. 2.3, against the low-wavenumber artefacts of RTM images):
+ * out = sum_a (f[i+1] - 2 f[i] + f[i-1]) / d_a^2 over the grid's axes (second-order central
+ * differences), with f = 0 outside the n1*n2[*n3] image.  in, out: device, z fastest, must not
+ * alias.  Only ndim, n1..n3 and d1..d3 of the grid are read.  SMI_E_ARG on bad sizes. */
+smi_status smi_laplacian(smi_ctx *ctx, const smi_grid *grid, const float *in, float *out,
                          void *hip_stream);
 
 /* FWI gradient (Sec. 2.2): forward with boundary saving, residual r = dcal - dobs,

@@ -8,6 +8,8 @@ with ctypes) and adds the host-side arithmetic of the method in plain numpy:
   * eq. (6)  L2 misfit and residual adjoint source         -> :func:`misfit`
   * eq. (7)  kappa gradient, chain rule to Vp (rho fixed)  -> :func:`fwi_grad`
   * eq. (10) cross-correlation image                       -> :func:`rtm_image`
+  * Sec. 2.3 source-normalised image, Laplace filter         -> :func:`normalized_image`,
+                                                               :func:`laplacian`
   * Alg. 2   forward loop, adjoint source, reverse loop, sum over shots
 
 Positions in metres are turned into padded grid nodes by rounding (on-grid positions only).
@@ -294,19 +296,54 @@ def fwi_grad(job, dobs, shots=None, vp=None, box=None, vmax=None, use_history=Fa
     return (2.0 * rho64 * vp64 * gk).reshape(job.vp.shape), J
 
 
-def rtm_image(job, dobs, shots=None, box=None, vmax=None):
-    """eq. (10): image and source illumination, summed over shots (G = dt dobs)."""
+def rtm_image(job, dobs, shots=None, box=None, vmax=None, per_shot=False):
+    """eq. (10): image and source illumination, summed over shots (G = dt dobs); with
+    per_shot, the lists of each shot's image and illumination instead."""
     vmax = model_vmax(job) if vmax is None else vmax
     gr = og_grid(job.grid, vmax=vmax, box=box)
     shots = list(range(job.acq.nshot)) if shots is None else list(shots)
-    I = interior_size(gr)
-    im = np.zeros(I)
-    il = np.zeros(I)
+    ims, ils = [], []
     for k, s in enumerate(shots):
         src, rec = shot_nodes(job.grid, job.acq, s)
         fw = forward(gr, job.vp, job.rho, src, job.stf[s], rec, bands=True, final=True)
         r = adjoint(gr, job.vp, job.rho, src, job.stf[s], rec, gr.dt * np.asarray(dobs[k]),
                     bands=fw["bands"], final=fw["final"], want=("image", "illum"))
-        im += r["image"]
-        il += r["illum"]
-    return im.reshape(job.vp.shape), il.reshape(job.vp.shape)
+        ims.append(r["image"].reshape(job.vp.shape))
+        ils.append(r["illum"].reshape(job.vp.shape))
+    if per_shot:
+        return ims, ils
+    return np.sum(ims, axis=0), np.sum(ils, axis=0)
+
+
+# Stabiliser of the source normalisation, as a fraction of each shot's peak illumination.
+NORM_EPS = 1e-3
+
+
+def normalized_image(images, illums, eps_frac: float = NORM_EPS):
+    """Sec. 2.3, normalised imaging condition: each shot's image divided by that shot's
+    source illumination, then summed over shots.  The paper gives no stabiliser; here the
+    division is by illum_s + eps_frac * max(illum_s)."""
+    out = np.zeros_like(np.asarray(images[0], np.float64))
+    for im, il in zip(images, illums):
+        il = np.asarray(il, np.float64)
+        out += np.asarray(im, np.float64) / (il + eps_frac * np.max(il))
+    return out
+
+
+def laplacian(img, spacing):
+    """Sec. 2.3, Laplace filter of an image: the second-order central-difference Laplacian
+    sum_a (f[i+1] - 2 f[i] + f[i-1]) / d_a^2 over the image's axes, with zero outside the
+    image.  `img` has numpy shape (n2, n1) or (n3, n2, n1); spacing = (d1, d2[, d3])."""
+    f = np.asarray(img, np.float64)
+    out = np.zeros_like(f)
+    nd = f.ndim
+    for a in range(nd):
+        ax = nd - 1 - a                     # axis a (z = 0) is the last numpy axis
+        d = float(spacing[a])
+        pad = [(0, 0)] * nd
+        pad[ax] = (1, 1)
+        g = np.pad(f, pad)
+        sl = lambda o: tuple(slice(1 + o, g.shape[i] - 1 + o) if i == ax else slice(None)
+                             for i in range(nd))
+        out += (g[sl(1)] - 2.0 * g[sl(0)] + g[sl(-1)]) / (d * d)
+    return out

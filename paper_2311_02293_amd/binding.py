@@ -64,10 +64,11 @@ def lib():
                                           C.POINTER(C.c_size_t)]
         L.smi_forward.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp,
                                   C.POINTER(vp), C.POINTER(C.c_int), C.c_int, vp, vp, C.c_size_t, vp]
-        L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.c_int,
+        L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.c_int,
                                               vp, vp]
         L.smi_rtm_image.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
-                                    vp, vp, C.c_size_t, vp]
+                                    vp, vp, vp, C.c_size_t, vp]
+        L.smi_laplacian.argtypes = [vp, C.POINTER(SmiGrid), vp, vp, vp]
         L.smi_fwi_grad.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
                                    vp, vp, vp, C.c_size_t, vp]
         L.smi_state_destroy.argtypes = [vp]
@@ -230,28 +231,32 @@ class Context:
         return dcal, out_snaps, state
 
     def adjoint_reconstruct(self, state: State, adj_src, *, grad=True, image=True, illum=True,
-                            snaps: Sequence[int] = (), nshot: Optional[int] = None, npts=None,
-                            stream=None):
-        """smi_adjoint_reconstruct.  Returns dict(grad, image, illum, snaps)."""
+                            image_norm=False, snaps: Sequence[int] = (),
+                            nshot: Optional[int] = None, npts=None, stream=None):
+        """smi_adjoint_reconstruct.  Returns dict(grad, image, illum, image_norm, snaps)."""
         import torch
         vp = state.keep[1]
         dev = vp.device
         n = vp.numel() if npts is None else npts
         out = {k: (torch.empty(n, dtype=torch.float32, device=dev) if want else None)
-               for k, want in (("grad", grad), ("image", image), ("illum", illum))}
+               for k, want in (("grad", grad), ("image", image), ("illum", illum),
+                               ("image_norm", image_norm))}
         snap_it = np.ascontiguousarray(list(snaps), np.int32)
         out["snaps"] = None
         if len(snap_it):
             out["snaps"] = torch.empty((nshot, len(snap_it), n), dtype=torch.float32, device=dev)
         rc = lib().smi_adjoint_reconstruct(
             self.h, state.handle, _ptr(adj_src), _ptr(out["grad"]), _ptr(out["image"]),
-            _ptr(out["illum"]), snap_it.ctypes.data_as(C.POINTER(C.c_int)) if len(snap_it) else None,
+            _ptr(out["illum"]), _ptr(out["image_norm"]),
+            snap_it.ctypes.data_as(C.POINTER(C.c_int)) if len(snap_it) else None,
             len(snap_it), _ptr(out["snaps"]), _stream(stream))
         self._check(rc)
         state.consumed = True
         return out
 
-    def rtm_image(self, grid, acq, vp, rho, stf, dobs, *, illum=True, ws=None, stream=None):
+    def rtm_image(self, grid, acq, vp, rho, stf, dobs, *, illum=True, norm=False, ws=None,
+                  stream=None):
+        """smi_rtm_image.  Returns (image, illum) -- (image, illum, image_norm) with norm."""
         import torch
         g = make_grid(grid)
         a = _Acq(acq)
@@ -259,10 +264,19 @@ class Context:
         ws = self.workspace(nb) if ws is None else ws
         image = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
         il = torch.empty_like(image) if illum else None
+        nm = torch.empty_like(image) if norm else None
         self._check(lib().smi_rtm_image(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
-                                        _ptr(stf), _ptr(dobs), _ptr(image), _ptr(il), _ptr(ws),
-                                        ws.numel(), _stream(stream)))
-        return image, il
+                                        _ptr(stf), _ptr(dobs), _ptr(image), _ptr(il), _ptr(nm),
+                                        _ptr(ws), ws.numel(), _stream(stream)))
+        return (image, il, nm) if norm else (image, il)
+
+    def laplacian(self, grid, image, out=None, stream=None):
+        """smi_laplacian: Laplace filter of an n1*n2[*n3] device image."""
+        import torch
+        g = make_grid(grid)
+        out = torch.empty_like(image) if out is None else out
+        self._check(lib().smi_laplacian(self.h, C.byref(g), _ptr(image), _ptr(out), _stream(stream)))
+        return out
 
     def fwi_grad(self, grid, acq, vp, rho, stf, dobs, *, want_dcal=False, ws=None, stream=None):
         import torch

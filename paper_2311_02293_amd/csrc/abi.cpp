@@ -255,11 +255,12 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
 
 // Alg. 2, reverse loop: adjoint source -> reconstruction (+gradient) -> adjoint step (+image).
 smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad, float *image,
-                       float *illum, const int *snap_it, int nsnap, float *snaps, hipStream_t st) {
+                       float *illum, float *image_norm, const int *snap_it, int nsnap,
+                       float *snaps, hipStream_t st) {
     const Plan &pl = stt->plan;
     Views w = smi::views(pl, stt->ws);
     bool adj = G != nullptr;
-    bool want_g = adj && grad, want_i = adj && (image || illum);
+    bool want_g = adj && grad, want_i = adj && (image || illum || image_norm);
     smi_status s = zero_fields(ctx, pl, w.q, st);
     if (s != SMI_OK) return s;
     HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
@@ -274,12 +275,13 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
             if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     }
     HIPCHK(smi::finalize(c, stt->vp, want_g ? grad : nullptr, want_i ? image : nullptr,
-                         want_i ? illum : nullptr), "finalize");
+                         want_i ? illum : nullptr, want_i ? image_norm : nullptr), "finalize");
     if (!adj) {
         size_t I = sizeof(float) * pl.I;
         if (grad) HIPCHK(hipMemsetAsync(grad, 0, I, st), "grad clear");
         if (image) HIPCHK(hipMemsetAsync(image, 0, I, st), "image clear");
         if (illum) HIPCHK(hipMemsetAsync(illum, 0, I, st), "illum clear");
+        if (image_norm) HIPCHK(hipMemsetAsync(image_norm, 0, I, st), "image_norm clear");
     }
     ctx->cnt[1] = adj ? pl.cnt_adj : 0;
     ctx->cnt[2] = pl.cnt_rec;
@@ -400,15 +402,15 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, c
 }
 
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
-                                   float *grad_vp, float *image, float *illum, const int *snap_it,
-                                   int nsnap, float *snaps, void *hip_stream) {
+                                   float *grad_vp, float *image, float *illum, float *image_norm,
+                                   const int *snap_it, int nsnap, float *snaps, void *hip_stream) {
     if (!ctx) return SMI_E_ARG;
     if (!state || state->consumed || !state->plan.save)
         return fail(ctx, SMI_E_STATE, "state missing, already consumed, or saved without boundaries");
     if (state->ctx != ctx) return fail(ctx, SMI_E_STATE, "state belongs to another context");
     smi_status s = check_snaps(ctx, &state->plan.g, snap_it, nsnap, snaps);
     if (s != SMI_OK) return s;
-    s = run_reverse(ctx, state, adj_src, grad_vp, image, illum, snap_it, nsnap, snaps,
+    s = run_reverse(ctx, state, adj_src, grad_vp, image, illum, image_norm, snap_it, nsnap, snaps,
                     (hipStream_t)hip_stream);
     if (s != SMI_OK) return s;
     state->consumed = true;
@@ -417,7 +419,8 @@ smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *
 
 smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
                          const float *rho, const float *stf, const float *dobs, float *image,
-                         float *illum, void *ws, size_t ws_bytes, void *hip_stream) {
+                         float *illum, float *image_norm, void *ws, size_t ws_bytes,
+                         void *hip_stream) {
     if (!ctx) return SMI_E_ARG;
     if (!dobs) return fail(ctx, SMI_E_ARG, "dobs is NULL");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -440,7 +443,8 @@ smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
     configure(c, ctx, stt->plan);
     HIPCHK(smi::scale_copy(c, dobs, w.G, (float)g.dt), "rtm source");
-    return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, nullptr, 0, nullptr, st);
+    return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, image_norm, nullptr, 0, nullptr,
+                       st);
 }
 
 smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
@@ -469,7 +473,8 @@ smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, 
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
     configure(c, ctx, stt->plan);
     HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
-    return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, 0, nullptr, st);
+    return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, nullptr, 0, nullptr,
+                       st);
 }
 
 void smi_state_destroy(smi_state *state) { delete state; }
@@ -493,6 +498,19 @@ smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double 
     if (fwd) *fwd = ctx->cnt[0];
     if (adj) *adj = ctx->cnt[1];
     if (rec) *rec = ctx->cnt[2];
+    return SMI_OK;
+}
+
+smi_status smi_laplacian(smi_ctx *ctx, const smi_grid *grid, const float *in, float *out,
+                         void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!grid || !in || !out) return fail(ctx, SMI_E_ARG, "grid, in and out are required");
+    if (in == out) return fail(ctx, SMI_E_ARG, "in and out must not alias");
+    if ((grid->ndim != 2 && grid->ndim != 3) || grid->n1 < 1 || grid->n2 < 1 ||
+        (grid->ndim == 3 && grid->n3 < 1) || !(grid->d1 > 0) || !(grid->d2 > 0) ||
+        (grid->ndim == 3 && !(grid->d3 > 0)))
+        return fail(ctx, SMI_E_ARG, "ndim must be 2 or 3 with positive sizes and spacings");
+    HIPCHK(smi::launch_laplacian(grid, in, out, (hipStream_t)hip_stream), "laplacian");
     return SMI_OK;
 }
 

@@ -858,6 +858,60 @@ __global__ __launch_bounds__(256) void k_finalize_sum(const float *__restrict__ 
     out[i] = s;
 }
 
+// Per-shot peak of the illumination (non-negative floats order like their bit patterns).
+__global__ __launch_bounds__(256) void k_shot_max(const float *__restrict__ acc, long long I,
+                                                  unsigned *mx) {
+    const int s = blockIdx.y;
+    unsigned hi = 0u;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < I;
+         i += (long long)gridDim.x * blockDim.x)
+        hi = max(hi, __float_as_uint(fmaxf(acc[s * I + i], 0.f)));
+    for (int o = 32; o > 0; o >>= 1) hi = max(hi, (unsigned)__shfl_down((int)hi, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx + s, hi);
+}
+
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Normalised imaging condition (Sec. 2.3): sum_s image_s / (illum_s + eps max(illum_s)).
+__global__ __launch_bounds__(256) void k_finalize_norm(const float *__restrict__ img,
+                                                       const float *__restrict__ ill, int nshot,
+                                                       long long I, const unsigned *__restrict__ mx,
+                                                       float eps, float *out) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= I) return;
+    float s = 0.f;
+    for (int k = 0; k < nshot; ++k) {
+        const float st = eps * __uint_as_float(mx[k]);
+        const float den = ill[k * I + i] + st;
+        s += den > 0.f ? img[k * I + i] / den : 0.f;
+    }
+    out[i] = s;
+}
+
+// Laplace filter of an image (Sec. 2.3): second-order central differences along each axis,
+// divided by the squared spacing, zero outside the image.
+__global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ f, float *out,
+                                                   int n1, int n2, int n3, float w1, float w2,
+                                                   float w3) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long tot = (long long)n1 * n2 * n3;
+    if (i >= tot) return;
+    const int z = (int)(i % n1);
+    const long long r = i / n1;
+    const int x = (int)(r % n2);
+    const int y = (int)(r / n2);
+    const long long s2 = n1, s3 = (long long)n1 * n2;
+    const float c = f[i];
+    float acc = w1 * ((z + 1 < n1 ? f[i + 1] : 0.f) - 2.f * c + (z > 0 ? f[i - 1] : 0.f));
+    acc += w2 * ((x + 1 < n2 ? f[i + s2] : 0.f) - 2.f * c + (x > 0 ? f[i - s2] : 0.f));
+    if (n3 > 1 || w3 != 0.f)
+        acc += w3 * ((y + 1 < n3 ? f[i + s3] : 0.f) - 2.f * c + (y > 0 ? f[i - s3] : 0.f));
+    out[i] = acc;
+}
+
 // interior p of every shot -> snaps[s][k][...]
 __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
                                               int k, int nsnap) {
@@ -1244,9 +1298,32 @@ hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, floa
     return hipGetLastError();
 }
 
-hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum) {
+hipError_t launch_laplacian(const smi_grid *g, const float *in, float *out, hipStream_t st) {
+    const int n3 = g->ndim == 3 ? g->n3 : 1;
+    const long long tot = (long long)g->n1 * g->n2 * n3;
+    const float w1 = 1.f / (g->d1 * g->d1), w2 = 1.f / (g->d2 * g->d2);
+    const float w3 = g->ndim == 3 ? 1.f / (g->d3 * g->d3) : 0.f;
+    hipLaunchKernelGGL(k_laplacian, dim3(blocks(tot)), dim3(256), 0, st, in, out, g->n1, g->n2, n3,
+                       w1, w2, w3);
+    return hipGetLastError();
+}
+
+// stabiliser of the normalised image, as a fraction of each shot's peak illumination
+constexpr float kNormEps = 1e-3f;
+
+hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum,
+                    float *image_norm) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    if (image_norm) {
+        unsigned *mx = (unsigned *)w.partial;
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks(pl.nshot)), dim3(256), 0, c.st, mx, pl.nshot, 0u);
+        hipLaunchKernelGGL(k_shot_max, dim3(std::min<unsigned>(blocks(pl.I), 1024u), pl.nshot),
+                           dim3(256), 0, c.st, (const float *)w.acc_l, pl.I, mx);
+        hipLaunchKernelGGL(k_finalize_norm, dim3(blocks(pl.I)), dim3(256), 0, c.st,
+                           (const float *)w.acc_i, (const float *)w.acc_l, pl.nshot, pl.I,
+                           (const unsigned *)mx, kNormEps, image_norm);
+    }
     if (grad)
         hipLaunchKernelGGL(k_finalize_grad, dim3(blocks(pl.I)), dim3(256), 0, c.st,
                            (const float *)w.acc_g, pl.nshot, pl.I, vp, (float)pl.g.dt, grad);

@@ -389,7 +389,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     pl.off_status = take(64);
     pl.off_misfit = take(16);
-    pl.npartial = 1024;
+    pl.npartial = std::max(1024, acq->nshot);   // also holds the per-shot peak illumination
     pl.off_partial = take(sizeof(double) * pl.npartial);
     pl.off_model = take(sizeof(float) * (size_t)pl.P * (1 + pl.nd));
     size_t cp = 0;

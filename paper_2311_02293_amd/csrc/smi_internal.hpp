@@ -199,6 +199,8 @@ hipError_t adj_inject(const StepCtx &c, int it, const float *G);
 hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image);
 hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
                     double *misfit);
-hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum);
+hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum,
+                    float *image_norm);
+hipError_t launch_laplacian(const smi_grid *g, const float *in, float *out, hipStream_t st);
 
 }  // namespace smi

@@ -249,21 +249,47 @@ def test_fwi_gradient_matches_oracle(ctx):
 
 
 def test_rtm_image_matches_oracle(ctx):
-    """eq. (10): image and illumination against the oracle (G = dt dobs)."""
+    """eq. (10): image and illumination against the oracle (G = dt dobs); the normalised
+    image of Sec. 2.3 (per-shot division by the source illumination) and its Laplace filter."""
     from oracle import oracle as O
     import torch
     job = _grad_job(nt=600, nshot=2)
     vmax = float(job.grid.vpmax)
     dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
-    ref_i, ref_l = O.rtm_image(job, dobs, vmax=vmax, box=0)
+    ims, ils = O.rtm_image(job, dobs, vmax=vmax, box=0, per_shot=True)
+    ref_i, ref_l = np.sum(ims, 0), np.sum(ils, 0)
+    ref_n = O.normalized_image(ims, ils)
     vp, rho, stf = dev(job)
     dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
-    im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    im, il, nm = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t, norm=True)
+    lap = ctx.laplacian(job.grid, nm).cpu().numpy().reshape(job.vp.shape)
     im = im.cpu().numpy().reshape(job.vp.shape)
     il = il.cpu().numpy().reshape(job.vp.shape)
-    say("image rel L2", rel_l2(im, ref_i), "illum rel L2", rel_l2(il, ref_l))
+    nm = nm.cpu().numpy().reshape(job.vp.shape)
+    ref_lap = O.laplacian(ref_n, (job.grid.d1, job.grid.d2))
+    say("image rel L2", rel_l2(im, ref_i), "illum rel L2", rel_l2(il, ref_l),
+        "normalised", rel_l2(nm, ref_n), "laplacian", rel_l2(lap, ref_lap))
     assert rel_l2(im, ref_i) <= 1e-4
     assert rel_l2(il, ref_l) <= 1e-4
+    assert rel_l2(nm, ref_n) <= 1e-4
+    assert rel_l2(lap, ref_lap) <= 1e-4
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_laplacian_matches_oracle(ctx, ndim):
+    """Laplace filter on a seeded random image with unequal spacings (edges included)."""
+    from oracle import oracle as O
+    import torch
+    rng = np.random.default_rng(7 + ndim)
+    shape = (9, 13, 17) if ndim == 3 else (21, 17)
+    f = rng.standard_normal(shape).astype(np.float32)
+    d = (2.0, 3.0, 5.0)[:ndim]
+    g = I.Grid(ndim=ndim, n1=shape[-1], n2=shape[-2], n3=shape[0] if ndim == 3 else 1,
+               d1=d[0], d2=d[1], d3=d[2] if ndim == 3 else 1.0, nb=10, order=8, nt=10,
+               dt=1e-3, fm=10.0)
+    out = ctx.laplacian(g, torch.from_numpy(f.ravel()).cuda()).cpu().numpy().reshape(shape)
+    ref = O.laplacian(f.astype(np.float64), d)
+    assert np.max(np.abs(out - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
 def test_forward_3d_matches_oracle(ctx):

@@ -81,3 +81,12 @@ def test_workspace_bytes_and_argument_errors():
     acq.rec[5] = acq.rec[6]
     a4 = B._Acq(acq)
     assert L.smi_workspace_bytes(None, C.byref(g), C.byref(a4.c), 0, C.byref(n0)) == -1
+
+
+def test_laplacian_rejects_bad_arguments_on_the_host():
+    """smi_laplacian validates before touching the device (no GPU needed)."""
+    import ctypes as C
+    from paper_2311_02293_amd import binding as B
+    L = B.lib()
+    g = B.make_grid(I.Grid(ndim=2, n1=8, n2=8, d1=1.0, d2=1.0, nb=4, order=4, nt=1, dt=1e-3, fm=1.0))
+    assert L.smi_laplacian(None, C.byref(g), None, None, None) == -1

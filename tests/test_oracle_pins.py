@@ -495,3 +495,56 @@ def test_decimated_forward_records_the_same_data(oracle):
     b = oracle.forward(gr, vp, rho, src, stf, rec)
     np.testing.assert_array_equal(a["dcal"], b["dcal"])
     assert a["bands"].shape[0] == (g.nt - 1) // g.dr + 4 + 1
+
+
+# ----------------------------------------------------------------------------- RTM post-processing
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_laplacian_matches_closed_forms(oracle, ndim):
+    """Sec. 2.3 Laplace filter: exact (to round-off) on quadratics inside the image, and the
+    discrete eigenvalue -(4/d^2) sin^2(k d / 2) on a sine that vanishes at the padding."""
+    n = (7, 6, 5)[:ndim]
+    d = (2.0, 3.0, 1.5)[:ndim]
+    axes = [np.arange(n[a]) * d[a] for a in range(ndim)]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")            # numpy order (y,) x, z
+    coords = grids[::-1]                                        # coords[a] for axis a
+    coef = (1.0, 2.0, -0.5)[:ndim]
+    f = sum(c * q * q for c, q in zip(coef, coords)) + 3.0 * coords[0]
+    L = oracle.laplacian(f, d)
+    inner = tuple(slice(1, -1) for _ in range(ndim))
+    np.testing.assert_allclose(L[inner], 2.0 * sum(coef), rtol=0, atol=1e-9)
+    # sine along z that is zero one node outside both ends (so the zero padding is exact)
+    m = n[0] + 1
+    k = 3 * math.pi / (m * d[0])
+    s = np.sin(k * (np.arange(n[0]) + 1) * d[0])
+    shape = [1] * ndim
+    shape[-1] = n[0]
+    g = np.broadcast_to(s.reshape(shape), f.shape).copy()
+    Lg = oracle.laplacian(g, (d[0],) + (1e30,) * (ndim - 1))   # other axes: no curvature weight
+    lam = -4.0 / d[0] ** 2 * math.sin(k * d[0] / 2) ** 2
+    np.testing.assert_allclose(Lg, lam * g, rtol=0, atol=1e-12)
+
+
+def test_normalized_image_divides_by_source_illumination(oracle):
+    """Sec. 2.3 normalised imaging condition: a source twice as strong doubles each shot's
+    image and quadruples its illumination (and the stabiliser, a fraction of the peak), so the
+    normalised image halves; the plain image doubles.  A receiver-side normalisation would not
+    scale this way."""
+    g = small_grid(order=4, n1=36, n2=48, nt=260, nb=8, fm=12)
+    vp, rho = smooth_random_model(g.n1, g.n2, 21)
+    d = g.d1
+    acq = I._surface_line(np.array([12.0, 36.0]) * d, 2 * d, np.arange(g.n2) * d, 2 * d)
+    stf = np.repeat(I.ricker(g.nt, g.dt, g.fm)[None, :], 2, 0).astype(np.float32)
+    vtrue = vp.copy()
+    vtrue[:, 24:] *= 1.1                                        # a reflector at depth 24
+    job = I.Job(g, vtrue, rho, acq, stf)
+    dobs = oracle.forward_job(job)
+    job = I.Job(g, vp, rho, acq, stf)
+    ims, ils = oracle.rtm_image(job, dobs, per_shot=True)
+    a = oracle.normalized_image(ims, ils)
+    job.stf = 2.0 * job.stf
+    ims2, ils2 = oracle.rtm_image(job, dobs, per_shot=True)
+    b = oracle.normalized_image(ims2, ils2)
+    assert np.max(np.abs(b - 0.5 * a)) <= 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(np.sum(ims2, 0) - 2.0 * np.sum(ims, 0))) <= 1e-12 * np.max(np.abs(np.sum(ims, 0)))
+    assert np.max(np.abs(a)) > 0
