@@ -7,6 +7,7 @@ with ctypes) and adds the host-side arithmetic of the method in plain numpy:
   * eq. (5)  CFL number                                    -> :func:`cfl_number`
   * eq. (6)  L2 misfit and residual adjoint source         -> :func:`misfit`
   * eq. (7)  kappa gradient, chain rule to Vp (rho fixed)  -> :func:`fwi_grad`
+  * eq. (7)  rho gradient, families (Vp, rho), (Vp, Ip)      -> :func:`fwi_grad_family`
   * eq. (10) cross-correlation image                       -> :func:`rtm_image`
   * Sec. 2.3 source-normalised image, Laplace filter         -> :func:`normalized_image`,
                                                                :func:`laplacian`
@@ -71,7 +72,7 @@ def lib():
         L.og_forward.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, C.c_int,
                                  ip, dp]
         L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp]
-        L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp]
+        L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp, dp]
         L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp]
         _lib = L
     return _lib
@@ -213,7 +214,8 @@ def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int
 
 def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, final=None,
             want=("gk", "image", "illum")):
-    """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum."""
+    """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum and,
+    when "grk" is wanted, dJ/drho at fixed kappa (the buoyancy part of eq. 7)."""
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -224,14 +226,15 @@ def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, fin
     gk = np.zeros(I) if "gk" in want else None
     im = np.zeros(I) if "image" in want else None
     il = np.zeros(I) if "illum" in want else None
+    grk = np.zeros(I) if "grk" in want else None
     rc = lib().og_adjoint(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
                           _d(G), _d(None if hist is None else np.ascontiguousarray(hist)),
                           _d(None if bands is None else np.ascontiguousarray(bands)),
                           _d(None if final is None else np.ascontiguousarray(final)),
-                          _d(gk), _d(im), _d(il))
+                          _d(gk), _d(im), _d(il), _d(grk))
     if rc:
         raise RuntimeError("og_adjoint failed: %d" % rc)
-    return {"gk": gk, "image": im, "illum": il}
+    return {"gk": gk, "image": im, "illum": il, "grk": grk}
 
 
 def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa):
@@ -294,6 +297,43 @@ def fwi_grad(job, dobs, shots=None, vp=None, box=None, vmax=None, use_history=Fa
     vp64 = np.asarray(vp, np.float64).ravel()
     rho64 = np.asarray(job.rho, np.float64).ravel()
     return (2.0 * rho64 * vp64 * gk).reshape(job.vp.shape), J
+
+
+def fwi_grad_family(job, dobs, family: int = 1, shots=None, vp=None, rho=None, box=None,
+                    vmax=None, use_history=False):
+    """eq. (7) with the chain rule of the two parametrisations of Sec. 2.2, summed over shots:
+    family 1 -> (dJ/dVp at fixed rho, dJ/drho at fixed Vp); family 2 -> (dJ/dVp at fixed Ip,
+    dJ/dIp at fixed Vp) with Ip = rho Vp; and J.  From dJ/dkappa (fixed rho) and dJ/drho (fixed
+    kappa): kappa = rho Vp^2 gives dJ/dVp|rho = 2 rho Vp gk, dJ/drho|Vp = Vp^2 gk + grk;
+    kappa = Ip Vp, rho = Ip / Vp give dJ/dVp|Ip = rho Vp gk - (rho / Vp) grk and
+    dJ/dIp|Vp = Vp gk + grk / Vp."""
+    vp = job.vp if vp is None else vp
+    rho = job.rho if rho is None else rho
+    vmax = model_vmax(job) if vmax is None else vmax
+    gr = og_grid(job.grid, vmax=vmax, box=box)
+    shots = list(range(job.acq.nshot)) if shots is None else list(shots)
+    gk = np.zeros(interior_size(gr))
+    grk = np.zeros(interior_size(gr))
+    J = 0.0
+    for k, s in enumerate(shots):
+        src, rec = shot_nodes(job.grid, job.acq, s)
+        fw = forward(gr, vp, rho, src, job.stf[s], rec, hist=use_history,
+                     bands=not use_history, final=not use_history)
+        Js, G = misfit(fw["dcal"], dobs[k], gr.dt)
+        J += Js
+        r = adjoint(gr, vp, rho, src, job.stf[s], rec, G, hist=fw["hist"],
+                    bands=fw["bands"], final=fw["final"], want=("gk", "grk"))
+        gk += r["gk"]
+        grk += r["grk"]
+    v = np.asarray(vp, np.float64).ravel()
+    rh = np.asarray(rho, np.float64).ravel()
+    if family == 1:
+        g1, g2 = 2.0 * rh * v * gk, v * v * gk + grk
+    elif family == 2:
+        g1, g2 = rh * v * gk - (rh / v) * grk, v * gk + grk / v
+    else:
+        raise ValueError("family must be 1 or 2")
+    return g1.reshape(job.vp.shape), g2.reshape(job.vp.shape), J
 
 
 def rtm_image(job, dobs, shots=None, box=None, vmax=None, per_shot=False):

@@ -613,10 +613,44 @@ int og_reconstruct(const og_grid *g, const double *vp, const double *rho, const 
  * hist != NULL: the plain definition (full forward history (nt+1) x 4P).
  * hist == NULL: reconstruction from bands + final_state.
  * gk, image, illum: interior arrays (accumulated into; any may be NULL).             */
+/* The density part of eq. (7) in the discrete scheme: J depends on rho through kappa and
+ * through the staggered buoyancy beta_a = 2/(rho_i + rho_{i+1}) of every v update.  With the
+ * same-solver adjoint velocity v~ (v~ = -beta vbar), dJ/dbeta_f = (dt/beta_f) sum_it
+ * v~^{it+1/2}_f (D+_a p^it)_f, and dbeta_f/drho = -beta_f^2/2 for either node of the face, so
+ * a face adds -(dt/2) beta_f v~ D+p to each interior node it touches (kappa held fixed).  The
+ * faces of an axis run from the one below the first interior node to the one above the last;
+ * the source field there comes from the restored bands.                                     */
+static void og_rho_faces(const og_model *m, const og_field *q, const og_field *f, double *grk)
+{
+    int nb = m->g.nb;
+    double dt = m->g.dt;
+    for (int a = 0; a < m->nd; a++) {
+        int lo[3], hi[3];
+        for (int b = 0; b < 3; b++) {
+            if (b >= m->nd) { lo[b] = 0; hi[b] = 0; }
+            else if (b == a) { lo[b] = nb - 1; hi[b] = nb + m->n[b] - 1; }
+            else { lo[b] = nb; hi[b] = nb + m->n[b] - 1; }
+        }
+        for (int i3 = lo[2]; i3 <= hi[2]; i3++)
+            for (int i2 = lo[1]; i2 <= hi[1]; i2++)
+                for (int i1 = lo[0]; i1 <= hi[0]; i1++) {
+                    size_t k = IDX(m, i1, i2, i3);
+                    double c = -0.5 * dt * m->bet[a][k] * q->v[a][k] * dplus(m, f->p, i1, i2, i3, a);
+                    int j[3] = {i1 - nb, i2 - nb, m->nd == 3 ? i3 - nb : 0};
+                    for (int side = 0; side < 2; side++) {     /* left node, right node */
+                        int jj[3] = {j[0], j[1], j[2]};
+                        jj[a] += side;
+                        if (jj[a] < 0 || jj[a] >= m->n[a]) continue;
+                        grk[(size_t)jj[0] + (size_t)m->n[0] * ((size_t)jj[1] + (size_t)m->n[1] * jj[2])] += c;
+                    }
+                }
+    }
+}
+
 int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, const double *G, const double *hist,
                const double *bands, const double *final_state, double *gk, double *image,
-               double *illum)
+               double *illum, double *grk)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -661,6 +695,8 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
                         if (illum) illum[s] += g->dt * f.p[k] * f.p[k];
                     }
         }
+        /* q.v holds v~^{it+1/2} (the p update of og_step leaves it), f.p holds p^it */
+        if (grk) og_rho_faces(&m, &q, &f, grk);
     }
     og_field_free(&f);
     og_field_free(&q);

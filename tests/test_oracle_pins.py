@@ -342,6 +342,72 @@ def test_fwi_gradient_matches_finite_differences(oracle, box):
     assert worst <= 1e-4, worst
 
 
+def _density_case(oracle):
+    g = small_grid(order=8, n1=46, n2=64, nt=400, nb=12, fm=15.0)
+    vp, rho = smooth_random_model(g.n1, g.n2, 19, vmin=1800.0, vmax=2500.0)
+    vtrue = vp.astype(np.float64).copy()
+    rtrue = rho.astype(np.float64).copy()
+    vtrue[18:36, 14:30] *= 1.06
+    rtrue[10:40, 24:40] *= 1.15
+    sx = np.array([14.0, 32.0, 50.0]) * g.d2
+    acq = I._surface_line(sx, 3 * g.d1, np.arange(0, g.n2, 2) * g.d2, 2 * g.d1)
+    stf = np.repeat(I.ricker(g.nt, g.dt, g.fm)[None], 3, 0)
+    job = I.Job(g, vp, rho, acq, stf)
+    vmax = 2800.0
+    dobs = oracle.forward_job(I.Job(g, vtrue, rtrue, acq, stf), vmax=vmax)
+
+    def J(v, r):
+        d = oracle.forward_job(I.Job(g, v, r, acq, stf), vmax=vmax)
+        return sum(oracle.misfit(d[s], dobs[s], g.dt)[0] for s in range(3))
+    return g, job, dobs, vmax, J
+
+
+def _fd_cells(g, grad, n, seed):
+    N = g.order // 2
+    cand = [(ix, iz) for ix in range(2 * N, g.n2 - 2 * N) for iz in range(2 * N, g.n1 - 2 * N)
+            if abs(grad[ix, iz]) >= 0.02 * np.max(np.abs(grad))]
+    rng = np.random.default_rng(seed)
+    return [cand[k] for k in rng.choice(len(cand), n, replace=False)]
+
+
+@pytest.mark.parametrize("family", [1, 2])
+def test_density_gradient_matches_finite_differences(oracle, family):
+    """eq. (7), density part, and the chain rule of Sec. 2.2: both gradients of family 1
+    (Vp, rho) and family 2 (Vp, Ip = rho Vp) from one reverse loop (boundary reconstruction)
+    against central differences of J on 12 cells each; the stored-history run agrees."""
+    g, job, dobs, vmax, J = _density_case(oracle)
+    g1, g2, J0 = oracle.fwi_grad_family(job, dobs, family, vmax=vmax)
+    h1, h2, _ = oracle.fwi_grad_family(job, dobs, family, vmax=vmax, use_history=True)
+    assert np.max(np.abs(g2 - h2)) <= 1e-10 * np.max(np.abs(h2))
+    vp = job.vp.astype(np.float64)
+    rho = job.rho.astype(np.float64)
+    worst = 0.0
+    for which, grad in ((1, g1), (2, g2)):
+        for ix, iz in _fd_cells(g, grad, 12, 40 + 2 * family + which):
+            if family == 1:
+                base = vp if which == 1 else rho
+            else:
+                base = vp if which == 1 else rho * vp            # Ip
+            eps = 1e-4 * float(base[ix, iz])
+            vals = []
+            for sgn in (1.0, -1.0):
+                v, r = vp.copy(), rho.copy()
+                if family == 1 and which == 1:
+                    v[ix, iz] += sgn * eps
+                elif family == 1:
+                    r[ix, iz] += sgn * eps
+                elif which == 1:                                  # Vp at fixed Ip
+                    ip = rho[ix, iz] * vp[ix, iz]
+                    v[ix, iz] += sgn * eps
+                    r[ix, iz] = ip / v[ix, iz]
+                else:                                             # Ip at fixed Vp
+                    r[ix, iz] = (rho[ix, iz] * vp[ix, iz] + sgn * eps) / vp[ix, iz]
+                vals.append(J(v, r))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            worst = max(worst, abs(fd - grad[ix, iz]) / abs(grad[ix, iz]))
+    assert worst <= 1e-4, worst
+
+
 # ----------------------------------------------------------------------------- P8, P9, P10
 
 @pytest.mark.parametrize("ndim,box", [(2, 0), (2, 1), (3, 0), (3, 1)])
