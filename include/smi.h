@@ -113,9 +113,13 @@ typedef enum {
                                 is launched with device-stamped start / stop events (read with
                                 smi_kernel_timing); 0: off (default).  Setting it clears the
                                 samples collected so far. */
-    SMI_OPT_TILEMAP = 4      /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
+    SMI_OPT_TILEMAP = 4,     /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
                                 then x-block); 1 each of the 8 XCDs takes a contiguous range of
                                 x-blocks, so tiles that share halos share an L2 */
+    SMI_OPT_FAMILY = 5       /* parametrisation of the gradients (Sec. 2.2): 1 (default) (Vp, rho):
+                                grad_vp = dJ/dVp at fixed rho, grad_rho = dJ/drho at fixed Vp;
+                                2 (Vp, Ip = rho Vp): grad_vp = dJ/dVp at fixed Ip, grad_rho =
+                                dJ/dIp at fixed Vp */
 } smi_option;
 
 /* Create a context on HIP device `hip_device`. */
@@ -159,6 +163,15 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
  *            vector-Jacobian product of any loss; G = dt dobs gives the RTM image (Sec. 2.3).
  *   grad_vp  device [n1*n2*n3] or NULL: sum over shots of dL/dVp, rho held fixed:
  *            -(2 dt / Vp) sum_it p~ div v^{it+1/2} (eq. 7 with kappa = rho Vp^2).  Overwritten.
+ *            With SMI_OPT_FAMILY 2: dL/dVp at fixed Ip = rho Vp.
+ *   grad_rho device [n1*n2*n3] or NULL: dL/drho at fixed Vp (family 1) or dL/dIp at fixed Vp
+ *            (family 2).  The density part of eq. (7) in the discrete scheme: every v update
+ *            uses beta_a = 2/(rho_i + rho_{i+1}) on the face, so dL/drho at fixed kappa sums
+ *            -(dt/2) beta_f v~^{it+1/2}_f (D+_a p^it)_f over the faces of the node (v~ the
+ *            adjoint velocity of the same solver); kappa = rho Vp^2 adds Vp^2 dL/dkappa.
+ *            Interior nodes only (the edge-replicated values in the absorbing layers are not
+ *            differentiated).  Needs a state saved for SMI_JOB_FORWARD_SAVE or
+ *            SMI_JOB_GRAD (SMI_E_ARG otherwise).  Overwritten.
  *   image    device [n1*n2*n3] or NULL: sum_s sum_it dt p~^it p^it (eq. 10).  Overwritten.
  *   illum    device [n1*n2*n3] or NULL: sum_s sum_it dt (p^it)^2.  Overwritten.
  *   image_norm device [n1*n2*n3] or NULL: the normalised imaging condition of Sec. 2.3, each
@@ -169,8 +182,8 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
  *            device [nshot][nsnap][n1*n2*n3].
  * The state must come from smi_forward on the same context. */
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
-                                   float *grad_vp, float *image, float *illum, float *image_norm,
-                                   const int *snap_it, int nsnap, float *snaps,
+                                   float *grad_vp, float *grad_rho, float *image, float *illum,
+                                   float *image_norm, const int *snap_it, int nsnap, float *snaps,
                                    void *hip_stream);
 
 /* RTM (Sec. 2.3): forward with boundary saving, then the reverse loop with G = dt dobs.
@@ -190,12 +203,13 @@ smi_status smi_laplacian(smi_ctx *ctx, const smi_grid *grid, const float *in, fl
 
 /* FWI gradient (Sec. 2.2): forward with boundary saving, residual r = dcal - dobs,
  * misfit J = 1/2 dt sum r^2 (eq. 6, rectangle rule; device double, may be NULL), G = dt r,
- * reverse loop -> grad_vp (device [n1*n2*n3]).  dcal_out (device, layout of dcal) receives
- * the synthetic data when not NULL. */
+ * reverse loop -> grad_vp and / or grad_rho (device [n1*n2*n3], as in
+ * smi_adjoint_reconstruct, at least one).  dcal_out (device, layout of dcal) receives the
+ * synthetic data when not NULL. */
 smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                         const float *vp, const float *rho, const float *stf, const float *dobs,
-                        float *grad_vp, double *misfit, float *dcal_out, void *ws,
-                        size_t ws_bytes, void *hip_stream);
+                        float *grad_vp, float *grad_rho, double *misfit, float *dcal_out,
+                        void *ws, size_t ws_bytes, void *hip_stream);
 
 void smi_state_destroy(smi_state *state);
 

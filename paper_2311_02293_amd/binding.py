@@ -19,7 +19,7 @@ STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
           -4: "SMI_E_WORKSPACE", -5: "SMI_E_HIP", -6: "SMI_E_UNSUPPORTED", -7: "SMI_E_STATE",
           -8: "SMI_E_NONFINITE"}
 JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD = 0, 1, 2, 3
-OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP = 0, 1, 2, 3, 4
+OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY = 0, 1, 2, 3, 4, 5
 
 
 class SmiError(RuntimeError):
@@ -64,13 +64,13 @@ def lib():
                                           C.POINTER(C.c_size_t)]
         L.smi_forward.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp,
                                   C.POINTER(vp), C.POINTER(C.c_int), C.c_int, vp, vp, C.c_size_t, vp]
-        L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.c_int,
-                                              vp, vp]
+        L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int),
+                                              C.c_int, vp, vp]
         L.smi_rtm_image.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
                                     vp, vp, vp, C.c_size_t, vp]
         L.smi_laplacian.argtypes = [vp, C.POINTER(SmiGrid), vp, vp, vp]
         L.smi_fwi_grad.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
-                                   vp, vp, vp, C.c_size_t, vp]
+                                   vp, vp, vp, vp, C.c_size_t, vp]
         L.smi_state_destroy.argtypes = [vp]
         L.smi_state_destroy.restype = None
         L.smi_poll_status.argtypes = [vp, vp]
@@ -145,6 +145,7 @@ class Context:
         import torch
         torch.cuda.init()
         self.device = device
+        self.options = {}
         h = C.c_void_p()
         rc = lib().smi_ctx_create(device, C.byref(h))
         if rc != SMI_OK:
@@ -164,6 +165,11 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._check(lib().smi_set_option(self.h, option, value))
+        self.options[option] = value
+
+    def option(self, option: int, default: int = 0) -> int:
+        """Last value set through this wrapper (the library's default otherwise)."""
+        return self.options.get(option, default)
 
     def check(self, grid, vpmin: float, vpmax: float) -> int:
         g = make_grid(grid)
@@ -230,23 +236,25 @@ class Context:
         state = State(self, st, (ws, vp, rho, stf)) if save else None
         return dcal, out_snaps, state
 
-    def adjoint_reconstruct(self, state: State, adj_src, *, grad=True, image=True, illum=True,
-                            image_norm=False, snaps: Sequence[int] = (),
+    def adjoint_reconstruct(self, state: State, adj_src, *, grad=True, grad_rho=False,
+                            image=True, illum=True, image_norm=False, snaps: Sequence[int] = (),
                             nshot: Optional[int] = None, npts=None, stream=None):
-        """smi_adjoint_reconstruct.  Returns dict(grad, image, illum, image_norm, snaps)."""
+        """smi_adjoint_reconstruct.  Returns dict(grad, grad_rho, image, illum, image_norm,
+        snaps)."""
         import torch
         vp = state.keep[1]
         dev = vp.device
         n = vp.numel() if npts is None else npts
         out = {k: (torch.empty(n, dtype=torch.float32, device=dev) if want else None)
-               for k, want in (("grad", grad), ("image", image), ("illum", illum),
-                               ("image_norm", image_norm))}
+               for k, want in (("grad", grad), ("grad_rho", grad_rho), ("image", image),
+                               ("illum", illum), ("image_norm", image_norm))}
         snap_it = np.ascontiguousarray(list(snaps), np.int32)
         out["snaps"] = None
         if len(snap_it):
             out["snaps"] = torch.empty((nshot, len(snap_it), n), dtype=torch.float32, device=dev)
         rc = lib().smi_adjoint_reconstruct(
-            self.h, state.handle, _ptr(adj_src), _ptr(out["grad"]), _ptr(out["image"]),
+            self.h, state.handle, _ptr(adj_src), _ptr(out["grad"]), _ptr(out["grad_rho"]),
+            _ptr(out["image"]),
             _ptr(out["illum"]), _ptr(out["image_norm"]),
             snap_it.ctypes.data_as(C.POINTER(C.c_int)) if len(snap_it) else None,
             len(snap_it), _ptr(out["snaps"]), _stream(stream))
@@ -278,19 +286,23 @@ class Context:
         self._check(lib().smi_laplacian(self.h, C.byref(g), _ptr(image), _ptr(out), _stream(stream)))
         return out
 
-    def fwi_grad(self, grid, acq, vp, rho, stf, dobs, *, want_dcal=False, ws=None, stream=None):
+    def fwi_grad(self, grid, acq, vp, rho, stf, dobs, *, want_dcal=False, rho_grad=False,
+                 ws=None, stream=None):
+        """smi_fwi_grad.  Returns (grad_vp, misfit, dcal) -- (grad_vp, grad_rho, misfit, dcal)
+        with rho_grad (the family set by OPT_FAMILY)."""
         import torch
         g = make_grid(grid)
         a = _Acq(acq)
         nb = self.workspace_bytes(grid, acq, JOB_GRAD)
         ws = self.workspace(nb) if ws is None else ws
         grad = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
+        gr = torch.empty_like(grad) if rho_grad else None
         mis = torch.zeros(1, dtype=torch.float64, device=vp.device)
         dcal = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=vp.device) if want_dcal else None
         self._check(lib().smi_fwi_grad(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
-                                       _ptr(stf), _ptr(dobs), _ptr(grad), _ptr(mis), _ptr(dcal),
-                                       _ptr(ws), ws.numel(), _stream(stream)))
-        return grad, mis, dcal
+                                       _ptr(stf), _ptr(dobs), _ptr(grad), _ptr(gr), _ptr(mis),
+                                       _ptr(dcal), _ptr(ws), ws.numel(), _stream(stream)))
+        return (grad, gr, mis, dcal) if rho_grad else (grad, mis, dcal)
 
 
 _default = {}

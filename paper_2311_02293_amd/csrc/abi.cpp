@@ -22,6 +22,7 @@ struct smi_ctx {
     int opt_graph = 0;
     int opt_chunk = 0;
     int opt_xcd = 0;
+    int opt_family = 1;
     void *last_ws = nullptr;
     size_t last_status_off = 0;
     double cnt[3] = {0, 0, 0};
@@ -254,16 +255,24 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
 }
 
 // Alg. 2, reverse loop: adjoint source -> reconstruction (+gradient) -> adjoint step (+image).
-smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad, float *image,
-                       float *illum, float *image_norm, const int *snap_it, int nsnap,
-                       float *snaps, hipStream_t st) {
+smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad,
+                       float *grad_rho, float *image, float *illum, float *image_norm,
+                       const int *snap_it, int nsnap, float *snaps, hipStream_t st) {
     const Plan &pl = stt->plan;
     Views w = smi::views(pl, stt->ws);
     bool adj = G != nullptr;
-    bool want_g = adj && grad, want_i = adj && (image || illum || image_norm);
+    const int family = ctx->opt_family;
+    // the density face sums are needed for the second gradient and for Vp at fixed Ip
+    const bool want_r = adj && (grad_rho || (grad && family == 2));
+    if (want_r && !pl.rho_acc)
+        return fail(ctx, SMI_E_ARG, "this job keeps no density accumulators (use a gradient job)");
+    bool want_g = adj && (grad || grad_rho), want_i = adj && (image || illum || image_norm);
     smi_status s = zero_fields(ctx, pl, w.q, st);
     if (s != SMI_OK) return s;
     HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
+    if (want_r)
+        HIPCHK(hipMemsetAsync(w.acc_r[0], 0, sizeof(float) * pl.nd * (size_t)pl.nshot * pl.P, st),
+               "density sums clear");
     smi::StepCtx c{&pl, &w, stt->stf, st, false};
     configure(c, ctx, pl);
     for (int k = 0; k < nsnap; ++k)
@@ -271,14 +280,18 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     for (int it = pl.g.nt - 1; it >= 0; --it) {
         if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
         HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+        if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
         for (int k = 0; k < nsnap; ++k)
             if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     }
-    HIPCHK(smi::finalize(c, stt->vp, want_g ? grad : nullptr, want_i ? image : nullptr,
+    HIPCHK(smi::finalize(c, stt->vp, want_g && !want_r ? grad : nullptr, want_i ? image : nullptr,
                          want_i ? illum : nullptr, want_i ? image_norm : nullptr), "finalize");
+    if (want_r)
+        HIPCHK(smi::finalize_family(c, stt->vp, stt->rho, family, grad, grad_rho), "finalize");
     if (!adj) {
         size_t I = sizeof(float) * pl.I;
         if (grad) HIPCHK(hipMemsetAsync(grad, 0, I, st), "grad clear");
+        if (grad_rho) HIPCHK(hipMemsetAsync(grad_rho, 0, I, st), "grad_rho clear");
         if (image) HIPCHK(hipMemsetAsync(image, 0, I, st), "image clear");
         if (illum) HIPCHK(hipMemsetAsync(illum, 0, I, st), "illum clear");
         if (image_norm) HIPCHK(hipMemsetAsync(image_norm, 0, I, st), "image_norm clear");
@@ -348,6 +361,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }
+    if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
     if (option == SMI_OPT_TIMING && value >= 0) {
         ctx->opt_timing = value;
         ctx->nsample = 0;
@@ -402,16 +416,17 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, c
 }
 
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
-                                   float *grad_vp, float *image, float *illum, float *image_norm,
-                                   const int *snap_it, int nsnap, float *snaps, void *hip_stream) {
+                                   float *grad_vp, float *grad_rho, float *image, float *illum,
+                                   float *image_norm, const int *snap_it, int nsnap, float *snaps,
+                                   void *hip_stream) {
     if (!ctx) return SMI_E_ARG;
     if (!state || state->consumed || !state->plan.save)
         return fail(ctx, SMI_E_STATE, "state missing, already consumed, or saved without boundaries");
     if (state->ctx != ctx) return fail(ctx, SMI_E_STATE, "state belongs to another context");
     smi_status s = check_snaps(ctx, &state->plan.g, snap_it, nsnap, snaps);
     if (s != SMI_OK) return s;
-    s = run_reverse(ctx, state, adj_src, grad_vp, image, illum, image_norm, snap_it, nsnap, snaps,
-                    (hipStream_t)hip_stream);
+    s = run_reverse(ctx, state, adj_src, grad_vp, grad_rho, image, illum, image_norm, snap_it,
+                    nsnap, snaps, (hipStream_t)hip_stream);
     if (s != SMI_OK) return s;
     state->consumed = true;
     return SMI_OK;
@@ -443,16 +458,17 @@ smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
     configure(c, ctx, stt->plan);
     HIPCHK(smi::scale_copy(c, dobs, w.G, (float)g.dt), "rtm source");
-    return run_reverse(ctx, stt.get(), w.G, nullptr, image, illum, image_norm, nullptr, 0, nullptr,
-                       st);
+    return run_reverse(ctx, stt.get(), w.G, nullptr, nullptr, image, illum, image_norm, nullptr, 0,
+                       nullptr, st);
 }
 
 smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
                         const float *rho, const float *stf, const float *dobs, float *grad_vp,
-                        double *misfit, float *dcal_out, void *ws, size_t ws_bytes,
-                        void *hip_stream) {
+                        float *grad_rho, double *misfit, float *dcal_out, void *ws,
+                        size_t ws_bytes, void *hip_stream) {
     if (!ctx) return SMI_E_ARG;
-    if (!dobs || !grad_vp) return fail(ctx, SMI_E_ARG, "dobs and grad_vp are required");
+    if (!dobs || (!grad_vp && !grad_rho))
+        return fail(ctx, SMI_E_ARG, "dobs and at least one of grad_vp, grad_rho are required");
     hipStream_t st = (hipStream_t)hip_stream;
     double vmin = 0, vmax = 0;
     smi_status s = speeds(ctx, grid, vp, ws, ws_bytes, st, vmin, vmax);
@@ -473,8 +489,8 @@ smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, 
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
     configure(c, ctx, stt->plan);
     HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
-    return run_reverse(ctx, stt.get(), w.G, grad_vp, nullptr, nullptr, nullptr, nullptr, 0, nullptr,
-                       st);
+    return run_reverse(ctx, stt.get(), w.G, grad_vp, grad_rho, nullptr, nullptr, nullptr, nullptr,
+                       0, nullptr, st);
 }
 
 void smi_state_destroy(smi_state *state) { delete state; }

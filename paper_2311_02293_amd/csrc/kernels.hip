@@ -912,6 +912,81 @@ __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ f, 
     out[i] = acc;
 }
 
+// Density part of eq. (7): per face of axis a, acc_r[a] += v~_a D+_a p with v~^{it+1/2} the
+// adjoint velocity and p^it the rebuilt source field, on the faces from the one below the
+// first interior node to the one above the last (interior along the other axes), inside the
+// shot's reconstruction region widened by one face downwards.  Lanes cover the region
+// [lo - 1, hi) per axis; blockIdx.z = shot * ny + y-plane.
+template <int ND, int N>
+__global__ __launch_bounds__(256) void k_rho_faces(Geom g, Fields f, Fields q, float *acc0,
+                                                   float *acc1, float *acc2,
+                                                   const int *__restrict__ rbox, int ny) {
+    const int s = (int)blockIdx.z / ny;
+    const int *b = rbox + 6 * s;
+    Cell c;
+    c.s = s;
+    c.z = b[0] - 1 + (int)blockIdx.x * 64 + (int)threadIdx.x;
+    c.x = b[2] - 1 + (int)blockIdx.y * 4 + (int)threadIdx.y;
+    c.y = ND == 3 ? b[4] - 1 + (int)blockIdx.z % ny : 0;
+    const int lo[3] = {b[0], b[2], b[4]}, hi[3] = {b[1], b[3], b[5]};
+    const int co[3] = {c.z, c.x, c.y};
+    c.k = g.org + c.z + (long long)g.ld1 * c.x + g.ld2 * c.y;
+    c.ok = true;
+    const float *p = f.p + s * g.P;
+    float *acc[3] = {acc0, acc1, acc2};
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        bool ok = co[a] >= max(lo[a] - 1, g.nb - 1) && co[a] < min(hi[a], g.nb + g.n[a]);
+#pragma unroll
+        for (int o = 0; o < ND; ++o)
+            if (o != a) ok = ok && co[o] >= lo[o] && co[o] < hi[o];
+        if (!ok) continue;
+        const float e = dplus<N>(g, p, c, a);
+        acc[a][s * g.P + c.k] += q.v[a][s * g.P + c.k] * e;
+    }
+}
+
+// Gradients of a parametrisation family from A = sum_s acc_g (g_kappa = -(dt/kappa) A) and
+// the face sums (g_rho at fixed kappa = -1/2 sum_a sum_s (dt beta S)_{face below} +
+// (dt beta S)_{face above}): family 1 (Vp, rho): g1 = 2 rho Vp g_kappa, g2 = Vp^2 g_kappa +
+// g_rho; family 2 (Vp, Ip = rho Vp): g1 = rho Vp g_kappa - (rho/Vp) g_rho,
+// g2 = Vp g_kappa + g_rho / Vp.  Shots are summed in order.
+__global__ __launch_bounds__(256) void k_finalize_family(Geom g, const float *__restrict__ acc_g,
+                                                         const float *__restrict__ r0,
+                                                         const float *__restrict__ r1,
+                                                         const float *__restrict__ r2, Model m,
+                                                         int nshot, const float *__restrict__ vp,
+                                                         const float *__restrict__ rho,
+                                                         int family, float *g1, float *g2) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= g.I) return;
+    const int iz = (int)(i % g.n[0]);
+    const long long r = i / g.n[0];
+    const int ix = (int)(r % g.n[1]);
+    const int iy = (int)(r / g.n[1]);
+    const long long k = g.org + (iz + g.nb) + (long long)g.ld1 * (ix + g.nb) +
+                        g.ld2 * (g.nd == 3 ? iy + g.nb : 0);
+    const float *ra[3] = {r0, r1, r2};
+    float A = 0.f, S = 0.f;
+    for (int sh = 0; sh < nshot; ++sh) {
+        A += acc_g[sh * g.I + i];
+        for (int a = 0; a < g.nd; ++a) {
+            const long long st = a == 0 ? 1 : (a == 1 ? (long long)g.ld1 : g.ld2);
+            S += m.bdt[a][k] * ra[a][sh * g.P + k] + m.bdt[a][k - st] * ra[a][sh * g.P + k - st];
+        }
+    }
+    const float v = vp[i], rh = rho[i];
+    const float gk = -g.dt / (rh * v * v) * A;
+    const float grk = -0.5f * S;
+    if (family == 2) {
+        if (g1) g1[i] = rh * v * gk - rh / v * grk;
+        if (g2) g2[i] = v * gk + grk / v;
+    } else {
+        if (g1) g1[i] = 2.f * rh * v * gk;
+        if (g2) g2[i] = v * v * gk + grk;
+    }
+}
+
 // interior p of every shot -> snaps[s][k][...]
 __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
                                               int k, int nsnap) {
@@ -1295,6 +1370,38 @@ hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, floa
                        (float)pl.g.dt, w.partial);
     hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, c.st, (const double *)w.partial,
                        pl.npartial, misfit ? misfit : w.misfit_tmp, 0.5 * pl.g.dt);
+    return hipGetLastError();
+}
+
+template <int ND, int N>
+hipError_t rho_faces_t(const StepCtx &c, int it) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    int ez = 0, ex = 0, ey = 0;
+    for (int s = 0; s < pl.nshot; ++s) {
+        const int *b = &pl.rbox[((size_t)it * pl.nshot + s) * 6];
+        ez = std::max(ez, b[1] - b[0] + 1);
+        ex = std::max(ex, b[3] - b[2] + 1);
+        ey = std::max(ey, ND == 3 ? b[5] - b[4] + 1 : 1);
+    }
+    const int ny = std::max(1, ey);
+    dim3 grid((unsigned)((ez + 63) / 64), (unsigned)((ex + 3) / 4), (unsigned)(pl.nshot * ny));
+    hipLaunchKernelGGL((k_rho_faces<ND, N>), grid, dim3(64, 4, 1), 0, c.st, pl.geom, w.f, w.q,
+                       w.acc_r[0], w.acc_r[1], w.acc_r[2],
+                       (const int *)(w.rbox + (size_t)it * pl.nshot * 6), ny);
+    return hipGetLastError();
+}
+
+hipError_t rho_faces(const StepCtx &c, int it) { SMI_DISPATCH(rho_faces_t, c, it); }
+
+hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
+                           float *g1, float *g2) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    hipLaunchKernelGGL(k_finalize_family, dim3(blocks(pl.I)), dim3(256), 0, c.st, pl.geom,
+                       (const float *)w.acc_g, (const float *)w.acc_r[0],
+                       (const float *)w.acc_r[1], (const float *)w.acc_r[2], w.model, pl.nshot,
+                       vp, rho, family, g1, g2);
     return hipGetLastError();
 }
 

@@ -281,6 +281,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.adjoint = pl.save;
     pl.need_G = job == SMI_JOB_GRAD || job == SMI_JOB_RTM;
     pl.need_dcal = pl.need_G;
+    pl.rho_acc = job == SMI_JOB_GRAD || job == SMI_JOB_FORWARD_SAVE;
 
     // computing boxes (Sec. 4.1)
     const int nt = g->nt, ns = pl.nshot;
@@ -408,6 +409,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * pl.nsave * (size_t)bd.B) : 0;
     pl.off_fin = pl.save && g->dr > 1 ? take(sizeof(float) * (size_t)ns * (size_t)pl.P * (1 + pl.nd)) : 0;
     pl.off_acc = pl.adjoint ? take(sizeof(float) * 3 * (size_t)ns * (size_t)pl.I) : 0;
+    pl.off_rho = pl.rho_acc ? take(sizeof(float) * pl.nd * (size_t)ns * (size_t)pl.P) : 0;
     pl.off_G = pl.need_G ? take(sizeof(float) * (size_t)nt * R) : 0;
     pl.off_dcal = pl.need_dcal ? take(sizeof(float) * (size_t)nt * R) : 0;
     pl.bytes = o;
@@ -475,6 +477,10 @@ Views views(const Plan &pl, void *ws) {
     if (pl.adjoint) {
         float *a = (float *)(b + pl.off_acc);
         w.acc_g = a;
+        for (int q = 0; q < 3; ++q)
+            w.acc_r[q] = pl.rho_acc && q < pl.nd
+                             ? (float *)(b + pl.off_rho) + (size_t)q * pl.nshot * pl.P
+                             : nullptr;
         w.acc_i = a + (size_t)pl.nshot * pl.I;
         w.acc_l = a + 2 * (size_t)pl.nshot * pl.I;
     }

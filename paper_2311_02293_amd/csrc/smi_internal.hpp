@@ -119,10 +119,12 @@ struct Plan {
     size_t off_status = 0, off_misfit = 0, off_partial = 0;
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
+    size_t off_rho = 0;
     size_t off_rcol = 0, off_fin = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
+    bool rho_acc = false;   // room for the density-gradient face sums (gradient-capable jobs)
     bool dbuf = false;  // second source-field buffer for the fused steps
     int chunk = 0;      // columns per workgroup of the fused 2D step (0: default)
     double cnt_fwd = 0, cnt_adj = 0, cnt_rec = 0;
@@ -158,6 +160,7 @@ struct Views {
     Fields f2;          // second buffer of the source field (fused, double-buffered steps)
     float *bands;       // [nshot][nsave][B]
     float *acc_g, *acc_i, *acc_l;   // [nshot][I] gradient / image / illumination
+    float *acc_r[3];    // [nshot][P] per axis: sum over steps of v~_a D+_a p on the faces
     float *G;           // [nt * R] adjoint source (when computed internally)
     float *dcal;        // internal dcal when the caller gave none
     float *fin;         // level-nt copy of p and v while the forward runs past nt (dr > 1)
@@ -201,6 +204,11 @@ hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, floa
                     double *misfit);
 hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum,
                     float *image_norm);
+// density part of eq. (7): accumulate v~ D+p on the faces of reverse step it
+hipError_t rho_faces(const StepCtx &c, int it);
+// gradients of a parametrisation family (1: Vp, rho; 2: Vp, Ip) from the kappa and face sums
+hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
+                           float *g1, float *g2);
 hipError_t launch_laplacian(const smi_grid *g, const float *in, float *out, hipStream_t st);
 
 }  // namespace smi

@@ -62,6 +62,31 @@ def test_autograd_matches_oracle_gradient(ctx):
     assert abs(float(J) - J_ref) <= 1e-4 * J_ref
 
 
+def test_autograd_density_gradient_matches_oracle(ctx):
+    """vp and rho both require grad: one backward gives dL/dVp at fixed rho and dL/drho at
+    fixed Vp (family 1), as the oracle's family gradients."""
+    import torch
+    from oracle import oracle as O
+    from paper_2311_02293_amd.autograd import forward_modelling, l2_misfit
+    job = grad_job(n1=60, n2=150, nt=500)
+    rtrue = job.rho.copy()
+    rtrue[70:110, 15:45] *= 1.12
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(I.Job(job.grid, job.extra["vp_true"], rtrue, job.acq, job.stf),
+                         vmax=vmax, box=0)
+    r1, r2, _ = O.fwi_grad_family(job, dobs, 1, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    d_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    v = vp.clone().requires_grad_(True)
+    r = rho.clone().requires_grad_(True)
+    J = l2_misfit(forward_modelling(v, r, stf, job.grid, job.acq, ctx), d_t, job.grid.dt)
+    J.backward()
+    e1 = rel_l2(v.grad.cpu().numpy(), r1)
+    e2 = rel_l2(r.grad.cpu().numpy(), r2)
+    say("autograd vp", e1, "rho", e2)
+    assert e1 <= 1e-4 and e2 <= 1e-4
+
+
 def test_gradient_matches_finite_differences(ctx):
     """dJ/dVp per cell against central differences of J computed with the GPU forward
     (FP32 fields, FP64 misfit sum), 20 cells drawn with seed 1003 at least 2N cells inside
