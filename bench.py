@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4000)
-    ap.add_argument("--timing-every", type=int, default=8,
+    ap.add_argument("--timing-every", type=int, default=32,
                     help="device-stamp the step kernels of every k-th time step (0: off)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")

@@ -103,7 +103,10 @@ typedef enum {
                                 SMI_OPT_CHUNK = 2, 4 or 8 cells per lane along the slowest
                                 axis and the order of SMI_OPT_TILEMAP; 4: batched one-cell-per-
                                 lane sweep kernels in the order of SMI_OPT_TILEMAP */
-    SMI_OPT_GRAPH = 1,       /* 1: replay the time loop from captured HIP graphs (default 0) */
+    SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
+                                first time a plan is seen (same geometry, boxes, kernels and
+                                buffers) and replayed on later calls; up to 8 graphs are kept
+                                per context (default 0).  Not combined with SMI_OPT_TIMING. */
     SMI_OPT_CHUNK = 2,       /* tuning.  SMI_OPT_KERNEL 3: cells per lane (2, 4, 8; else 4),
                                 plus 100 to take the z-neighbours from LDS.
                                 SMI_OPT_KERNEL 2: 1000 (2 order + t2) + L, with L the columns

@@ -4,6 +4,7 @@
 // the plan's small tables into the caller's workspace and enqueues the time loop on the
 // caller's stream.  No device memory is allocated here.
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -30,12 +31,17 @@ struct smi_ctx {
     // kernel timing (SMI_OPT_TIMING): every opt_timing-th forward step of the batched sweep
     // is launched with device-stamped events; events[4 k .. 4 k + 4) belong to sample k
     int opt_timing = 0;
+    // captured time loops (SMI_OPT_GRAPH), keyed by everything their launches bind
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+    hipStream_t cap = nullptr;
     std::vector<hipEvent_t> events;
     std::vector<double> sample_bytes;   // [samples][3], as Plan::step_bytes
     std::vector<int> sample_nk;         // kernels of the sampled step (2, or 1 for the fused step)
     size_t nsample = 0;
     ~smi_ctx() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -87,6 +93,67 @@ smi_status hip_fail(smi_ctx *c, hipError_t e, const char *where) {
         hipError_t e_ = (expr);                               \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
     } while (0)
+
+// ---------------------------------------------------------------- captured time loops
+
+constexpr size_t kMaxGraphs = 8;
+
+struct Key {
+    std::string b;
+    template <class T> Key &put(const T &v) {
+        b.append(reinterpret_cast<const char *>(&v), sizeof(T));
+        return *this;
+    }
+    template <class T> Key &vec(const std::vector<T> &v) {   // FNV-1a of the contents
+        uint64_t h = 1469598103934665603ull;
+        const unsigned char *q = reinterpret_cast<const unsigned char *>(v.data());
+        for (size_t i = 0; i < v.size() * sizeof(T); ++i) h = (h ^ q[i]) * 1099511628211ull;
+        return put(h).put(v.size());
+    }
+};
+
+// Everything a plan bakes into the launches of its time loop.
+Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
+    Key k;
+    k.put(tag).put(pl.geom).put(pl.band).put(pl.nshot).put(pl.nrun).put(pl.nsave);
+    k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl);
+    k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
+    return k;
+}
+
+// Enqueue the loop through a cached graph: captured on the context's own stream the first
+// time a key is seen, instantiated, then launched on the caller's stream (after the work the
+// call already enqueued there).  `enqueue(s)` must enqueue the loop on s.
+template <class F>
+smi_status graph_run(smi_ctx *ctx, const std::string &key, hipStream_t st, F enqueue) {
+    size_t i = 0;
+    while (i < ctx->graphs.size() && ctx->graphs[i].first != key) ++i;
+    if (i == ctx->graphs.size()) {
+        if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking), "capture stream");
+        HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal), "capture begin");
+        smi_status s = enqueue(ctx->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+        if (s != SMI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "capture end");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
+        if (ctx->graphs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(ctx->graphs.front().second);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.emplace_back(key, x);
+        i = ctx->graphs.size() - 1;
+    }
+    HIPCHK(hipGraphLaunch(ctx->graphs[i].second, st), "graph launch");
+    return SMI_OK;
+}
+
 
 // Model speed range: the grid's stated bounds, or a device reduction read back once.
 smi_status speeds(smi_ctx *ctx, const smi_grid *g, const float *vp, void *ws, size_t ws_bytes,
@@ -203,6 +270,8 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     const int nt = pl.g.nt, dr = pl.g.dr;
     const bool timed = ctx->opt_timing > 0 && !c.plain;
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
+    auto loop = [&](hipStream_t ls) -> smi_status {
+    c.st = ls;
     for (int it = 0; it < pl.nrun; ++it) {
         // fused steps alternate between the two buffers: level it lives in cur
         const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
@@ -235,17 +304,29 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         for (int k = 0; k < nsnap; ++k)
             if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
         if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
-            HIPCHK(hipMemcpyAsync(w.fin, w.f.p, state_bytes, hipMemcpyDeviceToDevice, st), "final copy");
+            HIPCHK(hipMemcpyAsync(w.fin, w.f.p, state_bytes, hipMemcpyDeviceToDevice, ls), "final copy");
     }
     if (fused && (pl.nrun & 1)) {
         // the final level is in the second buffer; the reverse pass works on the first
-        HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, st),
+        HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, ls),
                "final state copy");
     }
     if (pl.save && dr > 1) {
         HIPCHK(smi::band_save(c, w.f, pl.nsave - 1), "band save (last level)");
-        HIPCHK(hipMemcpyAsync(w.f.p, w.fin, state_bytes, hipMemcpyDeviceToDevice, st), "final restore");
+        HIPCHK(hipMemcpyAsync(w.f.p, w.fin, state_bytes, hipMemcpyDeviceToDevice, ls), "final restore");
     }
+    return SMI_OK;
+    };
+    if (ctx->opt_graph && !timed) {
+        Key k = plan_key('F', pl, c);
+        k.put(fused).put(w.status).put(stf).put(dcal).put(snaps).put(nsnap);
+        for (int q = 0; q < nsnap; ++q) k.put(snap_it[q]);
+        s = graph_run(ctx, k.b, st, loop);
+    } else {
+        s = loop(st);
+    }
+    c.st = st;
+    if (s != SMI_OK) return s;
     ctx->cnt[0] = pl.cnt_fwd;
     ctx->cnt[1] = ctx->cnt[2] = 0;
     ctx->bytes[0] = pl.bytes_fwd;
@@ -277,13 +358,28 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     configure(c, ctx, pl);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
-    for (int it = pl.g.nt - 1; it >= 0; --it) {
-        if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
-        HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
-        if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
-        for (int k = 0; k < nsnap; ++k)
-            if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    auto loop = [&](hipStream_t ls) -> smi_status {
+        c.st = ls;
+        for (int it = pl.g.nt - 1; it >= 0; --it) {
+            if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
+            HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+            if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
+            for (int k = 0; k < nsnap; ++k)
+                if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+        }
+        return SMI_OK;
+    };
+    if (ctx->opt_graph) {
+        Key k = plan_key('R', pl, c);
+        k.put(stt->ws).put(stt->stf).put(G).put(snaps).put(nsnap).put(adj).put(want_g);
+        k.put(want_i).put(want_r);
+        for (int q = 0; q < nsnap; ++q) k.put(snap_it[q]);
+        s = graph_run(ctx, k.b, st, loop);
+    } else {
+        s = loop(st);
     }
+    c.st = st;
+    if (s != SMI_OK) return s;
     HIPCHK(smi::finalize(c, stt->vp, want_g && !want_r ? grad : nullptr, want_i ? image : nullptr,
                          want_i ? illum : nullptr, want_i ? image_norm : nullptr), "finalize");
     if (want_r)

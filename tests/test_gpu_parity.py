@@ -414,3 +414,37 @@ def test_decimated_reconstruction_matches_oracle(ctx, ndim):
     e2 = rel_l2(im.cpu().numpy().reshape(job.vp.shape), im_ref)
     say(ndim, "decimated image rel L2", e2)
     assert e2 <= 1e-4
+
+
+def test_graph_replays_match_eager(ctx):
+    """SMI_OPT_GRAPH: the captured time loops (forward; forward + reverse of a gradient) give
+    bitwise the eager results on every replay, with other eager work and synchronisations
+    between the replays."""
+    from paper_2311_02293_amd import binding as B
+    import torch
+    job = _grad_job(nt=300, nshot=2)
+    vp, rho, stf = dev(job)
+    dref, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    dobs = (0.8 * dref).contiguous()
+    gref, Jref, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+    dref, gref, Jref = dref.cpu().numpy(), gref.cpu().numpy(), float(Jref.cpu()[0])
+    nrec = int(job.acq.rec_off[-1])
+    dcal = torch.empty(job.grid.nt * nrec, dtype=torch.float32, device="cuda")
+    ws_f = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_FORWARD)).clone()
+    ws_g = torch.empty(ctx.workspace_bytes(job.grid, job.acq, B.JOB_GRAD), dtype=torch.uint8,
+                       device="cuda")
+    ctx.set_option(B.OPT_GRAPH, 1)
+    try:
+        for rep in range(3):
+            say("graph replay", rep)
+            ctx.forward(job.grid, job.acq, vp, rho, stf, dcal=dcal, ws=ws_f)
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()                       # eager work between replays
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(dcal.cpu().numpy(), dref)
+            g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs, ws=ws_g)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.cpu().numpy(), gref)
+            assert float(J.cpu()[0]) == Jref
+    finally:
+        ctx.set_option(B.OPT_GRAPH, 0)
