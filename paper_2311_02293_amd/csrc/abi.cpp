@@ -63,6 +63,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.plain = ctx->opt_kernel == 1;
     c.march = 0;
     c.xcd = false;
+    c.y3 = 0;
     if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
@@ -75,6 +76,10 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
         c.xcd = ctx->opt_xcd != 0;
     } else if (ctx->opt_kernel == 4) {
         c.xcd = ctx->opt_xcd != 0;
+    } else if (ctx->opt_kernel == 5) {
+        c.march = pl.nd == 2 ? 4 : 2;
+        c.xcd = pl.nd == 2;
+        c.y3 = pl.nd == 3 ? (ctx->opt_chunk > 0 ? ctx->opt_chunk : 832) : 0;
     }
 }
 
@@ -453,7 +458,7 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 4) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 5) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }

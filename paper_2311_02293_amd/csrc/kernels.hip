@@ -1141,6 +1141,7 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
         if (c.march == 8) return c.zl ? fn<ND, N, 8, true>(__VA_ARGS__) : fn<ND, N, 8, false>(__VA_ARGS__); \
         return c.zl ? fn<ND, N, 4, true>(__VA_ARGS__) : fn<ND, N, 4, false>(__VA_ARGS__);          \
     } while (0)
+    if (!c.plain && c.y3 && ND == 3) return fwd_step_y3(c, it);
     if (!c.plain && c.march) SMI_MARCH(fwd_march_t, c, it);
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     int step = c.plain ? 1 : pl.nshot;
@@ -1201,6 +1202,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
         auto recon = [&]() -> hipError_t { SMI_MARCH(recon_march_t, c, it, grad, image); };
         hipError_t e = recon();
         if (e != hipSuccess) return e;
+        if (c.y3 && ND == 3) return adj_step_y3(c, it, image);
         SMI_MARCH(adj_march_t, c, it, image);
     }
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;

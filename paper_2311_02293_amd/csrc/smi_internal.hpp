@@ -186,9 +186,14 @@ struct StepCtx {
     bool xcd = false;       // XCD-contiguous tile order of the sweep kernels
     int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
+    int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);
+// 3D half steps marching along y (ymarch3d.hip)
+bool y3_available(const Plan &pl);
+hipError_t fwd_step_y3(const StepCtx &c, int it);
+hipError_t adj_step_y3(const StepCtx &c, int it, bool image);
 // fused 2D forward step (v, p, CPML, source in one kernel, level n from src, level n + 1 to
 // dst); false if not provided for this plan
 bool fused_fwd_available(const Plan &pl);

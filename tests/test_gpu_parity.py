@@ -448,3 +448,37 @@ def test_graph_replays_match_eager(ctx):
             assert float(J.cpu()[0]) == Jref
     finally:
         ctx.set_option(B.OPT_GRAPH, 0)
+
+
+@pytest.mark.parametrize("code", [832, 416, 464, 816])
+def test_y_march_3d_matches_sweep_kernels(ctx, code):
+    """3D half steps marching along y (register window along y, LDS plane tiles for z and x):
+    forward data, FWI gradient and RTM image agree with the one-cell-per-lane sweep kernels to
+    rounding, for several tile widths and march lengths; the data match the oracle."""
+    from paper_2311_02293_amd import binding as B
+    job = with_bounds(I.config4(n=40, nt=160, dr=1, nshot=2, rec_step=4))
+    say("y-march", code, job.grid)
+    vp, rho, stf = dev(job)
+    ctx.set_option(B.OPT_KERNEL, 4)
+    try:
+        ref, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+        dobs = (0.9 * ref).contiguous()
+        gref, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+        iref, _ = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+    ctx.set_option(B.OPT_KERNEL, 5)
+    ctx.set_option(B.OPT_CHUNK, code)
+    try:
+        got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+        g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+        im, _ = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+        ctx.set_option(B.OPT_CHUNK, 0)
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-6
+    assert rel_l2(g.cpu().numpy(), gref.cpu().numpy()) <= 1e-5
+    assert rel_l2(im.cpu().numpy(), iref.cpu().numpy()) <= 1e-5
+    o = oracle_dcal(job, shots=[1], box=0)[0]
+    assert rel_l2(split(dcal_t(got), job)[1], o) <= 1e-4
