@@ -59,7 +59,8 @@ typedef enum {
     SMI_JOB_FORWARD = 0,       /* smi_forward without state */
     SMI_JOB_FORWARD_SAVE = 1,  /* smi_forward with state, then smi_adjoint_reconstruct */
     SMI_JOB_RTM = 2,           /* smi_rtm_image */
-    SMI_JOB_GRAD = 3           /* smi_fwi_grad */
+    SMI_JOB_GRAD = 3,          /* smi_fwi_grad */
+    SMI_JOB_BORN = 4           /* smi_born */
 } smi_job;
 
 typedef struct smi_ctx smi_ctx;      /* device, options, last error text */
@@ -196,6 +197,19 @@ smi_status smi_rtm_image(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                          const float *vp, const float *rho, const float *stf, const float *dobs,
                          float *image, float *illum, float *image_norm, void *ws, size_t ws_bytes,
                          void *hip_stream);
+
+/* Born (tangent-linear) modelling with respect to kappa = rho Vp^2: the data perturbation
+ * of a model perturbation dkappa (the linearisation the paper lists as under development;
+ * the derivative of smi_forward's data).  The background field runs the forward step; the
+ * perturbation field obeys the same step (CPML included) plus the secondary source
+ * -dt dkappa div v^{it+1/2} in its p update, and ddata[it][r] = dp^{it+1} at receiver r.
+ *   dkappa  device [n1*n2*n3] (interior; zero in the absorbing layers).  For a velocity
+ *           perturbation at fixed rho, dkappa = 2 rho Vp dVp.
+ *   ddata   device, layout of dcal.
+ *   ws      device workspace of SMI_JOB_BORN. */
+smi_status smi_born(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
+                    const float *rho, const float *stf, const float *dkappa, float *ddata,
+                    void *ws, size_t ws_bytes, void *hip_stream);
 
 /* Laplace filter of an image (Sec. 2.3, against the low-wavenumber artefacts of RTM images):
  * out = sum_a (f[i+1] - 2 f[i] + f[i-1]) / d_a^2 over the grid's axes (second-order central

@@ -18,7 +18,7 @@ SMI_OK = 0
 STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
           -4: "SMI_E_WORKSPACE", -5: "SMI_E_HIP", -6: "SMI_E_UNSUPPORTED", -7: "SMI_E_STATE",
           -8: "SMI_E_NONFINITE"}
-JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD = 0, 1, 2, 3
+JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD, JOB_BORN = 0, 1, 2, 3, 4
 OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY = 0, 1, 2, 3, 4, 5
 
 
@@ -69,6 +69,8 @@ def lib():
         L.smi_rtm_image.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
                                     vp, vp, vp, C.c_size_t, vp]
         L.smi_laplacian.argtypes = [vp, C.POINTER(SmiGrid), vp, vp, vp]
+        L.smi_born.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp, vp,
+                               C.c_size_t, vp]
         L.smi_fwi_grad.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, C.c_size_t, vp]
         L.smi_state_destroy.argtypes = [vp]
@@ -277,6 +279,19 @@ class Context:
                                         _ptr(stf), _ptr(dobs), _ptr(image), _ptr(il), _ptr(nm),
                                         _ptr(ws), ws.numel(), _stream(stream)))
         return (image, il, nm) if norm else (image, il)
+
+    def born(self, grid, acq, vp, rho, stf, dkappa, *, ws=None, stream=None):
+        """smi_born: data perturbation (layout of dcal) of a kappa perturbation."""
+        import torch
+        g = make_grid(grid)
+        a = _Acq(acq)
+        nb = self.workspace_bytes(grid, acq, JOB_BORN)
+        ws = self.workspace(nb) if ws is None else ws
+        dd = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=vp.device)
+        self._check(lib().smi_born(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
+                                   _ptr(stf), _ptr(dkappa), _ptr(dd), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+        return dd
 
     def laplacian(self, grid, image, out=None, stream=None):
         """smi_laplacian: Laplace filter of an n1*n2[*n3] device image."""

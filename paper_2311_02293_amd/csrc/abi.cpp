@@ -484,7 +484,7 @@ smi_status smi_workspace_bytes(const smi_ctx *ctx, const smi_grid *grid, const s
                                smi_job job, size_t *bytes) {
     smi_ctx *c = const_cast<smi_ctx *>(ctx);
     if (!grid || !acq || !bytes) return fail(c, SMI_E_ARG, "NULL argument");
-    if (job < SMI_JOB_FORWARD || job > SMI_JOB_GRAD) return fail(c, SMI_E_ARG, "bad job");
+    if (job < SMI_JOB_FORWARD || job > SMI_JOB_BORN) return fail(c, SMI_E_ARG, "bad job");
     // the layout does not depend on the speeds; use a range that passes the checks
     smi_grid g = *grid;
     double vmin = grid->vpmin > 0 ? grid->vpmin : 0, vmax = grid->vpmax > 0 ? grid->vpmax : 0;
@@ -615,6 +615,45 @@ smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double 
     if (fwd) *fwd = ctx->cnt[0];
     if (adj) *adj = ctx->cnt[1];
     if (rec) *rec = ctx->cnt[2];
+    return SMI_OK;
+}
+
+smi_status smi_born(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, const float *vp,
+                    const float *rho, const float *stf, const float *dkappa, float *ddata,
+                    void *ws, size_t ws_bytes, void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!grid || !acq) return fail(ctx, SMI_E_ARG, "grid / acq is NULL");
+    if (!vp || !rho || !stf || !dkappa || !ddata)
+        return fail(ctx, SMI_E_ARG, "vp, rho, stf, dkappa and ddata are required");
+    if (!ws) return fail(ctx, SMI_E_WORKSPACE, "workspace is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    double vmin = 0, vmax = 0;
+    smi_status s = speeds(ctx, grid, vp, ws, ws_bytes, st, vmin, vmax);
+    if (s != SMI_OK) return s;
+    Plan pl;
+    s = smi::make_plan(grid, acq, SMI_JOB_BORN, vmin, vmax, pl, ctx->err);
+    if (s != SMI_OK) return s;
+    if (ws_bytes < pl.bytes) return fail(ctx, SMI_E_WORKSPACE, "workspace too small");
+    Views w = smi::views(pl, ws);
+    s = upload(ctx, pl, w, st);
+    if (s != SMI_OK) return s;
+    HIPCHK(smi::launch_model_prep(pl, w, vp, rho, st), "model prep");
+    s = zero_fields(ctx, pl, w.f, st);
+    if (s == SMI_OK) s = zero_fields(ctx, pl, w.q, st);
+    if (s != SMI_OK) return s;
+    smi::StepCtx c{&pl, &w, stf, st, false};
+    configure(c, ctx, pl);
+    c.plain = false;
+    for (int it = 0; it < pl.g.nt; ++it) {
+        HIPCHK(smi::fwd_step(c, it), "background step");
+        HIPCHK(smi::born_step(c, it, dkappa), "perturbation step");
+        HIPCHK(smi::extract(c, it, ddata, w.q.p), "extract");
+    }
+    ctx->cnt[0] = 2 * pl.cnt_fwd;
+    ctx->cnt[1] = ctx->cnt[2] = 0;
+    ctx->bytes[0] = 2 * pl.bytes_fwd;
+    ctx->bytes[1] = 0;
+    ctx->last_ws = (void *)w.status;
     return SMI_OK;
 }
 

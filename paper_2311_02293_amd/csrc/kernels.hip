@@ -946,6 +946,25 @@ __global__ __launch_bounds__(256) void k_rho_faces(Geom g, Fields f, Fields q, f
     }
 }
 
+// Secondary source of the tangent-linear step: dp -= dt dkappa div v^{it+1/2} (background v)
+// on the interior cells of the forward box.
+template <int ND, int N>
+__global__ __launch_bounds__(256) void k_born_src(Geom g, Fields f, Fields q,
+                                                  const int *__restrict__ box, int shot0, LG lg,
+                                                  const float *__restrict__ dkap) {
+    Cell c = cell_of(g, box, shot0, lg);
+    if (!c.ok) return;
+    const int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
+    if ((unsigned)iz >= (unsigned)g.n[0] || (unsigned)ix >= (unsigned)g.n[1] ||
+        (unsigned)iy >= (unsigned)g.n[2])
+        return;
+    const float dk = dkap[iz + (long long)g.n[0] * (ix + (long long)g.n[1] * iy)];
+    float div = 0.f;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) div += dminus<N>(g, f.v[a] + c.s * g.P, c, a);
+    q.p[c.s * g.P + c.k] -= g.dt * dk * div;
+}
+
 // Gradients of a parametrisation family from A = sum_s acc_g (g_kappa = -(dt/kappa) A) and
 // the face sums (g_rho at fixed kappa = -1/2 sum_a sum_s (dt beta S)_{face below} +
 // (dt beta S)_{face above}): family 1 (Vp, rho): g1 = 2 rho Vp g_kappa, g2 = Vp^2 g_kappa +
@@ -1395,6 +1414,27 @@ hipError_t rho_faces_t(const StepCtx &c, int it) {
 }
 
 hipError_t rho_faces(const StepCtx &c, int it) { SMI_DISPATCH(rho_faces_t, c, it); }
+
+template <int ND, int N>
+hipError_t born_step_t(const StepCtx &c, int it, const float *dkappa) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *box = w.fbox + (size_t)it * pl.nshot * 6;
+    Launch L = box_launch(pl, pl.fbox, it, 0, pl.nshot, c.xcd);
+    if (L.empty) return hipSuccess;
+    hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
+                       w.cpml, box, 0, L.ey);
+    hipLaunchKernelGGL((k_step_p<ND, N, false, false>), L.grid, L.block, 0, c.st, pl.geom, w.q,
+                       w.model, w.cpml, box, 0, L.ey, (const long long *)w.src_cell, c.stf,
+                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
+    hipLaunchKernelGGL((k_born_src<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.q, box, 0,
+                       L.ey, dkappa);
+    return hipGetLastError();
+}
+
+hipError_t born_step(const StepCtx &c, int it, const float *dkappa) {
+    SMI_DISPATCH(born_step_t, c, it, dkappa);
+}
 
 hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
                            float *g1, float *g2) {

@@ -282,6 +282,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.need_G = job == SMI_JOB_GRAD || job == SMI_JOB_RTM;
     pl.need_dcal = pl.need_G;
     pl.rho_acc = job == SMI_JOB_GRAD || job == SMI_JOB_FORWARD_SAVE;
+    pl.born = job == SMI_JOB_BORN;
 
     // computing boxes (Sec. 4.1)
     const int nt = g->nt, ns = pl.nshot;
@@ -405,7 +406,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.off_fields = take(fld);
     pl.dbuf = pl.nd == 2;
     pl.off_fields2 = pl.dbuf ? take(fld) : 0;
-    pl.off_adj = pl.adjoint ? take(fld) : 0;
+    pl.off_adj = pl.adjoint || pl.born ? take(fld) : 0;
     pl.off_bands = pl.save ? take(sizeof(float) * (size_t)ns * pl.nsave * (size_t)bd.B) : 0;
     pl.off_fin = pl.save && g->dr > 1 ? take(sizeof(float) * (size_t)ns * (size_t)pl.P * (1 + pl.nd)) : 0;
     pl.off_acc = pl.adjoint ? take(sizeof(float) * 3 * (size_t)ns * (size_t)pl.I) : 0;
@@ -472,7 +473,7 @@ Views views(const Plan &pl, void *ws) {
     };
     w.f = fields(pl.off_fields);
     w.f2 = pl.dbuf ? fields(pl.off_fields2) : Fields{};
-    w.q = pl.adjoint ? fields(pl.off_adj) : Fields{};
+    w.q = pl.adjoint || pl.born ? fields(pl.off_adj) : Fields{};
     w.bands = pl.save ? (float *)(b + pl.off_bands) : nullptr;
     if (pl.adjoint) {
         float *a = (float *)(b + pl.off_acc);

@@ -125,6 +125,7 @@ struct Plan {
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
     bool rho_acc = false;   // room for the density-gradient face sums (gradient-capable jobs)
+    bool born = false;      // a perturbation field beside the background (tangent-linear job)
     bool dbuf = false;  // second source-field buffer for the fused steps
     int chunk = 0;      // columns per workgroup of the fused 2D step (0: default)
     double cnt_fwd = 0, cnt_adj = 0, cnt_rec = 0;
@@ -211,6 +212,9 @@ hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image
                     float *image_norm);
 // density part of eq. (7): accumulate v~ D+p on the faces of reverse step it
 hipError_t rho_faces(const StepCtx &c, int it);
+// tangent-linear step: the perturbation field (q) over the forward box, with the secondary
+// source -dt dkappa div v of the background (f, after its own step)
+hipError_t born_step(const StepCtx &c, int it, const float *dkappa);
 // gradients of a parametrisation family (1: Vp, rho; 2: Vp, Ip) from the kappa and face sums
 hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
                            float *g1, float *g2);

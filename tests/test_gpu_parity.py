@@ -482,3 +482,32 @@ def test_y_march_3d_matches_sweep_kernels(ctx, code):
     assert rel_l2(im.cpu().numpy(), iref.cpu().numpy()) <= 1e-5
     o = oracle_dcal(job, shots=[1], box=0)[0]
     assert rel_l2(split(dcal_t(got), job)[1], o) <= 1e-4
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_born_matches_oracle(ctx, ndim):
+    """Tangent-linear (Born) data of a kappa perturbation against the oracle's linearisation
+    (itself pinned by finite differences of the forward map)."""
+    from oracle import oracle as O
+    import torch
+    if ndim == 2:
+        job = with_bounds(I.config2(n1=60, n2=140, nt=500, nshot=2))
+    else:
+        job = with_bounds(I.config4(n=32, nt=180, nshot=1, dr=1, rec_step=4))
+    rng = np.random.default_rng(31 + ndim)
+    kap = job.rho.astype(np.float64) * job.vp.astype(np.float64) ** 2
+    dk = np.zeros_like(kap)
+    sl = (slice(10, 22), slice(10, 22), slice(8, 20)) if ndim == 3 else (slice(50, 90), slice(20, 40))
+    dk[sl] = 0.05 * kap[sl] * (1.0 + 0.3 * rng.standard_normal(dk[sl].shape))
+    gr = O.og_grid(job.grid, vmax=float(job.grid.vpmax), box=0)
+    vp, rho, stf = dev(job)
+    dd = ctx.born(job.grid, job.acq, vp, rho, stf,
+                  torch.from_numpy(dk.astype(np.float32).ravel()).cuda())
+    from paper_2311_02293_amd import binding as B
+    got = [d.cpu().numpy() for d in B.split_dcal(dd, job.acq, job.grid.nt)]
+    for s in range(job.acq.nshot):
+        src, rec = O.shot_nodes(job.grid, job.acq, s)
+        ref = O.born(gr, job.vp, job.rho, src, job.stf[s], rec, dk)
+        err = rel_l2(got[s], ref)
+        say("born", ndim, "shot", s, err)
+        assert err <= 1e-4
