@@ -308,3 +308,40 @@ def sgd(ctx, job, dobs, *, batch: int, epochs: int = 1, seed: int = 0, family=1,
             log.append((b, J0, J0))
     vp, rho = prob.to_model(x)
     return vp, rho, log
+
+
+# ----------------------------------------------------------------------------- data weighting
+
+def offset_weights(acq, nt: int, dxw: float, xw: Sequence[float]) -> np.ndarray:
+    """Offset weighting (Sec. 3.7, data weighting): receiver r of shot s gets the weight of its
+    offset |x_r - x_s| linearly interpolated in the table xw sampled every dxw metres (the last
+    value beyond the table).  Returned in the layout of the data (float32)."""
+    xw = np.asarray(xw, np.float64)
+    out = np.empty(nt * int(acq.rec_off[-1]), np.float32)
+    for s in range(acq.nshot):
+        a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
+        h = np.hypot(acq.rec[a:b, 1] - acq.src[s, 1], acq.rec[a:b, 2] - acq.src[s, 2])
+        w = np.interp(h / dxw, np.arange(len(xw)), xw)
+        out[nt * a: nt * b] = np.tile(w.astype(np.float32), nt)
+    return out
+
+
+def mute_weights(acq, nt: int, dt: float, xmute: Sequence[float], tmute: Sequence[float],
+                 ntaper: int, mode: int) -> np.ndarray:
+    """Front (mode 1) or tail (mode 2) muting (Sec. 3.7): the mute time of a trace is the line
+    (xmute, tmute) interpolated at the trace's offset; mode 1 zeroes the samples before it
+    (keeping later arrivals, the reflections), mode 2 those after it (keeping the first
+    arrivals); ntaper samples of a cosine taper join the muted and kept parts."""
+    xm, tm = np.asarray(xmute, np.float64), np.asarray(tmute, np.float64)
+    out = np.empty(nt * int(acq.rec_off[-1]), np.float32)
+    t = np.arange(nt) * dt
+    for s in range(acq.nshot):
+        a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
+        h = np.hypot(acq.rec[a:b, 1] - acq.src[s, 1], acq.rec[a:b, 2] - acq.src[s, 2])
+        tcut = np.interp(h, xm, tm)                            # per receiver
+        u = (t[:, None] - tcut[None, :]) / max(ntaper * dt, 1e-30)   # samples past the line
+        ramp = np.clip(u, 0.0, 1.0)
+        taper = 0.5 - 0.5 * np.cos(np.pi * ramp)               # 0 before, 1 after the taper
+        w = taper if mode == 1 else 1.0 - taper
+        out[nt * a: nt * b] = w.astype(np.float32).ravel()
+    return out

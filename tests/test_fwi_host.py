@@ -111,3 +111,41 @@ def test_family_transforms_round_trip():
             np.testing.assert_allclose(np.exp(x[4:].numpy()), (vp * rho).numpy(), rtol=1e-6)
         lo, hi = p.x_bounds()
         assert lo.shape == x.shape and bool((lo < hi).all())
+
+
+def _line_acq():
+    from paper_2311_02293_amd import inputs as I
+    return I._surface_line(np.array([100.0, 500.0]), 20.0, np.arange(0, 1000, 50.0), 20.0)
+
+
+def test_offset_weights_follow_the_table():
+    acq = _line_acq()
+    nt = 7
+    w = F.offset_weights(acq, nt, dxw=200.0, xw=[0.0, 0.5, 1.0])
+    assert w.shape == (nt * int(acq.rec_off[-1]),)
+    s = 0
+    a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
+    block = w[nt * a: nt * b].reshape(nt, b - a)
+    off = np.abs(acq.rec[a:b, 1] - acq.src[s, 1])
+    exp = np.clip(off / 200.0 * 0.5, 0.0, 1.0)
+    np.testing.assert_allclose(block[3], exp, atol=1e-6)
+    assert np.all(block == block[0])                      # constant in time
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_mute_weights_cut_at_the_mute_line(mode):
+    acq = _line_acq()
+    nt, dt = 200, 0.01
+    w = F.mute_weights(acq, nt, dt, xmute=[0.0, 1000.0], tmute=[0.2, 1.2], ntaper=10, mode=mode)
+    a, b = int(acq.rec_off[0]), int(acq.rec_off[1])
+    block = w[nt * a: nt * b].reshape(nt, b - a)
+    for r in range(b - a):
+        off = abs(acq.rec[a + r, 1] - acq.src[0, 1])
+        tcut = 0.2 + off / 1000.0
+        i0 = int(np.floor(tcut / dt + 1e-9))
+        before, after = block[: max(i0 - 1, 0), r], block[i0 + 11:, r]
+        if mode == 1:
+            assert np.all(before == 0) and np.all(after == 1)
+        else:
+            assert np.all(before == 1) and np.all(after == 0)
+        assert np.all((block[:, r] >= 0) & (block[:, r] <= 1))
