@@ -32,6 +32,27 @@ _SRC = os.path.join(_HERE, "smi_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
+class OgTaps(C.Structure):
+    _fields_ = [("n", C.c_int), ("off", C.POINTER(C.c_int)), ("idx", C.POINTER(C.c_int)),
+                ("w", C.POINTER(C.c_double))]
+
+
+class Taps:
+    """Point operators (off-grid sources / receivers) and the arrays they point to."""
+
+    def __init__(self, off, idx, w):
+        self.off = np.ascontiguousarray(off, np.int32)
+        self.idx = np.ascontiguousarray(idx, np.int32).reshape(-1, 3)
+        self.w = np.ascontiguousarray(w, np.float64)
+        self.c = OgTaps(len(self.off) - 1, self.off.ctypes.data_as(C.POINTER(C.c_int)),
+                        self.idx.ctypes.data_as(C.POINTER(C.c_int)),
+                        self.w.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def _tp(t: Optional["Taps"]):
+    return None if t is None else C.byref(t.c)
+
+
 class OgGrid(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
                 ("d1", C.c_double), ("d2", C.c_double), ("d3", C.c_double),
@@ -69,11 +90,13 @@ def lib():
         L.og_band_size.restype = C.c_size_t
         L.og_band_levels.argtypes = [gp]
         L.og_band_levels.restype = C.c_size_t
+        tp = C.POINTER(OgTaps)
         L.og_forward.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, C.c_int,
-                                 ip, dp]
-        L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp]
-        L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp, dp]
-        L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp]
+                                 ip, dp, tp, tp]
+        L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp, tp]
+        L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp, dp,
+                                 tp, tp]
+        L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, tp, tp]
         _lib = L
     return _lib
 
@@ -129,6 +152,77 @@ def node(g, pos) -> np.ndarray:
     return out
 
 
+# Kaiser window parameter b of the windowed-sinc point operators for half-width r (Hicks'
+# table for a maximum wavenumber of half the Nyquist one); the half-width is order / 2.
+KAISER_B = {1: 1.24, 2: 2.94, 3: 4.53, 4: 6.31}
+ON_GRID = 1e-3          # positions within this fraction of a spacing of a node are on it
+
+
+def _i0(x: float) -> float:
+    s, t, k = 1.0, 1.0, 1
+    while True:
+        t *= (x / (2.0 * k)) ** 2
+        s += t
+        if t < 1e-17 * s:
+            return s
+        k += 1
+
+
+def hicks_weights_1d(u: float, r: int, M: int):
+    """Nodes and weights of the windowed-sinc operator of a point at fractional padded index
+    u along one axis: sinc(j - u) times the Kaiser window I0(b sqrt(1 - ((j-u)/r)^2)) / I0(b)
+    on the 2r nodes around u; a point within ON_GRID of a node is that node, weight 1.  Nodes
+    outside [0, M) are dropped."""
+    j0 = int(round(u))
+    if abs(u - j0) <= ON_GRID:
+        return [j0], [1.0]
+    b = KAISER_B[r]
+    nodes, w = [], []
+    base = int(math.floor(u))
+    for j in range(base - r + 1, base + r + 1):
+        x = j - u
+        win = _i0(b * math.sqrt(max(0.0, 1.0 - (x / r) ** 2))) / _i0(b)
+        if 0 <= j < M:
+            nodes.append(j)
+            w.append(math.sin(math.pi * x) / (math.pi * x) * win)
+    return nodes, w
+
+
+def point_taps(g, positions) -> Taps:
+    """Tensor-product windowed-sinc operators (Sec. 2.1) of a list of positions (z, x, y) in
+    metres: padded nodes and weights per point."""
+    ds = [g.d1, g.d2, g.d3]
+    Ms = [g.n1 + 2 * g.nb, g.n2 + 2 * g.nb, (g.n3 + 2 * g.nb) if g.ndim == 3 else 1]
+    r = g.order // 2
+    off, idx, w = [0], [], []
+    for pos in positions:
+        per = []
+        for a in range(3):
+            if a >= g.ndim:
+                per.append(([0], [1.0]))
+            else:
+                per.append(hicks_weights_1d(g.nb + float(pos[a]) / ds[a], r, Ms[a]))
+        for i3, w3 in zip(*per[2]):
+            for i2, w2 in zip(*per[1]):
+                for i1, w1 in zip(*per[0]):
+                    idx.append((i1, i2, i3))
+                    w.append(w1 * w2 * w3)
+        off.append(len(w))
+    return Taps(off, np.array(idx, np.int32).reshape(-1, 3), np.array(w))
+
+
+def shot_ops(g, acq, s: int):
+    """(src node, receiver nodes, source operator, receiver operator) of shot s; the operators
+    are None when every point of the kind lies on a node.  The nodes (nearest) centre the
+    computing boxes."""
+    src, rec = shot_nodes(g, acq, s)
+    a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
+    st = point_taps(g, [acq.src[s]])
+    rt = point_taps(g, acq.rec[a:b])
+    return (src, rec, None if len(st.w) == 1 else st,
+            None if len(rt.w) == b - a else rt)
+
+
 def shot_nodes(g, acq, s: int):
     src = node(g, acq.src[s])
     a, b = int(acq.rec_off[s]), int(acq.rec_off[s + 1])
@@ -171,9 +265,10 @@ def interior_size(gr: OgGrid) -> int:
 # ------------------------------------------------------------------ single-shot drivers
 
 def forward(gr: OgGrid, vp, rho, src, stf, rec, *, init=None, hist=False, bands=False,
-            final=False, snaps: Sequence[int] = ()):
+            final=False, snaps: Sequence[int] = (), st: Optional[Taps] = None,
+            rt: Optional[Taps] = None):
     """Forward loop of Alg. 2 for one shot.  Returns dict(dcal[nt, nrec], hist, bands,
-    final, snaps)."""
+    final, snaps).  st / rt: off-grid source / receiver operators (None: at the nodes)."""
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -191,13 +286,14 @@ def forward(gr: OgGrid, vp, rho, src, stf, rec, *, init=None, hist=False, bands=
     rc = lib().og_forward(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), nrec, _i(rec),
                           _d(out["dcal"]), _d(init_a), _d(out["hist"]), _d(out["bands"]),
                           _d(out["final"]), len(snap_it), _i(snap_it) if len(snap_it) else None,
-                          _d(out["snaps"]) if len(snap_it) else None)
+                          _d(out["snaps"]) if len(snap_it) else None, _tp(st), _tp(rt))
     if rc:
         raise RuntimeError("og_forward failed: %d" % rc)
     return out
 
 
-def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int]):
+def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int],
+                st: Optional[Taps] = None):
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -206,14 +302,14 @@ def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int
     out = np.zeros((len(snap_it), interior_size(gr)))
     rc = lib().og_reconstruct(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf),
                               _d(np.ascontiguousarray(bands)), _d(np.ascontiguousarray(final)),
-                              len(snap_it), _i(snap_it), _d(out))
+                              len(snap_it), _i(snap_it), _d(out), _tp(st))
     if rc:
         raise RuntimeError("og_reconstruct failed: %d" % rc)
     return out
 
 
 def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, final=None,
-            want=("gk", "image", "illum")):
+            want=("gk", "image", "illum"), st: Optional[Taps] = None, rt: Optional[Taps] = None):
     """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum and,
     when "grk" is wanted, dJ/drho at fixed kappa (the buoyancy part of eq. 7)."""
     vp = np.ascontiguousarray(vp, np.float64)
@@ -231,13 +327,14 @@ def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, fin
                           _d(G), _d(None if hist is None else np.ascontiguousarray(hist)),
                           _d(None if bands is None else np.ascontiguousarray(bands)),
                           _d(None if final is None else np.ascontiguousarray(final)),
-                          _d(gk), _d(im), _d(il), _d(grk))
+                          _d(gk), _d(im), _d(il), _d(grk), _tp(st), _tp(rt))
     if rc:
         raise RuntimeError("og_adjoint failed: %d" % rc)
     return {"gk": gk, "image": im, "illum": il, "grk": grk}
 
 
-def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa):
+def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa, st: Optional[Taps] = None,
+         rt: Optional[Taps] = None):
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -246,7 +343,7 @@ def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa):
     dk = np.ascontiguousarray(dkappa, np.float64).ravel()
     dd = np.zeros((gr.nt, rec.shape[0]))
     rc = lib().og_born(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
-                       _d(dk), _d(dd))
+                       _d(dk), _d(dd), _tp(st), _tp(rt))
     if rc:
         raise RuntimeError("og_born failed: %d" % rc)
     return dd
@@ -272,8 +369,8 @@ def forward_job(job, shots=None, vp=None, box=None, pml=1, vmax=None):
     shots = range(job.acq.nshot) if shots is None else shots
     out = []
     for s in shots:
-        src, rec = shot_nodes(job.grid, job.acq, s)
-        out.append(forward(gr, vp, job.rho, src, job.stf[s], rec)["dcal"])
+        src, rec, st, rt = shot_ops(job.grid, job.acq, s)
+        out.append(forward(gr, vp, job.rho, src, job.stf[s], rec, st=st, rt=rt)["dcal"])
     return out
 
 
@@ -286,13 +383,13 @@ def fwi_grad(job, dobs, shots=None, vp=None, box=None, vmax=None, use_history=Fa
     gk = np.zeros(interior_size(gr))
     J = 0.0
     for k, s in enumerate(shots):
-        src, rec = shot_nodes(job.grid, job.acq, s)
+        src, rec, st, rt = shot_ops(job.grid, job.acq, s)
         fw = forward(gr, vp, job.rho, src, job.stf[s], rec, hist=use_history,
-                     bands=not use_history, final=not use_history)
+                     bands=not use_history, final=not use_history, st=st, rt=rt)
         Js, G = misfit(fw["dcal"], dobs[k], gr.dt)
         J += Js
         r = adjoint(gr, vp, job.rho, src, job.stf[s], rec, G, hist=fw["hist"],
-                    bands=fw["bands"], final=fw["final"], want=("gk",))
+                    bands=fw["bands"], final=fw["final"], want=("gk",), st=st, rt=rt)
         gk += r["gk"]
     vp64 = np.asarray(vp, np.float64).ravel()
     rho64 = np.asarray(job.rho, np.float64).ravel()
@@ -316,13 +413,13 @@ def fwi_grad_family(job, dobs, family: int = 1, shots=None, vp=None, rho=None, b
     grk = np.zeros(interior_size(gr))
     J = 0.0
     for k, s in enumerate(shots):
-        src, rec = shot_nodes(job.grid, job.acq, s)
+        src, rec, st, rt = shot_ops(job.grid, job.acq, s)
         fw = forward(gr, vp, rho, src, job.stf[s], rec, hist=use_history,
-                     bands=not use_history, final=not use_history)
+                     bands=not use_history, final=not use_history, st=st, rt=rt)
         Js, G = misfit(fw["dcal"], dobs[k], gr.dt)
         J += Js
         r = adjoint(gr, vp, rho, src, job.stf[s], rec, G, hist=fw["hist"],
-                    bands=fw["bands"], final=fw["final"], want=("gk", "grk"))
+                    bands=fw["bands"], final=fw["final"], want=("gk", "grk"), st=st, rt=rt)
         gk += r["gk"]
         grk += r["grk"]
     v = np.asarray(vp, np.float64).ravel()
@@ -344,10 +441,12 @@ def rtm_image(job, dobs, shots=None, box=None, vmax=None, per_shot=False):
     shots = list(range(job.acq.nshot)) if shots is None else list(shots)
     ims, ils = [], []
     for k, s in enumerate(shots):
-        src, rec = shot_nodes(job.grid, job.acq, s)
-        fw = forward(gr, job.vp, job.rho, src, job.stf[s], rec, bands=True, final=True)
+        src, rec, st, rt = shot_ops(job.grid, job.acq, s)
+        fw = forward(gr, job.vp, job.rho, src, job.stf[s], rec, bands=True, final=True, st=st,
+                     rt=rt)
         r = adjoint(gr, job.vp, job.rho, src, job.stf[s], rec, gr.dt * np.asarray(dobs[k]),
-                    bands=fw["bands"], final=fw["final"], want=("image", "illum"))
+                    bands=fw["bands"], final=fw["final"], want=("image", "illum"), st=st,
+                    rt=rt)
         ims.append(r["image"].reshape(job.vp.shape))
         ils.append(r["illum"].reshape(job.vp.shape))
     if per_shot:

@@ -62,6 +62,16 @@ typedef struct {
     double *p, *v[3], *psp[3], *psv[3];
 } og_field;
 
+/* Point operators of sources and receivers at positions off the grid (Sec. 2.1, Kaiser-
+ * windowed sinc of Hicks): point i acts on the padded nodes idx[3t..3t+2] with weights w[t],
+ * t in off[i] .. off[i+1].  A NULL operator means "the node given with the point".          */
+typedef struct {
+    int n;
+    const int *off;
+    const int *idx;
+    const double *w;
+} og_taps;
+
 /* ------------------------------------------------------------------ coefficients */
 
 /* Staggered first-derivative weights of order 2N (eq. 4): the unique a_l that make
@@ -213,6 +223,32 @@ static void og_field_free(og_field *f)
 {
     free(f->p);
     for (int a = 0; a < 3; a++) { free(f->v[a]); free(f->psp[a]); free(f->psv[a]); }
+}
+
+/* f at point i of operator t (or at `node` when t is NULL) */
+static double og_sample(const og_model *m, const double *f, const og_taps *t, int i, const int *node)
+{
+    if (!t) return f[IDX(m, node[0], node[1], node[2])];
+    double s = 0.0;
+    for (int q = t->off[i]; q < t->off[i + 1]; q++)
+        s += t->w[q] * f[IDX(m, t->idx[3 * q], t->idx[3 * q + 1], t->idx[3 * q + 2])];
+    return s;
+}
+
+/* f += amp * (operator weights of point i), scaled node-wise by `scale` when not NULL (the
+ * transpose of og_sample, times the scale) */
+static void og_spread(const og_model *m, double *f, const og_taps *t, int i, const int *node,
+                      double amp, const double *scale)
+{
+    if (!t) {
+        size_t k = IDX(m, node[0], node[1], node[2]);
+        f[k] += amp * (scale ? scale[k] : 1.0);
+        return;
+    }
+    for (int q = t->off[i]; q < t->off[i + 1]; q++) {
+        size_t k = IDX(m, t->idx[3 * q], t->idx[3 * q + 1], t->idx[3 * q + 2]);
+        f[k] += amp * t->w[q] * (scale ? scale[k] : 1.0);
+    }
 }
 
 /* value of f at node i shifted by `off` along axis a; 0 outside the padded grid */
@@ -476,7 +512,7 @@ static void og_take_snaps(const og_model *m, const double *p, int level, int nsn
 int og_forward(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, double *dcal, const double *init,
                double *hist, double *bands, double *final_state, int nsnap, const int *snap_it,
-               double *snaps)
+               double *snaps, const og_taps *st, const og_taps *rt)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -484,7 +520,6 @@ int og_forward(const og_grid *g, const double *vp, const double *rho, const int 
     og_field_alloc(&f, m.P);
     if (init) og_state_set(&m, &f, init);
     size_t B = og_band_size(g);
-    size_t sidx = IDX(&m, src[0], src[1], src[2]);
     /* with decimated bands the loop continues (source off, nothing recorded) until the last
      * saved level the interpolator needs */
     int last = g->nt;
@@ -500,9 +535,9 @@ int og_forward(const og_grid *g, const double *vp, const double *rho, const int 
         og_fwd_box_m(&m, src, it, lo, hi);
         og_step(&m, &f, lo, hi);
         if (it < g->nt) {
-            f.p[sidx] += g->dt * stf[it] / m.dV;
+            og_spread(&m, f.p, st, 0, src, g->dt * stf[it] / m.dV, NULL);
             for (int r = 0; r < nrec; r++)
-                dcal[(size_t)it * nrec + r] = f.p[IDX(&m, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+                dcal[(size_t)it * nrec + r] = og_sample(&m, f.p, rt, r, rec + 3 * r);
             og_take_snaps(&m, f.p, it + 1, nsnap, snap_it, snaps);
         }
     }
@@ -542,11 +577,11 @@ static void og_restore(const og_model *m, og_field *f, const double *bands, int 
  *   p[src] -= dt stf[it]/dV;  p^it = p^{it+1} + dt kappa div v^{it+1/2};  restore p band;
  *   v_a^{it-1/2} = v_a^{it+1/2} + dt beta_a d_a p^it;                      restore v bands. */
 static void og_recon_iter(const og_model *m, og_field *f, const int *src, const double *stf,
-                          const double *bands, int it)
+                          const double *bands, int it, const og_taps *st)
 {
     const double dt = m->g.dt;
     int nb = m->g.nb;
-    f->p[IDX(m, src[0], src[1], src[2])] -= dt * stf[it] / m->dV;
+    og_spread(m, f->p, st, 0, src, -dt * stf[it] / m->dV, NULL);
     int blo[3], bhi[3];
     og_fwd_box_m(m, src, it, blo, bhi);
     int lo[3], hi[3];
@@ -581,7 +616,7 @@ static void og_recon_iter(const og_model *m, og_field *f, const int *src, const 
  * snaps receive interior p at the requested levels 0..nt.                            */
 int og_reconstruct(const og_grid *g, const double *vp, const double *rho, const int *src,
                    const double *stf, const double *bands, const double *final_state, int nsnap,
-                   const int *snap_it, double *snaps)
+                   const int *snap_it, double *snaps, const og_taps *st)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -590,7 +625,7 @@ int og_reconstruct(const og_grid *g, const double *vp, const double *rho, const 
     og_state_set(&m, &f, final_state);
     og_take_snaps(&m, f.p, g->nt, nsnap, snap_it, snaps);
     for (int it = g->nt - 1; it >= 0; it--) {
-        og_recon_iter(&m, &f, src, stf, bands, it);
+        og_recon_iter(&m, &f, src, stf, bands, it, st);
         og_take_snaps(&m, f.p, it, nsnap, snap_it, snaps);
     }
     og_field_free(&f);
@@ -650,7 +685,7 @@ static void og_rho_faces(const og_model *m, const og_field *q, const og_field *f
 int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, const double *G, const double *hist,
                const double *bands, const double *final_state, double *gk, double *image,
-               double *illum, double *grk)
+               double *illum, double *grk, const og_taps *st, const og_taps *rt)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -663,10 +698,8 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
     }
     int nb = m.g.nb;
     for (int it = g->nt - 1; it >= 0; it--) {
-        for (int r = 0; r < nrec; r++) {
-            size_t k = IDX(&m, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2]);
-            q.p[k] += m.kap[k] * G[(size_t)it * nrec + r];
-        }
+        for (int r = 0; r < nrec; r++)
+            og_spread(&m, q.p, rt, r, rec + 3 * r, G[(size_t)it * nrec + r], m.kap);
         if (hist) og_state_set(&m, &f, hist + (size_t)(it + 1) * 4 * m.P); /* v^{it+1/2} */
         if (gk) {
 #pragma omp parallel for collapse(2) schedule(static)
@@ -683,7 +716,7 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
         og_adj_box_m(&m, nrec, rec, it, lo, hi);
         og_step(&m, &q, lo, hi);
         if (hist) og_state_set(&m, &f, hist + (size_t)it * 4 * m.P);
-        else og_recon_iter(&m, &f, src, stf, bands, it);
+        else og_recon_iter(&m, &f, src, stf, bands, it, st);
         if (image || illum) {
 #pragma omp parallel for collapse(2) schedule(static)
             for (int i3 = 0; i3 < m.n[2]; i3++)
@@ -710,14 +743,14 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
  * absorbing layers): the perturbation field obeys the same step, plus the secondary
  * source -dt dkappa div v^{n+1/2} in its p update; ddata[it][r] = dp^{it+1}[rec_r].    */
 int og_born(const og_grid *g, const double *vp, const double *rho, const int *src,
-            const double *stf, int nrec, const int *rec, const double *dkap, double *ddata)
+            const double *stf, int nrec, const int *rec, const double *dkap, double *ddata,
+            const og_taps *st, const og_taps *rt)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
     og_field f, df;
     og_field_alloc(&f, m.P);
     og_field_alloc(&df, m.P);
-    size_t sidx = IDX(&m, src[0], src[1], src[2]);
     int nb = m.g.nb;
     int lo[3] = {0, 0, 0}, hi[3] = {m.M[0] - 1, m.M[1] - 1, m.M[2] - 1};
     for (int it = 0; it < g->nt; it++) {
@@ -732,9 +765,9 @@ int og_born(const og_grid *g, const double *vp, const double *rho, const int *sr
                     size_t s = (size_t)i1 + (size_t)m.n[0] * ((size_t)i2 + (size_t)m.n[1] * i3);
                     df.p[k] -= g->dt * dkap[s] * divv(&m, &f, i1 + nb, i2 + nb, j3);
                 }
-        f.p[sidx] += g->dt * stf[it] / m.dV;
+        og_spread(&m, f.p, st, 0, src, g->dt * stf[it] / m.dV, NULL);
         for (int r = 0; r < nrec; r++)
-            ddata[(size_t)it * nrec + r] = df.p[IDX(&m, rec[3 * r], rec[3 * r + 1], rec[3 * r + 2])];
+            ddata[(size_t)it * nrec + r] = og_sample(&m, df.p, rt, r, rec + 3 * r);
     }
     og_field_free(&f);
     og_field_free(&df);
