@@ -692,13 +692,15 @@ def test_off_grid_source_matches_the_green_function(oracle):
 def test_gradient_with_off_grid_points_matches_finite_differences(oracle):
     """eq. (6)-(8) with sources and receivers off the grid: the adjoint source is injected
     with the transpose of the receivers' sampling operator, so dJ/dVp still matches central
-    differences of J (10 cells)."""
+    differences of J (10 cells).  Every operator's nodes lie in the interior: where they
+    reach into the CPML the same-solver adjoint is not the exact transpose (the level of the
+    dot-product test with CPML, 1e-4)."""
     g = small_grid(order=8, n1=44, n2=60, nt=380, nb=12, fm=15.0)
     vp, rho = smooth_random_model(g.n1, g.n2, 23, vmin=1800.0, vmax=2500.0)
     vtrue = vp.astype(np.float64).copy()
     vtrue[18:36, 14:30] *= 1.08
     sx = (np.array([14.0, 33.0, 47.0]) + 0.37) * g.d2
-    acq = I._surface_line(sx, 3.6 * g.d1, (np.arange(1, g.n2 - 1, 2) + 0.5) * g.d2, 2.3 * g.d1)
+    acq = I._surface_line(sx, 3.6 * g.d1, (np.arange(6, 54, 2) + 0.5) * g.d2, 4.3 * g.d1)
     stf = np.repeat(I.ricker(g.nt, g.dt, g.fm)[None], 3, 0)
     job = I.Job(g, vp, rho, acq, stf)
     assert oracle.shot_ops(g, acq, 0)[2] is not None and oracle.shot_ops(g, acq, 0)[3] is not None
