@@ -19,8 +19,12 @@
  *   - Every array is float32 unless stated.  Model arrays have n1*n2*n3 entries with
  *     n1 = z fastest, then x (n2), then y (n3) -- the layout of the paper's binary files
  *     (Sec. 3.5, 3.6).  In 2D set ndim = 2 and n3 = 1.
- *   - Positions are (z, x, y) in metres from interior cell 0 and must fall on grid nodes
- *     (within 1e-3 of a cell); off-grid (Kaiser-sinc) positions return SMI_E_UNSUPPORTED.
+ *   - Positions are (z, x, y) in metres from interior cell 0, inside the interior extent.
+ *     A point within 1e-3 of a spacing of a node acts on that node; any other point acts
+ *     through a Kaiser-windowed sinc of half-width order/2 per axis (Sec. 2.1; tensor product,
+ *     window parameter 2.94 for order 4 and 6.31 for order 8): sources spread
+ *     dt stf / dV w_j over the nodes j, receivers record sum_j w_j p_j, and adjoint sources are
+ *     injected with the same weights (the transpose of the sampling).
  *   - "device" pointers are HIP device memory of the context's device; "host" pointers are
  *     ordinary host memory, read during the call only.
  *   - All device work is enqueued on the caller's HIP stream (hip_stream; NULL = the null
@@ -49,7 +53,7 @@ typedef enum {
     SMI_E_DISPERSION = -3,   /* too few points per wavelength (Sec. 3.8) */
     SMI_E_WORKSPACE = -4,    /* workspace missing or smaller than smi_workspace_bytes */
     SMI_E_HIP = -5,          /* HIP runtime error */
-    SMI_E_UNSUPPORTED = -6,  /* free surface, off-grid positions, order not in {4, 8} */
+    SMI_E_UNSUPPORTED = -6,  /* free surface, order not in {4, 8}, grid too large */
     SMI_E_STATE = -7,        /* state missing, consumed, or saved without boundaries */
     SMI_E_NONFINITE = -8     /* device status: non-finite / non-positive model or field */
 } smi_status;

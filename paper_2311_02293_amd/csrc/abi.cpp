@@ -207,30 +207,32 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
     }
     int R = pl.rec_off[pl.nshot];
     if (R > 0) {
-        std::vector<long long> cell(R), obase(R);
+        std::vector<long long> obase(R);
         std::vector<int> shot(R), stride(R);
         for (int s = 0; s < pl.nshot; ++s)
             for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
-                const int *q = &pl.rec[3 * (size_t)r];
-                cell[r] = pl.cell(q[0], q[1], q[2]);
                 obase[r] = (long long)pl.g.nt * pl.rec_off[s] + (r - pl.rec_off[s]);
                 shot[r] = s;
                 stride[r] = pl.rec_off[s + 1] - pl.rec_off[s];
             }
-        HIPCHK(hipMemcpyAsync(w.recv.cell, cell.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rec");
         HIPCHK(hipMemcpyAsync(w.recv.obase, obase.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rec");
         HIPCHK(hipMemcpyAsync(w.recv.shot, shot.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rec");
         HIPCHK(hipMemcpyAsync(w.recv.stride, stride.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.toff, pl.rec_toff.data(), pl.rec_toff.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.tcell, pl.rec_tcell.data(), pl.rec_tcell.size() * sizeof(long long),
+                              hipMemcpyHostToDevice, st), "rec");
+        HIPCHK(hipMemcpyAsync(w.recv.tw, pl.rec_tw.data(), pl.rec_tw.size() * sizeof(float),
+                              hipMemcpyHostToDevice, st), "rec");
     }
     HIPCHK(hipMemcpyAsync(w.src_cell, pl.src_cell.data(), pl.nshot * sizeof(long long),
                           hipMemcpyHostToDevice, st), "src");
-    HIPCHK(hipMemcpyAsync(w.rcol_off, pl.rcol_off.data(), pl.rcol_off.size() * sizeof(int),
-                          hipMemcpyHostToDevice, st), "rcol");
-    if (R > 0) {
-        HIPCHK(hipMemcpyAsync(w.rcol_z, pl.rcol_z.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rcol");
-        HIPCHK(hipMemcpyAsync(w.rcol_out, pl.rcol_out.data(), R * sizeof(long long), hipMemcpyHostToDevice, st), "rcol");
-        HIPCHK(hipMemcpyAsync(w.rcol_stride, pl.rcol_stride.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "rcol");
-    }
+    HIPCHK(hipMemcpyAsync(w.src_toff, pl.src_toff.data(), pl.src_toff.size() * sizeof(int),
+                          hipMemcpyHostToDevice, st), "src");
+    HIPCHK(hipMemcpyAsync(w.src_tcell, pl.src_tcell.data(), pl.src_tcell.size() * sizeof(long long),
+                          hipMemcpyHostToDevice, st), "src");
+    HIPCHK(hipMemcpyAsync(w.src_tw, pl.src_tw.data(), pl.src_tw.size() * sizeof(float),
+                          hipMemcpyHostToDevice, st), "src");
     return SMI_OK;
 }
 
@@ -300,10 +302,12 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         if (fused) {
             HIPCHK(smi::fwd_step_fused(c, cur, nxt, it), "forward step");
             c.ev = nullptr;
+            if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
             if (it < nt) HIPCHK(smi::extract(c, it, dcal, nxt.p), "extract");
         } else {
             HIPCHK(smi::fwd_step(c, it), "forward step");
             c.ev = nullptr;
+            if (it < nt) HIPCHK(smi::src_taps(c, it, w.f.p, 1.f), "source");
             if (it < nt) HIPCHK(smi::extract(c, it, dcal), "extract");
         }
         for (int k = 0; k < nsnap; ++k)
@@ -367,6 +371,7 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
         c.st = ls;
         for (int it = pl.g.nt - 1; it >= 0; --it) {
             if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
+            HIPCHK(smi::src_taps(c, it, w.f.p, -1.f), "source removal");
             HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
             if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
             for (int k = 0; k < nsnap; ++k)
@@ -646,6 +651,7 @@ smi_status smi_born(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, cons
     c.plain = false;
     for (int it = 0; it < pl.g.nt; ++it) {
         HIPCHK(smi::fwd_step(c, it), "background step");
+        HIPCHK(smi::src_taps(c, it, w.f.p, 1.f), "source");
         HIPCHK(smi::born_step(c, it, dkappa), "perturbation step");
         HIPCHK(smi::extract(c, it, ddata, w.q.p), "extract");
     }

@@ -770,14 +770,32 @@ __global__ __launch_bounds__(256) void k_band_mix(Geom g, Fields f, BandDesc bd,
 
 // ---------------------------------------------------------------- receivers
 
-// dcal[it][r] = p^{it+1}[rec_r]  (Alg. 2 extract_wavefield)
+// dcal[it][r] = p^{it+1} sampled by receiver r's operator  (Alg. 2 extract_wavefield)
 __global__ __launch_bounds__(256) void k_extract(Geom g, const float *__restrict__ p, Recv rv,
                                                  float *dcal, int it, unsigned *status) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rv.R) return;
-    float v = p[rv.shot[r] * g.P + rv.cell[r]];
+    const long long so = rv.shot[r] * g.P;
+    float v = 0.f;
+    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) v += rv.tw[t] * p[so + rv.tcell[t]];
     dcal[rv.obase[r] + (long long)it * rv.stride[r]] = v;
     if (!isfinite(v)) atomicOr(status, 2u);
+}
+
+// p += sign (dt / dV) stf[s][it] w_t on the nodes of the operators of the sources that spread
+// over several nodes (blockIdx.y = shot; one-tap sources have src_cell >= 0 and are injected
+// inside the p kernels)
+__global__ __launch_bounds__(256) void k_src_taps(Geom g, float *p, const long long *__restrict__ src_cell,
+                                                  const int *__restrict__ toff,
+                                                  const long long *__restrict__ tcell,
+                                                  const float *__restrict__ tw,
+                                                  const float *__restrict__ stf, int nt, int it,
+                                                  float sign) {
+    const int s = blockIdx.y;
+    if (src_cell[s] >= 0) return;
+    const int t = toff[s] + blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= toff[s + 1]) return;
+    p[s * g.P + tcell[t]] += sign * g.src_scale * tw[t] * stf[(long long)s * nt + it];
 }
 
 __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, float *out, long long n,
@@ -786,14 +804,19 @@ __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, flo
     if (t < n) out[t] = a * in[t];
 }
 
-// p~[rec_r] += kappa(rec_r) G[it][r]  (eq. 8 source in the scaled adjoint variable)
+// p~ += kappa G[it][r] w_t on receiver r's operator nodes (eq. 8 source in the scaled adjoint
+// variable; the transpose of the sampling).  Atomic: operators of nearby receivers overlap.
 __global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *__restrict__ kdt,
                                                 Recv rv, const float *__restrict__ G, int it,
                                                 float inv_dt) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rv.R) return;
-    long long c = rv.cell[r];
-    qp[rv.shot[r] * g.P + c] += kdt[c] * inv_dt * G[rv.obase[r] + (long long)it * rv.stride[r]];
+    const float Gr = G[rv.obase[r] + (long long)it * rv.stride[r]];
+    const long long so = rv.shot[r] * g.P;
+    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) {
+        const long long c = rv.tcell[t];
+        atomicAdd(qp + so + c, kdt[c] * inv_dt * rv.tw[t] * Gr);
+    }
 }
 
 // ---------------------------------------------------------------- misfit (eq. 6)
@@ -1296,6 +1319,19 @@ hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p) {
     if (w.recv.R == 0) return hipSuccess;
     hipLaunchKernelGGL(k_extract, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom,
                        p ? p : (const float *)w.f.p, w.recv, dcal, it, w.status);
+    return hipGetLastError();
+}
+
+hipError_t src_taps(const StepCtx &c, int it, float *p, float sign) {
+    const Plan &pl = *c.pl;
+    if (!pl.src_multi) return hipSuccess;
+    const Views &w = *c.w;
+    int most = 0;
+    for (int s = 0; s < pl.nshot; ++s) most = std::max(most, pl.src_toff[s + 1] - pl.src_toff[s]);
+    hipLaunchKernelGGL(k_src_taps, dim3(blocks(most), pl.nshot), dim3(256), 0, c.st, pl.geom, p,
+                       (const long long *)w.src_cell, (const int *)w.src_toff,
+                       (const long long *)w.src_tcell, (const float *)w.src_tw, c.stf, pl.g.nt,
+                       it, sign);
     return hipGetLastError();
 }
 

@@ -4,7 +4,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <set>
 
 #include "smi_internal.hpp"
 
@@ -112,12 +111,66 @@ void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vecto
         }
 }
 
-static bool to_node(double pos, double h, int n, int nb, int &node) {
-    double q = pos / h;
-    double r = std::nearbyint(q);
-    if (std::fabs(q - r) > 1e-3) return false;
-    if (r < 0 || r > n - 1) return false;
-    node = nb + (int)r;
+// Kaiser window parameter of the windowed-sinc point operators of half-width r (Hicks' table
+// for a maximum wavenumber of half the Nyquist one); the half-width is order / 2.
+static double kaiser_b(int r) { return r == 1 ? 1.24 : r == 2 ? 2.94 : r == 3 ? 4.53 : 6.31; }
+
+static double bessel_i0(double x) {
+    double s = 1.0, t = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        t *= (x / (2.0 * k)) * (x / (2.0 * k));
+        s += t;
+        if (t < 1e-17 * s) break;
+    }
+    return s;
+}
+
+// Nodes and weights along one axis of the operator of a point at `pos` metres (interior
+// coordinates): the node itself (weight 1) when the point is within 1e-3 of a spacing of it,
+// else sinc(j - u) I0(b sqrt(1 - ((j-u)/r)^2)) / I0(b) on the 2r nodes around u, dropping
+// nodes outside the padded grid.  False when the point lies outside [0, (n-1) h].
+static bool axis_taps(double pos, double h, int n, int nb, int M, int r, int &near,
+                      std::vector<int> &nodes, std::vector<double> &w) {
+    const double q = pos / h;
+    if (!(q >= -1e-3 && q <= n - 1 + 1e-3)) return false;
+    const double u = nb + q;
+    const double j0 = std::nearbyint(u);
+    near = std::min(std::max((int)j0, nb), nb + n - 1);
+    nodes.clear();
+    w.clear();
+    if (std::fabs(u - j0) <= 1e-3) {
+        nodes.push_back(near);
+        w.push_back(1.0);
+        return true;
+    }
+    const double b = kaiser_b(r), i0b = bessel_i0(b);
+    const int base = (int)std::floor(u);
+    for (int j = base - r + 1; j <= base + r; ++j) {
+        const double x = j - u;
+        const double win = bessel_i0(b * std::sqrt(std::max(0.0, 1.0 - (x / r) * (x / r)))) / i0b;
+        if (j < 0 || j >= M) continue;
+        nodes.push_back(j);
+        w.push_back(std::sin(M_PI * x) / (M_PI * x) * win);
+    }
+    return true;
+}
+
+// Tensor-product operator of one point: appends its taps; `node` receives the nearest node.
+static bool point_taps(const Plan &pl, const double *pos, const double *hs, int *node,
+                       std::vector<long long> &cell, std::vector<float> &wt) {
+    std::vector<int> nd[3];
+    std::vector<double> ww[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a >= pl.nd) { nd[a] = {0}; ww[a] = {1.0}; node[a] = 0; continue; }
+        if (!axis_taps(pos[a], hs[a], pl.n[a], pl.g.nb, pl.M[a], pl.N, node[a], nd[a], ww[a]))
+            return false;
+    }
+    for (size_t k = 0; k < nd[2].size(); ++k)
+        for (size_t j = 0; j < nd[1].size(); ++j)
+            for (size_t i = 0; i < nd[0].size(); ++i) {
+                cell.push_back(pl.cell(nd[0][i], nd[1][j], nd[2][k]));
+                wt.push_back((float)(ww[0][i] * ww[1][j] * ww[2][k]));
+            }
     return true;
 }
 
@@ -224,57 +277,31 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     double hs[3] = {g->d1, g->d2, g->ndim == 3 ? g->d3 : 1.0};
     pl.src.assign(3 * pl.nshot, 0);
     pl.src_cell.resize(pl.nshot);
+    pl.src_toff.assign(1, 0);
+    pl.src_tcell.clear();
+    pl.src_tw.clear();
+    pl.src_multi = false;
     for (int s = 0; s < pl.nshot; ++s) {
-        for (int a = 0; a < pl.nd; ++a)
-            if (!to_node(acq->src[3 * s + a], hs[a], pl.n[a], g->nb, pl.src[3 * s + a])) {
-                err = "source " + std::to_string(s) + " is off-grid or outside the model";
-                return std::fabs(acq->src[3 * s + a] / hs[a] - std::nearbyint(acq->src[3 * s + a] / hs[a])) > 1e-3
-                           ? SMI_E_UNSUPPORTED : SMI_E_ARG;
-            }
-        pl.src_cell[s] = pl.cell(pl.src[3 * s], pl.src[3 * s + 1], pl.src[3 * s + 2]);
+        if (!point_taps(pl, &acq->src[3 * s], hs, &pl.src[3 * s], pl.src_tcell, pl.src_tw)) {
+            err = "source " + std::to_string(s) + " lies outside the model";
+            return SMI_E_ARG;
+        }
+        pl.src_toff.push_back((int)pl.src_tcell.size());
+        const bool one = pl.src_toff[s + 1] - pl.src_toff[s] == 1;
+        pl.src_cell[s] = one ? pl.src_tcell[pl.src_toff[s]] : -1;
+        pl.src_multi = pl.src_multi || !one;
     }
     pl.rec.assign(3 * (size_t)R, 0);
-    for (int s = 0; s < pl.nshot; ++s) {
-        std::set<long long> seen;
-        for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r) {
-            for (int a = 0; a < pl.nd; ++a)
-                if (!to_node(acq->rec[3 * (size_t)r + a], hs[a], pl.n[a], g->nb, pl.rec[3 * (size_t)r + a])) {
-                    err = "receiver " + std::to_string(r) + " is off-grid or outside the model";
-                    double q = acq->rec[3 * (size_t)r + a] / hs[a];
-                    return std::fabs(q - std::nearbyint(q)) > 1e-3 ? SMI_E_UNSUPPORTED : SMI_E_ARG;
-                }
-            long long c = pl.cell(pl.rec[3 * (size_t)r], pl.rec[3 * (size_t)r + 1], pl.rec[3 * (size_t)r + 2]);
-            if (!seen.insert(c).second) {
-                err = "two receivers of shot " + std::to_string(s) + " share a grid node";
-                return SMI_E_ARG;
-            }
+    pl.rec_toff.assign(1, 0);
+    pl.rec_tcell.clear();
+    pl.rec_tw.clear();
+    for (int r = 0; r < R; ++r) {
+        if (!point_taps(pl, &acq->rec[3 * (size_t)r], hs, &pl.rec[3 * (size_t)r], pl.rec_tcell,
+                        pl.rec_tw)) {
+            err = "receiver " + std::to_string(r) + " lies outside the model";
+            return SMI_E_ARG;
         }
-    }
-
-    // receivers grouped by column (x + M2 y), stable within a column
-    {
-        long long ncol = (long long)pl.M[1] * pl.M[2];
-        pl.rcol_off.assign((size_t)pl.nshot * (ncol + 1), 0);
-        pl.rcol_z.resize(R);
-        pl.rcol_out.resize(R);
-        pl.rcol_stride.resize(R);
-        for (int s = 0; s < pl.nshot; ++s) {
-            int *off = &pl.rcol_off[(size_t)s * (ncol + 1)];
-            int base = pl.rec_off[s], nr = pl.rec_off[s + 1] - base;
-            std::vector<int> cnt(ncol + 1, 0);
-            for (int r = base; r < base + nr; ++r)
-                cnt[pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2] + 1]++;
-            for (long long q = 0; q < ncol; ++q) cnt[q + 1] += cnt[q];
-            for (long long q = 0; q <= ncol; ++q) off[q] = base + cnt[q];
-            std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-            for (int r = base; r < base + nr; ++r) {
-                long long col = pl.rec[3 * (size_t)r + 1] + (long long)pl.M[1] * pl.rec[3 * (size_t)r + 2];
-                int dst = base + fill[col]++;
-                pl.rcol_z[dst] = pl.rec[3 * (size_t)r];
-                pl.rcol_out[dst] = (long long)g->nt * base + (r - base);
-                pl.rcol_stride[dst] = nr;
-            }
-        }
+        pl.rec_toff.push_back((int)pl.rec_tcell.size());
     }
 
     pl.save = job != SMI_JOB_FORWARD;
@@ -398,9 +425,10 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     for (int a = 0; a < pl.nd; ++a) cp += 4 * (size_t)pl.M[a];
     pl.off_cpml = take(sizeof(float) * cp);
     pl.off_tables = take(sizeof(int) * (pl.fbox.size() + pl.abox.size() + pl.rbox.size()));
-    pl.off_recv = take((size_t)R * (sizeof(int) * 2 + sizeof(long long) * 2) +
+    pl.off_recv = take((size_t)R * (sizeof(int) * 2 + sizeof(long long)) +
                        sizeof(long long) * (size_t)ns + 64);
-    pl.off_rcol = take(sizeof(int) * pl.rcol_off.size() + (size_t)R * (2 * sizeof(int) + sizeof(long long)) + 64);
+    pl.off_taps = take(sizeof(int) * (pl.src_toff.size() + pl.rec_toff.size()) +
+                       (sizeof(long long) + sizeof(float)) * (pl.src_tcell.size() + pl.rec_tcell.size()) + 64);
     size_t fld = sizeof(float) * (size_t)ns * ((size_t)pl.P * (1 + pl.nd) +
                  2 * (size_t)(G.psz[0] + G.psz[1] + G.psz[2]));
     pl.off_fields = take(fld);
@@ -440,20 +468,24 @@ Views views(const Plan &pl, void *ws) {
     int R = pl.rec_off[pl.nshot];
     char *r = b + pl.off_recv;
     w.recv.R = R;
-    w.recv.cell = (long long *)r;
-    w.recv.obase = (long long *)(r + sizeof(long long) * R);
-    w.recv.shot = (int *)(r + 2 * sizeof(long long) * R);
-    w.recv.stride = (int *)(r + 2 * sizeof(long long) * R + sizeof(int) * R);
-    w.src_cell = (long long *)(r + align_up(2 * (sizeof(long long) + sizeof(int)) * (size_t)R, 8));
+    w.recv.obase = (long long *)r;
+    w.recv.shot = (int *)(r + sizeof(long long) * R);
+    w.recv.stride = (int *)(r + sizeof(long long) * R + sizeof(int) * R);
+    w.src_cell = (long long *)(r + align_up((sizeof(long long) + 2 * sizeof(int)) * (size_t)R, 8));
     {
-        char *q = b + pl.off_rcol;
-        w.rcol_out = (long long *)q;
-        q += sizeof(long long) * (size_t)R;
-        w.rcol_off = (int *)q;
-        q += sizeof(int) * pl.rcol_off.size();
-        w.rcol_z = (int *)q;
-        q += sizeof(int) * (size_t)R;
-        w.rcol_stride = (int *)q;
+        // taps: cells (8-byte) first, then weights and offsets
+        char *q = b + pl.off_taps;
+        w.src_tcell = (long long *)q;
+        q += sizeof(long long) * pl.src_tcell.size();
+        w.recv.tcell = (long long *)q;
+        q += sizeof(long long) * pl.rec_tcell.size();
+        w.src_tw = (float *)q;
+        q += sizeof(float) * pl.src_tw.size();
+        w.recv.tw = (float *)q;
+        q += sizeof(float) * pl.rec_tw.size();
+        w.src_toff = (int *)q;
+        q += sizeof(int) * pl.src_toff.size();
+        w.recv.toff = (int *)q;
     }
     auto fields = [&](size_t off) {
         Fields f{};

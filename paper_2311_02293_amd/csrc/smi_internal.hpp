@@ -81,9 +81,11 @@ struct BandDesc {
 struct Recv {           // flattened receivers of all shots
     int R;
     int *shot;          // [R]
-    long long *cell;    // [R] cell offset inside one shot's field
     long long *obase;   // [R] offset of sample 0 in dcal
     int *stride;        // [R] nrec of its shot
+    int *toff;          // [R + 1] point operator of receiver r: taps toff[r] .. toff[r+1]
+    long long *tcell;   // [taps] cell offset inside one shot's field
+    float *tw;          // [taps] weight
 };
 
 // ---------------------------------------------------------------- host plan
@@ -106,11 +108,13 @@ struct Plan {
     std::vector<int> fbox;         // [nt][nshot][6] forward box (lo, hi exclusive per axis)
     std::vector<int> abox;         // [nt][nshot][6] adjoint box
     std::vector<int> rbox;         // [nt][nshot][6] reconstruction region (interior clip)
-    // receivers grouped by grid column (x, and y in 3D): CSR per shot over the M2*M3 columns
-    std::vector<int> rcol_off;     // [nshot][M2*M3 + 1]
-    std::vector<int> rcol_z;       // [R] padded z node
-    std::vector<long long> rcol_out;   // [R] dcal offset of sample 0
-    std::vector<int> rcol_stride;  // [R] samples per time step of that shot
+    // point operators of sources and receivers (Sec. 2.1): the Kaiser-windowed sinc of a
+    // point off the grid, or its node with weight 1; CSR over shots / receivers, cells are
+    // offsets inside one shot's field.  src_cell[s] is the node of a one-tap source, else -1.
+    std::vector<int> src_toff, rec_toff;
+    std::vector<long long> src_tcell, rec_tcell;
+    std::vector<float> src_tw, rec_tw;
+    bool src_multi = false;        // some source spreads over several nodes
     BandDesc band{};
     int nsave = 0;      // saved band levels k dr, k = 0 .. nsave-1
     int nrun = 0;       // forward steps: nt, or past nt until the last saved level (dr > 1)
@@ -120,7 +124,7 @@ struct Plan {
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
     size_t off_rho = 0;
-    size_t off_rcol = 0, off_fin = 0;
+    size_t off_taps = 0, off_fin = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
@@ -155,8 +159,9 @@ struct Views {
     int *fbox, *abox, *rbox;
     Recv recv;
     long long *src_cell;  // [nshot] source cell offset inside one shot's field
-    int *rcol_off, *rcol_z, *rcol_stride;   // receivers by column (see Plan)
-    long long *rcol_out;
+    int *src_toff;        // [nshot + 1] source operators (see Plan)
+    long long *src_tcell;
+    float *src_tw;
     Fields f, q;        // source field, adjoint field
     Fields f2;          // second buffer of the source field (fused, double-buffered steps)
     float *bands;       // [nshot][nsave][B]
@@ -200,6 +205,9 @@ hipError_t adj_step_y3(const StepCtx &c, int it, bool image);
 bool fused_fwd_available(const Plan &pl);
 hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it);
 hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p = nullptr);
+// p += sign dt stf[it] / dV through the operators of the sources that spread over several
+// nodes (one-tap sources are injected inside the p kernels); nothing when there are none
+hipError_t src_taps(const StepCtx &c, int it, float *p, float sign);
 hipError_t band_save(const StepCtx &c, const Fields &f, int slot);
 hipError_t band_restore(const StepCtx &c, int it, int which);
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
