@@ -59,7 +59,7 @@ class OgGrid(C.Structure):
                 ("nb", C.c_int), ("order", C.c_int), ("nt", C.c_int),
                 ("dt", C.c_double), ("fm", C.c_double), ("vmax", C.c_double),
                 ("pml", C.c_int), ("box", C.c_int), ("margin", C.c_int), ("dr", C.c_int),
-                ("band_p", C.c_int), ("band_v", C.c_int)]
+                ("band_p", C.c_int), ("band_v", C.c_int), ("freesurf", C.c_int)]
 
 
 def build(force: bool = False) -> str:
@@ -134,7 +134,7 @@ def og_grid(g, *, vmax: float, pml: int = 1, box: Optional[int] = None,
                   float(g.d1), float(g.d2), float(g.d3 if g.ndim == 3 else 1.0),
                   g.nb, g.order, g.nt, float(g.dt), float(g.fm), float(vmax), int(pml),
                   int(g.box if box is None else box), int(margin), int(getattr(g, "dr", 1)),
-                  int(band_p), int(band_v))
+                  int(band_p), int(band_v), int(getattr(g, "freesurf", 0) or 0))
 
 
 def cfl_number(g, vmax: float) -> float:

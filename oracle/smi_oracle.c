@@ -42,6 +42,7 @@ typedef struct {
     int margin;          /* box margin in cells */
     int dr;              /* boundary decimation ratio */
     int band_p, band_v;  /* saved planes per face for p and the face-normal v (0: N) */
+    int freesurf;        /* 1: free surface on the first interior row (no absorbing layer above) */
 } og_grid;
 
 typedef struct {
@@ -112,7 +113,7 @@ int og_cpml_profile(const og_grid *g, int axis, int half, double *cpa, double *c
     for (int i = 0; i < M; i++) {
         double x = i + (half ? 0.5 : 0.0);
         double dist = 0.0;
-        if (x < nb) dist = nb - x;
+        if (x < nb) dist = g->freesurf && axis == 0 ? 0.0 : nb - x;   /* no layer above a free surface */
         else if (x > nb + n - 1) dist = x - (nb + n - 1);
         double l = dist / nb;
         double damp = d0 * l * l;
@@ -288,6 +289,29 @@ static double divv(const og_model *m, const og_field *f, int i1, int i2, int i3)
 
 /* One leap-frog step of eq. (3) with CPML on the region lo..hi (inclusive):
  * all v_a first (from p^n), then p (from v^{n+1/2}).                                 */
+/* Free surface by the image method (Sec. 2.1, after Levander): the surface is the first
+ * interior row z = nb; p is odd about it (zero on it), v_z (at half rows) even.  The rows
+ * above the surface hold the mirror images, over the columns of [lo, hi].                */
+static void og_fs_v(const og_model *m, og_field *f, const int *lo, const int *hi)
+{
+    int nb = m->g.nb;
+    for (int i3 = lo[2]; i3 <= hi[2]; i3++)
+        for (int i2 = lo[1]; i2 <= hi[1]; i2++)
+            for (int k = 0; k < m->N; k++)
+                f->v[0][IDX(m, nb - 1 - k, i2, i3)] = f->v[0][IDX(m, nb + k, i2, i3)];
+}
+
+static void og_fs_p(const og_model *m, double *p, const int *lo, const int *hi)
+{
+    int nb = m->g.nb;
+    for (int i3 = lo[2]; i3 <= hi[2]; i3++)
+        for (int i2 = lo[1]; i2 <= hi[1]; i2++) {
+            p[IDX(m, nb, i2, i3)] = 0.0;
+            for (int k = 1; k <= m->N; k++)
+                p[IDX(m, nb - k, i2, i3)] = -p[IDX(m, nb + k, i2, i3)];
+        }
+}
+
 static void og_step(const og_model *m, og_field *f, const int *lo, const int *hi)
 {
     const double dt = m->g.dt;
@@ -303,6 +327,7 @@ static void og_step(const og_model *m, og_field *f, const int *lo, const int *hi
                     f->v[a][k] -= dt * m->bet[a][k] * (e + f->psp[a][k]);
                 }
     }
+    if (m->g.freesurf) og_fs_v(m, f, lo, hi);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int i3 = lo[2]; i3 <= hi[2]; i3++)
         for (int i2 = lo[1]; i2 <= hi[1]; i2++)
@@ -317,6 +342,7 @@ static void og_step(const og_model *m, og_field *f, const int *lo, const int *hi
                 }
                 f->p[k] -= dt * m->kap[k] * s;
             }
+    if (m->g.freesurf) og_fs_p(m, f->p, lo, hi);
 }
 
 /* ------------------------------------------------------------------ computing box (Sec. 4.1) */
@@ -536,6 +562,7 @@ int og_forward(const og_grid *g, const double *vp, const double *rho, const int 
         og_step(&m, &f, lo, hi);
         if (it < g->nt) {
             og_spread(&m, f.p, st, 0, src, g->dt * stf[it] / m.dV, NULL);
+            if (g->freesurf) og_fs_p(&m, f.p, lo, hi);
             for (int r = 0; r < nrec; r++)
                 dcal[(size_t)it * nrec + r] = og_sample(&m, f.p, rt, r, rec + 3 * r);
             og_take_snaps(&m, f.p, it + 1, nsnap, snap_it, snaps);
@@ -597,6 +624,9 @@ static void og_recon_iter(const og_model *m, og_field *f, const int *src, const 
                 size_t k = IDX(m, i1, i2, i3);
                 f->p[k] += dt * m->kap[k] * divv(m, f, i1, i2, i3);
             }
+    if (m->g.freesurf && lo[0] == nb)   /* p^it vanishes on the surface */
+        for (int i3 = lo[2]; i3 <= hi[2]; i3++)
+            for (int i2 = lo[1]; i2 <= hi[1]; i2++) f->p[IDX(m, nb, i2, i3)] = 0.0;
     og_restore(m, f, bands, it, 0);
     for (int a = 0; a < m->nd; a++) {
         int vhi[3] = {hi[0], hi[1], hi[2]};
@@ -700,6 +730,10 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
     for (int it = g->nt - 1; it >= 0; it--) {
         for (int r = 0; r < nrec; r++)
             og_spread(&m, q.p, rt, r, rec + 3 * r, G[(size_t)it * nrec + r], m.kap);
+        if (g->freesurf) {          /* the injected values get their images too */
+            int flo[3] = {0, 0, 0}, fhi[3] = {m.M[0] - 1, m.M[1] - 1, m.M[2] - 1};
+            og_fs_p(&m, q.p, flo, fhi);
+        }
         if (hist) og_state_set(&m, &f, hist + (size_t)(it + 1) * 4 * m.P); /* v^{it+1/2} */
         if (gk) {
 #pragma omp parallel for collapse(2) schedule(static)
@@ -766,6 +800,10 @@ int og_born(const og_grid *g, const double *vp, const double *rho, const int *sr
                     df.p[k] -= g->dt * dkap[s] * divv(&m, &f, i1 + nb, i2 + nb, j3);
                 }
         og_spread(&m, f.p, st, 0, src, g->dt * stf[it] / m.dV, NULL);
+        if (g->freesurf) {
+            og_fs_p(&m, f.p, lo, hi);
+            og_fs_p(&m, df.p, lo, hi);
+        }
         for (int r = 0; r < nrec; r++)
             ddata[(size_t)it * nrec + r] = og_sample(&m, df.p, rt, r, rec + 3 * r);
     }

@@ -237,13 +237,14 @@ def test_reciprocity(oracle, ndim):
 
 # ----------------------------------------------------------------------------- P6
 
-def _dot_case(oracle, pml, ndim=2):
+def _dot_case(oracle, pml, ndim=2, freesurf=0):
     if ndim == 2:
         g = small_grid(order=8, n1=40, n2=48, nt=220, nb=8)
         vp, rho = smooth_random_model(g.n1, g.n2, 3)
     else:
         g = small_grid(order=4, n1=18, n2=20, n3=22, nt=90, nb=4, ndim=3)
         vp, rho = smooth_random_model(g.n1, g.n2, 4, n3=g.n3)
+    g.freesurf = freesurf
     gr = oracle.og_grid(g, vmax=float(vp.max()), pml=pml)
     rng = np.random.default_rng(21)
     src = np.array([g.nb + 3, g.nb + g.n2 // 3, g.nb + 5 if ndim == 3 else 0], np.int32)
@@ -721,3 +722,98 @@ def test_gradient_with_off_grid_points_matches_finite_differences(oracle):
         fd = (J(vpl) - J(vmi)) / (2 * eps)
         worst = max(worst, abs(fd - grad[ix, iz]) / abs(grad[ix, iz]))
     assert worst <= 1e-4, worst
+
+
+# ----------------------------------------------------------------------------- free surface
+
+def test_free_surface_matches_the_image_source(oracle):
+    """Sec. 2.1 free surface (image method): in a homogeneous half-space the trace is the
+    direct wave minus the wave of the image source mirrored above the surface,
+    G(r1) - G(r2); the pressure-release sign, the surface position and the v_z symmetry all
+    enter.  Without the surface (absorbing top) the ghost is absent and the error is large."""
+    from oracle import analytic as A
+    n1, n2, nb, c, fm, dt, d = 120, 201, 20, 2000.0, 10.0, 1e-3, 10.0
+    nt = 500
+    t = (np.arange(nt) + 1) * dt
+    zs, zr, off = 100.0, 50.0, 300.0
+    r1 = math.hypot(off, zr - zs)
+    r2 = math.hypot(off, zr + zs)
+    ref = (A.green2d_trace(r1, c, t, fm, 1.2 / fm, dt, ntau=20000)
+           - A.green2d_trace(r2, c, t, fm, 1.2 / fm, dt, ntau=20000))
+    errs = []
+    for fs in (1, 0):
+        g = I.Grid(ndim=2, n1=n1, n2=n2, d1=d, d2=d, nb=nb, order=8, nt=nt, dt=dt, fm=fm,
+                   freesurf=fs)
+        vp = np.full((n2, n1), c, np.float32)
+        rho = np.full((n2, n1), 1000.0, np.float32)
+        gr = oracle.og_grid(g, vmax=c)
+        xs = 60
+        src = np.array([nb + int(zs / d), nb + xs, 0], np.int32)
+        rec = np.array([[nb + int(zr / d), nb + xs + int(off / d), 0]], np.int32)
+        out = oracle.forward(gr, vp, rho, src, I.ricker(nt, dt, fm), rec)["dcal"][:, 0]
+        errs.append(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    assert errs[0] <= 1.5e-2 and errs[1] >= 0.3, errs
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_free_surface_reconstruction_is_exact(oracle, ndim):
+    """Sec. 4.2 with a free surface: the bands above the surface are the mirror images and the
+    rebuilt p vanishes on the surface, so the reconstruction is still exact."""
+    if ndim == 2:
+        g = small_grid(order=8, n1=40, n2=50, nt=260, nb=10)
+        vp, rho = smooth_random_model(g.n1, g.n2, 51)
+        src = np.array([g.nb + 3, g.nb + 25, 0], np.int32)
+    else:
+        g = small_grid(order=4, n1=18, n2=20, n3=20, nt=100, nb=5, ndim=3)
+        vp, rho = smooth_random_model(g.n1, g.n2, 52, n3=g.n3)
+        src = np.array([g.nb + 2, g.nb + 10, g.nb + 9], np.int32)
+    g.freesurf = 1
+    gr = oracle.og_grid(g, vmax=float(vp.max()))
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    levels = list(range(0, g.nt + 1, 9)) + [g.nt]
+    fw = oracle.forward(gr, vp, rho, src, stf, src[None], bands=True, final=True, snaps=levels)
+    rc = oracle.reconstruct(gr, vp, rho, src, stf, fw["bands"], fw["final"], levels)
+    err = np.max(np.linalg.norm(rc - fw["snaps"], axis=1)) / np.max(np.linalg.norm(fw["snaps"], axis=1))
+    assert err <= 1e-13, err
+    assert np.max(np.abs(fw["snaps"][-1].reshape(vp.shape)[..., 0])) == 0.0   # p = 0 on the surface
+
+
+def test_free_surface_gradient_matches_finite_differences(oracle):
+    """eq. (6)-(8) with a free surface: the same-solver adjoint with the same mirroring is the
+    transpose of the forward map; dJ/dVp against central differences on 10 cells."""
+    g = small_grid(order=8, n1=40, n2=56, nt=360, nb=12, fm=15.0)
+    g.freesurf = 1
+    vp, rho = smooth_random_model(g.n1, g.n2, 53, vmin=1800.0, vmax=2500.0)
+    vtrue = vp.astype(np.float64).copy()
+    vtrue[14:34, 12:26] *= 1.08
+    sx = np.array([12.0, 28.0, 44.0]) * g.d2
+    acq = I._surface_line(sx, 3 * g.d1, np.arange(2, g.n2 - 2, 2) * g.d2, 1 * g.d1)
+    stf = np.repeat(I.ricker(g.nt, g.dt, g.fm)[None], 3, 0)
+    job = I.Job(g, vp, rho, acq, stf)
+    vmax = 2800.0
+    dobs = oracle.forward_job(job, vp=vtrue, vmax=vmax)
+    grad, _ = oracle.fwi_grad(job, dobs, vmax=vmax)
+    grad_h, _ = oracle.fwi_grad(job, dobs, vmax=vmax, use_history=True)
+    assert np.max(np.abs(grad - grad_h)) <= 1e-10 * np.max(np.abs(grad_h))
+
+    def J(v):
+        d = oracle.forward_job(job, vp=v, vmax=vmax)
+        return sum(oracle.misfit(d[s], dobs[s], g.dt)[0] for s in range(3))
+    worst = 0.0
+    for ix, iz in _fd_cells(g, grad, 10, 91):
+        eps = 1e-4 * float(vp[ix, iz])
+        a = vp.astype(np.float64).copy()
+        a[ix, iz] += eps
+        b = vp.astype(np.float64).copy()
+        b[ix, iz] -= eps
+        fd = (J(a) - J(b)) / (2 * eps)
+        worst = max(worst, abs(fd - grad[ix, iz]) / abs(grad[ix, iz]))
+    assert worst <= 1e-4, worst
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_dot_product_with_free_surface_is_exact(oracle, ndim):
+    """<L dk, d> = <dk, L* d> with the image-method surface (no absorption elsewhere): the
+    adjoint sources near the surface receive their images like the forward sources, and the
+    same solver is then the exact transpose."""
+    assert _dot_case(oracle, 0, ndim, freesurf=1) <= 1e-12
