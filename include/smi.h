@@ -53,7 +53,7 @@ typedef enum {
     SMI_E_DISPERSION = -3,   /* too few points per wavelength (Sec. 3.8) */
     SMI_E_WORKSPACE = -4,    /* workspace missing or smaller than smi_workspace_bytes */
     SMI_E_HIP = -5,          /* HIP runtime error */
-    SMI_E_UNSUPPORTED = -6,  /* free surface, order not in {4, 8}, grid too large */
+    SMI_E_UNSUPPORTED = -6,  /* order not in {4, 8}, grid too large */
     SMI_E_STATE = -7,        /* state missing, consumed, or saved without boundaries */
     SMI_E_NONFINITE = -8     /* device status: non-finite / non-positive model or field */
 } smi_status;
@@ -77,7 +77,9 @@ typedef struct {
     double d1, d2, d3;       /* spacing [m] */
     int nb;                  /* absorbing (CPML) layers per side, >= order/2 */
     int order;               /* spatial order 2N: 4 or 8 */
-    int freesurf;            /* must be 0 (free surface not provided) */
+    int freesurf;            /* 1: free surface (p = 0) on the first interior row z = 0, by the
+                                image method (Sec. 2.1): p odd and v_z even about it, no CPML
+                                above; 0: absorbing on all sides */
     int nt;                  /* time steps */
     double dt;               /* time step [s] */
     double fm;               /* wavelet centre frequency [Hz]: CPML alpha, dispersion check */
@@ -107,7 +109,11 @@ typedef enum {
                                 double-buffered levels); 3: register-blocked kernels with
                                 SMI_OPT_CHUNK = 2, 4 or 8 cells per lane along the slowest
                                 axis and the order of SMI_OPT_TILEMAP; 4: batched one-cell-per-
-                                lane sweep kernels in the order of SMI_OPT_TILEMAP */
+                                lane sweep kernels in the order of SMI_OPT_TILEMAP; 5: as 0, and
+                                in 3D half steps that march along y (SMI_OPT_CHUNK = 100 BX + CY:
+                                BX = 4 or 8 x-columns of 64 z cells per wavefront, CY = 16,
+                                32 or 64 y-planes per workgroup, 32 at order 4; 0: 832).  With a free surface, 2 and the y-marching
+                                kernels of 5 give way to the kernels of 0. */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and
                                 buffers) and replayed on later calls; up to 8 graphs are kept

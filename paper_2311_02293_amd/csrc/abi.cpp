@@ -79,7 +79,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     } else if (ctx->opt_kernel == 5) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
-        c.y3 = pl.nd == 3 ? (ctx->opt_chunk > 0 ? ctx->opt_chunk : 832) : 0;
+        c.y3 = smi::y3_available(pl) ? (ctx->opt_chunk > 0 ? ctx->opt_chunk : 832) : 0;
     }
 }
 

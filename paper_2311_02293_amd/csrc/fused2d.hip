@@ -196,7 +196,8 @@ __global__ __launch_bounds__(256) void k_fused2d(Geom g, Fields src, Fields dst,
 
 }  // namespace
 
-bool fused_fwd_available(const Plan &pl) { return pl.nd == 2 && pl.dbuf; }
+// (not with a free surface: its mirror images would be needed between the v and p updates)
+bool fused_fwd_available(const Plan &pl) { return pl.nd == 2 && pl.dbuf && !pl.g.freesurf; }
 
 hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it) {
     const Plan &pl = *c.pl;

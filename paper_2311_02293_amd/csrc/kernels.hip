@@ -1029,6 +1029,26 @@ __global__ __launch_bounds__(256) void k_finalize_family(Geom g, const float *__
     }
 }
 
+// Free surface by the image method (Sec. 2.1): the surface is the first interior row z = nb,
+// and the rows above it hold mirror images.  mode 0 (v_z, at half rows): even, row nb-1-k =
+// row nb+k for k < N; mode 1 (p): odd, row nb = 0 and row nb-k = -(row nb+k) for k = 1..N;
+// mode 2: row nb of p = 0 only.  One lane per column (x, y) of the padded plane, blockIdx.y =
+// shot - shot0.  nb >= N keeps every row inside the padded grid.
+__global__ __launch_bounds__(256) void k_free_surface(Geom g, float *f, int shot0, int mode) {
+    const long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (col >= (long long)g.M[1] * g.M[2]) return;
+    const int x = (int)(col % g.M[1]), y = (int)(col / g.M[1]);
+    float *c = f + (long long)(shot0 + (int)blockIdx.y) * g.P + g.org + g.nb +
+               (long long)g.ld1 * x + g.ld2 * y;
+    if (mode == 0) {
+        for (int k = 0; k < g.N; ++k) c[-1 - k] = c[k];
+        return;
+    }
+    c[0] = 0.f;
+    if (mode == 1)
+        for (int k = 1; k <= g.N; ++k) c[-k] = -c[k];
+}
+
 // interior p of every shot -> snaps[s][k][...]
 __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
                                               int k, int nsnap) {
@@ -1044,6 +1064,20 @@ __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ 
 }
 
 unsigned blocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+#define SMI_TRY(x)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return e_;                                                  \
+    } while (0)
+
+// mirror images of a free surface over the shots [s0, s1) (nothing without one)
+hipError_t fs_launch(const Plan &pl, hipStream_t st, float *f, int mode, int s0, int s1) {
+    if (!pl.g.freesurf || s1 <= s0) return hipSuccess;
+    hipLaunchKernelGGL(k_free_surface, dim3(blocks((long long)pl.M[1] * pl.M[2]), s1 - s0),
+                       dim3(256), 0, st, pl.geom, f, s0, mode);
+    return hipGetLastError();
+}
 
 // launch geometry of one step over a box table row: max extents over the shots [s0, s1)
 struct Launch {
@@ -1137,18 +1171,21 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     if (c.ev) {
         hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
                               0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg);
+        SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
         hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                               (const float *)nullptr, (float *)nullptr);
-        return hipGetLastError();
+        return fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
     }
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
                        w.cpml, box, 0, L.mg);
+    SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
     hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
                        pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
 }
 
 // adjoint half steps with the marching kernels (image with the source field when asked)
@@ -1161,6 +1198,7 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, ab, 0, L.mg);
+    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
     if (image)
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                            w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
@@ -1170,7 +1208,8 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
                            pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
                            (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                            (const float *)w.f.p, w.acc_i);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
 }
 
 template <int ND, int N>
@@ -1195,17 +1234,21 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
             // timed step: the device stamps the events at each kernel's start and end
             hipExtLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
                                   0, pl.geom, w.f, w.model, w.cpml, box, s0, L.ey);
+            SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, s0, s1));
             hipExtLaunchKernelGGL((k_step_p<ND, N, true, false>), L.grid, L.block, 0, c.st,
                                   c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, s0,
                                   L.ey, (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                                   (const float *)nullptr, (float *)nullptr);
+            SMI_TRY(fs_launch(pl, c.st, w.f.p, 1, s0, s1));
             continue;
         }
         hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
                            w.cpml, box, s0, L.ey);
+        SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, s0, s1));
         hipLaunchKernelGGL((k_step_p<ND, N, true, false>), L.grid, L.block, 0, c.st, pl.geom,
                            w.f, w.model, w.cpml, box, s0, L.ey, (const long long *)w.src_cell,
                            c.stf, pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
+        SMI_TRY(fs_launch(pl, c.st, w.f.p, 1, s0, s1));
     }
     return hipGetLastError();
 }
@@ -1227,6 +1270,7 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
         else if (image) SMI_MRECON_P(false, true);
         else SMI_MRECON_P(false, false);
 #undef SMI_MRECON_P
+        SMI_TRY(fs_launch(pl, c.st, w.f.p, 2, 0, pl.nshot));   // p^it vanishes on a free surface
     }
     hipError_t e = band_restore(c, it, 0);
     if (e != hipSuccess) return e;
@@ -1264,6 +1308,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
         else if (image) SMI_RECON_P(false, true);
         else SMI_RECON_P(false, false);
 #undef SMI_RECON_P
+        SMI_TRY(fs_launch(pl, c.st, w.f.p, 2, s0, s1));   // p^it vanishes on a free surface
     }
     hipError_t e = band_restore(c, it, 0);
     if (e != hipSuccess) return e;
@@ -1283,6 +1328,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
         if (L.empty) continue;
         hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                            w.cpml, ab, s0, L.ey);
+        SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
         if (image)
             hipLaunchKernelGGL((k_step_p<ND, N, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                                w.q, w.model, w.cpml, ab, s0, L.ey, (const long long *)w.src_cell,
@@ -1292,6 +1338,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
                                pl.geom, w.q, w.model, w.cpml, ab, s0, L.ey,
                                (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                                (const float *)w.f.p, w.acc_i);
+        SMI_TRY(fs_launch(pl, c.st, w.q.p, 1, s0, s1));
     }
     return hipGetLastError();
 }
@@ -1332,6 +1379,9 @@ hipError_t src_taps(const StepCtx &c, int it, float *p, float sign) {
                        (const long long *)w.src_cell, (const int *)w.src_toff,
                        (const long long *)w.src_tcell, (const float *)w.src_tw, c.stf, pl.g.nt,
                        it, sign);
+    // an injection on a free-surface grid is followed by the images of what it added (the
+    // removal in the reconstruction is not: the rows above the surface come from the bands)
+    if (sign > 0.f) SMI_TRY(fs_launch(pl, c.st, p, 1, 0, pl.nshot));
     return hipGetLastError();
 }
 
@@ -1415,6 +1465,9 @@ hipError_t adj_inject(const StepCtx &c, int it, const float *G) {
     if (w.recv.R == 0) return hipSuccess;
     hipLaunchKernelGGL(k_inject, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom, w.q.p,
                        (const float *)w.model.kdt, w.recv, G, it, (float)(1.0 / c.pl->g.dt));
+    // the injected adjoint sources get their images too (the transpose of the sampling of a
+    // mirrored field)
+    SMI_TRY(fs_launch(*c.pl, c.st, w.q.p, 1, 0, c.pl->nshot));
     return hipGetLastError();
 }
 
@@ -1460,12 +1513,14 @@ hipError_t born_step_t(const StepCtx &c, int it, const float *dkappa) {
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, box, 0, L.ey);
+    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
     hipLaunchKernelGGL((k_step_p<ND, N, false, false>), L.grid, L.block, 0, c.st, pl.geom, w.q,
                        w.model, w.cpml, box, 0, L.ey, (const long long *)w.src_cell, c.stf,
                        pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
     hipLaunchKernelGGL((k_born_src<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.q, box, 0,
                        L.ey, dkappa);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
 }
 
 hipError_t born_step(const StepCtx &c, int it, const float *dkappa) {

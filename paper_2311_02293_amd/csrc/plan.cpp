@@ -44,7 +44,7 @@ smi_status check_grid(const smi_grid *g, double vmin, double vmax, std::string &
         err = "order must be 4 or 8";
         return SMI_E_UNSUPPORTED;
     }
-    if (g->freesurf) { err = "free surface is not provided"; return SMI_E_UNSUPPORTED; }
+    if (g->freesurf != 0 && g->freesurf != 1) { err = "freesurf must be 0 or 1"; return SMI_E_ARG; }
     if (g->n1 < 1 || g->n2 < 1 || (g->ndim == 3 ? g->n3 < 1 : g->n3 != 1)) {
         err = "bad n1/n2/n3";
         return SMI_E_ARG;
@@ -101,7 +101,9 @@ void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vecto
     for (int half = 0; half < 2; ++half)
         for (int i = 0; i < M; ++i) {
             double x = i + 0.5 * half;
-            double dist = x < nb ? nb - x : (x > nb + n - 1 ? x - (nb + n - 1) : 0.0);
+            // no layer above a free surface (the rows there hold its mirror images)
+            double top = g.freesurf && axis == 0 ? 0.0 : nb - x;
+            double dist = x < nb ? top : (x > nb + n - 1 ? x - (nb + n - 1) : 0.0);
             double l = dist / nb;
             double dd = d0 * l * l, al = M_PI * g.fm * (1.0 - l);
             double b = std::exp(-(dd + al) * g.dt);

@@ -321,7 +321,8 @@ hipError_t adj_y3_t(const StepCtx &c, int it, bool image) {
 
 }  // namespace
 
-bool y3_available(const Plan &pl) { return pl.nd == 3; }
+// (not with a free surface, whose mirror images the y-marching kernels do not write)
+bool y3_available(const Plan &pl) { return pl.nd == 3 && !pl.g.freesurf; }
 
 hipError_t fwd_step_y3(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;

@@ -572,3 +572,117 @@ def test_off_grid_source_in_the_fused_step(ctx):
     finally:
         ctx.set_option(B.OPT_KERNEL, 0)
     assert rel_l2(got.cpu().numpy(), ref.cpu().numpy()) <= 1e-6
+
+
+def _free_surface_job(ndim, dr=1):
+    """Sources and receivers two cells below a free surface (Sec. 2.1 image method)."""
+    if ndim == 2:
+        job = _grad_job(nt=500, nshot=2)
+        job.grid.dr = dr
+    else:
+        job = with_bounds(I.config4(n=32, nt=180, nshot=1, dr=dr, rec_step=4))
+        job.grid.vpmax = float(max(job.grid.vpmax, np.max(job.extra["vp_true"])))
+    job.grid.freesurf = 1
+    return job
+
+
+@pytest.mark.parametrize("ndim,dr", [(2, 1), (3, 1), (2, 3)])
+def test_free_surface_forward_gradient_and_image_match_oracle(ctx, ndim, dr):
+    """Free surface: seismograms, the kappa and density gradients (family 1) and the RTM
+    image against the oracle (mirror images after every update and every injection, no
+    absorbing layer above, p = 0 on the surface in the reconstruction); decimated bands too."""
+    from oracle import oracle as O
+    import torch
+    job = _free_surface_job(ndim, dr)
+    vmax = float(job.grid.vpmax)
+    say("free surface", ndim, "dr", dr, job.grid)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    got = split(dcal, job)
+    ref = O.forward_job(job, vmax=vmax, box=0)
+    for s in range(job.acq.nshot):
+        e = rel_l2(got[s], ref[s])
+        say("free-surface forward", s, e)
+        assert e <= 1e-4
+    # the surface matters: the same job without it differs by far more than the tolerance
+    import copy
+    g0 = copy.copy(job.grid)
+    g0.freesurf = 0
+    d0, _, _ = ctx.forward(g0, job.acq, vp, rho, stf)
+    assert rel_l2(split(d0, job)[0], ref[0]) > 0.1
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    r1, r2, rJ = O.fwi_grad_family(job, dobs, 1, vmax=vmax, box=0)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    g1, g2, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs_t, rho_grad=True)
+    g1 = g1.cpu().numpy().reshape(job.vp.shape)
+    g2 = g2.cpu().numpy().reshape(job.vp.shape)
+    say("free-surface gradient", rel_l2(g1, r1), rel_l2(g2, r2), float(J.cpu()[0]), rJ)
+    assert abs(float(J.cpu()[0]) - rJ) <= 1e-4 * rJ
+    assert rel_l2(g1, r1) <= 1e-4
+    assert rel_l2(g2, r2) <= 1e-4
+    ims, ils = O.rtm_image(job, dobs, vmax=vmax, box=0, per_shot=True)
+    im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    ei = rel_l2(im.cpu().numpy().reshape(job.vp.shape), np.sum(ims, 0))
+    el = rel_l2(il.cpu().numpy().reshape(job.vp.shape), np.sum(ils, 0))
+    say("free-surface image", ei, el)
+    assert ei <= 1e-4 and el <= 1e-4
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 4, 5])
+def test_free_surface_in_every_kernel_choice(ctx, kernel):
+    """Plain, sweep and register-blocked kernels agree with a free surface; the fused 2D
+    step and the y-marching 3D kernels give way to the default kernels."""
+    from paper_2311_02293_amd import binding as B
+    job = _free_surface_job(3 if kernel == 5 else 2)
+    vp, rho, stf = dev(job)
+    ref, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    ctx.set_option(B.OPT_KERNEL, kernel)
+    try:
+        got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+    e = rel_l2(got.cpu().numpy(), ref.cpu().numpy())
+    say("free surface kernel", kernel, e)
+    assert e <= 1e-6
+
+
+def test_free_surface_born_and_off_grid_match_oracle(ctx):
+    """Born data with a free surface; off-grid sources and receivers whose windowed-sinc
+    taps reach above the surface (injected there, then overwritten by the images)."""
+    from oracle import oracle as O
+    import torch
+    job = _off_grid(_free_surface_job(2), dz=-0.63)
+    assert O.shot_ops(job.grid, job.acq, 0)[2] is not None
+    vmax = float(job.grid.vpmax)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    got = split(dcal, job)
+    ref = O.forward_job(job, vmax=vmax, box=0)
+    for s in range(job.acq.nshot):
+        e = rel_l2(got[s], ref[s])
+        say("free-surface off-grid forward", s, e)
+        assert e <= 1e-4
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    ref_g, ref_J = O.fwi_grad(job, dobs, vmax=vmax, box=0)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs_t)
+    eg = rel_l2(g.cpu().numpy().reshape(job.vp.shape), ref_g)
+    say("free-surface off-grid gradient", eg)
+    assert abs(float(J.cpu()[0]) - ref_J) <= 1e-4 * ref_J
+    assert eg <= 1e-4
+    kap = job.rho.astype(np.float64) * job.vp.astype(np.float64) ** 2
+    dk = np.zeros_like(kap)
+    sl = (slice(70, 90), slice(10, 25))     # x, z: shallow, between the two shots
+    dk[sl] = 0.05 * kap[sl]
+    gr = O.og_grid(job.grid, vmax=vmax, box=0)
+    dd = ctx.born(job.grid, job.acq, vp, rho, stf,
+                  torch.from_numpy(dk.astype(np.float32).ravel()).cuda())
+    from paper_2311_02293_amd import binding as B
+    gotb = [d.cpu().numpy() for d in B.split_dcal(dd, job.acq, job.grid.nt)]
+    for s in range(job.acq.nshot):
+        src, rec, st, rt = O.shot_ops(job.grid, job.acq, s)
+        refb = O.born(gr, job.vp, job.rho, src, job.stf[s], rec, dk, st, rt)
+        e = rel_l2(gotb[s], refb)
+        say("free-surface born", s, e, np.abs(refb).max())
+        assert np.abs(refb).max() > 1e-3 * np.abs(dobs[s]).max()
+        assert e <= 1e-4

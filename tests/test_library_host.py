@@ -41,8 +41,10 @@ def test_check_cfl_and_dispersion():
     g.order = 6
     assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -6
     g.order = 4
-    g.freesurf = 1
-    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -6
+    g.freesurf = 1          # Sec. 2.1 free surface: accepted
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == 0
+    g.freesurf = 2
+    assert L.smi_check(None, C.byref(g), 1500.0, 2500.0) == -1
 
 
 @pytest.mark.parametrize("cfg", ["config2", "config3"])
