@@ -120,9 +120,9 @@ typedef enum {
                                 per context (default 0).  Not combined with SMI_OPT_TIMING. */
     SMI_OPT_CHUNK = 2,       /* tuning.  SMI_OPT_KERNEL 3: cells per lane (2, 4, 8; else 4),
                                 plus 100 to take the z-neighbours from LDS.
-                                SMI_OPT_KERNEL 2: 1000 (2 order + t2) + L, with L the columns
-                                marched by one wavefront, t2 = 1 for 2-column chunks and order
-                                0/1/2 the workgroup order (0: default 16) */
+                                SMI_OPT_KERNEL 2: 4 or 8 columns per lane (else 4); plus 100:
+                                the tiled variant (64 rows x 4 C columns per workgroup, p and
+                                the new v staged in LDS) */
     SMI_OPT_TIMING = 3,      /* S > 0: every S-th forward time step of the batched kernels
                                 is launched with device-stamped start / stop events (read with
                                 smi_kernel_timing); 0: off (default).  Setting it clears the

@@ -68,7 +68,8 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
     } else if (ctx->opt_kernel == 2) {
-        c.march = ctx->opt_chunk == 8 ? 8 : 4;
+        c.march = ctx->opt_chunk % 100 == 8 ? 8 : 4;
+        c.zl = ctx->opt_chunk >= 100;   // the tiled variant of the fused step
     } else if (ctx->opt_kernel == 3) {
         const int cm = ctx->opt_chunk % 100;
         c.march = cm == 2 || cm == 8 ? cm : 4;
@@ -276,6 +277,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     }
     const int nt = pl.g.nt, dr = pl.g.dr;
     const bool timed = ctx->opt_timing > 0 && !c.plain;
+    const bool defer = !fused && smi::march_forward(c);
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
     auto loop = [&](hipStream_t ls) -> smi_status {
     c.st = ls;
@@ -305,15 +307,27 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
             if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
             if (it < nt) HIPCHK(smi::extract(c, it, dcal, nxt.p), "extract");
         } else {
+            // the register-blocked kernels sample the receivers of step it inside the v launch
+            // of step it + 1 (the v update leaves p alone); the last one is sampled below
             HIPCHK(smi::fwd_step(c, it), "forward step");
             c.ev = nullptr;
+            c.ext_it = -1;
             if (it < nt) HIPCHK(smi::src_taps(c, it, w.f.p, 1.f), "source");
-            if (it < nt) HIPCHK(smi::extract(c, it, dcal), "extract");
+            if (it < nt && defer) {
+                c.ext_it = it;
+                c.ext_dcal = dcal;
+            } else if (it < nt) {
+                HIPCHK(smi::extract(c, it, dcal), "extract");
+            }
         }
         for (int k = 0; k < nsnap; ++k)
             if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
         if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
             HIPCHK(hipMemcpyAsync(w.fin, w.f.p, state_bytes, hipMemcpyDeviceToDevice, ls), "final copy");
+    }
+    if (c.ext_it >= 0) {
+        HIPCHK(smi::extract(c, c.ext_it, dcal), "extract");
+        c.ext_it = -1;
     }
     if (fused && (pl.nrun & 1)) {
         // the final level is in the second buffer; the reverse pass works on the first

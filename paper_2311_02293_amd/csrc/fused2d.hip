@@ -194,6 +194,192 @@ __global__ __launch_bounds__(256) void k_fused2d(Geom g, Fields src, Fields dst,
     }
 }
 
+// Tiled variant: a workgroup owns a tile of 64 rows x TX = 4 CW columns; its four wavefronts
+// stage p^n over the tile plus a halo of H = 2N - 1 nodes along each axis (a plus-shaped
+// region: the corners are never read) in LDS, form v_z^{n+1/2} over the tile's columns on
+// rows z0-N .. z0+63+N-1 and v_x^{n+1/2} over the tile's rows on columns lo-N .. lo+TX+N-2
+// (both staged in LDS), then p^{n+1} on the tile.  Every global load of phase 1 is issued
+// before any arithmetic, and each halo value is loaded once per tile (neighbouring tiles
+// share it through L2); the 8 XCDs take contiguous ranges of column tiles.
+template <int N, int CW>
+__global__ __launch_bounds__(256) void k_fused2d_tile(Geom g, Fields src, Fields dst, Model m,
+                                                      Cpml cp, const int *__restrict__ box,
+                                                      int nxc,
+                                                      const long long *__restrict__ src_cell,
+                                                      const float *__restrict__ stf, int nt,
+                                                      int it) {
+    constexpr int H = 2 * N - 1;
+    constexpr int TX = 4 * CW;
+    constexpr int RP = 64 + 2 * H;      // staged p rows: z0-H .. z0+63+H
+    constexpr int CP = TX + 2 * H;      // staged p columns: lo-H .. lo+TX-1+H
+    constexpr int RV = 64 + 2 * N - 1;  // v_z rows: z0-N .. z0+63+N-1
+    constexpr int CV = TX + 2 * N - 1;  // v_x columns: lo-N .. lo+TX+N-2
+    constexpr int QP = (2 * H + 3) / 4; // p halo columns per wavefront
+    constexpr int QV = (2 * N - 1 + 3) / 4;  // v_x halo columns per wavefront
+    __shared__ float sp[CP][RP];
+    __shared__ float svz[TX][RV];
+    __shared__ float svx[CV][64];
+
+    const int lane = threadIdx.x, wv = threadIdx.y;
+    const int xcd = (int)blockIdx.x & 7;
+    const int bz = (int)blockIdx.x >> 3;
+    const int s = (int)blockIdx.z;
+    const int *b = box + 6 * s;
+    const int b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+    const int z0 = zalign(b0) + bz * 64;
+    const int lo = b2 + (xcd * nxc + (int)blockIdx.y) * TX;
+    if (lo >= b3 || z0 >= b1) return;                 // uniform over the workgroup
+    const int z = z0 + lane;
+    const int ld1 = g.ld1;
+    const long long so = (long long)s * g.P;
+    const float *__restrict__ P0 = src.p + so;
+    const float *__restrict__ VZ0 = src.v[0] + so;
+    const float *__restrict__ VX0 = src.v[1] + so;
+    const float *__restrict__ BZ = m.bdt[0];
+    const float *__restrict__ BX = m.bdt[1];
+    auto cell = [&](int zz, int xx) -> long long { return g.org + zz + (long long)ld1 * xx; };
+    auto inp = [&](int zz, int xx) { return zz >= b0 - H && zz < b1 + H && xx >= b2 - H && xx < b3 + H; };
+    auto inb = [&](int zz, int xx) { return zz >= b0 && zz < b1 && xx >= b2 && xx < b3; };
+
+    // ---- phase 1: loads
+    const int hr = lane < H ? z0 - H + lane : z0 + 64 + lane - H;   // p halo row (lane < 2H)
+    const int vr = lane < N ? z0 - N + lane : z0 + 64 + lane - N;   // v_z extra row (lane < 2N-1)
+    float pc[CW], ph[CW], vzc[CW], bzc[CW], vzh[CW], bzh[CW], vxc[CW], bxc[CW], kd[CW];
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+        const int x = lo + wv * CW + t;
+        const long long k = cell(z, x);
+        pc[t] = inp(z, x) ? P0[k] : 0.f;
+        const bool own = inb(z, x);
+        vzc[t] = own ? VZ0[k] : 0.f;
+        bzc[t] = own ? BZ[k] : 0.f;
+        vxc[t] = own ? VX0[k] : 0.f;
+        bxc[t] = own ? BX[k] : 0.f;
+        kd[t] = own ? m.kdt[k] : 0.f;
+        ph[t] = lane < 2 * H && inp(hr, x) ? P0[cell(hr, x)] : 0.f;
+        const bool hv = lane < 2 * N - 1 && inb(vr, x);
+        vzh[t] = hv ? VZ0[cell(vr, x)] : 0.f;
+        bzh[t] = hv ? BZ[cell(vr, x)] : 0.f;
+    }
+    float pq[QP];
+#pragma unroll
+    for (int q = 0; q < QP; ++q) {
+        const int j = wv + 4 * q;
+        const int x = j < H ? lo - H + j : lo + TX + j - H;
+        pq[q] = j < 2 * H && inp(z, x) ? P0[cell(z, x)] : 0.f;
+    }
+    float vxq[QV], bxq[QV];
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+        const int j = wv + 4 * q;
+        const int x = j < N ? lo - N + j : lo + TX + j - N;
+        const bool ok = j < 2 * N - 1 && inb(z, x);
+        vxq[q] = ok ? VX0[cell(z, x)] : 0.f;
+        bxq[q] = ok ? BX[cell(z, x)] : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+        sp[H + wv * CW + t][H + lane] = pc[t];
+        if (lane < 2 * H) sp[H + wv * CW + t][lane < H ? lane : 64 + lane] = ph[t];
+    }
+#pragma unroll
+    for (int q = 0; q < QP; ++q) {
+        const int j = wv + 4 * q;
+        if (j < 2 * H) sp[j < H ? j : TX + j][H + lane] = pq[q];
+    }
+    __syncthreads();
+
+    // ---- phase 2: v^{n+1/2}
+    // v_z at row r of tile column c (LDS column H + c of sp); own: store the CPML variable
+    auto vz_new = [&](int r, int c, float vold, float bdz, bool own) -> float {
+        const int x = lo + c;
+        if (!inb(r, x)) return vold;
+        const int i = r - z0 + H;
+        float e = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) e += g.c[0][l - 1] * (sp[H + c][i + l] - sp[H + c][i - l + 1]);
+        const int zc = slab_index(r, g.M[0], g.nb);
+        if (zc >= 0) {
+            const long long q = (long long)s * g.psz[0] + zc + (long long)g.W * x;
+            const float psi = cp.b_h[0][r] * src.psp[0][q] + cp.a_h[0][r] * e;
+            if (own) dst.psp[0][q] = psi;
+            e += psi;
+        }
+        return vold - bdz * e;
+    };
+    // v_x at column x (LDS column x - lo + H of sp) on this lane's row
+    auto vx_new = [&](int x, float vold, float bdx, bool own) -> float {
+        if (!inb(z, x)) return vold;
+        const int ci = x - lo + H;
+        float e = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) e += g.c[1][l - 1] * (sp[ci + l][H + lane] - sp[ci - l + 1][H + lane]);
+        const int xc = slab_index(x, g.M[1], g.nb);
+        if (xc >= 0) {
+            const long long q = (long long)s * g.psz[1] + z + (long long)ld1 * xc;
+            const float psi = cp.b_h[1][x] * src.psp[1][q] + cp.a_h[1][x] * e;
+            if (own) dst.psp[1][q] = psi;
+            e += psi;
+        }
+        return vold - bdx * e;
+    };
+    float vzn[CW], vxn[CW];
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+        const int c = wv * CW + t;
+        vzn[t] = vz_new(z, c, vzc[t], bzc[t], true);
+        svz[c][N + lane] = vzn[t];
+        if (lane < 2 * N - 1)
+            svz[c][lane < N ? lane : 64 + lane] = vz_new(vr, c, vzh[t], bzh[t], false);
+        vxn[t] = vx_new(lo + c, vxc[t], bxc[t], true);
+        svx[N + c][lane] = vxn[t];
+    }
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+        const int j = wv + 4 * q;
+        if (j < 2 * N - 1) {
+            const int x = j < N ? lo - N + j : lo + TX + j - N;
+            svx[j < N ? j : TX + j][lane] = vx_new(x, vxq[q], bxq[q], false);
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: p^{n+1} on the owned cells; store the owned v
+    const long long sc = src_cell[s];
+    const int zc = slab_index(z, g.M[0], g.nb);
+#pragma unroll
+    for (int t = 0; t < CW; ++t) {
+        const int c = wv * CW + t;
+        const int x = lo + c;
+        if (!inb(z, x)) continue;
+        const long long k = cell(z, x);
+        float ez = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) ez += g.c[0][l - 1] * (svz[c][lane + N + l - 1] - svz[c][lane + N - l]);
+        if (zc >= 0) {
+            const long long q = (long long)s * g.psz[0] + zc + (long long)g.W * x;
+            const float psi = cp.b_i[0][z] * src.psv[0][q] + cp.a_i[0][z] * ez;
+            dst.psv[0][q] = psi;
+            ez += psi;
+        }
+        float ex = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) ex += g.c[1][l - 1] * (svx[N + c + l - 1][lane] - svx[N + c - l][lane]);
+        const int xc = slab_index(x, g.M[1], g.nb);
+        if (xc >= 0) {
+            const long long q = (long long)s * g.psz[1] + z + (long long)ld1 * xc;
+            const float psi = cp.b_i[1][x] * src.psv[1][q] + cp.a_i[1][x] * ex;
+            dst.psv[1][q] = psi;
+            ex += psi;
+        }
+        float pn = pc[t] - kd[t] * (ez + ex);
+        if (it < nt && k == sc) pn += g.src_scale * stf[(long long)s * nt + it];
+        dst.p[so + k] = pn;
+        dst.v[0][so + k] = vzn[t];
+        dst.v[1][so + k] = vxn[t];
+    }
+}
+
 }  // namespace
 
 // (not with a free surface: its mirror images would be needed between the v and p updates)
@@ -203,6 +389,34 @@ hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int cm = c.march == 8 ? 8 : 4;
+    if (c.zl) {   // tiled variant: 64 rows x 4 cm columns per workgroup
+        int ez = 0, ex = 0;
+        for (int s = 0; s < pl.nshot; ++s) {
+            const int *b = &pl.fbox[((size_t)it * pl.nshot + s) * 6];
+            ez = std::max(ez, b[1] - zalign(b[0]));
+            ex = std::max(ex, b[3] - b[2]);
+        }
+        if (ez <= 0 || ex <= 0) return hipSuccess;
+        const int gz = (ez + 63) / 64, gx = (ex + 4 * cm - 1) / (4 * cm);
+        const int nxc = (gx + 7) / 8;
+        dim3 grid((unsigned)(8 * gz), (unsigned)nxc, (unsigned)pl.nshot), block(64, 4, 1);
+        const int *box = w.fbox + (size_t)it * pl.nshot * 6;
+#define SMI_TILE(N_, CW_)                                                                      \
+    do {                                                                                       \
+        if (c.ev)                                                                              \
+            hipExtLaunchKernelGGL((k_fused2d_tile<N_, CW_>), grid, block, 0, c.st, c.ev[0],     \
+                                  c.ev[1], 0, pl.geom, src, dst, w.model, w.cpml, box, nxc,    \
+                                  (const long long *)w.src_cell, c.stf, pl.g.nt, it);          \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_fused2d_tile<N_, CW_>), grid, block, 0, c.st, pl.geom, src,   \
+                               dst, w.model, w.cpml, box, nxc, (const long long *)w.src_cell,  \
+                               c.stf, pl.g.nt, it);                                            \
+    } while (0)
+        if (pl.N == 2) { if (cm == 8) SMI_TILE(2, 8); else SMI_TILE(2, 4); }
+        else { if (cm == 8) SMI_TILE(4, 8); else SMI_TILE(4, 4); }
+#undef SMI_TILE
+        return hipGetLastError();
+    }
     int ez = 0, ex = 0;
     for (int s = 0; s < pl.nshot; ++s) {
         const int *b = &pl.fbox[((size_t)it * pl.nshot + s) * 6];

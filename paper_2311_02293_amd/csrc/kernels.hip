@@ -224,6 +224,28 @@ struct MG {
                         // consecutive blocks of x (2D: march strips, 3D: 4-column groups)
 };
 
+// Receiver sampling of the previous step carried by a v launch (it < 0: none).  The v update
+// does not write p, so the seismogram row of step it (p^{it+1}) can be taken while the next
+// step's v kernel runs: the launch gets one extra shot slot of workgroups in front (blockIdx.z
+// < nmarch) that sample the receivers, and the shots start at shot0 = -1.
+struct Ext {
+    Recv rv;
+    float *dcal;
+    int it;
+    unsigned *status;
+};
+
+// dcal[it][r] = sum over the taps of receiver r of w p (Alg. 2 recording; one tap on a node)
+__device__ __forceinline__ void sample_receiver(const Geom &g, const float *__restrict__ p,
+                                                const Recv &rv, float *dcal, int it,
+                                                unsigned *status, int r) {
+    const long long so = rv.shot[r] * g.P;
+    float v = 0.f;
+    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) v += rv.tw[t] * p[so + rv.tcell[t]];
+    dcal[rv.obase[r] + (long long)it * rv.stride[r]] = v;
+    if (!isfinite(v)) atomicOr(status, 2u);
+}
+
 struct MCell {
     int s, z, x, y;     // y unused in 2D
     int lo, hi;         // march range [lo, hi) along the march axis
@@ -316,7 +338,16 @@ __device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
 // the wavefront's LDS slice instead of seven unaligned global loads per cell.
 template <int ND, int N, int CM, bool ZL>
 __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
-                                                 const int *__restrict__ box, int shot0, MG mg) {
+                                                 const int *__restrict__ box, int shot0, MG mg,
+                                                 Ext ex) {
+    if (ex.it >= 0 && (int)blockIdx.z < mg.nmarch) {   // receivers of the previous step
+        const int nthr = (int)(gridDim.x * gridDim.y) * mg.nmarch * 256;
+        const int t0 = (((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x +
+                        (int)blockIdx.x) * 256 + (int)threadIdx.y * 64 + (int)threadIdx.x;
+        for (int r = t0; r < ex.rv.R; r += nthr)
+            sample_receiver(g, f.p, ex.rv, ex.dcal, ex.it, ex.status, r);
+        return;
+    }
     constexpr int MA = ND - 1;              // march axis
     constexpr int NW = CM + 2 * N - 1;      // window: march offsets -(N-1) .. CM-1+N
     constexpr int A0 = ZL ? 1 : 0;          // first axis read through global stencil loads
@@ -775,11 +806,7 @@ __global__ __launch_bounds__(256) void k_extract(Geom g, const float *__restrict
                                                  float *dcal, int it, unsigned *status) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rv.R) return;
-    const long long so = rv.shot[r] * g.P;
-    float v = 0.f;
-    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) v += rv.tw[t] * p[so + rv.tcell[t]];
-    dcal[rv.obase[r] + (long long)it * rv.stride[r]] = v;
-    if (!isfinite(v)) atomicOr(status, 2u);
+    sample_receiver(g, p, rv, dcal, it, status, r);
 }
 
 // p += sign (dt / dV) stf[s][it] w_t on the nodes of the operators of the sources that spread
@@ -1167,10 +1194,15 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const Views &w = *c.w;
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd);
-    if (L.empty) return hipSuccess;
+    const bool ext = c.ext_it >= 0 && w.recv.R > 0;
+    if (L.empty) return ext ? extract(c, c.ext_it, c.ext_dcal) : hipSuccess;
+    const Ext ex{w.recv, c.ext_dcal, ext ? c.ext_it : -1, w.status};
+    dim3 gv = L.grid;
+    if (ext) gv.z += L.mg.nmarch;
+    const int s0 = ext ? -1 : 0;
     if (c.ev) {
-        hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1],
-                              0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg);
+        hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, c.ev[0], c.ev[1],
+                              0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex);
         SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
         hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
@@ -1178,8 +1210,8 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
                               (const float *)nullptr, (float *)nullptr);
         return fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
     }
-    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
-                       w.cpml, box, 0, L.mg);
+    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, pl.geom, w.f, w.model,
+                       w.cpml, box, s0, L.mg, ex);
     SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
     hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
@@ -1197,7 +1229,7 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
-                       w.cpml, ab, 0, L.mg);
+                       w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr});
     SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
     if (image)
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
@@ -1356,6 +1388,10 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     } while (0)
 
 hipError_t fwd_step(const StepCtx &c, int it) { SMI_DISPATCH(fwd_step_t, c, it); }
+
+bool march_forward(const StepCtx &c) {
+    return !c.plain && c.march && !(c.y3 && c.pl->nd == 3);
+}
 
 hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {
     SMI_DISPATCH(rev_step_t, c, it, grad, image);

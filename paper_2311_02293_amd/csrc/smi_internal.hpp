@@ -193,9 +193,16 @@ struct StepCtx {
     int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
+    // receiver sampling of forward step ext_it into ext_dcal, carried by the next forward
+    // step's v launch (register-blocked kernels only, see march_forward); -1: none pending
+    int ext_it = -1;
+    float *ext_dcal = nullptr;
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);
+// true when fwd_step runs the register-blocked half-step kernels (which can carry the
+// previous step's receiver sampling)
+bool march_forward(const StepCtx &c);
 // 3D half steps marching along y (ymarch3d.hip)
 bool y3_available(const Plan &pl);
 hipError_t fwd_step_y3(const StepCtx &c, int it);

@@ -79,7 +79,8 @@ def test_plain_stepper_equals_batched(ctx):
 def test_fused_step_matches_sweep_kernels(ctx):
     """The fused 2D step (v and p in one kernel, levels in alternating buffers) computes the
     half-step kernels' update, for 4 and 8 cells per lane: forward data and the FWI gradient
-    (whose reverse pass starts from the fused forward's last level) agree to rounding."""
+    (whose reverse pass starts from the fused forward's last level) agree to rounding; the
+    tiled variant (64 x 16 and 64 x 32 tiles) too."""
     from paper_2311_02293_amd import binding as B
     job = with_bounds(I.config2(n1=70, n2=230, nt=401, nshot=3, box=1))
     vp, rho, stf = dev(job)
@@ -89,7 +90,7 @@ def test_fused_step_matches_sweep_kernels(ctx):
     ref = ref.cpu().numpy()
     ctx.set_option(B.OPT_KERNEL, 2)
     try:
-        for cm in (4, 8):
+        for cm in (4, 8, 104, 108):        # + 100: the tiled variant
             ctx.set_option(B.OPT_CHUNK, cm)
             got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
             got = got.cpu().numpy()
