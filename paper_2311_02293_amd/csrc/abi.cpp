@@ -64,6 +64,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.march = 0;
     c.xcd = false;
     c.y3 = 0;
+    c.zl = false;
     if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
