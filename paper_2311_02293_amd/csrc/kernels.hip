@@ -1304,12 +1304,14 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
 #undef SMI_MRECON_P
         SMI_TRY(fs_launch(pl, c.st, w.f.p, 2, 0, pl.nshot));   // p^it vanishes on a free surface
     }
-    hipError_t e = band_restore(c, it, 0);
+    // p and v bands of level it in one launch: the v reconstruction reads the p bands and
+    // neither reads nor writes the v band cells (they lie outside the interior)
+    hipError_t e = band_restore(c, it, 2);
     if (e != hipSuccess) return e;
     if (!L.empty)
         hipLaunchKernelGGL((k_march_recon_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.f,
                            w.model, rb, 0, L.mg);
-    return band_restore(c, it, 1);
+    return hipGetLastError();
 }
 
 template <int ND, int N>

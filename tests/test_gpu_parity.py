@@ -687,3 +687,59 @@ def test_free_surface_born_and_off_grid_match_oracle(ctx):
         say("free-surface born", s, e, np.abs(refb).max())
         assert np.abs(refb).max() > 1e-3 * np.abs(dobs[s]).max()
         assert e <= 1e-4
+
+
+# ---------------------------------------------------------------- full-size workloads, sampled
+
+def test_bench_workload_at_full_size_matches_oracle_on_sampled_shots(ctx):
+    """The timed workload itself (2D, 500 x 1500, order 8, 16 shots in one launch, nt 4000,
+    box on, default kernels): the seismograms of the first and the last shot against the
+    oracle run of that shot alone."""
+    job = with_bounds(I.config2())
+    say("full-size bench workload", job.grid.n1, job.grid.n2, job.acq.nshot, job.grid.nt)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    ctx.poll_status()
+    got = split(dcal, job)
+    ref = oracle_dcal(job, shots=[0, job.acq.nshot - 1], box=1)
+    for k, s in enumerate([0, job.acq.nshot - 1]):
+        e = rel_l2(got[s], ref[k])
+        say("full-size shot", s, "rel L2", e)
+        assert got[s].shape == (4000, 1500)
+        assert e <= 1e-4
+
+
+def test_gradient_at_full_size_matches_oracle_for_one_shot(ctx):
+    """The gradient workload's grid and time axis (300 x 900, order 8, nt 4000, box on) for one
+    shot, with dobs = 0 (J = dt/2 sum dcal^2): misfit and dJ/dVp against the oracle."""
+    from oracle import oracle as O
+    import torch
+    full = I.config3()
+    job = with_bounds(I.Job(full.grid, full.vp, full.rho, full.acq.shot(0), full.stf[:1].copy()))
+    say("full-size gradient, one shot", job.grid.n1, job.grid.n2, job.grid.nt)
+    dobs = [np.zeros((job.grid.nt, int(job.acq.rec_off[1])))]
+    ref_g, ref_J = O.fwi_grad(job, dobs, box=1, vmax=float(job.grid.vpmax))
+    vp, rho, stf = dev(job)
+    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf,
+                           torch.zeros(job.grid.nt * int(job.acq.rec_off[1]), device="cuda"))
+    g = g.cpu().numpy().reshape(job.vp.shape)
+    say("full-size gradient rel L2", rel_l2(g, ref_g), "J", float(J.cpu()[0]), ref_J)
+    assert abs(float(J.cpu()[0]) - ref_J) <= 1e-4 * ref_J
+    assert rel_l2(g, ref_g) <= 1e-4
+
+
+def test_3d_rtm_grid_at_full_size_matches_oracle_on_a_sampled_shot(ctx):
+    """The 3D RTM grid (400^3, order 8, 4 shots in one launch, 200 x 200 receivers each, box
+    on), first 300 steps: the seismogram of shot 0 against the oracle."""
+    job = with_bounds(I.config4(n=400, nt=300, dr=10))
+    job.grid.vpmax = float(max(job.grid.vpmax, np.max(job.extra["vp_true"])))
+    say("full-size 3D grid", job.grid.n1, job.acq.nshot, job.grid.nt)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    ctx.poll_status()
+    got = split(dcal, job)
+    ref = oracle_dcal(job, shots=[0], box=1)[0]
+    e = rel_l2(got[0], ref)
+    say("full-size 3D shot 0 rel L2", e)
+    assert got[0].shape == (300, 40000)
+    assert e <= 1e-4
