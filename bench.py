@@ -183,6 +183,9 @@ def main():
                       "nb": job.grid.nb, "box": job.grid.box,
                       "gpts_per_step": gpts, "wall_s": wall},
            "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
+           # every padded cell of every shot at every step, over the same time: credits the box
+           "full_grid_equiv_GPts_s": (job.grid.n1 + 2 * job.grid.nb) * (job.grid.n2 + 2 * job.grid.nb)
+                                     * job.acq.nshot * job.grid.nt / (np.mean(ms) / 1e3) / 1e9,
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS if achieved else None,
                         "traffic": counter_traffic(),
