@@ -96,6 +96,81 @@ def counter_traffic():
         return None
 
 
+def serve(torch, njobs: int):
+    """Served stream of mixed requests: a capacity run (every request queued at t = 0), then the
+    same requests arriving as a Poisson stream at 0.7 x that capacity (latency p50 / p99), then
+    every request alone on the plain stepper (one shot per launch, box off)."""
+    from paper_2311_02293_amd import binding as B
+    from paper_2311_02293_amd import inputs as I
+    from paper_2311_02293_amd.server import HipBackend, Request, ShotServer
+
+    be = HipBackend(0, nstreams=4)
+    jobs = I.stream_config5(njobs=njobs, rate=1.0, seed=1005)
+    gaps = np.diff([0.0] + [sj.arrival for sj in jobs])     # unit-rate exponential gaps
+    reqs = []
+    for sj in jobs:
+        j = sj.job
+        vs = [j.vp] + ([j.extra["vp_true"]] if "vp_true" in j.extra else [])
+        j.grid.vpmin = float(min(v.min() for v in vs))
+        j.grid.vpmax = float(1.02 * max(v.max() for v in vs))
+        kind = "grad" if sj.kind == "grad2d" else "forward"
+        r = Request(kind, j, arrival=0.0)
+        if kind == "grad":          # observed data: forward of the true model, before the stream
+            rho = torch.from_numpy(j.rho).cuda()
+            stf = torch.from_numpy(j.stf).cuda()
+            vt = torch.from_numpy(j.extra["vp_true"]).cuda()
+            d, _, _ = be.ctx.forward(j.grid, j.acq, vt, rho, stf)
+            r.dobs = d.cpu().numpy()
+        reqs.append(r)
+    torch.cuda.synchronize()
+    counts = {k: sum(1 for r in reqs if (r.kind, r.job.grid.ndim) == k)
+              for k in (("forward", 2), ("grad", 2), ("forward", 3))}
+    print(f"bench: serve {njobs} requests {counts}", file=sys.stderr, flush=True)
+    srv = ShotServer(be, max_inflight=4)
+    cap = srv.run(reqs)
+    capacity = njobs / cap["makespan"]
+    print(f"bench: capacity {capacity:.2f} requests/s", file=sys.stderr, flush=True)
+    rate = 0.7 * capacity
+    t = 0.0
+    for r, gp in zip(reqs, gaps):
+        t += gp / rate
+        r.arrival = t
+    srv = ShotServer(be, max_inflight=4)
+    st = srv.run(reqs)
+    print("bench: plain stepper, every request alone", file=sys.stderr, flush=True)
+    be.ctx.set_option(B.OPT_KERNEL, 1)
+    plain_s, plain_gpts = 0.0, 0.0
+    for r in reqs:
+        j = r.job
+        box = j.grid.box
+        j.grid.box = 0
+        vp, rho, stf = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (j.vp, j.rho, j.stf))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if r.kind == "forward":
+            be.ctx.forward(j.grid, j.acq, vp, rho, stf)
+        else:
+            be.ctx.fwi_grad(j.grid, j.acq, vp, rho, stf, torch.from_numpy(r.dobs).cuda())
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t0
+        plain_gpts += sum(be.ctx.last_counts())
+        j.grid.box = box
+    be.ctx.set_option(B.OPT_KERNEL, 0)
+    print(json.dumps({
+        "metric": "served shot stream: requests/s, GPts/s, latency p50/p99",
+        "requests": njobs, "mix": {"forward2d": counts[("forward", 2)], "grad2d": counts[("grad", 2)],
+                                   "forward3d": counts[("forward", 3)]},
+        "capacity": {"requests_per_s": capacity, "GPts_s": cap["gpts_per_s"] / 1e9,
+                     "makespan_s": cap["makespan"], "failed": cap["failed"]},
+        "stream": {"arrival_rate_per_s": rate, "p50_s": st["p50"], "p99_s": st["p99"],
+                   "GPts_s": st["gpts_per_s"] / 1e9, "makespan_s": st["makespan"], "failed": st["failed"]},
+        "plain_alone": {"requests_per_s": njobs / plain_s, "GPts_s_full_grid": plain_gpts / plain_s / 1e9,
+                        "total_s": plain_s,
+                        "what": "each request alone, one shot per launch, separate v and p kernels, box off"},
+        "served_vs_plain_requests_per_s": capacity / (njobs / plain_s),
+        "data": "synthetic", "dtype": "f32"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +184,9 @@ def main():
                     help="device-stamp the step kernels of every k-th time step (0: off)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="served-stream mode: N jobs of the mixed request stream (2D forward, "
+                         "2D gradient, 3D forward) instead of the batched-forward benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not provided "
@@ -118,6 +196,9 @@ def main():
     import torch
     if args.probe_copy:
         probe_copy(torch)
+        return
+    if args.serve > 0:
+        serve(torch, args.serve)
         return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
