@@ -237,6 +237,117 @@ __global__ __launch_bounds__(256) void k_fused2d_tile(Geom g, Fields src, Fields
     const float *__restrict__ VX0 = src.v[1] + so;
     const float *__restrict__ BZ = m.bdt[0];
     const float *__restrict__ BX = m.bdt[1];
+
+    // Tiles whose halo lies inside the box and outside the absorbing slabs, without the
+    // source: no masks, no CPML variables, 32-bit offsets.
+    {
+        const int M0 = g.M[0], M1 = g.M[1], nb = g.nb;
+        const long long scell = src_cell[s];
+        const int sx = scell >= 0 ? (int)((scell - g.org) / ld1) : -(1 << 30);
+        const int sz = scell >= 0 ? (int)(scell - g.org - (long long)sx * ld1) : -(1 << 30);
+        const bool fast = z0 - H >= max(b0, nb) && z0 + 64 + H <= min(b1, M0 - nb - 1) &&
+                          lo - H >= max(b2, nb) && lo + TX + H <= min(b3, M1 - nb - 1) &&
+                          !(sz >= z0 && sz < z0 + 64 && sx >= lo && sx < lo + TX);
+        if (fast) {
+            const int oz = (int)g.org + z;
+            const int hr = lane < H ? z0 - H + lane : (lane < 2 * H ? z0 + 64 + lane - H : z);
+            const int oh = (int)g.org + hr;
+            const int vr = lane < N ? z0 - N + lane : (lane < 2 * N - 1 ? z0 + 64 + lane - N : z);
+            const int ov = (int)g.org + vr;
+            float pc[CW], ph[CW], vzc[CW], bzc[CW], vzh[CW], bzh[CW], vxc[CW], bxc[CW], kd[CW];
+#pragma unroll
+            for (int t = 0; t < CW; ++t) {
+                const int cx = ld1 * (lo + wv * CW + t);
+                pc[t] = P0[oz + cx];
+                ph[t] = P0[oh + cx];
+                vzc[t] = VZ0[oz + cx];
+                bzc[t] = BZ[oz + cx];
+                vxc[t] = VX0[oz + cx];
+                bxc[t] = BX[oz + cx];
+                kd[t] = m.kdt[oz + cx];
+                vzh[t] = VZ0[ov + cx];
+                bzh[t] = BZ[ov + cx];
+            }
+            float pq[QP];
+#pragma unroll
+            for (int q = 0; q < QP; ++q) {
+                const int j = min(wv + 4 * q, 2 * H - 1);
+                const int x = j < H ? lo - H + j : lo + TX + j - H;
+                pq[q] = P0[oz + ld1 * x];
+            }
+            float vxq[QV], bxq[QV];
+#pragma unroll
+            for (int q = 0; q < QV; ++q) {
+                const int j = min(wv + 4 * q, 2 * N - 2);
+                const int x = j < N ? lo - N + j : lo + TX + j - N;
+                vxq[q] = VX0[oz + ld1 * x];
+                bxq[q] = BX[oz + ld1 * x];
+            }
+#pragma unroll
+            for (int t = 0; t < CW; ++t) {
+                sp[H + wv * CW + t][H + lane] = pc[t];
+                if (lane < 2 * H) sp[H + wv * CW + t][lane < H ? lane : 64 + lane] = ph[t];
+            }
+#pragma unroll
+            for (int q = 0; q < QP; ++q) {
+                const int j = wv + 4 * q;
+                if (j < 2 * H) sp[j < H ? j : TX + j][H + lane] = pq[q];
+            }
+            __syncthreads();
+            float vzn[CW], vxn[CW];
+#pragma unroll
+            for (int t = 0; t < CW; ++t) {
+                const int c = wv * CW + t;
+                float e = 0.f, ex = 0.f;
+#pragma unroll
+                for (int l = 1; l <= N; ++l) {
+                    e += g.c[0][l - 1] * (sp[H + c][H + lane + l] - sp[H + c][H + lane - l + 1]);
+                    ex += g.c[1][l - 1] * (sp[H + c + l][H + lane] - sp[H + c - l + 1][H + lane]);
+                }
+                vzn[t] = vzc[t] - bzc[t] * e;
+                vxn[t] = vxc[t] - bxc[t] * ex;
+                svz[c][N + lane] = vzn[t];
+                svx[N + c][lane] = vxn[t];
+                if (lane < 2 * N - 1) {
+                    const int i = vr - z0 + H;
+                    float eh = 0.f;
+#pragma unroll
+                    for (int l = 1; l <= N; ++l) eh += g.c[0][l - 1] * (sp[H + c][i + l] - sp[H + c][i - l + 1]);
+                    svz[c][lane < N ? lane : 64 + lane] = vzh[t] - bzh[t] * eh;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QV; ++q) {
+                const int j = wv + 4 * q;
+                if (j < 2 * N - 1) {
+                    const int ci = (j < N ? j - N : TX + j - N) + H;
+                    float e = 0.f;
+#pragma unroll
+                    for (int l = 1; l <= N; ++l) e += g.c[1][l - 1] * (sp[ci + l][H + lane] - sp[ci - l + 1][H + lane]);
+                    svx[j < N ? j : TX + j][lane] = vxq[q] - bxq[q] * e;
+                }
+            }
+            __syncthreads();
+            float *__restrict__ P1 = dst.p + so;
+            float *__restrict__ VZ1 = dst.v[0] + so;
+            float *__restrict__ VX1 = dst.v[1] + so;
+#pragma unroll
+            for (int t = 0; t < CW; ++t) {
+                const int c = wv * CW + t;
+                float ez = 0.f, ex = 0.f;
+#pragma unroll
+                for (int l = 1; l <= N; ++l) {
+                    ez += g.c[0][l - 1] * (svz[c][lane + N + l - 1] - svz[c][lane + N - l]);
+                    ex += g.c[1][l - 1] * (svx[N + c + l - 1][lane] - svx[N + c - l][lane]);
+                }
+                const int k = oz + ld1 * (lo + c);
+                P1[k] = pc[t] - kd[t] * (ez + ex);
+                VZ1[k] = vzn[t];
+                VX1[k] = vxn[t];
+            }
+            return;
+        }
+    }
     auto cell = [&](int zz, int xx) -> long long { return g.org + zz + (long long)ld1 * xx; };
     auto inp = [&](int zz, int xx) { return zz >= b0 - H && zz < b1 + H && xx >= b2 - H && xx < b3 + H; };
     auto inb = [&](int zz, int xx) { return zz >= b0 && zz < b1 && xx >= b2 && xx < b3; };
