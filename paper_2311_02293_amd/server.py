@@ -74,16 +74,23 @@ def merge_requests(reqs: List[Request]) -> I.Job:
 
 
 class HipBackend:
-    """Runs calls through libsmi on one device, one HIP stream per in-flight call."""
+    """Runs calls through libsmi on one device: one HIP stream, one library context and one
+    host thread per in-flight slot.  Enqueueing a call's time loop costs a few microseconds of
+    host time per launch, which for small single-shot calls is as long as the device work, so
+    the slots enqueue in parallel (the library call releases the interpreter lock; a context
+    is used by one thread at a time)."""
 
     def __init__(self, device: int = 0, nstreams: int = 4):
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         from . import binding as B
         self.torch = torch
         self.B = B
-        self.ctx = B.Context(device)
         self.dev = f"cuda:{device}"
+        self.ctxs = [B.Context(device) for _ in range(nstreams)]
+        self.ctx = self.ctxs[0]
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(nstreams)]
+        self.pool = ThreadPoolExecutor(max_workers=nstreams)
 
     def budget(self, frac: float = 0.85) -> int:
         free, _ = self.torch.cuda.mem_get_info(self.dev)
@@ -98,43 +105,50 @@ class HipBackend:
         model = 4 * job.grid.npts * (2 + (2 if kind != "forward" else 0))
         return ws + data + model + 4 * job.stf.size
 
-    def launch(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
+    def _run(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
         torch = self.torch
         st = self.streams[slot]
+        ctx = self.ctxs[slot]
         with torch.cuda.stream(st):
-            vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(self.dev, non_blocking=False)
+            vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(self.dev)
             rho = torch.from_numpy(np.ascontiguousarray(job.rho)).to(self.dev)
             stf = torch.from_numpy(np.ascontiguousarray(job.stf)).to(self.dev)
             jt = {"forward": self.B.JOB_FORWARD, "grad": self.B.JOB_GRAD, "rtm": self.B.JOB_RTM}[kind]
-            ws = torch.empty(self.ctx.workspace_bytes(job.grid, job.acq, jt), dtype=torch.uint8,
+            ws = torch.empty(ctx.workspace_bytes(job.grid, job.acq, jt), dtype=torch.uint8,
                              device=self.dev)
             if kind == "forward":
-                out, _, _ = self.ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=st)
+                out, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=st)
                 keep = (vp, rho, stf, ws, out)
             else:
                 d = torch.from_numpy(np.ascontiguousarray(dobs, np.float32)).to(self.dev)
                 if kind == "grad":
-                    g, J, _ = self.ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
                     out = (g, J)
                 else:
-                    out = self.ctx.rtm_image(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                    out = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
                 keep = (vp, rho, stf, ws, d, out)
             ev = torch.cuda.Event()
             ev.record(st)
-        counts = self.ctx.last_counts()
-        return {"ev": ev, "out": out, "keep": keep, "gpts": sum(counts)}
+        return {"ev": ev, "out": out, "keep": keep, "gpts": sum(ctx.last_counts())}
+
+    def launch(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
+        return {"fut": self.pool.submit(self._run, job, kind, dobs, slot)}
 
     def done(self, h) -> bool:
-        return h["ev"].query()
+        f = h["fut"]
+        if not f.done():
+            return False
+        return f.exception() is not None or f.result()["ev"].query()
 
     def result(self, h):
-        out = h["out"]
+        out = h["fut"].result()["out"]          # re-raises an error of the call
         if isinstance(out, tuple):
             return tuple(None if o is None else o.cpu().numpy() for o in out)
         return out.cpu().numpy()
 
     def gpts(self, h) -> float:
-        return h["gpts"]
+        f = h["fut"]
+        return f.result()["gpts"] if f.exception() is None else 0.0
 
     def now(self) -> float:
         return time.perf_counter()
@@ -237,7 +251,14 @@ class ShotServer:
             for h, rs, fp, slot in inflight:
                 if be.done(h):
                     tdone = be.now() - t0
-                    res = be.result(h)
+                    try:
+                        res = be.result(h)
+                    except Exception as e:      # an error raised while the call ran
+                        for r in rs:
+                            outcomes[r.rid] = Outcome(r.rid, r.kind, False, error=str(e))
+                        used -= fp
+                        free_slots.append(slot)
+                        continue
                     for k, r in enumerate(rs):
                         outcomes[r.rid] = Outcome(r.rid, r.kind, True, tdone - r.arrival,
                                                   res if len(rs) == 1 else (k, res),
