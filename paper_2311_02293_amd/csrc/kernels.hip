@@ -544,7 +544,8 @@ __global__ __launch_bounds__(256) void k_recon_p(Geom g, Fields f, Model m,
     float *pp = f.p + c.s * g.P + c.k;
     float pv = *pp;
     if (c.k == src_cell[c.s]) pv -= g.src_scale * stf[(long long)c.s * nt + it];
-    float pn = pv + m.kdt[c.k] * div;
+    // p^it vanishes on a free surface (the update gives the value before its image)
+    float pn = g.fs && c.z == g.nb ? 0.f : pv + m.kdt[c.k] * div;
     *pp = pn;
     long long ii = c.s * g.I + (c.z - g.nb) +
                    (long long)g.n[0] * ((c.x - g.nb) + (long long)g.n[1] * (ND == 3 ? c.y - g.nb : 0));
@@ -653,7 +654,8 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
         }
         float pv = po[t];
         if (k == sc) pv -= g.src_scale * stf[(long long)mc.s * nt + it];
-        const float pn = pv + kd[t] * div;
+        // p^it vanishes on a free surface (the update gives the value before its image)
+        const float pn = g.fs && mc.z == g.nb ? 0.f : pv + kd[t] * div;
         f.p[so0 + k] = pn;
         if (GRAD) acc_g[ii0 + t * iis] = ag[t] + qv[t] * div;
         if (ILL) acc_l[ii0 + t * iis] = al[t] + g.dt * pn * pn;
@@ -1302,7 +1304,6 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
         else if (image) SMI_MRECON_P(false, true);
         else SMI_MRECON_P(false, false);
 #undef SMI_MRECON_P
-        SMI_TRY(fs_launch(pl, c.st, w.f.p, 2, 0, pl.nshot));   // p^it vanishes on a free surface
     }
     // p and v bands of level it in one launch: the v reconstruction reads the p bands and
     // neither reads nor writes the v band cells (they lie outside the interior)
@@ -1342,7 +1343,6 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
         else if (image) SMI_RECON_P(false, true);
         else SMI_RECON_P(false, false);
 #undef SMI_RECON_P
-        SMI_TRY(fs_launch(pl, c.st, w.f.p, 2, s0, s1));   // p^it vanishes on a free surface
     }
     hipError_t e = band_restore(c, it, 0);
     if (e != hipSuccess) return e;

@@ -413,6 +413,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     for (int a = 0; a < 3; ++a)
         for (int l = 0; l < kMaxN; ++l) G.c[a][l] = l < pl.N ? (float)(aw[l] / hs[a]) : 0.f;
     G.dt = (float)g->dt;
+    G.fs = g->freesurf;
     G.src_scale = (float)(g->dt / (hs[0] * hs[1] * (pl.nd == 3 ? hs[2] : 1.0)));
 
     // workspace layout

@@ -44,6 +44,7 @@ struct Geom {
     float c[3][kMaxN];  // a_l / d_a
     float dt;
     float src_scale;    // dt / (d1 d2 [d3])
+    int fs;             // free surface on row nb (p = 0 there)
 };
 
 struct Model {

@@ -638,6 +638,9 @@ def test_free_surface_forward_gradient_and_image_match_oracle(ctx, ndim, dr):
     el = rel_l2(il.cpu().numpy().reshape(job.vp.shape), np.sum(ils, 0))
     say("free-surface image", ei, el)
     assert ei <= 1e-4 and el <= 1e-4
+    # p vanishes on the surface row (z index 0): no illumination there, as in the oracle
+    assert np.all(il.cpu().numpy().reshape(job.vp.shape)[..., 0] == 0)
+    assert np.all(np.sum(ils, 0)[..., 0] == 0)
 
 
 @pytest.mark.parametrize("kernel", [1, 2, 4, 5])
