@@ -130,10 +130,15 @@ typedef enum {
     SMI_OPT_TILEMAP = 4,     /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
                                 then x-block); 1 each of the 8 XCDs takes a contiguous range of
                                 x-blocks, so tiles that share halos share an L2 */
-    SMI_OPT_FAMILY = 5       /* parametrisation of the gradients (Sec. 2.2): 1 (default) (Vp, rho):
+    SMI_OPT_FAMILY = 5,      /* parametrisation of the gradients (Sec. 2.2): 1 (default) (Vp, rho):
                                 grad_vp = dJ/dVp at fixed rho, grad_rho = dJ/drho at fixed Vp;
                                 2 (Vp, Ip = rho Vp): grad_vp = dJ/dVp at fixed Ip, grad_rho =
                                 dJ/dIp at fixed Vp */
+    SMI_OPT_REVERSE = 6      /* 2D reverse step of the default kernels: 0 (default) two launches
+                                per step (reconstruction of p with the adjoint v update and the p
+                                bands; then reconstruction of v with the adjoint p update and the
+                                v bands) for batches of up to 8 M padded cells, five launches
+                                above; 1 always two; 2 always five.  Same results. */
 } smi_option;
 
 /* Create a context on HIP device `hip_device`. */

@@ -19,7 +19,7 @@ STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
           -4: "SMI_E_WORKSPACE", -5: "SMI_E_HIP", -6: "SMI_E_UNSUPPORTED", -7: "SMI_E_STATE",
           -8: "SMI_E_NONFINITE"}
 JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD, JOB_BORN = 0, 1, 2, 3, 4
-OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY = 0, 1, 2, 3, 4, 5
+OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY, OPT_REVERSE = 0, 1, 2, 3, 4, 5, 6
 
 
 class SmiError(RuntimeError):

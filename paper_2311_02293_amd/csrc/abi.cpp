@@ -22,6 +22,7 @@ struct smi_ctx {
     int opt_kernel = 0;
     int opt_graph = 0;
     int opt_chunk = 0;
+    int opt_rev = 0;
     int opt_xcd = 0;
     int opt_family = 1;
     void *last_ws = nullptr;
@@ -65,6 +66,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.xcd = false;
     c.y3 = 0;
     c.zl = false;
+    c.rev = ctx->opt_rev;
     if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
@@ -123,7 +125,7 @@ struct Key {
 Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
     Key k;
     k.put(tag).put(pl.geom).put(pl.band).put(pl.nshot).put(pl.nrun).put(pl.nsave);
-    k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl);
+    k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl).put(c.rev);
     k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
     return k;
 }
@@ -481,6 +483,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_KERNEL && value >= 0 && value <= 5) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
+    if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }
     if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
     if (option == SMI_OPT_TIMING && value >= 0) {

@@ -286,6 +286,9 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.zb1 = b[1];
         c.run = c.lo < c.hi && c.x < b[3] && c.z - lane < b[1];
     }
+    // in a grid shared with another half step, blocks past this one's x-blocks per XCD would
+    // repeat the next XCD's blocks
+    if (mg.nxc && (int)blockIdx.y >= mg.nxc) c.run = false;
     c.ok = c.run && c.z >= c.zb0 && c.z < c.zb1;
     c.need = c.run && c.z >= c.zb0 - 4 && c.z < c.zb1 + 4;
     return c;
@@ -337,7 +340,7 @@ __device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
 // the march range re-read the last cell and store nothing.  ZL: the z-neighbours come from
 // the wavefront's LDS slice instead of seven unaligned global loads per cell.
 template <int ND, int N, int CM, bool ZL>
-__global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
+__device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  Ext ex) {
     if (ex.it >= 0 && (int)blockIdx.z < mg.nmarch) {   // receivers of the previous step
@@ -431,10 +434,17 @@ __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml
     }
 }
 
+template <int ND, int N, int CM, bool ZL>
+__global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
+                                                 const int *__restrict__ box, int shot0, MG mg,
+                                                 Ext ex) {
+    march_v_body<ND, N, CM, ZL>(g, f, m, cp, box, shot0, mg, ex);
+}
+
 // p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
 // first, as in k_march_v.
 template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG>
-__global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml cp,
+__device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
@@ -524,6 +534,15 @@ __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml
     }
 }
 
+template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG>
+__global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml cp,
+                                                 const int *__restrict__ box, int shot0, MG mg,
+                                                 const long long *__restrict__ src_cell,
+                                                 const float *__restrict__ stf, int nt, int it,
+                                                 const float *__restrict__ pf, float *acc_i) {
+    march_p_body<ND, N, CM, ZL, SRC, IMG>(g, f, m, cp, box, shot0, mg, src_cell, stf, nt, it, pf, acc_i);
+}
+
 // ---------------------------------------------------------------- reconstruction (Sec. 4.2)
 
 // p^it = p^{it+1} - dt stf[it]/dV [at the source] + dt kappa div v^{it+1/2}  on the interior;
@@ -572,7 +591,7 @@ __global__ __launch_bounds__(256) void k_recon_v(Geom g, Fields f, Model m,
 // Register-blocked forms of the two reconstruction kernels (cells per lane along the slowest
 // axis, loads first, z-neighbours through LDS when ZL), as k_march_v / k_march_p.
 template <int ND, int N, int CM, bool ZL, bool GRAD, bool ILL>
-__global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m,
+__device__ __forceinline__ void march_recon_p_body(Geom g, Fields f, Model m,
                                                        const int *__restrict__ rbox, int shot0,
                                                        MG mg, const long long *__restrict__ src_cell,
                                                        const float *__restrict__ stf, int nt, int it,
@@ -662,8 +681,18 @@ __global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m
     }
 }
 
+template <int ND, int N, int CM, bool ZL, bool GRAD, bool ILL>
+__global__ __launch_bounds__(256) void k_march_recon_p(Geom g, Fields f, Model m,
+                                                       const int *__restrict__ rbox, int shot0,
+                                                       MG mg, const long long *__restrict__ src_cell,
+                                                       const float *__restrict__ stf, int nt, int it,
+                                                       const float *__restrict__ qp, float *acc_g,
+                                                       float *acc_l) {
+    march_recon_p_body<ND, N, CM, ZL, GRAD, ILL>(g, f, m, rbox, shot0, mg, src_cell, stf, nt, it, qp, acc_g, acc_l);
+}
+
 template <int ND, int N, int CM, bool ZL>
-__global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m,
+__device__ __forceinline__ void march_recon_v_body(Geom g, Fields f, Model m,
                                                        const int *__restrict__ rbox, int shot0,
                                                        MG mg) {
     constexpr int MA = ND - 1;
@@ -745,16 +774,21 @@ __global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m
     }
 }
 
+template <int ND, int N, int CM, bool ZL>
+__global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m,
+                                                       const int *__restrict__ rbox, int shot0,
+                                                       MG mg) {
+    march_recon_v_body<ND, N, CM, ZL>(g, f, m, rbox, shot0, mg);
+}
+
 // ---------------------------------------------------------------- saved boundaries (Sec. 4.2)
 
-// dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt) buf + wt buf2.
-// which: 0 p blocks, 1 v blocks, 2 all.  One lane per band cell; blockIdx.y = shot.
-__global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, float *buf,
-                                              const float *buf2, long long shot_stride, int shot0,
-                                              int dir, int which, float wt) {
-    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+// Band cell q of shot s.  dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt)
+// buf + wt buf2.  which: 0 p blocks, 1 v blocks, 2 all.
+__device__ __forceinline__ void band_cell(const Geom &g, const Fields &f, const BandDesc &bd,
+                                          float *buf, const float *buf2, long long shot_stride,
+                                          int s, long long q, int dir, int which, float wt) {
     if (q >= bd.B) return;
-    int s = shot0 + blockIdx.y;
     int b = 0;
 #pragma unroll 1
     while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
@@ -766,11 +800,82 @@ __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, flo
     int x = bl.org[1] + (int)(r % bl.ext[1]);
     int y = bl.org[2] + (int)(r / bl.ext[1]);
     long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
-    float *fld = (bl.field == 0 ? f.p : f.v[bl.axis]) + s * g.P + k;
+    // constant indices only: a dynamic index into the Fields of a reference would place a
+    // copy of it in LDS
+    float *base = bl.field == 0 ? f.p : (bl.axis == 0 ? f.v[0] : (bl.axis == 1 ? f.v[1] : f.v[2]));
+    float *fld = base + s * g.P + k;
     long long bo = s * shot_stride + q;
     if (dir == 0) buf[bo] = *fld;
     else if (dir == 1) *fld = buf[bo];
     else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
+}
+
+// one lane per band cell; blockIdx.y = shot
+__global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, float *buf,
+                                              const float *buf2, long long shot_stride, int shot0,
+                                              int dir, int which, float wt) {
+    band_cell(g, f, bd, buf, buf2, shot_stride, shot0 + (int)blockIdx.y,
+              blockIdx.x * (long long)blockDim.x + threadIdx.x, dir, which, wt);
+}
+
+// The reverse step of the 2D default path in two launches.  Launch 1 runs, on disjoint
+// blocks of one grid, the reconstruction of p^it with the gradient and illumination sums
+// (blockIdx.z < nshot), the adjoint v update (the next nshot planes) and, with bands saved
+// at every step, the restore of the p band cells of level it (the planes after); launch 2 runs
+// the reconstruction of v^{it-1/2}, the adjoint p update with the image, and the restore of
+// the v band cells.  The parts of a launch touch disjoint data: the bands lie outside the
+// interior that the reconstruction writes, the adjoint fields are separate, and the v bands are
+// restored only after the gradient has read v^{it+1/2} next to the interior.
+struct BandArg {
+    BandDesc bd;
+    const float *buf;   // saved level it of shot 0
+    long long stride;   // floats between shots
+    int nqb;            // 256-cell blocks per shot
+    int nshot;
+};
+
+__device__ __forceinline__ void band_part(const Geom &g, const Fields &f, const BandArg &ba,
+                                          int z0, int which) {
+    const long long lin = ((long long)((int)blockIdx.z - z0) * gridDim.y + blockIdx.y) *
+                              gridDim.x + blockIdx.x;
+    const int s = (int)(lin / ba.nqb);
+    if (s < ba.nshot)
+        band_cell(g, f, ba.bd, const_cast<float *>(ba.buf), nullptr, ba.stride, s,
+                  (lin % ba.nqb) * 256 + (int)threadIdx.y * 64 + (int)threadIdx.x, 1, which, 0.f);
+}
+
+template <int N, int CM, bool GRAD, bool ILL, bool BAND>
+__global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Model m, Cpml cp,
+                                                const int *__restrict__ rb,
+                                                const int *__restrict__ ab, MG mgr, MG mga,
+                                                int nshot, const long long *__restrict__ src_cell,
+                                                const float *__restrict__ stf, int nt, int it,
+                                                float *acc_g, float *acc_l, BandArg ba) {
+    const int bz = (int)blockIdx.z;
+    if (bz < nshot)
+        march_recon_p_body<2, N, CM, false, GRAD, ILL>(g, f, m, rb, 0, mgr, src_cell, stf, nt, it,
+                                                       q.p, acc_g, acc_l);
+    else if (bz < 2 * nshot)
+        march_v_body<2, N, CM, false>(g, q, m, cp, ab, -nshot, mga, Ext{Recv{}, nullptr, -1, nullptr});
+    else if (BAND)
+        band_part(g, f, ba, 2 * nshot, 0);
+}
+
+template <int N, int CM, bool IMG, bool BAND>
+__global__ __launch_bounds__(256) void k_rev_vp(Geom g, Fields f, Fields q, Model m, Cpml cp,
+                                                const int *__restrict__ rb,
+                                                const int *__restrict__ ab, MG mgr, MG mga,
+                                                int nshot, const long long *__restrict__ src_cell,
+                                                const float *__restrict__ stf, int nt, int it,
+                                                float *acc_i, BandArg ba) {
+    const int bz = (int)blockIdx.z;
+    if (bz < nshot)
+        march_recon_v_body<2, N, CM, false>(g, f, m, rb, 0, mgr);
+    else if (bz < 2 * nshot)
+        march_p_body<2, N, CM, false, false, IMG>(g, q, m, cp, ab, -nshot, mga, src_cell, stf, nt,
+                                                  it, f.p, acc_i);
+    else if (BAND)
+        band_part(g, f, ba, 2 * nshot, 1);
 }
 
 // Band cells at level it = sum_j w[j] * saved level slot[j] (decimated bands, dr > 1).
@@ -1315,10 +1420,62 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     return hipGetLastError();
 }
 
+// the two-launch reverse step of the 2D default path (see k_rev_pv)
+template <int N>
+hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
+    constexpr int CM = 4;
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
+    const int *ab = w.abox + (size_t)it * pl.nshot * 6;
+    const MLaunch LR = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
+    const MLaunch LA = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
+    const bool band = pl.g.dr == 1;
+    const BandArg ba{pl.band, w.bands + (size_t)it * pl.band.B, (long long)pl.nsave * pl.band.B,
+                     (int)((pl.band.B + 255) / 256), pl.nshot};
+    dim3 grid(std::max(LR.grid.x, LA.grid.x), std::max(LR.grid.y, LA.grid.y), 2u * pl.nshot);
+    if (band) {
+        const long long per = (long long)grid.x * grid.y;
+        grid.z += (unsigned)(((long long)pl.nshot * ba.nqb + per - 1) / per);
+    }
+    const dim3 block(64, 4, 1);
+#define SMI_RPV(G_, L_, B_)                                                                    \
+    hipLaunchKernelGGL((k_rev_pv<N, CM, G_, L_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,   \
+                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, pl.nshot,                         \
+                       (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_g, w.acc_l, ba)
+#define SMI_RPV_B(G_, L_) do { if (band) SMI_RPV(G_, L_, true); else SMI_RPV(G_, L_, false); } while (0)
+    if (grad && image) SMI_RPV_B(true, true);
+    else if (grad) SMI_RPV_B(true, false);
+    else if (image) SMI_RPV_B(false, true);
+    else SMI_RPV_B(false, false);
+#undef SMI_RPV_B
+#undef SMI_RPV
+    if (!band) SMI_TRY(band_restore(c, it, 2));      // interpolated levels: one launch of their own
+    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
+#define SMI_RVP(I_, B_)                                                                        \
+    hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,       \
+                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, pl.nshot,                         \
+                       (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_i, ba)
+    if (image) { if (band) SMI_RVP(true, true); else SMI_RVP(true, false); }
+    else { if (band) SMI_RVP(false, true); else SMI_RVP(false, false); }
+#undef SMI_RVP
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
+}
+
 template <int ND, int N>
 hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    // Batches up to 8 M padded cells take the two-launch step (10 % faster on 8 shots of
+    // 300 x 900, 30 % less host time on one); above, where the host keeps ahead and the two
+    // orders measure the same, the five-launch order keeps consecutive kernels on one field.
+    constexpr double kPairCells = 8.0e6;
+    if constexpr (ND == 2) {
+        const bool small = (double)pl.nshot * (double)pl.P <= kPairCells;
+        if (!c.plain && c.march == 4 && !c.zl && (c.rev == 1 || (c.rev == 0 && small)))
+            return rev_pair_t<N>(c, it, grad, image);
+    }
     if (!c.plain && c.march) {
         auto recon = [&]() -> hipError_t { SMI_MARCH(recon_march_t, c, it, grad, image); };
         hipError_t e = recon();

@@ -194,6 +194,7 @@ struct StepCtx {
     int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
+    int rev = 0;            // 2D reverse step: 0 by batch size, 1 two launches, 2 five launches
     // receiver sampling of forward step ext_it into ext_dcal, carried by the next forward
     // step's v launch (register-blocked kernels only, see march_forward); -1: none pending
     int ext_it = -1;

@@ -788,3 +788,28 @@ def test_non_finite_values_are_reported(ctx):
     dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
     ctx.poll_status()
     assert np.isfinite(dcal.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("dr", [1, 3])
+def test_two_and_five_launch_reverse_steps_agree(ctx, dr):
+    """The 2D reverse step in two launches (reconstruction and adjoint half steps sharing a
+    grid, band restores folded in) and in five: bitwise the same gradient, image and
+    illumination, with bands saved at every step and decimated."""
+    from paper_2311_02293_amd import binding as B
+    job = _grad_job(nt=400, nshot=3)
+    job.grid.dr = dr
+    vp, rho, stf = dev(job)
+    d0, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    dobs = (0.8 * d0).contiguous()
+    out = {}
+    try:
+        for mode in (1, 2):
+            ctx.set_option(B.OPT_REVERSE, mode)
+            g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+            im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs)
+            out[mode] = [t.cpu().numpy() for t in (g, J, im, il)]
+    finally:
+        ctx.set_option(B.OPT_REVERSE, 0)
+    for a, b in zip(out[1], out[2]):
+        np.testing.assert_array_equal(a, b)
+    assert np.abs(out[1][0]).max() > 0 and np.abs(out[1][2]).max() > 0
