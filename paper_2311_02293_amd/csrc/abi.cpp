@@ -192,6 +192,8 @@ smi_status speeds(smi_ctx *ctx, const smi_grid *g, const float *vp, void *ws, si
 // Upload CPML profiles, box tables, receivers and sources; clear the status word.
 smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) {
     HIPCHK(hipMemsetAsync(w.status, 0, 64, st), "status clear");
+    HIPCHK(hipMemcpyAsync((void *)w.bdesc, &pl.band, sizeof(pl.band), hipMemcpyHostToDevice, st),
+           "band layout");
     for (int a = 0; a < pl.nd; ++a) {
         std::vector<float> ai, bi, ah, bh;
         smi::cpml_profiles(pl, a, ai, bi, ah, bh);
@@ -288,7 +290,14 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         // fused steps alternate between the two buffers: level it lives in cur
         const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
         const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
-        if (pl.save && it % dr == 0) HIPCHK(smi::band_save(c, cur, it / dr), "band save");
+        // saved levels: on the register-blocked path the p cells of level it ride on this
+        // step's v launch and its v cells rode on the previous step's p launch
+        c.save_p_slot = c.save_v_slot = -1;
+        if (pl.save && it % dr == 0) {
+            if (defer && it > 0) c.save_p_slot = it / dr;
+            else HIPCHK(smi::band_save(c, cur, it / dr), "band save");
+        }
+        if (pl.save && defer && (it + 1) % dr == 0 && it + 1 < pl.nrun) c.save_v_slot = (it + 1) / dr;
         if (timed && it % ctx->opt_timing == 0) {
             const size_t k = ctx->nsample;
             while (ctx->events.size() < 4 * (k + 1)) {

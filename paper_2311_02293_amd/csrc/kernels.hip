@@ -235,6 +235,54 @@ struct Ext {
     unsigned *status;
 };
 
+// Band cell q of shot s.  dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt)
+// buf + wt buf2.  which: 0 p blocks, 1 v blocks, 2 all.
+__device__ __forceinline__ void band_cell(const Geom &g, const Fields &f, const BandDesc &bd,
+                                          float *buf, const float *buf2, long long shot_stride,
+                                          int s, long long q, int dir, int which, float wt) {
+    if (q >= bd.B) return;
+    int b = 0;
+#pragma unroll 1
+    while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
+    const BandBlock &bl = bd.blk[b];
+    if (which != 2 && bl.field != which) return;
+    long long r = q - bl.off;
+    int z = bl.org[0] + (int)(r % bl.ext[0]);
+    r /= bl.ext[0];
+    int x = bl.org[1] + (int)(r % bl.ext[1]);
+    int y = bl.org[2] + (int)(r / bl.ext[1]);
+    long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
+    // constant indices only: a dynamic index into the Fields of a reference would place a
+    // copy of it in LDS
+    float *base = bl.field == 0 ? f.p : (bl.axis == 0 ? f.v[0] : (bl.axis == 1 ? f.v[1] : f.v[2]));
+    float *fld = base + s * g.P + k;
+    long long bo = s * shot_stride + q;
+    if (dir == 0) buf[bo] = *fld;
+    else if (dir == 1) *fld = buf[bo];
+    else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
+}
+
+// Band cells carried by a launch of other work: saved levels (dir 0) during the forward half
+// steps, restored levels (dir 1) in the two-launch reverse step.
+struct BandArg {
+    const BandDesc *bd; // band layout (device copy)
+    float *buf;         // saved level of shot 0 (nullptr: nothing to do)
+    long long stride;   // floats between shots
+    int nqb;            // 256-cell blocks per shot
+    int nshot;
+};
+
+// the band cells of every shot over the blocks from grid plane z0 on (one lane per cell)
+__device__ __forceinline__ void band_part(const Geom &g, const Fields &f, const BandArg &ba,
+                                          int z0, int dir, int which) {
+    const long long lin = ((long long)((int)blockIdx.z - z0) * gridDim.y + blockIdx.y) *
+                              gridDim.x + blockIdx.x;
+    const int s = (int)(lin / ba.nqb);
+    if (s < ba.nshot)
+        band_cell(g, f, *ba.bd, ba.buf, nullptr, ba.stride, s,
+                  (lin % ba.nqb) * 256 + (int)threadIdx.y * 64 + (int)threadIdx.x, dir, which, 0.f);
+}
+
 // dcal[it][r] = sum over the taps of receiver r of w p (Alg. 2 recording; one tap on a node)
 __device__ __forceinline__ void sample_receiver(const Geom &g, const float *__restrict__ p,
                                                 const Recv &rv, float *dcal, int it,
@@ -342,7 +390,12 @@ __device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
 template <int ND, int N, int CM, bool ZL>
 __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
-                                                 Ext ex) {
+                                                 Ext ex, BandArg sv, int sv_z0) {
+    // the p band cells of this level (the v update leaves p alone), on the planes from sv_z0
+    if (sv.buf && (int)blockIdx.z >= sv_z0) {
+        band_part(g, f, sv, sv_z0, 0, 0);
+        return;
+    }
     if (ex.it >= 0 && (int)blockIdx.z < mg.nmarch) {   // receivers of the previous step
         const int nthr = (int)(gridDim.x * gridDim.y) * mg.nmarch * 256;
         const int t0 = (((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x +
@@ -437,8 +490,8 @@ __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
 template <int ND, int N, int CM, bool ZL>
 __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
-                                                 Ext ex) {
-    march_v_body<ND, N, CM, ZL>(g, f, m, cp, box, shot0, mg, ex);
+                                                 Ext ex, BandArg sv, int sv_z0) {
+    march_v_body<ND, N, CM, ZL>(g, f, m, cp, box, shot0, mg, ex, sv, sv_z0);
 }
 
 // p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
@@ -448,7 +501,12 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
-                                                 const float *__restrict__ pf, float *acc_i) {
+                                                 const float *__restrict__ pf, float *acc_i, BandArg sv, int sv_z0) {
+    // the v band cells of the next level (the p update leaves v alone), on the planes from sv_z0
+    if (sv.buf && (int)blockIdx.z >= sv_z0) {
+        band_part(g, f, sv, sv_z0, 0, 1);
+        return;
+    }
     constexpr int MA = ND - 1;
     constexpr int NW = CM + 2 * N - 1;      // window: march offsets -N .. CM-1+N-1
     constexpr int A0 = ZL ? 1 : 0;
@@ -539,8 +597,9 @@ __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
-                                                 const float *__restrict__ pf, float *acc_i) {
-    march_p_body<ND, N, CM, ZL, SRC, IMG>(g, f, m, cp, box, shot0, mg, src_cell, stf, nt, it, pf, acc_i);
+                                                 const float *__restrict__ pf, float *acc_i, BandArg sv, int sv_z0) {
+    march_p_body<ND, N, CM, ZL, SRC, IMG>(g, f, m, cp, box, shot0, mg, src_cell, stf, nt, it, pf, acc_i,
+                                          sv, sv_z0);
 }
 
 // ---------------------------------------------------------------- reconstruction (Sec. 4.2)
@@ -783,33 +842,6 @@ __global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m
 
 // ---------------------------------------------------------------- saved boundaries (Sec. 4.2)
 
-// Band cell q of shot s.  dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt)
-// buf + wt buf2.  which: 0 p blocks, 1 v blocks, 2 all.
-__device__ __forceinline__ void band_cell(const Geom &g, const Fields &f, const BandDesc &bd,
-                                          float *buf, const float *buf2, long long shot_stride,
-                                          int s, long long q, int dir, int which, float wt) {
-    if (q >= bd.B) return;
-    int b = 0;
-#pragma unroll 1
-    while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
-    const BandBlock &bl = bd.blk[b];
-    if (which != 2 && bl.field != which) return;
-    long long r = q - bl.off;
-    int z = bl.org[0] + (int)(r % bl.ext[0]);
-    r /= bl.ext[0];
-    int x = bl.org[1] + (int)(r % bl.ext[1]);
-    int y = bl.org[2] + (int)(r / bl.ext[1]);
-    long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
-    // constant indices only: a dynamic index into the Fields of a reference would place a
-    // copy of it in LDS
-    float *base = bl.field == 0 ? f.p : (bl.axis == 0 ? f.v[0] : (bl.axis == 1 ? f.v[1] : f.v[2]));
-    float *fld = base + s * g.P + k;
-    long long bo = s * shot_stride + q;
-    if (dir == 0) buf[bo] = *fld;
-    else if (dir == 1) *fld = buf[bo];
-    else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
-}
-
 // one lane per band cell; blockIdx.y = shot
 __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, float *buf,
                                               const float *buf2, long long shot_stride, int shot0,
@@ -826,24 +858,6 @@ __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, flo
 // the v band cells.  The parts of a launch touch disjoint data: the bands lie outside the
 // interior that the reconstruction writes, the adjoint fields are separate, and the v bands are
 // restored only after the gradient has read v^{it+1/2} next to the interior.
-struct BandArg {
-    BandDesc bd;
-    const float *buf;   // saved level it of shot 0
-    long long stride;   // floats between shots
-    int nqb;            // 256-cell blocks per shot
-    int nshot;
-};
-
-__device__ __forceinline__ void band_part(const Geom &g, const Fields &f, const BandArg &ba,
-                                          int z0, int which) {
-    const long long lin = ((long long)((int)blockIdx.z - z0) * gridDim.y + blockIdx.y) *
-                              gridDim.x + blockIdx.x;
-    const int s = (int)(lin / ba.nqb);
-    if (s < ba.nshot)
-        band_cell(g, f, ba.bd, const_cast<float *>(ba.buf), nullptr, ba.stride, s,
-                  (lin % ba.nqb) * 256 + (int)threadIdx.y * 64 + (int)threadIdx.x, 1, which, 0.f);
-}
-
 template <int N, int CM, bool GRAD, bool ILL, bool BAND>
 __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Model m, Cpml cp,
                                                 const int *__restrict__ rb,
@@ -856,9 +870,10 @@ __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Mode
         march_recon_p_body<2, N, CM, false, GRAD, ILL>(g, f, m, rb, 0, mgr, src_cell, stf, nt, it,
                                                        q.p, acc_g, acc_l);
     else if (bz < 2 * nshot)
-        march_v_body<2, N, CM, false>(g, q, m, cp, ab, -nshot, mga, Ext{Recv{}, nullptr, -1, nullptr});
+        march_v_body<2, N, CM, false>(g, q, m, cp, ab, -nshot, mga, Ext{Recv{}, nullptr, -1, nullptr},
+                                      BandArg{}, 0);
     else if (BAND)
-        band_part(g, f, ba, 2 * nshot, 0);
+        band_part(g, f, ba, 2 * nshot, 1, 0);
 }
 
 template <int N, int CM, bool IMG, bool BAND>
@@ -873,9 +888,9 @@ __global__ __launch_bounds__(256) void k_rev_vp(Geom g, Fields f, Fields q, Mode
         march_recon_v_body<2, N, CM, false>(g, f, m, rb, 0, mgr);
     else if (bz < 2 * nshot)
         march_p_body<2, N, CM, false, false, IMG>(g, q, m, cp, ab, -nshot, mga, src_cell, stf, nt,
-                                                  it, f.p, acc_i);
+                                                  it, f.p, acc_i, BandArg{}, 0);
     else if (BAND)
-        band_part(g, f, ba, 2 * nshot, 1);
+        band_part(g, f, ba, 2 * nshot, 1, 1);
 }
 
 // Band cells at level it = sum_j w[j] * saved level slot[j] (decimated bands, dr > 1).
@@ -1302,27 +1317,53 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd);
     const bool ext = c.ext_it >= 0 && w.recv.R > 0;
-    if (L.empty) return ext ? extract(c, c.ext_it, c.ext_dcal) : hipSuccess;
+    if (L.empty) {
+        // nothing to update: the carried work runs on its own
+        if (c.save_p_slot >= 0) SMI_TRY(band_save_part(c, w.f, c.save_p_slot, 0));
+        if (c.save_v_slot >= 0) SMI_TRY(band_save_part(c, w.f, c.save_v_slot, 1));
+        return ext ? extract(c, c.ext_it, c.ext_dcal) : hipSuccess;
+    }
     const Ext ex{w.recv, c.ext_dcal, ext ? c.ext_it : -1, w.status};
     dim3 gv = L.grid;
     if (ext) gv.z += L.mg.nmarch;
     const int s0 = ext ? -1 : 0;
+    // bands of the saved levels ride on the half steps: the p cells of level it on the v launch,
+    // the v cells of level it + 1 on the p launch (planes after the shots)
+    const int nqb = (int)((pl.band.B + 255) / 256);
+    auto band_planes = [&](const dim3 &gr) {
+        const long long per = (long long)gr.x * gr.y;
+        return (unsigned)(((long long)pl.nshot * nqb + per - 1) / per);
+    };
+    const long long sstride = (long long)pl.nsave * pl.band.B;
+    BandArg svp{}, svv{};
+    int zp = 0, zv = 0;
+    if (c.save_p_slot >= 0) {
+        svp = BandArg{w.bdesc, w.bands + (size_t)c.save_p_slot * pl.band.B, sstride, nqb, pl.nshot};
+        zp = (int)gv.z;
+        gv.z += band_planes(gv);
+    }
+    dim3 gp = L.grid;
+    if (c.save_v_slot >= 0) {
+        svv = BandArg{w.bdesc, w.bands + (size_t)c.save_v_slot * pl.band.B, sstride, nqb, pl.nshot};
+        zv = (int)gp.z;
+        gp.z += band_planes(gp);
+    }
     if (c.ev) {
         hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, c.ev[0], c.ev[1],
-                              0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex);
+                              0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex, svp, zp);
         SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
-        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st,
+        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
-                              (const float *)nullptr, (float *)nullptr);
+                              (const float *)nullptr, (float *)nullptr, svv, zv);
         return fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
     }
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, pl.geom, w.f, w.model,
-                       w.cpml, box, s0, L.mg, ex);
+                       w.cpml, box, s0, L.mg, ex, svp, zp);
     SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
-    hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), L.grid, L.block, 0, c.st, pl.geom,
+    hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
-                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
+                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr, svv, zv);
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
 }
@@ -1336,17 +1377,17 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
-                       w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr});
+                       w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr}, BandArg{}, 0);
     SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
     if (image)
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                            w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
-                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
+                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i, BandArg{}, 0);
     else
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, false>), L.grid, L.block, 0, c.st,
                            pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
                            (const long long *)w.src_cell, c.stf, pl.g.nt, it,
-                           (const float *)w.f.p, w.acc_i);
+                           (const float *)w.f.p, w.acc_i, BandArg{}, 0);
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
 }
@@ -1431,7 +1472,7 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
     const MLaunch LR = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
     const MLaunch LA = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
     const bool band = pl.g.dr == 1;
-    const BandArg ba{pl.band, w.bands + (size_t)it * pl.band.B, (long long)pl.nsave * pl.band.B,
+    const BandArg ba{w.bdesc, w.bands + (size_t)it * pl.band.B, (long long)pl.nsave * pl.band.B,
                      (int)((pl.band.B + 255) / 256), pl.nshot};
     dim3 grid(std::max(LR.grid.x, LA.grid.x), std::max(LR.grid.y, LA.grid.y), 2u * pl.nshot);
     if (band) {
@@ -1577,6 +1618,16 @@ hipError_t src_taps(const StepCtx &c, int it, float *p, float sign) {
     // an injection on a free-surface grid is followed by the images of what it added (the
     // removal in the reconstruction is not: the rows above the surface come from the bands)
     if (sign > 0.f) SMI_TRY(fs_launch(pl, c.st, p, 1, 0, pl.nshot));
+    return hipGetLastError();
+}
+
+hipError_t band_save_part(const StepCtx &c, const Fields &f, int slot, int which) {
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    long long ss = (long long)pl.nsave * pl.band.B;
+    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
+                       f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
+                       ss, 0, 0, which, 0.f);
     return hipGetLastError();
 }
 

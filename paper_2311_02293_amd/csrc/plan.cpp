@@ -421,6 +421,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     pl.off_status = take(64);
     pl.off_misfit = take(16);
+    pl.off_bdesc = take(sizeof(BandDesc));
     pl.npartial = std::max(1024, acq->nshot);   // also holds the per-shot peak illumination
     pl.off_partial = take(sizeof(double) * pl.npartial);
     pl.off_model = take(sizeof(float) * (size_t)pl.P * (1 + pl.nd));
@@ -452,6 +453,7 @@ Views views(const Plan &pl, void *ws) {
     char *b = (char *)ws;
     Views w{};
     w.status = (unsigned *)(b + pl.off_status);
+    w.bdesc = (const BandDesc *)(b + pl.off_bdesc);
     w.misfit_tmp = (double *)(b + pl.off_misfit);
     w.partial = (double *)(b + pl.off_partial);
     float *m = (float *)(b + pl.off_model);

@@ -121,7 +121,7 @@ struct Plan {
     int nrun = 0;       // forward steps: nt, or past nt until the last saved level (dr > 1)
     Geom geom{};
     // workspace layout (byte offsets)
-    size_t off_status = 0, off_misfit = 0, off_partial = 0;
+    size_t off_status = 0, off_misfit = 0, off_partial = 0, off_bdesc = 0;
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
     size_t off_rho = 0;
@@ -153,6 +153,7 @@ void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vecto
 
 struct Views {
     unsigned *status;
+    const BandDesc *bdesc;  // copy of the plan's band layout in device memory
     double *misfit_tmp;
     double *partial;
     Model model;
@@ -199,6 +200,11 @@ struct StepCtx {
     // step's v launch (register-blocked kernels only, see march_forward); -1: none pending
     int ext_it = -1;
     float *ext_dcal = nullptr;
+    // band cells of saved levels carried by the register-blocked forward half steps: the p
+    // cells of level it on the v launch of step it, the v cells of level it + 1 on the p launch
+    // of step it (-1: none)
+    int save_p_slot = -1;
+    int save_v_slot = -1;
 };
 
 hipError_t fwd_step(const StepCtx &c, int it);
@@ -218,6 +224,8 @@ hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p = nullp
 // nodes (one-tap sources are injected inside the p kernels); nothing when there are none
 hipError_t src_taps(const StepCtx &c, int it, float *p, float sign);
 hipError_t band_save(const StepCtx &c, const Fields &f, int slot);
+// the p (which 0) or v (which 1) cells of a saved level
+hipError_t band_save_part(const StepCtx &c, const Fields &f, int slot, int which);
 hipError_t band_restore(const StepCtx &c, int it, int which);
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
 hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a);
