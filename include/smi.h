@@ -129,7 +129,9 @@ typedef enum {
                                 samples collected so far. */
     SMI_OPT_TILEMAP = 4,     /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
                                 then x-block); 1 each of the 8 XCDs takes a contiguous range of
-                                x-blocks, so tiles that share halos share an L2 */
+                                x-blocks, so tiles that share halos share an L2; 2 (3D, kernel
+                                3) each XCD takes a contiguous range of tiles ordered y-strip
+                                fastest, so a tile's y-neighbours run just before it there */
     SMI_OPT_FAMILY = 5,      /* parametrisation of the gradients (Sec. 2.2): 1 (default) (Vp, rho):
                                 grad_vp = dJ/dVp at fixed rho, grad_rho = dJ/drho at fixed Vp;
                                 2 (Vp, Ip = rho Vp): grad_vp = dJ/dVp at fixed Ip, grad_rho =

@@ -66,6 +66,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.xcd = false;
     c.y3 = 0;
     c.zl = false;
+    c.ymap = false;
     c.rev = ctx->opt_rev;
     if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
@@ -77,7 +78,8 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
         const int cm = ctx->opt_chunk % 100;
         c.march = cm == 2 || cm == 8 ? cm : 4;
         c.zl = ctx->opt_chunk >= 100;
-        c.xcd = ctx->opt_xcd != 0;
+        c.xcd = ctx->opt_xcd == 1;
+        c.ymap = ctx->opt_xcd == 2 && pl.nd == 3;
     } else if (ctx->opt_kernel == 4) {
         c.xcd = ctx->opt_xcd != 0;
     } else if (ctx->opt_kernel == 5) {
@@ -125,7 +127,7 @@ struct Key {
 Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
     Key k;
     k.put(tag).put(pl.geom).put(pl.band).put(pl.nshot).put(pl.nrun).put(pl.nsave);
-    k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl).put(c.rev);
+    k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl).put(c.rev).put(c.ymap);
     k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
     return k;
 }
@@ -493,7 +495,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
-    if (option == SMI_OPT_TILEMAP && (value == 0 || value == 1)) { ctx->opt_xcd = value; return SMI_OK; }
+    if (option == SMI_OPT_TILEMAP && value >= 0 && value <= 2) { ctx->opt_xcd = value; return SMI_OK; }
     if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
     if (option == SMI_OPT_TIMING && value >= 0) {
         ctx->opt_timing = value;

@@ -222,6 +222,11 @@ struct MG {
     int nmarch;         // march strips per shot along the march axis (3D: grid z = strip + nmarch shot)
     int nxc;            // > 0: XCD-contiguous order, blockIdx.x & 7 = XCD, which takes nxc
                         // consecutive blocks of x (2D: march strips, 3D: 4-column groups)
+    // 3D y-strip order (ymap = 1, one-dimensional grid): the tiles (shot, z-block, x-group,
+    // y-strip), y-strip fastest, are cut into 8 contiguous ranges of `per` tiles, one per XCD
+    // (blockIdx.x & 7), so that a tile's y-neighbours run just before it on the same XCD and
+    // its y-halo planes are still in that XCD's L2
+    int gz, gx, per, ntile, ymap;
 };
 
 // Receiver sampling of the previous step carried by a v launch (it < 0: none).  The v update
@@ -322,17 +327,30 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.zb1 = b[1];
         c.run = c.lo < c.hi && c.z - lane < b[1];
     } else {
-        const int strip = (int)blockIdx.z % mg.nmarch;
+        int strip = (int)blockIdx.z % mg.nmarch;
         c.s = shot0 + (int)blockIdx.z / mg.nmarch;
+        int zb3 = bz, xg3 = bx;
+        bool live = true;
+        if (mg.ymap) {
+            const int t = ((int)blockIdx.x & 7) * mg.per + ((int)blockIdx.x >> 3);
+            live = t < mg.ntile;
+            const int tt = live ? t : 0;
+            strip = tt % mg.nmarch;
+            int r = tt / mg.nmarch;
+            xg3 = r % mg.gx;
+            r /= mg.gx;
+            zb3 = r % mg.gz;
+            c.s = shot0 + r / mg.gz;
+        }
         const int *b = box + 6 * c.s;
-        c.z = zalign(b[0]) + bz * 64 + lane;
-        c.x = b[2] + bx * 4 + wv;
+        c.z = zalign(b[0]) + zb3 * 64 + lane;
+        c.x = b[2] + xg3 * 4 + wv;
         c.lo = b[4] + strip * CM;
         c.hi = min(c.lo + CM, b[5]);
         c.y = c.lo;
         c.zb0 = b[0];
         c.zb1 = b[1];
-        c.run = c.lo < c.hi && c.x < b[3] && c.z - lane < b[1];
+        c.run = live && c.lo < c.hi && c.x < b[3] && c.z - lane < b[1];
     }
     // in a grid shared with another half step, blocks past this one's x-blocks per XCD would
     // repeat the next XCD's blocks
@@ -1263,7 +1281,7 @@ struct MLaunch {
 };
 
 MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1,
-                     int cm, bool xcd) {
+                     int cm, bool xcd, bool ymap = false) {
     int ez = 0, ex = 0, ey = 0;
     for (int s = s0; s < s1; ++s) {
         const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
@@ -1283,8 +1301,15 @@ MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0
         gz = std::max(1, (ez + 63) / 64);
         gx = std::max(1, (ex + 3) / 4);
     }
+    if (pl.nd == 3 && ymap) {
+        const int ntile = (s1 - s0) * gz * gx * nm;
+        const int per = (ntile + 7) / 8;
+        L.mg = MG{nm, 0, gz, gx, per, ntile, 1};
+        L.grid = dim3((unsigned)(8 * per), 1u, 1u);
+        return L;
+    }
     const int nxc = xcd ? (gx + 7) / 8 : 0;
-    L.mg = MG{nm, nxc};
+    L.mg = MG{nm, nxc, 0, 0, 0, 0, 0};
     L.grid = dim3((unsigned)(xcd ? 8 * gz : gz), (unsigned)(xcd ? nxc : gx), (unsigned)((s1 - s0) * nm));
     return L;
 }
@@ -1315,7 +1340,7 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd);
+    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
     const bool ext = c.ext_it >= 0 && w.recv.R > 0;
     if (L.empty) {
         // nothing to update: the carried work runs on its own
@@ -1374,7 +1399,7 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
+    MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr}, BandArg{}, 0);
@@ -1439,7 +1464,7 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
+    MLaunch L = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
     if (!L.empty) {
 #define SMI_MRECON_P(G_, L_)                                                                   \
     hipLaunchKernelGGL((k_march_recon_p<ND, N, CM, ZL, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, \
@@ -1590,7 +1615,8 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
 hipError_t fwd_step(const StepCtx &c, int it) { SMI_DISPATCH(fwd_step_t, c, it); }
 
 bool march_forward(const StepCtx &c) {
-    return !c.plain && c.march && !(c.y3 && c.pl->nd == 3);
+    // (the y-strip order uses a one-dimensional grid: no planes to carry other work)
+    return !c.plain && c.march && !(c.y3 && c.pl->nd == 3) && !c.ymap;
 }
 
 hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {

@@ -133,8 +133,10 @@ def test_xcd_tile_order_is_bitwise_identical(ctx, ndim, kernel):
     assert np.abs(outs[0][1]).max() > 0
 
 
-@pytest.mark.parametrize("ndim,cm", [(2, 2), (2, 4), (2, 8), (3, 2), (3, 4), (2, 104), (2, 108), (3, 102), (3, 104)])
-def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm):
+@pytest.mark.parametrize("ndim,cm,tmap", [(2, 2, 0), (2, 4, 0), (2, 8, 0), (3, 2, 0), (3, 4, 0),
+                                          (2, 104, 0), (2, 108, 0), (3, 102, 0), (3, 104, 0),
+                                          (3, 2, 2), (3, 4, 2), (3, 102, 2)])
+def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm, tmap):
     """The register-blocked half steps (cm cells per lane along the slowest axis) compute the
     one-cell-per-lane sweep kernels' update: forward data and FWI gradient agree to rounding,
     and the data also match the oracle."""
@@ -143,7 +145,7 @@ def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm):
         job = with_bounds(I.config2(n1=70, n2=230, nt=300, nshot=3, box=1))
     else:
         job = with_bounds(I.config4(n=40, nt=160, dr=1, nshot=2, rec_step=4))
-    say("marching kernels", ndim, cm, job.grid)
+    say("marching kernels", ndim, cm, tmap, job.grid)
     vp, rho, stf = dev(job)
     ctx.set_option(B.OPT_KERNEL, 4)
     try:
@@ -154,12 +156,14 @@ def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm):
         ctx.set_option(B.OPT_KERNEL, 0)
     ctx.set_option(B.OPT_KERNEL, 3)
     ctx.set_option(B.OPT_CHUNK, cm)
+    ctx.set_option(B.OPT_TILEMAP, tmap)     # 2: 3D y-strip-fastest order per XCD
     try:
         got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
         g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
     finally:
         ctx.set_option(B.OPT_KERNEL, 0)
         ctx.set_option(B.OPT_CHUNK, 0)
+        ctx.set_option(B.OPT_TILEMAP, 0)
     got, ref = got.cpu().numpy(), ref.cpu().numpy()
     assert rel_l2(got, ref) <= 1e-6
     assert rel_l2(g.cpu().numpy(), gref.cpu().numpy()) <= 1e-5
