@@ -96,6 +96,60 @@ def counter_traffic():
         return None
 
 
+def latency(torch):
+    """Per-call latency of the four fixed workloads: repetitions of the library call after two
+    warm-ups, each timed with events on the call's stream; one JSON line per workload."""
+    from paper_2311_02293_amd import binding as B
+    from paper_2311_02293_amd import inputs as I
+
+    ctx = B.Context(0)
+    stream = torch.cuda.current_stream()
+    cases = [("2d-forward-201x201-order4-1shot", I.config1(), "forward", 20),
+             ("2d-batched-forward-500x1500-order8-16shots", I.config2(), "forward", 20),
+             ("2d-fwi-gradient-300x900-order8-32shots", I.config3(), "grad", 20),
+             ("3d-rtm-400^3-order8-4shots-dr10", I.config4(), "rtm", 2)]
+    for name, job, kind, reps in cases:
+        vs = [job.vp] + ([job.extra["vp_true"]] if "vp_true" in job.extra else [])
+        job.grid.vpmin = float(min(v.min() for v in vs))
+        job.grid.vpmax = float(max(v.max() for v in vs))
+        vp, rho, stf = (torch.from_numpy(np.ascontiguousarray(a)).cuda()
+                        for a in (job.vp, job.rho, job.stf))
+        jt = {"forward": B.JOB_FORWARD, "grad": B.JOB_GRAD, "rtm": B.JOB_RTM}[kind]
+        ws = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, jt))
+        dobs = None
+        if kind != "forward":
+            vt = torch.from_numpy(job.extra["vp_true"]).cuda()
+            dobs, _, _ = ctx.forward(job.grid, job.acq, vt, rho, stf)
+
+        def call():
+            if kind == "forward":
+                ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=stream)
+            elif kind == "grad":
+                ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs, ws=ws, stream=stream)
+            else:
+                ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs, ws=ws, stream=stream)
+        print(f"bench: latency {name}", file=sys.stderr, flush=True)
+        for w in range(2):
+            call()
+            torch.cuda.synchronize()
+            print(f"bench: {name} warm-up {w} done", file=sys.stderr, flush=True)
+        ms = []
+        for r in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            call()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+            print(f"bench: {name} rep {r}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+        upd = sum(ctx.last_counts())
+        print(json.dumps({"metric": "per-call latency", "workload": name, "call": kind, "reps": reps,
+                          "warmup": 2, "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
+                          "GPts_s": upd / (np.median(ms) / 1e3) / 1e9,
+                          "data": "synthetic", "dtype": "f32"}), flush=True)
+        del ws, dobs
+
+
 def serve(torch, njobs: int):
     """Served stream of mixed requests: a capacity run (every request queued at t = 0), then the
     same requests arriving as a Poisson stream at 0.7 x that capacity (latency p50 / p99), then
@@ -184,6 +238,9 @@ def main():
                     help="device-stamp the step kernels of every k-th time step (0: off)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--latency", action="store_true",
+                    help="per-call latency p50 / p99 of the four fixed workloads (2D forward one "
+                         "shot, 2D batched forward, 2D gradient, 3D RTM) instead of the benchmark")
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
@@ -199,6 +256,9 @@ def main():
         return
     if args.serve > 0:
         serve(torch, args.serve)
+        return
+    if args.latency:
+        latency(torch)
         return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
