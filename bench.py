@@ -96,18 +96,23 @@ def counter_traffic():
         return None
 
 
-def latency(torch):
+def latency(torch, graph: bool = False):
     """Per-call latency of the four fixed workloads: repetitions of the library call after two
-    warm-ups, each timed with events on the call's stream; one JSON line per workload."""
+    warm-ups, each timed with events on the call's stream; one JSON line per workload.  With
+    `graph`, the two forward workloads with their time loops replayed as HIP graphs."""
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
 
     ctx = B.Context(0)
+    if graph:
+        ctx.set_option(B.OPT_GRAPH, 1)
     stream = torch.cuda.current_stream()
     cases = [("2d-forward-201x201-order4-1shot", I.config1(), "forward", 20),
              ("2d-batched-forward-500x1500-order8-16shots", I.config2(), "forward", 20),
              ("2d-fwi-gradient-300x900-order8-32shots", I.config3(), "grad", 20),
              ("3d-rtm-400^3-order8-4shots-dr10", I.config4(), "rtm", 2)]
+    if graph:
+        cases = [c for c in cases if c[2] == "forward"]
     for name, job, kind, reps in cases:
         vs = [job.vp] + ([job.extra["vp_true"]] if "vp_true" in job.extra else [])
         job.grid.vpmin = float(min(v.min() for v in vs))
@@ -121,9 +126,12 @@ def latency(torch):
             vt = torch.from_numpy(job.extra["vp_true"]).cuda()
             dobs, _, _ = ctx.forward(job.grid, job.acq, vt, rho, stf)
 
+        # one output buffer for every call (a captured graph is keyed by its buffers)
+        dcal = torch.empty(job.grid.nt * int(job.acq.rec_off[-1]), dtype=torch.float32, device="cuda")
+
         def call():
             if kind == "forward":
-                ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=stream)
+                ctx.forward(job.grid, job.acq, vp, rho, stf, dcal=dcal, ws=ws, stream=stream)
             elif kind == "grad":
                 ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs, ws=ws, stream=stream)
             else:
@@ -143,7 +151,8 @@ def latency(torch):
             ms.append(a.elapsed_time(b))
             print(f"bench: {name} rep {r}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
         upd = sum(ctx.last_counts())
-        print(json.dumps({"metric": "per-call latency", "workload": name, "call": kind, "reps": reps,
+        print(json.dumps({"metric": "per-call latency", "workload": name, "call": kind,
+                          "graph_replay": graph, "reps": reps,
                           "warmup": 2, "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
                           "GPts_s": upd / (np.median(ms) / 1e3) / 1e9,
                           "data": "synthetic", "dtype": "f32"}), flush=True)
@@ -241,6 +250,9 @@ def main():
     ap.add_argument("--latency", action="store_true",
                     help="per-call latency p50 / p99 of the four fixed workloads (2D forward one "
                          "shot, 2D batched forward, 2D gradient, 3D RTM) instead of the benchmark")
+    ap.add_argument("--latency-graph", action="store_true",
+                    help="as --latency for the two forward workloads, with the time loop replayed "
+                         "as a HIP graph (SMI_OPT_GRAPH)")
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
@@ -257,8 +269,8 @@ def main():
     if args.serve > 0:
         serve(torch, args.serve)
         return
-    if args.latency:
-        latency(torch)
+    if args.latency or args.latency_graph:
+        latency(torch, graph=args.latency_graph)
         return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
