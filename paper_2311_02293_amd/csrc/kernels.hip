@@ -3,10 +3,19 @@
 // reconstruction (Sec. 4.2), adjoint propagation and gradient / image accumulation (eq. 7,
 // 8, 10), misfit (eq. 6) and the shot reduction.
 //
-// These are the sweep kernels: one lane per cell, 64 consecutive z cells per wavefront (a
-// 256-byte coalesced row), 4 x-columns per 256-lane workgroup; neighbours come from the
-// L1/L2 caches.  Each launch covers one time step of every shot of the batch, restricted to
-// that shot's computing box (grid z-dimension = shot x y-plane).
+// Two families of half-step kernels cover one time step of every shot of the batch per
+// launch, each shot restricted to its computing box:
+//   * sweep kernels (k_step_*, k_recon_*): one lane per cell, 64 consecutive z cells per
+//     wavefront (a 256-byte coalesced row), 4 x-columns per 256-lane workgroup, neighbours
+//     from the L1/L2 caches -- the plain stepper and an option;
+//   * register-blocked kernels (k_march_*, the default): a lane updates a short run of cells
+//     along the slowest axis from one register window of the stencil along that axis, with
+//     every load issued before the arithmetic, in an XCD-contiguous tile order in 2D.
+// The register-blocked launches also carry small side work on extra workgroups (receiver
+// sampling of the previous step, band cells of saved levels), and the 2D reverse step of small
+// batches runs its reconstruction and adjoint half steps on one shared grid (k_rev_*).  The
+// free surface (image method), the density face sums, the tangent-linear source and the
+// small data kernels (bands, receivers, adjoint sources, misfit, reductions) close the file.
 #include <cmath>
 
 #include <hip/hip_ext.h>
