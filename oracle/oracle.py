@@ -95,7 +95,7 @@ def lib():
                                  ip, dp, tp, tp]
         L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp, tp]
         L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp, dp,
-                                 tp, tp]
+                                 tp, tp, C.c_int]
         L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, tp, tp]
         _lib = L
     return _lib
@@ -309,9 +309,11 @@ def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int
 
 
 def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, final=None,
-            want=("gk", "image", "illum"), st: Optional[Taps] = None, rt: Optional[Taps] = None):
+            want=("gk", "image", "illum"), st: Optional[Taps] = None, rt: Optional[Taps] = None,
+            literal: bool = False):
     """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum and,
-    when "grk" is wanted, dJ/drho at fixed kappa (the buoyancy part of eq. 7)."""
+    when "grk" is wanted, dJ/drho at fixed kappa (the buoyancy part of eq. 7).  `literal` takes
+    gk after both updates of each iteration, where Alg. 2 writes it (a comparison only)."""
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -327,7 +329,7 @@ def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, fin
                           _d(G), _d(None if hist is None else np.ascontiguousarray(hist)),
                           _d(None if bands is None else np.ascontiguousarray(bands)),
                           _d(None if final is None else np.ascontiguousarray(final)),
-                          _d(gk), _d(im), _d(il), _d(grk), _tp(st), _tp(rt))
+                          _d(gk), _d(im), _d(il), _d(grk), _tp(st), _tp(rt), int(literal))
     if rc:
         raise RuntimeError("og_adjoint failed: %d" % rc)
     return {"gk": gk, "image": im, "illum": il, "grk": grk}

@@ -712,10 +712,28 @@ static void og_rho_faces(const og_model *m, const og_field *q, const og_field *f
     }
 }
 
+/* g_kappa += dt (p~ / kappa) (-div v) over the interior (eq. 7, kappa part) */
+static void og_grad_kappa(const og_model *m, const og_field *q, const og_field *f, double *gk)
+{
+    int nb = m->g.nb;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int i3 = 0; i3 < m->n[2]; i3++)
+        for (int i2 = 0; i2 < m->n[1]; i2++)
+            for (int i1 = 0; i1 < m->n[0]; i1++) {
+                int j3 = m->nd == 3 ? i3 + nb : 0;
+                size_t k = IDX(m, i1 + nb, i2 + nb, j3);
+                size_t s = (size_t)i1 + (size_t)m->n[0] * ((size_t)i2 + (size_t)m->n[1] * i3);
+                gk[s] += m->g.dt * (q->p[k] / m->kap[k]) * (-divv(m, f, i1 + nb, i2 + nb, j3));
+            }
+}
+
+/* literal != 0: the kappa gradient is taken where Alg. 2 writes it, after both updates of the
+ * iteration (p~ at level it before the next injection, with v^{it-1/2}) -- a variant kept only
+ * to show that it differs from the exact pairing at receiver cells alone. */
 int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, const double *G, const double *hist,
                const double *bands, const double *final_state, double *gk, double *image,
-               double *illum, double *grk, const og_taps *st, const og_taps *rt)
+               double *illum, double *grk, const og_taps *st, const og_taps *rt, int literal)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -735,22 +753,13 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
             og_fs_p(&m, q.p, flo, fhi);
         }
         if (hist) og_state_set(&m, &f, hist + (size_t)(it + 1) * 4 * m.P); /* v^{it+1/2} */
-        if (gk) {
-#pragma omp parallel for collapse(2) schedule(static)
-            for (int i3 = 0; i3 < m.n[2]; i3++)
-                for (int i2 = 0; i2 < m.n[1]; i2++)
-                    for (int i1 = 0; i1 < m.n[0]; i1++) {
-                        int j3 = m.nd == 3 ? i3 + nb : 0;
-                        size_t k = IDX(&m, i1 + nb, i2 + nb, j3);
-                        size_t s = (size_t)i1 + (size_t)m.n[0] * ((size_t)i2 + (size_t)m.n[1] * i3);
-                        gk[s] += g->dt * (q.p[k] / m.kap[k]) * (-divv(&m, &f, i1 + nb, i2 + nb, j3));
-                    }
-        }
+        if (gk && !literal) og_grad_kappa(&m, &q, &f, gk);
         int lo[3], hi[3];
         og_adj_box_m(&m, nrec, rec, it, lo, hi);
         og_step(&m, &q, lo, hi);
         if (hist) og_state_set(&m, &f, hist + (size_t)it * 4 * m.P);
         else og_recon_iter(&m, &f, src, stf, bands, it, st);
+        if (gk && literal) og_grad_kappa(&m, &q, &f, gk);
         if (image || illum) {
 #pragma omp parallel for collapse(2) schedule(static)
             for (int i3 = 0; i3 < m.n[2]; i3++)

@@ -817,3 +817,36 @@ def test_dot_product_with_free_surface_is_exact(oracle, ndim):
     adjoint sources near the surface receive their images like the forward sources, and the
     same solver is then the exact transpose."""
     assert _dot_case(oracle, 0, ndim, freesurf=1) <= 1e-12
+
+
+# ----------------------------------------------------------------------------- P16
+
+def test_literal_gradient_position_differs_only_at_receiver_cells(oracle):
+    """Reading of the gradient time pairing (Alg. 2 writes the gradient after both updates of
+    an iteration): taking it there pairs p~ before the next adjoint injection, and the sum
+    over the iterations differs from the exact pairing (p~ right after its own injection) only
+    at the receiver cells: bitwise equal everywhere else with the stored history; with the
+    reconstruction from bands the literal sum also takes p~^0 times the rebuilt v^{-1/2}, which
+    is zero up to the reconstruction's rounding."""
+    g = small_grid(order=4, n1=40, n2=56, nt=300, nb=10, fm=15.0)
+    vp, rho = smooth_random_model(g.n1, g.n2, 31, vmin=1800.0, vmax=2500.0)
+    sx = np.array([28.0]) * g.d2
+    acq = I._surface_line(sx, 3 * g.d1, np.arange(4, g.n2 - 4, 3) * g.d2, 5 * g.d1)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    gr = oracle.og_grid(g, vmax=2600.0)
+    src, rec = oracle.shot_nodes(g, acq, 0)
+    fw = oracle.forward(gr, vp, rho, src, stf, rec, hist=True, bands=True, final=True)
+    G = g.dt * fw["dcal"] * np.linspace(0.5, 1.5, rec.shape[0])[None, :]
+    nb = g.nb
+    onrec = np.zeros((g.n2, g.n1), bool)
+    onrec[rec[:, 1] - nb, rec[:, 0] - nb] = True
+    for kw in ({"hist": fw["hist"]}, {"bands": fw["bands"], "final": fw["final"]}):
+        ex = oracle.adjoint(gr, vp, rho, src, stf, rec, G, want=("gk",), **kw)["gk"]
+        li = oracle.adjoint(gr, vp, rho, src, stf, rec, G, want=("gk",), literal=True, **kw)["gk"]
+        ex, li = ex.reshape(g.n2, g.n1), li.reshape(g.n2, g.n1)
+        if "hist" in kw:
+            np.testing.assert_array_equal(ex[~onrec], li[~onrec])
+        else:
+            assert np.max(np.abs(ex[~onrec] - li[~onrec])) <= 1e-12 * np.abs(ex).max()
+        d = np.abs(ex[onrec] - li[onrec])
+        assert np.all(d > 0) and d.max() > 1e-3 * np.abs(ex).max()
