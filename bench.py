@@ -258,7 +258,7 @@ def main():
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not provided "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not provided "
                                    "(shots would shard across GPUs with one gradient all-reduce)"}))
         sys.exit(2)
 
