@@ -94,3 +94,20 @@ def test_laplacian_rejects_bad_arguments_on_the_host():
     L = B.lib()
     g = B.make_grid(I.Grid(ndim=2, n1=8, n2=8, d1=1.0, d2=1.0, nb=4, order=4, nt=1, dt=1e-3, fm=1.0))
     assert L.smi_laplacian(None, C.byref(g), None, None, None) == -1
+
+
+def test_binding_constants_match_the_header():
+    """Every status, job and option value the binding uses is the one include/smi.h declares,
+    and SmiGrid has the header's field order."""
+    txt = open(os.path.join(ROOT, "include", "smi.h")).read()
+    decl = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(SMI_[A-Z_]+)\s*=\s*(-?\d+)", txt)}
+    for code, name in B.STATUS.items():
+        assert decl[name] == code, name
+    for short in ("FORWARD", "FORWARD_SAVE", "RTM", "GRAD", "BORN"):
+        assert decl["SMI_JOB_" + short] == getattr(B, "JOB_" + short), short
+    for short in ("KERNEL", "GRAPH", "CHUNK", "TIMING", "TILEMAP", "FAMILY", "REVERSE"):
+        assert decl["SMI_OPT_" + short] == getattr(B, "OPT_" + short), short
+    body = txt[txt.index("typedef struct {", txt.index("smi_grid") - 2000):txt.index("} smi_grid;")]
+    fields = re.findall(r"\b(?:int|double)\s+([a-z0-9_, ]+);", body)
+    names = [f.strip() for grp in fields for f in grp.split(",")]
+    assert names == [f for f, _ in B.SmiGrid._fields_], (names, [f for f, _ in B.SmiGrid._fields_])
