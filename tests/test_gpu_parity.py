@@ -817,3 +817,52 @@ def test_two_and_five_launch_reverse_steps_agree(ctx, dr):
     for a, b in zip(out[1], out[2]):
         np.testing.assert_array_equal(a, b)
     assert np.abs(out[1][0]).max() > 0 and np.abs(out[1][2]).max() > 0
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_order4_reverse_path_matches_oracle(ctx, ndim):
+    """Order 4 (N = 2) through the whole path: seismograms, both gradients (family 1), the
+    image and illumination, and Born data against the oracle, in 2D and 3D."""
+    from oracle import oracle as O
+    import torch
+    from paper_2311_02293_amd import binding as B
+    if ndim == 2:
+        job = _grad_job(nt=500, nshot=2)
+    else:
+        job = with_bounds(I.config4(n=32, nt=180, nshot=1, dr=1, rec_step=4))
+        job.grid.vpmax = float(max(job.grid.vpmax, np.max(job.extra["vp_true"])))
+    job.grid.order = 4
+    job.grid.fm = 9.0                      # enough points per wavelength at order 4
+    job.stf = np.repeat(I.ricker(job.grid.nt, job.grid.dt, 9.0)[None, :], job.acq.nshot, 0).astype(np.float32)
+    vmax = float(job.grid.vpmax)
+    say("order 4", ndim, job.grid)
+    vp, rho, stf = dev(job)
+    dcal, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    got = split(dcal, job)
+    ref = O.forward_job(job, vmax=vmax, box=0)
+    for s in range(job.acq.nshot):
+        assert rel_l2(got[s], ref[s]) <= 1e-4
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    r1, r2, rJ = O.fwi_grad_family(job, dobs, 1, vmax=vmax, box=0)
+    g1, g2, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs_t, rho_grad=True)
+    e1 = rel_l2(g1.cpu().numpy().reshape(job.vp.shape), r1)
+    e2 = rel_l2(g2.cpu().numpy().reshape(job.vp.shape), r2)
+    ims, ils = O.rtm_image(job, dobs, vmax=vmax, box=0, per_shot=True)
+    im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    ei = rel_l2(im.cpu().numpy().reshape(job.vp.shape), np.sum(ims, 0))
+    el = rel_l2(il.cpu().numpy().reshape(job.vp.shape), np.sum(ils, 0))
+    kap = job.rho.astype(np.float64) * job.vp.astype(np.float64) ** 2
+    dk = np.zeros_like(kap)
+    sl = (slice(10, 22), slice(10, 22), slice(8, 20)) if ndim == 3 else (slice(60, 100), slice(10, 30))
+    dk[sl] = 0.05 * kap[sl]
+    dd = ctx.born(job.grid, job.acq, vp, rho, stf, torch.from_numpy(dk.astype(np.float32).ravel()).cuda())
+    gotb = [d.cpu().numpy() for d in B.split_dcal(dd, job.acq, job.grid.nt)]
+    gr = O.og_grid(job.grid, vmax=vmax, box=0)
+    eb = 0.0
+    for s in range(job.acq.nshot):
+        src, rec = O.shot_nodes(job.grid, job.acq, s)
+        eb = max(eb, rel_l2(gotb[s], O.born(gr, job.vp, job.rho, src, job.stf[s], rec, dk)))
+    say("order 4", ndim, "grad", e1, e2, "image", ei, el, "born", eb)
+    assert abs(float(J.cpu()[0]) - rJ) <= 1e-4 * rJ
+    assert max(e1, e2, ei, el, eb) <= 1e-4
