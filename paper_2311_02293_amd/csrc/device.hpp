@@ -24,6 +24,16 @@ __device__ __forceinline__ float ldz(const float *__restrict__ f, long long k, i
     return ok ? v : 0.f;
 }
 
+// The amplitude a source adds to p at one node, rounded once: contraction is off here, so the
+// product never fuses with the add or subtract that uses it (a plain product, or __fmul_rn,
+// which HIP defines as one, would become an FMA there).  The forward injection adds this value
+// and the reconstruction subtracts the same value, so a node that held zero before the
+// injection returns to exactly zero.
+__device__ __forceinline__ float src_amp(float scale, float stf) {
+#pragma clang fp contract(off)
+    return scale * stf;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Give each
 // XCD a contiguous range of logical work items so that neighbouring tiles, which share halos
 // and model data, are resident in the same L2.

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_fused2d(Geom g, Fields src, Fields dst,
             ex += psi;
         }
         float pn = pw[H + t] - kd[t] * (ez + ex);
-        if (it < nt && k == sc) pn += g.src_scale * stf[(long long)s * nt + it];
+        if (it < nt && k == sc) pn += src_amp(g.src_scale, stf[(long long)s * nt + it]);
         dst.p[so + k] = pn;
         dst.v[0][so + k] = vzn[t];
         dst.v[1][so + k] = vxn[N + t];
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(256) void k_fused2d_tile(Geom g, Fields src, Fields
             ex += psi;
         }
         float pn = pc[t] - kd[t] * (ez + ex);
-        if (it < nt && k == sc) pn += g.src_scale * stf[(long long)s * nt + it];
+        if (it < nt && k == sc) pn += src_amp(g.src_scale, stf[(long long)s * nt + it]);
         dst.p[so + k] = pn;
         dst.v[0][so + k] = vzn[t];
         dst.v[1][so + k] = vxn[t];

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_step_p(Geom g, Fields f, Model m, Cpml 
     }
     float *pp = f.p + c.s * g.P + c.k;
     float pn = *pp - m.kdt[c.k] * sdiv;
-    if (SRC && it < nt && c.k == src_cell[c.s]) pn += g.src_scale * stf[(long long)c.s * nt + it];
+    if (SRC && it < nt && c.k == src_cell[c.s]) pn += src_amp(g.src_scale, stf[(long long)c.s * nt + it]);
     *pp = pn;
     if (IMG) {
         int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
@@ -606,7 +606,7 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
             sdiv += e;
         }
         float pn = po[t] - kd[t] * sdiv;
-        if (SRC && it < nt && c.k == sc) pn += g.src_scale * stf[(long long)c.s * nt + it];
+        if (SRC && it < nt && c.k == sc) pn += src_amp(g.src_scale, stf[(long long)c.s * nt + it]);
         f.p[so0 + c.k] = pn;
         if (IMG) {
             int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256) void k_recon_p(Geom g, Fields f, Model m,
     for (int a = 0; a < ND; ++a) div += dminus<N>(g, f.v[a] + c.s * g.P, c, a);
     float *pp = f.p + c.s * g.P + c.k;
     float pv = *pp;
-    if (c.k == src_cell[c.s]) pv -= g.src_scale * stf[(long long)c.s * nt + it];
+    if (c.k == src_cell[c.s]) pv -= src_amp(g.src_scale, stf[(long long)c.s * nt + it]);
     // p^it vanishes on a free surface (the update gives the value before its image)
     float pn = g.fs && c.z == g.nb ? 0.f : pv + m.kdt[c.k] * div;
     *pp = pn;
@@ -758,7 +758,7 @@ __device__ __forceinline__ void march_recon_p_body(Geom g, Fields f, Model m,
             div += e;
         }
         float pv = po[t];
-        if (k == sc) pv -= g.src_scale * stf[(long long)mc.s * nt + it];
+        if (k == sc) pv -= src_amp(g.src_scale, stf[(long long)mc.s * nt + it]);
         // p^it vanishes on a free surface (the update gives the value before its image)
         const float pn = g.fs && mc.z == g.nb ? 0.f : pv + kd[t] * div;
         f.p[so0 + k] = pn;
@@ -971,7 +971,7 @@ __global__ __launch_bounds__(256) void k_src_taps(Geom g, float *p, const long l
     if (src_cell[s] >= 0) return;
     const int t = toff[s] + blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= toff[s + 1]) return;
-    p[s * g.P + tcell[t]] += sign * g.src_scale * tw[t] * stf[(long long)s * nt + it];
+    p[s * g.P + tcell[t]] += sign * src_amp(src_amp(g.src_scale, tw[t]), stf[(long long)s * nt + it]);
 }
 
 __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, float *out, long long n,

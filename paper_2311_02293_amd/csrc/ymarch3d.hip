@@ -219,7 +219,7 @@ __global__ __launch_bounds__(64 * BX) void k_y3_p(Geom g, Fields f, Model m, Cpm
                 sdiv += e;
             }
             float pn = cur.po - cur.kd * sdiv;
-            if (SRC && it < nt && k == sc) pn += g.src_scale * stf[(long long)t.s * nt + it];
+            if (SRC && it < nt && k == sc) pn += src_amp(g.src_scale, stf[(long long)t.s * nt + it]);
             f.p[so + k] = pn;
             if (IMG) {
                 const int iz = t.z - g.nb, ix = t.x - g.nb, iy = y - g.nb;
