@@ -111,3 +111,45 @@ def test_binding_constants_match_the_header():
     fields = re.findall(r"\b(?:int|double)\s+([a-z0-9_, ]+);", body)
     names = [f.strip() for grp in fields for f in grp.split(",")]
     assert names == [f for f, _ in B.SmiGrid._fields_], (names, [f for f, _ in B.SmiGrid._fields_])
+
+
+def test_degenerate_and_oversized_jobs_are_rejected_on_the_host():
+    """The planner answers before any device work: bad extents, widths, steps, decimation and
+    flags are argument errors; an order outside {4, 8} and grids beyond the launch geometry
+    (more than 4 x 65535 columns along x, more than 65535 y-planes x shots in 3D) are
+    unsupported; an acquisition without shots or with decreasing offsets is an argument
+    error; a shot without receivers is accepted."""
+    import copy
+    L = B.lib()
+    base = I.Grid(ndim=2, n1=40, n2=60, d1=10.0, d2=10.0, nb=6, order=8, nt=20, dt=1e-3,
+                  fm=10.0, box=1)
+    base.vpmin, base.vpmax = 1500.0, 2500.0
+    acq = I.Acquisition(np.array([[100.0, 200.0, 0.0], [100.0, 300.0, 0.0]]),
+                        np.array([0, 1, 1], np.int32), np.array([[50.0, 300.0, 0.0]]))
+
+    def ws(g, a=acq):
+        n = C.c_size_t()
+        aa = B._Acq(a)
+        return L.smi_workspace_bytes(None, C.byref(B.make_grid(g)), C.byref(aa.c), B.JOB_GRAD,
+                                     C.byref(n)), n.value
+
+    st, n = ws(base)
+    assert st == 0 and n > 0          # the second shot has no receivers
+    for field, bad, want in [("nt", 0, -1), ("n1", 0, -1), ("nb", 3, -1), ("dr", 0, -1),
+                             ("box", 2, -1), ("order", 6, -6), ("d1", 0.0, -1)]:
+        g = copy.copy(base)
+        setattr(g, field, bad)
+        assert ws(g)[0] == want, (field, bad)
+    g = copy.copy(base)
+    g.n2 = 4 * 65535 + 10
+    assert ws(g)[0] == -6
+    g3 = I.Grid(ndim=3, n1=16, n2=16, n3=65535, d1=10.0, d2=10.0, d3=10.0, nb=4, order=4, nt=10,
+                dt=1e-3, fm=10.0, box=1)
+    g3.vpmin, g3.vpmax = 1500.0, 2500.0
+    acq3 = I.Acquisition(np.array([[50.0, 50.0, 50.0]]), np.array([0, 1], np.int32),
+                         np.array([[20.0, 50.0, 60.0]]))
+    assert ws(g3, acq3)[0] == -6
+    none = I.Acquisition(np.zeros((0, 3)), np.array([0], np.int32), np.zeros((0, 3)))
+    assert ws(base, none)[0] == -1
+    bad_off = I.Acquisition(acq.src, np.array([0, 1, 0], np.int32), acq.rec)
+    assert ws(base, bad_off)[0] == -1
