@@ -96,10 +96,11 @@ def counter_traffic():
         return None
 
 
-def latency(torch, graph: bool = False):
+def latency(torch, graph: bool = False, only: str = "", reps_override: int = 0):
     """Per-call latency of the four fixed workloads: repetitions of the library call after two
     warm-ups, each timed with events on the call's stream; one JSON line per workload.  With
-    `graph`, the two forward workloads with their time loops replayed as HIP graphs."""
+    `graph`, the two forward workloads with their time loops replayed as HIP graphs.  `only`
+    keeps the workloads whose name contains it; `reps_override` > 0 replaces the repetitions."""
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
 
@@ -107,13 +108,18 @@ def latency(torch, graph: bool = False):
     if graph:
         ctx.set_option(B.OPT_GRAPH, 1)
     stream = torch.cuda.current_stream()
-    cases = [("2d-forward-201x201-order4-1shot", I.config1(), "forward", 20),
-             ("2d-batched-forward-500x1500-order8-16shots", I.config2(), "forward", 20),
-             ("2d-fwi-gradient-300x900-order8-32shots", I.config3(), "grad", 20),
-             ("3d-rtm-400^3-order8-4shots-dr10", I.config4(), "rtm", 2)]
+    cases = [("2d-forward-201x201-order4-1shot", I.config1, "forward", 20),
+             ("2d-batched-forward-500x1500-order8-16shots", I.config2, "forward", 20),
+             ("2d-fwi-gradient-300x900-order8-32shots", I.config3, "grad", 20),
+             ("3d-rtm-400^3-order8-4shots-dr10", I.config4, "rtm", 2)]
     if graph:
         cases = [c for c in cases if c[2] == "forward"]
-    for name, job, kind, reps in cases:
+    cases = [c for c in cases if only in c[0]]
+    if not cases:
+        raise SystemExit(f"no latency workload matches {only!r}")
+    for name, make, kind, reps in cases:
+        job = make()
+        reps = reps_override if reps_override > 0 else reps
         vs = [job.vp] + ([job.extra["vp_true"]] if "vp_true" in job.extra else [])
         job.grid.vpmin = float(min(v.min() for v in vs))
         job.grid.vpmax = float(max(v.max() for v in vs))
@@ -253,6 +259,10 @@ def main():
     ap.add_argument("--latency-graph", action="store_true",
                     help="as --latency for the two forward workloads, with the time loop replayed "
                          "as a HIP graph (SMI_OPT_GRAPH)")
+    ap.add_argument("--workload", default="",
+                    help="with --latency: only the workloads whose name contains this text")
+    ap.add_argument("--reps", type=int, default=0,
+                    help="with --latency: repetitions per workload (0: the defaults, 20 or 2)")
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
@@ -270,7 +280,7 @@ def main():
         serve(torch, args.serve)
         return
     if args.latency or args.latency_graph:
-        latency(torch, graph=args.latency_graph)
+        latency(torch, graph=args.latency_graph, only=args.workload, reps_override=args.reps)
         return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
