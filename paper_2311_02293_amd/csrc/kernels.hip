@@ -16,6 +16,7 @@
 // batches runs its reconstruction and adjoint half steps on one shared grid (k_rev_*).  The
 // free surface (image method), the density face sums, the tangent-linear source and the
 // small data kernels (bands, receivers, adjoint sources, misfit, reductions) close the file.
+#include <algorithm>
 #include <cmath>
 
 #include <hip/hip_ext.h>
@@ -234,7 +235,11 @@ struct MG {
     // 3D y-strip order (ymap = 1, one-dimensional grid): the tiles (shot, z-block, x-group,
     // y-strip), y-strip fastest, are cut into 8 contiguous ranges of `per` tiles, one per XCD
     // (blockIdx.x & 7), so that a tile's y-neighbours run just before it on the same XCD and
-    // its y-halo planes are still in that XCD's L2
+    // its y-halo planes are still in that XCD's L2.
+    // 2D shot-inner order (ymap = 2; every shot of the launch has the same box): XCD k still
+    // takes the strips [k nxc, (k + 1) nxc), but its consecutive workgroups run one tile of
+    // every shot (`per` shots, then gz z-blocks, then the strips), so the model under a tile
+    // is read once from HBM for all shots
     int gz, gx, per, ntile, ymap;
 };
 
@@ -318,13 +323,36 @@ struct MCell {
     bool need;          // this lane's row is within 4 of the box along z (z-neighbour of a cell)
 };
 
-template <int ND, int CM>
+// SI: the kernel may be launched in the 2D shot-inner order (compiled out of the forward p
+// update, whose launches never use it)
+template <int ND, int CM, bool SI = true>
 __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0, MG mg) {
     MCell c;
     const int wv = threadIdx.y, lane = threadIdx.x;
     const int bz = mg.nxc ? (int)blockIdx.x >> 3 : (int)blockIdx.x;
     const int bx = mg.nxc ? ((int)blockIdx.x & 7) * mg.nxc + (int)blockIdx.y : (int)blockIdx.y;
-    if (ND == 2) {
+    if (ND == 2 && SI && mg.ymap == 2) {
+        // planes in front of the shots (receiver sampling, or another part of a shared grid)
+        // are counted by shot0 < 0; the workgroup's rank among the shots' workgroups keeps
+        // the hardware XCD in its low 3 bits
+        const int front = shot0 < 0 ? -shot0 : 0;
+        const long long rk = (long long)blockIdx.x +
+                             (long long)gridDim.x * ((long long)blockIdx.y +
+                                                     (long long)gridDim.y * ((int)blockIdx.z - front));
+        const long long slot = rk >> 3;
+        const long long r = slot / mg.per;
+        const int sx = (int)(r / mg.gz);
+        c.s = shot0 + front + (int)(slot % mg.per);
+        const int *b = box + 6 * c.s;
+        c.z = zalign(b[0]) + ((int)(r % mg.gz) * 4 + wv) * 64 + lane;
+        c.lo = b[2] + ((int)(rk & 7) * mg.nxc + sx) * CM;
+        c.hi = min(c.lo + CM, b[3]);
+        c.x = c.lo;
+        c.y = 0;
+        c.zb0 = b[0];
+        c.zb1 = b[1];
+        c.run = sx < mg.nxc && c.lo < c.hi && c.z - lane < b[1];
+    } else if (ND == 2) {
         c.s = shot0 + (int)blockIdx.z;
         const int *b = box + 6 * c.s;
         c.z = zalign(b[0]) + (bz * 4 + wv) * 64 + lane;
@@ -363,7 +391,7 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
     }
     // in a grid shared with another half step, blocks past this one's x-blocks per XCD would
     // repeat the next XCD's blocks
-    if (mg.nxc && (int)blockIdx.y >= mg.nxc) c.run = false;
+    if (mg.nxc && mg.ymap != 2 && (int)blockIdx.y >= mg.nxc) c.run = false;
     c.ok = c.run && c.z >= c.zb0 && c.z < c.zb1;
     c.need = c.run && c.z >= c.zb0 - 4 && c.z < c.zb1 + 4;
     return c;
@@ -538,7 +566,7 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
     constexpr int NW = CM + 2 * N - 1;      // window: march offsets -N .. CM-1+N-1
     constexpr int A0 = ZL ? 1 : 0;
     __shared__ float zsh[ZL ? 4 : 1][ZL ? CM : 1][ZS];
-    MCell mc = mcell_of<ND, CM>(box, shot0, mg);
+    MCell mc = mcell_of<ND, CM, !SRC>(box, shot0, mg);
     if (ZL ? !mc.run : !mc.ok) return;
     const int cnt = mc.hi - mc.lo;
     const long long ms = MA == 1 ? (long long)g.ld1 : g.ld2;
@@ -1290,7 +1318,7 @@ struct MLaunch {
 };
 
 MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0, int s1,
-                     int cm, bool xcd, bool ymap = false) {
+                     int cm, bool xcd, bool ymap = false, bool inner = true) {
     int ez = 0, ex = 0, ey = 0;
     for (int s = s0; s < s1; ++s) {
         const int *b = &tab[((size_t)it * pl.nshot + s) * 6];
@@ -1319,6 +1347,13 @@ MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0
     }
     const int nxc = xcd ? (gx + 7) / 8 : 0;
     L.mg = MG{nm, nxc, 0, 0, 0, 0, 0};
+    // several shots with one box (the adjoint pass under a common receiver spread, or the box
+    // off): the shot-inner order shares the model of each tile in L2 across the shots
+    bool same = inner && pl.nd == 2 && xcd && s1 - s0 > 1;
+    const int *b0 = &tab[((size_t)it * pl.nshot + s0) * 6];
+    for (int s = s0 + 1; same && s < s1; ++s)
+        same = std::equal(b0, b0 + 6, &tab[((size_t)it * pl.nshot + s) * 6]);
+    if (same) L.mg = MG{nm, nxc, gz, 0, s1 - s0, 0, 2};
     L.grid = dim3((unsigned)(xcd ? 8 * gz : gz), (unsigned)(xcd ? nxc : gx), (unsigned)((s1 - s0) * nm));
     return L;
 }
@@ -1349,7 +1384,9 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
+    // the forward half steps keep the shot-outer order (the shots' boxes differ while the
+    // source fields grow, and the p update is compiled without the shot-inner order)
+    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd, c.ymap, false);
     const bool ext = c.ext_it >= 0 && w.recv.R > 0;
     if (L.empty) {
         // nothing to update: the carried work runs on its own
