@@ -239,7 +239,8 @@ struct MG {
     // 2D shot-inner order (ymap = 2; every shot of the launch has the same box): XCD k still
     // takes the strips [k nxc, (k + 1) nxc), but its consecutive workgroups run one tile of
     // every shot (`per` shots, then gz z-blocks, then the strips), so the model under a tile
-    // is read once from HBM for all shots
+    // is read once from HBM for all shots.  3D shot-inner order (ymap = 3): grid plane z holds
+    // y-strip z / per of shot z % per, so one strip of every shot runs before the next strip
     int gz, gx, per, ntile, ymap;
 };
 
@@ -366,9 +367,13 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
     } else {
         int strip = (int)blockIdx.z % mg.nmarch;
         c.s = shot0 + (int)blockIdx.z / mg.nmarch;
+        if (SI && mg.ymap == 3) {       // shot-inner: consecutive planes take one strip of every shot
+            c.s = shot0 + (int)blockIdx.z % mg.per;
+            strip = (int)blockIdx.z / mg.per;
+        }
         int zb3 = bz, xg3 = bx;
         bool live = true;
-        if (mg.ymap) {
+        if (mg.ymap == 1) {
             const int t = ((int)blockIdx.x & 7) * mg.per + ((int)blockIdx.x >> 3);
             live = t < mg.ntile;
             const int tt = live ? t : 0;
@@ -1348,12 +1353,12 @@ MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0
     const int nxc = xcd ? (gx + 7) / 8 : 0;
     L.mg = MG{nm, nxc, 0, 0, 0, 0, 0};
     // several shots with one box (the adjoint pass under a common receiver spread, or the box
-    // off): the shot-inner order shares the model of each tile in L2 across the shots
-    bool same = inner && pl.nd == 2 && xcd && s1 - s0 > 1;
+    // off): the shot-inner order shares the model of each tile across the shots
+    bool same = inner && (pl.nd == 3 || xcd) && s1 - s0 > 1;
     const int *b0 = &tab[((size_t)it * pl.nshot + s0) * 6];
     for (int s = s0 + 1; same && s < s1; ++s)
         same = std::equal(b0, b0 + 6, &tab[((size_t)it * pl.nshot + s) * 6]);
-    if (same) L.mg = MG{nm, nxc, gz, 0, s1 - s0, 0, 2};
+    if (same) L.mg = pl.nd == 2 ? MG{nm, nxc, gz, 0, s1 - s0, 0, 2} : MG{nm, nxc, 0, 0, s1 - s0, 0, 3};
     L.grid = dim3((unsigned)(xcd ? 8 * gz : gz), (unsigned)(xcd ? nxc : gx), (unsigned)((s1 - s0) * nm));
     return L;
 }

@@ -363,6 +363,33 @@ def test_rtm_3d_matches_oracle(ctx):
     assert err <= 1e-4
 
 
+def test_3d_shots_over_one_receiver_spread_match_oracle(ctx):
+    """Two 3D shots recorded by one receiver spread: their adjoint boxes coincide, so the
+    reverse launches take one y-strip of every shot before the next strip.  Image,
+    illumination, misfit and gradient against the oracle."""
+    from oracle import oracle as O
+    import torch
+    job = I.config4(n=28, nt=160, nshot=2, dr=1, rec_step=3)
+    job = with_bounds(job, [job.extra["vp_true"]])
+    assert np.array_equal(job.acq.rec[:job.acq.nrec(0)], job.acq.rec[job.acq.nrec(0):])
+    vmax = float(job.grid.vpmax)
+    dobs = O.forward_job(job, vp=job.extra["vp_true"], vmax=vmax, box=0)
+    ref_i, ref_l = O.rtm_image(job, dobs, vmax=vmax, box=0)
+    ref_g, ref_J = O.fwi_grad(job, dobs, vmax=vmax, box=0)
+    vp, rho, stf = dev(job)
+    dobs_t = torch.from_numpy(np.concatenate([d.ravel() for d in dobs]).astype(np.float32)).cuda()
+    im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs_t)
+    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs_t)
+    ctx.poll_status()
+    ei = rel_l2(im.cpu().numpy().reshape(job.vp.shape), ref_i)
+    el = rel_l2(il.cpu().numpy().reshape(job.vp.shape), ref_l)
+    eg = rel_l2(g.cpu().numpy().reshape(job.vp.shape), ref_g)
+    J = float(J.cpu().numpy()[0])
+    say("3d shared spread: image", ei, "illum", el, "grad", eg, "J", J, ref_J)
+    assert max(ei, el, eg) <= 1e-4
+    assert abs(J - ref_J) <= 1e-4 * ref_J
+
+
 def test_errors_are_synchronous(ctx):
     """Validation errors return before any work: CFL (eq. 5), workspace too small."""
     from paper_2311_02293_amd import binding as B
