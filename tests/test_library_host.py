@@ -48,7 +48,7 @@ def test_check_cfl_and_dispersion():
 
 
 @pytest.mark.parametrize("cfg", ["config2", "config3"])
-def test_baseline_configs_pass_the_checks(cfg):
+def test_benchmark_workloads_pass_the_checks(cfg):
     job = getattr(I, cfg)(nt=10) if cfg != "config3" else I.config3(nt=10)
     g = B.make_grid(job.grid)
     vmin = float(np.min(job.vp))
