@@ -324,8 +324,8 @@ struct MCell {
     bool need;          // this lane's row is within 4 of the box along z (z-neighbour of a cell)
 };
 
-// SI: the kernel may be launched in the 2D shot-inner order (compiled out of the forward p
-// update, whose launches never use it)
+// SI: the kernel may be launched in a shot-inner order (2D: ymap 2, 3D: ymap 3; compiled out
+// of the forward p update, whose launches never use it)
 template <int ND, int CM, bool SI = true>
 __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0, MG mg) {
     MCell c;
