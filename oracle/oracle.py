@@ -9,6 +9,7 @@ with ctypes) and adds the host-side arithmetic of the method in plain numpy:
   * eq. (7)  kappa gradient, chain rule to Vp (rho fixed)  -> :func:`fwi_grad`
   * eq. (7)  rho gradient, families (Vp, rho), (Vp, Ip)      -> :func:`fwi_grad_family`
   * eq. (10) cross-correlation image                       -> :func:`rtm_image`
+  * eq. (10) the map whose transpose is the image            -> :func:`react`
   * Sec. 2.3 source-normalised image, Laplace filter         -> :func:`normalized_image`,
                                                                :func:`laplacian`
   * Alg. 2   forward loop, adjoint source, reverse loop, sum over shots
@@ -95,8 +96,10 @@ def lib():
                                  ip, dp, tp, tp]
         L.og_reconstruct.argtypes = [gp, dp, dp, ip, dp, dp, dp, C.c_int, ip, dp, tp]
         L.og_adjoint.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp, dp,
-                                 tp, tp, C.c_int]
+                                 tp, tp, C.c_int, C.c_int, ip, dp]
         L.og_born.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, dp, tp, tp]
+        L.og_react.argtypes = [gp, dp, dp, ip, dp, C.c_int, ip, dp, C.c_double, C.c_int, dp,
+                               tp, tp]
         _lib = L
     return _lib
 
@@ -310,10 +313,13 @@ def reconstruct(gr: OgGrid, vp, rho, src, stf, bands, final, snaps: Sequence[int
 
 def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, final=None,
             want=("gk", "image", "illum"), st: Optional[Taps] = None, rt: Optional[Taps] = None,
-            literal: bool = False):
+            literal: bool = False, planted: int = 0, snaps: Sequence[int] = ()):
     """Reverse loop of Alg. 2 for one shot; returns interior gk (dJ/dkappa), image, illum and,
     when "grk" is wanted, dJ/drho at fixed kappa (the buoyancy part of eq. 7).  `literal` takes
-    gk after both updates of each iteration, where Alg. 2 writes it (a comparison only)."""
+    gk after both updates of each iteration, where Alg. 2 writes it (a comparison only).
+    `planted` (tests of the pins only) puts a known mistake into the image: 1 pairs p^it with
+    the adjoint field one level early, 2 drops the factor dt.  `snaps`: levels at which the
+    source-field p of the interior (as the reverse loop rebuilds it) is returned as "snaps"."""
     vp = np.ascontiguousarray(vp, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     stf = np.ascontiguousarray(stf, np.float64)
@@ -325,14 +331,18 @@ def adjoint(gr: OgGrid, vp, rho, src, stf, rec, G, *, hist=None, bands=None, fin
     im = np.zeros(I) if "image" in want else None
     il = np.zeros(I) if "illum" in want else None
     grk = np.zeros(I) if "grk" in want else None
+    snap_it = np.ascontiguousarray(np.asarray(list(snaps), np.int32))
+    sn = np.zeros((len(snap_it), I)) if len(snap_it) else None
     rc = lib().og_adjoint(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
                           _d(G), _d(None if hist is None else np.ascontiguousarray(hist)),
                           _d(None if bands is None else np.ascontiguousarray(bands)),
                           _d(None if final is None else np.ascontiguousarray(final)),
-                          _d(gk), _d(im), _d(il), _d(grk), _tp(st), _tp(rt), int(literal))
+                          _d(gk), _d(im), _d(il), _d(grk), _tp(st), _tp(rt),
+                          int(literal) | (2 if planted == 1 else 0) | (4 if planted == 2 else 0),
+                          len(snap_it), _i(snap_it) if len(snap_it) else None, _d(sn))
     if rc:
         raise RuntimeError("og_adjoint failed: %d" % rc)
-    return {"gk": gk, "image": im, "illum": il, "grk": grk}
+    return {"gk": gk, "image": im, "illum": il, "grk": grk, "snaps": sn}
 
 
 def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa, st: Optional[Taps] = None,
@@ -349,6 +359,25 @@ def born(gr: OgGrid, vp, rho, src, stf, rec, dkappa, st: Optional[Taps] = None,
     if rc:
         raise RuntimeError("og_born failed: %d" % rc)
     return dd
+
+
+def react(gr: OgGrid, vp, rho, src, stf, rec, dm, *, eps: float = 0.0, lin: bool = True,
+          st: Optional[Taps] = None, rt: Optional[Taps] = None):
+    """The map whose exact transpose is the eq. (10) image (see og_react): with lin, the data
+    of a field driven by dt kappa m p^it added before every step; without, the data of the
+    forward run whose steps start with p *= 1 + eps dt kappa m (its finite-difference check)."""
+    vp = np.ascontiguousarray(vp, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    stf = np.ascontiguousarray(stf, np.float64)
+    src = np.ascontiguousarray(src, np.int32)
+    rec = np.ascontiguousarray(np.asarray(rec, np.int32).reshape(-1, 3))
+    m = np.ascontiguousarray(dm, np.float64).ravel()
+    out = np.zeros((gr.nt, rec.shape[0]))
+    rc = lib().og_react(C.byref(gr), _d(vp), _d(rho), _i(src), _d(stf), rec.shape[0], _i(rec),
+                        _d(m), float(eps), int(bool(lin)), _d(out), _tp(st), _tp(rt))
+    if rc:
+        raise RuntimeError("og_react failed: %d" % rc)
+    return out
 
 
 # ------------------------------------------------------------------ multi-shot jobs

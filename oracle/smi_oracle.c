@@ -727,13 +727,19 @@ static void og_grad_kappa(const og_model *m, const og_field *q, const og_field *
             }
 }
 
-/* literal != 0: the kappa gradient is taken where Alg. 2 writes it, after both updates of the
- * iteration (p~ at level it before the next injection, with v^{it-1/2}) -- a variant kept only
- * to show that it differs from the exact pairing at receiver cells alone. */
+/* literal, bit 0: the kappa gradient is taken where Alg. 2 writes it, after both updates of
+ * the iteration (p~ at level it before the next injection, with v^{it-1/2}) -- a variant kept
+ * only to show that it differs from the exact pairing at receiver cells alone.
+ * Bits 1 and 2 plant mistakes in the image, kept only so that a test can show the image pin
+ * catches them: bit 1 pairs p^it with the adjoint field before its step (one level early),
+ * bit 2 drops the factor dt. */
+/* nsnap, snap_it, snaps (optional): the source-field p of the interior at the listed levels
+ * as the reverse loop holds it (from the stored history, or rebuilt from the bands). */
 int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int *src,
                const double *stf, int nrec, const int *rec, const double *G, const double *hist,
                const double *bands, const double *final_state, double *gk, double *image,
-               double *illum, double *grk, const og_taps *st, const og_taps *rt, int literal)
+               double *illum, double *grk, const og_taps *st, const og_taps *rt, int literal,
+               int nsnap, const int *snap_it, double *snaps)
 {
     og_model m;
     if (og_setup(&m, g, vp, rho)) return -1;
@@ -745,6 +751,9 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
         og_state_set(&m, &f, final_state);
     }
     int nb = m.g.nb;
+    if (!hist) og_take_snaps(&m, f.p, g->nt, nsnap, snap_it, snaps);
+    double *qearly = (literal & 2) ? calloc(m.P, sizeof(double)) : NULL;
+    const double wdt = (literal & 4) ? 1.0 : g->dt;
     for (int it = g->nt - 1; it >= 0; it--) {
         for (int r = 0; r < nrec; r++)
             og_spread(&m, q.p, rt, r, rec + 3 * r, G[(size_t)it * nrec + r], m.kap);
@@ -753,13 +762,16 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
             og_fs_p(&m, q.p, flo, fhi);
         }
         if (hist) og_state_set(&m, &f, hist + (size_t)(it + 1) * 4 * m.P); /* v^{it+1/2} */
-        if (gk && !literal) og_grad_kappa(&m, &q, &f, gk);
+        if (gk && !(literal & 1)) og_grad_kappa(&m, &q, &f, gk);
+        if (qearly) memcpy(qearly, q.p, m.P * sizeof(double));
         int lo[3], hi[3];
         og_adj_box_m(&m, nrec, rec, it, lo, hi);
         og_step(&m, &q, lo, hi);
         if (hist) og_state_set(&m, &f, hist + (size_t)it * 4 * m.P);
         else og_recon_iter(&m, &f, src, stf, bands, it, st);
-        if (gk && literal) og_grad_kappa(&m, &q, &f, gk);
+        if (gk && (literal & 1)) og_grad_kappa(&m, &q, &f, gk);
+        og_take_snaps(&m, f.p, it, nsnap, snap_it, snaps);
+        const double *qi = qearly ? qearly : q.p;
         if (image || illum) {
 #pragma omp parallel for collapse(2) schedule(static)
             for (int i3 = 0; i3 < m.n[2]; i3++)
@@ -767,13 +779,14 @@ int og_adjoint(const og_grid *g, const double *vp, const double *rho, const int 
                     for (int i1 = 0; i1 < m.n[0]; i1++) {
                         size_t k = IDX(&m, i1 + nb, i2 + nb, m.nd == 3 ? i3 + nb : 0);
                         size_t s = (size_t)i1 + (size_t)m.n[0] * ((size_t)i2 + (size_t)m.n[1] * i3);
-                        if (image) image[s] += g->dt * q.p[k] * f.p[k];
+                        if (image) image[s] += wdt * qi[k] * f.p[k];
                         if (illum) illum[s] += g->dt * f.p[k] * f.p[k];
                     }
         }
         /* q.v holds v~^{it+1/2} (the p update of og_step leaves it), f.p holds p^it */
         if (grk) og_rho_faces(&m, &q, &f, grk);
     }
+    free(qearly);
     og_field_free(&f);
     og_field_free(&q);
     og_free_model(&m);
@@ -818,6 +831,65 @@ int og_born(const og_grid *g, const double *vp, const double *rho, const int *sr
     }
     og_field_free(&f);
     og_field_free(&df);
+    og_free_model(&m);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ the image as a transpose (eq. 10) */
+
+/* The zero-lag cross-correlation image of eq. (10), paired as og_adjoint pairs it (the adjoint
+ * pressure after its step of reverse iteration it, times the source pressure p^it), is the
+ * exact transpose of a linear map from an interior model perturbation m to data.  That map is
+ * the derivative, at eps = 0, of a forward run in which every step starts by scaling p on the
+ * interior by (1 + eps dt kappa m): a reaction term kappa eps m p added to the right-hand side
+ * of the pressure equation of eq. (1), taken explicitly at level n.
+ *   lin = 0: that perturbed forward run, data[it][r] = p^{it+1} sampled at receiver r;
+ *   lin = 1: its tangent: a second field u obeys the same step and, before each step,
+ *            u.p += dt kappa m p^it (p^it the unperturbed source field); data = u.p^{it+1}.
+ * Both run on the whole padded grid (no computing box).  With the absorbing layers off, the
+ * same-solver adjoint step is the exact transpose of the forward step in the scaled adjoint
+ * variables, so <lin(m), G> = <m, image(G)> to rounding: a one-level slip in the pairing, a
+ * lost dt or a lost kappa in the image breaks the identity.                                    */
+static void og_scale_interior(const og_model *m, double *p, const double *dm, double c,
+                              const double *by)
+{
+    int nb = m->g.nb;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int i3 = 0; i3 < m->n[2]; i3++)
+        for (int i2 = 0; i2 < m->n[1]; i2++)
+            for (int i1 = 0; i1 < m->n[0]; i1++) {
+                size_t k = IDX(m, i1 + nb, i2 + nb, m->nd == 3 ? i3 + nb : 0);
+                size_t s = (size_t)i1 + (size_t)m->n[0] * ((size_t)i2 + (size_t)m->n[1] * i3);
+                p[k] += c * m->g.dt * m->kap[k] * dm[s] * by[k];
+            }
+}
+
+int og_react(const og_grid *g, const double *vp, const double *rho, const int *src,
+             const double *stf, int nrec, const int *rec, const double *dm, double eps, int lin,
+             double *data, const og_taps *st, const og_taps *rt)
+{
+    og_model m;
+    if (og_setup(&m, g, vp, rho)) return -1;
+    og_field f, u;
+    og_field_alloc(&f, m.P);
+    og_field_alloc(&u, m.P);
+    int lo[3] = {0, 0, 0}, hi[3] = {m.M[0] - 1, m.M[1] - 1, m.M[2] - 1};
+    for (int it = 0; it < g->nt; it++) {
+        if (lin) og_scale_interior(&m, u.p, dm, 1.0, f.p);     /* u.p += dt kappa m p^it */
+        else og_scale_interior(&m, f.p, dm, eps, f.p);         /* p *= 1 + eps dt kappa m */
+        og_step(&m, &f, lo, hi);
+        if (lin) og_step(&m, &u, lo, hi);
+        og_spread(&m, f.p, st, 0, src, g->dt * stf[it] / m.dV, NULL);
+        if (g->freesurf) {
+            og_fs_p(&m, f.p, lo, hi);
+            if (lin) og_fs_p(&m, u.p, lo, hi);
+        }
+        const double *rp = lin ? u.p : f.p;
+        for (int r = 0; r < nrec; r++)
+            data[(size_t)it * nrec + r] = og_sample(&m, rp, rt, r, rec + 3 * r);
+    }
+    og_field_free(&f);
+    og_field_free(&u);
     og_free_model(&m);
     return 0;
 }

@@ -850,3 +850,146 @@ def test_literal_gradient_position_differs_only_at_receiver_cells(oracle):
             assert np.max(np.abs(ex[~onrec] - li[~onrec])) <= 1e-12 * np.abs(ex).max()
         d = np.abs(ex[onrec] - li[onrec])
         assert np.all(d > 0) and d.max() > 1e-3 * np.abs(ex).max()
+
+
+# ----------------------------------------------------------------------------- eq. (10) image
+
+def _image_case(oracle, ndim, pml, box=0, off_grid=False):
+    """A small heterogeneous job with a reflector, its forward history, its bands and an
+    adjoint source G; returns everything the image pins need."""
+    if ndim == 2:
+        g = small_grid(order=8, n1=40, n2=48, nt=220, nb=8, box=box)
+        vp, rho = smooth_random_model(g.n1, g.n2, 31)
+        vp[:, 22:] *= 1.08
+    else:
+        g = small_grid(order=4, n1=18, n2=20, n3=22, nt=90, nb=4, ndim=3, box=box)
+        vp, rho = smooth_random_model(g.n1, g.n2, 32, n3=g.n3)
+        vp[..., 10:] *= 1.08
+    gr = oracle.og_grid(g, vmax=float(vp.max()), pml=pml)
+    src = np.array([g.nb + 3, g.nb + g.n2 // 3, g.nb + 5 if ndim == 3 else 0], np.int32)
+    rec = np.array([[g.nb + 2, g.nb + j, g.nb + 6 if ndim == 3 else 0]
+                    for j in range(1, g.n2 - 1, 3)], np.int32)
+    rt = None
+    if off_grid:   # receivers 0.37 / 0.61 of a cell off the nodes (Kaiser-windowed sinc)
+        pos = [((r[0] - g.nb + 0.37) * g.d1, (r[1] - g.nb + 0.61) * g.d2, 0.0) for r in rec]
+        rt = oracle.point_taps(g, pos)
+    stf = I.ricker(g.nt, g.dt, g.fm)
+    rng = np.random.default_rng(41 + ndim)
+    G = rng.standard_normal((g.nt, len(rec)))
+    dm = np.zeros(vp.shape)
+    core = tuple(slice(2, s - 2) for s in vp.shape)
+    dm[core] = rng.standard_normal(dm[core].shape)
+    fw = oracle.forward(gr, vp, rho, src, stf, rec, hist=True, bands=True, final=True, rt=rt)
+    return g, gr, vp, rho, src, rec, stf, G, dm, fw, rt
+
+
+def test_image_map_is_the_derivative_of_the_reaction_forward(oracle):
+    """The map of og_react (data of a field driven by dt kappa m p^it before every step) is the
+    derivative of the forward run whose steps start with p *= 1 + eps dt kappa m: central
+    finite differences of the second match the first."""
+    g, gr, vp, rho, src, rec, stf, G, dm, fw, rt = _image_case(oracle, 2, pml=1)
+    lin = oracle.react(gr, vp, rho, src, stf, rec, dm, lin=True)
+    kmax = float(np.max(rho.astype(np.float64) * vp.astype(np.float64) ** 2))
+    eps = 1e-5 / (g.dt * kmax)            # |eps dt kappa m| ~ 1e-5 of p per step
+    dp = oracle.react(gr, vp, rho, src, stf, rec, dm, eps=eps, lin=False)
+    dn = oracle.react(gr, vp, rho, src, stf, rec, dm, eps=-eps, lin=False)
+    fd = (dp - dn) / (2 * eps)
+    assert np.linalg.norm(lin) > 0
+    assert np.linalg.norm(fd - lin) / np.linalg.norm(lin) < 1e-5
+    # eps = 0 is the plain forward run
+    d0 = oracle.react(gr, vp, rho, src, stf, rec, dm, eps=0.0, lin=False)
+    np.testing.assert_allclose(d0, fw["dcal"], rtol=0, atol=1e-14 * np.max(np.abs(fw["dcal"])))
+
+
+def _image_dot(oracle, case, planted=0, use_history=True):
+    g, gr, vp, rho, src, rec, stf, G, dm, fw, rt = case
+    lin = oracle.react(gr, vp, rho, src, stf, rec, dm, lin=True, rt=rt)
+    if use_history:
+        im = oracle.adjoint(gr, vp, rho, src, stf, rec, G, hist=fw["hist"], want=("image",),
+                            rt=rt, planted=planted)["image"]
+    else:
+        im = oracle.adjoint(gr, vp, rho, src, stf, rec, G, bands=fw["bands"], final=fw["final"],
+                            want=("image",), rt=rt, planted=planted)["image"]
+    lhs = float(np.sum(lin * G))
+    rhs = float(np.sum(dm.ravel() * im))
+    return abs(lhs - rhs) / abs(lhs)
+
+
+@pytest.mark.parametrize("ndim,off_grid", [(2, False), (2, True), (3, False)])
+def test_image_is_the_exact_transpose_of_the_reaction_map(oracle, ndim, off_grid):
+    """eq. (10) as the oracle pairs it: <L m, G> = <m, I(G)> with L the map of og_react and
+    I(G) the image of adjoint source G, exact without absorption, from the stored history and
+    from the boundary reconstruction alike."""
+    case = _image_case(oracle, ndim, pml=0, off_grid=off_grid)
+    assert _image_dot(oracle, case, use_history=True) <= 1e-12
+    assert _image_dot(oracle, case, use_history=False) <= 1e-12
+
+
+@pytest.mark.parametrize("planted", [1, 2])
+def test_image_pin_catches_planted_slips(oracle, planted):
+    """The transpose identity above fails for the image paired one level early (the adjoint
+    field before its step) and for the image without its factor dt."""
+    case = _image_case(oracle, 2, pml=0)
+    assert _image_dot(oracle, case, planted=planted) > 1e-3
+
+
+@pytest.mark.parametrize("ndim,box", [(2, 0), (2, 1), (3, 1)])
+def test_image_and_illumination_from_history_equal_reconstructed(oracle, ndim, box):
+    """With the absorbing layers on, the image and the source illumination from the boundary
+    reconstruction equal those from the stored forward history; the illumination equals its
+    plain definition dt sum_{it < nt} (p^it)^2 read off that history (p at levels 0..nt-1)."""
+    g, gr, vp, rho, src, rec, stf, G, dm, fw, rt = _image_case(oracle, ndim, pml=1, box=box)
+    a = oracle.adjoint(gr, vp, rho, src, stf, rec, G, hist=fw["hist"], want=("image", "illum"))
+    b = oracle.adjoint(gr, vp, rho, src, stf, rec, G, bands=fw["bands"], final=fw["final"],
+                       want=("image", "illum"))
+    for key in ("image", "illum"):
+        assert np.max(np.abs(a[key])) > 0
+        assert np.max(np.abs(a[key] - b[key])) <= 1e-12 * np.max(np.abs(a[key])), key
+    shape = [gr.n1 + 2 * gr.nb, gr.n2 + 2 * gr.nb] + ([gr.n3 + 2 * gr.nb] if ndim == 3 else [])
+    hist_p = fw["hist"][:, 0, :].reshape([g.nt + 1] + shape[::-1])
+    inner = (slice(None),) + tuple(slice(g.nb, s - g.nb) for s in shape[::-1])
+    p_int = hist_p[inner].reshape(g.nt + 1, -1)
+    plain = g.dt * np.sum(p_int[:g.nt] ** 2, axis=0)
+    assert np.max(np.abs(b["illum"] - plain)) <= 1e-12 * np.max(plain)
+    late = g.dt * np.sum(p_int[1:] ** 2, axis=0)      # levels 1..nt: a one-level slip
+    assert np.max(np.abs(late - plain)) > 1e-6 * np.max(plain)
+
+
+def test_normalized_image_is_per_shot(oracle):
+    """Sec. 2.3 normalisation is per shot: with shot 0's wavelet doubled and shot 1's kept,
+    the normalised image is N0 / 2 + N1 (Ns: shot s's own normalised image), which a
+    normalisation by the illumination summed over shots does not give."""
+    g = small_grid(order=4, n1=36, n2=48, nt=260, nb=8, fm=12)
+    vp, rho = smooth_random_model(g.n1, g.n2, 22)
+    d = g.d1
+    acq = I._surface_line(np.array([12.0, 36.0]) * d, 2 * d, np.arange(g.n2) * d, 2 * d)
+    w = I.ricker(g.nt, g.dt, g.fm)
+    stf = np.stack([w, w]).astype(np.float32)
+    vtrue = vp.copy()
+    vtrue[:, 24:] *= 1.1
+    dobs = oracle.forward_job(I.Job(g, vtrue, rho, acq, stf))
+    job = I.Job(g, vp, rho, acq, stf)
+    ims, ils = oracle.rtm_image(job, dobs, per_shot=True)
+    n0 = oracle.normalized_image(ims[:1], ils[:1])
+    n1 = oracle.normalized_image(ims[1:], ils[1:])
+    job.stf = np.stack([2.0 * w, w]).astype(np.float32)
+    ims2, ils2 = oracle.rtm_image(job, dobs, per_shot=True)
+    got = oracle.normalized_image(ims2, ils2)
+    want = 0.5 * n0 + n1
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    summed = np.sum(ims2, 0) / (np.sum(ils2, 0) + 1e-3 * np.max(np.sum(ils2, 0)))
+    assert np.max(np.abs(summed - want)) > 1e-3 * np.max(np.abs(want))
+
+
+def test_reverse_loop_snapshots_equal_the_reconstruction(oracle):
+    """The source field the reverse loop holds at each level (the snapshots of og_adjoint) is
+    the field og_reconstruct rebuilds from the same bands, and, with dr = 1, the forward field
+    itself to rounding."""
+    g, gr, vp, rho, src, rec, stf, G, dm, fw, rt = _image_case(oracle, 2, pml=1, box=1)
+    levels = [0, 40, 110, g.nt - 1, g.nt]
+    a = oracle.adjoint(gr, vp, rho, src, stf, rec, G, bands=fw["bands"], final=fw["final"],
+                       want=("image",), snaps=levels)["snaps"]
+    b = oracle.reconstruct(gr, vp, rho, src, stf, fw["bands"], fw["final"], levels)
+    np.testing.assert_array_equal(a, b)
+    f = oracle.forward(gr, vp, rho, src, stf, rec, snaps=levels)["snaps"]
+    assert np.max(np.abs(a - f)) <= 1e-12 * np.max(np.abs(f))
