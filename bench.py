@@ -266,6 +266,9 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
+    ap.add_argument("--kernel", type=int, default=-1,
+                    help="SMI_OPT_KERNEL for the timed forward (-1: the library's default)")
+    ap.add_argument("--chunk", type=int, default=-1, help="SMI_OPT_CHUNK (-1: default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not provided "
@@ -293,6 +296,10 @@ def main():
     rho = torch.from_numpy(job.rho).to(dev)
     stf = torch.from_numpy(job.stf).to(dev)
     ctx = B.Context(0)
+    if args.kernel >= 0:
+        ctx.set_option(B.OPT_KERNEL, args.kernel)
+    if args.chunk >= 0:
+        ctx.set_option(B.OPT_CHUNK, args.chunk)
     nrec = int(job.acq.rec_off[-1])
     dcal = torch.empty(job.grid.nt * nrec, dtype=torch.float32, device=dev)
     ws = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_FORWARD))
@@ -371,7 +378,7 @@ def main():
         torch.cuda.synchronize()
         pms = a.elapsed_time(b)
         pg = ctx.last_counts()[0]
-        ctx.set_option(B.OPT_KERNEL, 0)
+        ctx.set_option(B.OPT_KERNEL, max(args.kernel, 0))
         job.grid.box = 1
         out["plain"] = {"value": pg / (pms / 1e3) / 1e9, "unit": "GPts/s", "ms_per_step": pms,
                         "gpts_per_step": pg,

@@ -150,6 +150,17 @@ void smi_ctx_destroy(smi_ctx *ctx);
 const char *smi_last_error(const smi_ctx *ctx);
 smi_status smi_set_option(smi_ctx *ctx, int option, int value);
 
+/* Results per group of shots (the sum over shots of Alg. 2 / Sec. 3.2 taken per group instead
+ * of over the whole call), for callers that batch the shots of several independent jobs on one
+ * model into one call.  shot_off: host [ngroup + 1], shot_off[0] = 0, strictly increasing; group
+ * k is the shots [shot_off[k], shot_off[k+1]).  While set, every reduced output of
+ * smi_adjoint_reconstruct, smi_rtm_image and smi_fwi_grad (grad_vp, grad_rho, image, illum,
+ * image_norm: device [ngroup][n1*n2*n3]; misfit: device double [ngroup]) holds one result per
+ * group, each summed over its own shots in order -- bitwise what the group's shots give in a
+ * call of their own.  A call whose shot count differs from shot_off[ngroup] fails with
+ * SMI_E_ARG.  ngroup = 0 returns to one result per call (the default).  Copied; host only. */
+smi_status smi_set_shot_groups(smi_ctx *ctx, int ngroup, const int *shot_off);
+
 /* Host checks run by every entry point (Sec. 3.8): eq. (5) with Vmax = vp_max, and at least
  * 5 (order 4) or 3 (order 8) points per wavelength at the highest frequency 2.5 fm:
  * vp_min / (2.5 fm max(d)) >= ppw.  Returns SMI_OK, SMI_E_CFL, SMI_E_DISPERSION or SMI_E_ARG. */

@@ -59,6 +59,7 @@ def lib():
         L.smi_last_error.argtypes = [vp]
         L.smi_last_error.restype = C.c_char_p
         L.smi_set_option.argtypes = [vp, C.c_int, C.c_int]
+        L.smi_set_shot_groups.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
         L.smi_check.argtypes = [vp, C.POINTER(SmiGrid), C.c_double, C.c_double]
         L.smi_workspace_bytes.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), C.c_int,
                                           C.POINTER(C.c_size_t)]
@@ -154,6 +155,7 @@ class Context:
             raise SmiError(rc, "smi_ctx_create failed")
         self.h = h
         self._ws = None
+        self.ngroup = 1
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -168,6 +170,18 @@ class Context:
     def set_option(self, option: int, value: int):
         self._check(lib().smi_set_option(self.h, option, value))
         self.options[option] = value
+
+    def set_shot_groups(self, shot_off=None):
+        """smi_set_shot_groups: reduced outputs per group of consecutive shots (None: off).
+        Outputs of the reverse entry points then have ngroup rows."""
+        if shot_off is None:
+            self._check(lib().smi_set_shot_groups(self.h, 0, None))
+            self.ngroup = 1
+            return
+        off = np.ascontiguousarray(shot_off, np.int32)
+        self._check(lib().smi_set_shot_groups(self.h, len(off) - 1,
+                                              off.ctypes.data_as(C.POINTER(C.c_int))))
+        self.ngroup = len(off) - 1
 
     def option(self, option: int, default: int = 0) -> int:
         """Last value set through this wrapper (the library's default otherwise)."""
@@ -247,7 +261,7 @@ class Context:
         vp = state.keep[1]
         dev = vp.device
         n = vp.numel() if npts is None else npts
-        out = {k: (torch.empty(n, dtype=torch.float32, device=dev) if want else None)
+        out = {k: (torch.empty(self.ngroup * n, dtype=torch.float32, device=dev) if want else None)
                for k, want in (("grad", grad), ("grad_rho", grad_rho), ("image", image),
                                ("illum", illum), ("image_norm", image_norm))}
         snap_it = np.ascontiguousarray(list(snaps), np.int32)
@@ -272,7 +286,7 @@ class Context:
         a = _Acq(acq)
         nb = self.workspace_bytes(grid, acq, JOB_RTM)
         ws = self.workspace(nb) if ws is None else ws
-        image = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
+        image = torch.empty(self.ngroup * vp.numel(), dtype=torch.float32, device=vp.device)
         il = torch.empty_like(image) if illum else None
         nm = torch.empty_like(image) if norm else None
         self._check(lib().smi_rtm_image(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
@@ -310,9 +324,9 @@ class Context:
         a = _Acq(acq)
         nb = self.workspace_bytes(grid, acq, JOB_GRAD)
         ws = self.workspace(nb) if ws is None else ws
-        grad = torch.empty(vp.numel(), dtype=torch.float32, device=vp.device)
+        grad = torch.empty(self.ngroup * vp.numel(), dtype=torch.float32, device=vp.device)
         gr = torch.empty_like(grad) if rho_grad else None
-        mis = torch.zeros(1, dtype=torch.float64, device=vp.device)
+        mis = torch.zeros(self.ngroup, dtype=torch.float64, device=vp.device)
         dcal = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=vp.device) if want_dcal else None
         self._check(lib().smi_fwi_grad(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
                                        _ptr(stf), _ptr(dobs), _ptr(grad), _ptr(gr), _ptr(mis),

@@ -39,6 +39,8 @@ struct smi_ctx {
     std::vector<double> sample_bytes;   // [samples][3], as Plan::step_bytes
     std::vector<int> sample_nk;         // kernels of the sampled step (2, or 1 for the fused step)
     size_t nsample = 0;
+    // shot groups (smi_set_shot_groups): offsets [ngroup + 1]; empty = one group of all shots
+    std::vector<int> groups;
     ~smi_ctx() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -68,7 +70,18 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.zl = false;
     c.ymap = false;
     c.rev = ctx->opt_rev;
-    if (ctx->opt_kernel == 0) {
+    c.step2d = false;
+    c.run = 32;
+    c.depth = 2;
+    if (ctx->opt_kernel == 6) {
+        // the fused marching 2D forward step (other passes and 3D: the kernels of 0)
+        c.march = pl.nd == 2 ? 4 : 2;
+        c.xcd = pl.nd == 2;
+        c.step2d = smi::step2d_available(pl);
+        c.run = ctx->opt_chunk % 100 == 64 ? 64 : 32;
+        const int d = ctx->opt_chunk / 100;
+        c.depth = d == 1 || d == 4 ? d : 2;
+    } else if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
     } else if (ctx->opt_kernel == 2) {
@@ -123,12 +136,17 @@ struct Key {
     }
 };
 
-// Everything a plan bakes into the launches of its time loop.
+// Everything a plan bakes into the launches of its time loop: geometry, boxes and kernel
+// choice, and the point-operator layout that decides which launches exist and how wide their
+// grids are (sources spread over several nodes or not, the taps per source, the nodes of the
+// adjoint-source gather).
 Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
     Key k;
     k.put(tag).put(pl.geom).put(pl.band).put(pl.nshot).put(pl.nrun).put(pl.nsave);
     k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl).put(c.rev).put(c.ymap);
+    k.put(c.y3).put(pl.chunk).put(c.step2d).put(c.run).put(c.depth);
     k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
+    k.put(pl.src_multi).vec(pl.src_toff).vec(pl.src_cell).vec(pl.inj_off);
     return k;
 }
 
@@ -233,6 +251,14 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
         HIPCHK(hipMemcpyAsync(w.recv.tw, pl.rec_tw.data(), pl.rec_tw.size() * sizeof(float),
                               hipMemcpyHostToDevice, st), "rec");
     }
+    const size_t U = pl.inj_cell.size(), T = pl.inj_rec.size();
+    if (U > 0) {
+        HIPCHK(hipMemcpyAsync(w.inj.cell, pl.inj_cell.data(), U * sizeof(long long), hipMemcpyHostToDevice, st), "inj");
+        HIPCHK(hipMemcpyAsync(w.inj.shot, pl.inj_shot.data(), U * sizeof(int), hipMemcpyHostToDevice, st), "inj");
+        HIPCHK(hipMemcpyAsync(w.inj.off, pl.inj_off.data(), (U + 1) * sizeof(int), hipMemcpyHostToDevice, st), "inj");
+        HIPCHK(hipMemcpyAsync(w.inj.rec, pl.inj_rec.data(), T * sizeof(int), hipMemcpyHostToDevice, st), "inj");
+        HIPCHK(hipMemcpyAsync(w.inj.w, pl.inj_w.data(), T * sizeof(float), hipMemcpyHostToDevice, st), "inj");
+    }
     HIPCHK(hipMemcpyAsync(w.src_cell, pl.src_cell.data(), pl.nshot * sizeof(long long),
                           hipMemcpyHostToDevice, st), "src");
     HIPCHK(hipMemcpyAsync(w.src_toff, pl.src_toff.data(), pl.src_toff.size() * sizeof(int),
@@ -251,6 +277,19 @@ size_t field_bytes(const Plan &pl) {
 
 smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipStream_t st) {
     HIPCHK(hipMemsetAsync(f.p, 0, field_bytes(pl), st), "field clear");
+    return SMI_OK;
+}
+
+// The shot ranges the results are reduced over: the context's groups, or all shots.
+smi_status shot_groups(smi_ctx *ctx, int nshot, std::vector<int> &off) {
+    if (ctx->groups.empty()) {
+        off = {0, nshot};
+        return SMI_OK;
+    }
+    if (ctx->groups.back() != nshot)
+        return fail(ctx, SMI_E_ARG, "the shot groups cover " + std::to_string(ctx->groups.back()) +
+                                        " shots, the call has " + std::to_string(nshot));
+    off = ctx->groups;
     return SMI_OK;
 }
 
@@ -277,7 +316,8 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     configure(c, ctx, pl);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
-    bool fused = ctx->opt_kernel == 2 && pl.dbuf && pl.g.dr == 1 && smi::fused_fwd_available(pl);
+    const bool f2d = c.step2d;
+    bool fused = f2d || (ctx->opt_kernel == 2 && pl.dbuf && pl.g.dr == 1 && smi::fused_fwd_available(pl));
     if (fused) {
         s = zero_fields(ctx, pl, w.f2, st);
         if (s != SMI_OK) return s;
@@ -296,7 +336,8 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         // step's v launch and its v cells rode on the previous step's p launch
         c.save_p_slot = c.save_v_slot = -1;
         if (pl.save && it % dr == 0) {
-            if (defer && it > 0) c.save_p_slot = it / dr;
+            // the fused marching step reads level it from cur and carries the whole saved level
+            if (f2d || (defer && it > 0)) c.save_p_slot = it / dr;
             else HIPCHK(smi::band_save(c, cur, it / dr), "band save");
         }
         if (pl.save && defer && (it + 1) % dr == 0 && it + 1 < pl.nrun) c.save_v_slot = (it + 1) / dr;
@@ -315,7 +356,17 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
             ctx->nsample = k + 1;
             c.ev = &ctx->events[4 * k];
         }
-        if (fused) {
+        if (f2d) {
+            // receivers of step it - 1 are sampled by this launch from cur (level it)
+            HIPCHK(smi::fwd_step_2d(c, cur, nxt, it), "forward step");
+            c.ev = nullptr;
+            c.ext_it = -1;
+            if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
+            if (it < nt) {
+                c.ext_it = it;
+                c.ext_dcal = dcal;
+            }
+        } else if (fused) {
             HIPCHK(smi::fwd_step_fused(c, cur, nxt, it), "forward step");
             c.ev = nullptr;
             if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
@@ -337,10 +388,13 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
         for (int k = 0; k < nsnap; ++k)
             if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
         if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
-            HIPCHK(hipMemcpyAsync(w.fin, w.f.p, state_bytes, hipMemcpyDeviceToDevice, ls), "final copy");
+            HIPCHK(hipMemcpyAsync(w.fin, nxt.p, state_bytes, hipMemcpyDeviceToDevice, ls), "final copy");
     }
     if (c.ext_it >= 0) {
-        HIPCHK(smi::extract(c, c.ext_it, dcal), "extract");
+        // the last sampled step: level ext_it + 1 is in the second buffer after an odd step of
+        // the fused steps
+        const bool second = fused && ((c.ext_it + 1) & 1);
+        HIPCHK(smi::extract(c, c.ext_it, dcal, second ? w.f2.p : w.f.p), "extract");
         c.ext_it = -1;
     }
     if (fused && (pl.nrun & 1)) {
@@ -385,7 +439,10 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     if (want_r && !pl.rho_acc)
         return fail(ctx, SMI_E_ARG, "this job keeps no density accumulators (use a gradient job)");
     bool want_g = adj && (grad || grad_rho), want_i = adj && (image || illum || image_norm);
-    smi_status s = zero_fields(ctx, pl, w.q, st);
+    std::vector<int> grp;
+    smi_status s = shot_groups(ctx, pl.nshot, grp);
+    if (s != SMI_OK) return s;
+    s = zero_fields(ctx, pl, w.q, st);
     if (s != SMI_OK) return s;
     HIPCHK(hipMemsetAsync(w.acc_g, 0, sizeof(float) * 3 * (size_t)pl.nshot * pl.I, st), "acc clear");
     if (want_r)
@@ -418,12 +475,20 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     }
     c.st = st;
     if (s != SMI_OK) return s;
-    HIPCHK(smi::finalize(c, stt->vp, want_g && !want_r ? grad : nullptr, want_i ? image : nullptr,
-                         want_i ? illum : nullptr, want_i ? image_norm : nullptr), "finalize");
-    if (want_r)
-        HIPCHK(smi::finalize_family(c, stt->vp, stt->rho, family, grad, grad_rho), "finalize");
+    // one output array per shot group, each the fixed-order sum over its own shots
+    const size_t ng = grp.size() - 1;
+    for (size_t k = 0; k < ng; ++k) {
+        const size_t o = k * (size_t)pl.I;
+        auto at = [&](float *p) { return p ? p + o : nullptr; };
+        HIPCHK(smi::finalize(c, stt->vp, want_g && !want_r ? at(grad) : nullptr,
+                             want_i ? at(image) : nullptr, want_i ? at(illum) : nullptr,
+                             want_i ? at(image_norm) : nullptr, grp[k], grp[k + 1]), "finalize");
+        if (want_r)
+            HIPCHK(smi::finalize_family(c, stt->vp, stt->rho, family, at(grad), at(grad_rho),
+                                        grp[k], grp[k + 1]), "finalize");
+    }
     if (!adj) {
-        size_t I = sizeof(float) * pl.I;
+        size_t I = sizeof(float) * pl.I * ng;
         if (grad) HIPCHK(hipMemsetAsync(grad, 0, I, st), "grad clear");
         if (grad_rho) HIPCHK(hipMemsetAsync(grad_rho, 0, I, st), "grad_rho clear");
         if (image) HIPCHK(hipMemsetAsync(image, 0, I, st), "image clear");
@@ -491,7 +556,7 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 5) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 6) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
@@ -505,6 +570,20 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
         return SMI_OK;
     }
     return fail(ctx, SMI_E_ARG, "unknown option or value");
+}
+
+smi_status smi_set_shot_groups(smi_ctx *ctx, int ngroup, const int *shot_off) {
+    if (!ctx) return SMI_E_ARG;
+    if (ngroup == 0) {
+        ctx->groups.clear();
+        return SMI_OK;
+    }
+    if (ngroup < 0 || !shot_off || shot_off[0] != 0)
+        return fail(ctx, SMI_E_ARG, "shot groups: ngroup > 0 and shot_off[0] = 0 required");
+    for (int k = 0; k < ngroup; ++k)
+        if (shot_off[k + 1] <= shot_off[k]) return fail(ctx, SMI_E_ARG, "shot groups must not be empty");
+    ctx->groups.assign(shot_off, shot_off + ngroup + 1);
+    return SMI_OK;
 }
 
 smi_status smi_check(const smi_ctx *ctx, const smi_grid *grid, double vp_min, double vp_max) {
@@ -623,7 +702,12 @@ smi_status smi_fwi_grad(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, 
     if (s != SMI_OK) return s;
     smi::StepCtx c{&stt->plan, &w, stf, st, false};
     configure(c, ctx, stt->plan);
-    HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit), "residual");
+    std::vector<int> grp;
+    s = shot_groups(ctx, stt->plan.nshot, grp);
+    if (s != SMI_OK) return s;
+    for (size_t k = 0; k + 1 < grp.size(); ++k)
+        HIPCHK(smi::residual(c, dcal, dobs, w.G, misfit ? misfit + k : nullptr, grp[k], grp[k + 1]),
+               "residual");
     return run_reverse(ctx, stt.get(), w.G, grad_vp, grad_rho, nullptr, nullptr, nullptr, nullptr,
                        0, nullptr, st);
 }

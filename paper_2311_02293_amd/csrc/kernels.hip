@@ -23,6 +23,7 @@
 
 #include "smi_internal.hpp"
 #include "device.hpp"
+#include "side.hpp"
 
 namespace smi {
 
@@ -244,74 +245,12 @@ struct MG {
     int gz, gx, per, ntile, ymap;
 };
 
-// Receiver sampling of the previous step carried by a v launch (it < 0: none).  The v update
-// does not write p, so the seismogram row of step it (p^{it+1}) can be taken while the next
-// step's v kernel runs: the launch gets one extra shot slot of workgroups in front (blockIdx.z
-// < nmarch) that sample the receivers, and the shots start at shot0 = -1.
-struct Ext {
-    Recv rv;
-    float *dcal;
-    int it;
-    unsigned *status;
-};
-
-// Band cell q of shot s.  dir 0: field -> buf; dir 1: buf -> field; dir 2: field <- (1-wt)
-// buf + wt buf2.  which: 0 p blocks, 1 v blocks, 2 all.
-__device__ __forceinline__ void band_cell(const Geom &g, const Fields &f, const BandDesc &bd,
-                                          float *buf, const float *buf2, long long shot_stride,
-                                          int s, long long q, int dir, int which, float wt) {
-    if (q >= bd.B) return;
-    int b = 0;
-#pragma unroll 1
-    while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
-    const BandBlock &bl = bd.blk[b];
-    if (which != 2 && bl.field != which) return;
-    long long r = q - bl.off;
-    int z = bl.org[0] + (int)(r % bl.ext[0]);
-    r /= bl.ext[0];
-    int x = bl.org[1] + (int)(r % bl.ext[1]);
-    int y = bl.org[2] + (int)(r / bl.ext[1]);
-    long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
-    // constant indices only: a dynamic index into the Fields of a reference would place a
-    // copy of it in LDS
-    float *base = bl.field == 0 ? f.p : (bl.axis == 0 ? f.v[0] : (bl.axis == 1 ? f.v[1] : f.v[2]));
-    float *fld = base + s * g.P + k;
-    long long bo = s * shot_stride + q;
-    if (dir == 0) buf[bo] = *fld;
-    else if (dir == 1) *fld = buf[bo];
-    else *fld = (1.f - wt) * buf[bo] + wt * buf2[bo];
-}
-
-// Band cells carried by a launch of other work: saved levels (dir 0) during the forward half
-// steps, restored levels (dir 1) in the two-launch reverse step.
-struct BandArg {
-    const BandDesc *bd; // band layout (device copy)
-    float *buf;         // saved level of shot 0 (nullptr: nothing to do)
-    long long stride;   // floats between shots
-    int nqb;            // 256-cell blocks per shot
-    int nshot;
-};
-
 // the band cells of every shot over the blocks from grid plane z0 on (one lane per cell)
 __device__ __forceinline__ void band_part(const Geom &g, const Fields &f, const BandArg &ba,
                                           int z0, int dir, int which) {
     const long long lin = ((long long)((int)blockIdx.z - z0) * gridDim.y + blockIdx.y) *
                               gridDim.x + blockIdx.x;
-    const int s = (int)(lin / ba.nqb);
-    if (s < ba.nshot)
-        band_cell(g, f, *ba.bd, ba.buf, nullptr, ba.stride, s,
-                  (lin % ba.nqb) * 256 + (int)threadIdx.y * 64 + (int)threadIdx.x, dir, which, 0.f);
-}
-
-// dcal[it][r] = sum over the taps of receiver r of w p (Alg. 2 recording; one tap on a node)
-__device__ __forceinline__ void sample_receiver(const Geom &g, const float *__restrict__ p,
-                                                const Recv &rv, float *dcal, int it,
-                                                unsigned *status, int r) {
-    const long long so = rv.shot[r] * g.P;
-    float v = 0.f;
-    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) v += rv.tw[t] * p[so + rv.tcell[t]];
-    dcal[rv.obase[r] + (long long)it * rv.stride[r]] = v;
-    if (!isfinite(v)) atomicOr(status, 2u);
+    band_lin(g, f, ba, lin, (int)threadIdx.y * 64 + (int)threadIdx.x, dir, which);
 }
 
 struct MCell {
@@ -1013,19 +952,22 @@ __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, flo
     if (t < n) out[t] = a * in[t];
 }
 
-// p~ += kappa G[it][r] w_t on receiver r's operator nodes (eq. 8 source in the scaled adjoint
-// variable; the transpose of the sampling).  Atomic: operators of nearby receivers overlap.
+// p~ += kappa sum_r w_r G[it][r] on every node that receiver operators touch (eq. 8 source in
+// the scaled adjoint variable; the transpose of the sampling).  One lane per distinct node sums
+// its contributions in the plan's fixed order (ascending receiver), so overlapping operators and
+// co-located receivers give the same bits on every run.
 __global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *__restrict__ kdt,
-                                                Recv rv, const float *__restrict__ G, int it,
-                                                float inv_dt) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rv.R) return;
-    const float Gr = G[rv.obase[r] + (long long)it * rv.stride[r]];
-    const long long so = rv.shot[r] * g.P;
-    for (int t = rv.toff[r]; t < rv.toff[r + 1]; ++t) {
-        const long long c = rv.tcell[t];
-        atomicAdd(qp + so + c, kdt[c] * inv_dt * rv.tw[t] * Gr);
+                                                Recv rv, Inj in, const float *__restrict__ G,
+                                                int it, float inv_dt) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= in.U) return;
+    float acc = 0.f;
+    for (int t = in.off[u]; t < in.off[u + 1]; ++t) {
+        const int r = in.rec[t];
+        acc += in.w[t] * G[rv.obase[r] + (long long)it * rv.stride[r]];
     }
+    const long long c = in.cell[u];
+    qp[in.shot[u] * g.P + c] += kdt[c] * inv_dt * acc;
 }
 
 // ---------------------------------------------------------------- misfit (eq. 6)
@@ -1785,9 +1727,9 @@ hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsna
 
 hipError_t adj_inject(const StepCtx &c, int it, const float *G) {
     const Views &w = *c.w;
-    if (w.recv.R == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_inject, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom, w.q.p,
-                       (const float *)w.model.kdt, w.recv, G, it, (float)(1.0 / c.pl->g.dt));
+    if (w.inj.U == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inject, dim3(blocks(w.inj.U)), dim3(256), 0, c.st, c.pl->geom, w.q.p,
+                       (const float *)w.model.kdt, w.recv, w.inj, G, it, (float)(1.0 / c.pl->g.dt));
     // the injected adjoint sources get their images too (the transpose of the sampling of a
     // mirrored field)
     SMI_TRY(fs_launch(*c.pl, c.st, w.q.p, 1, 0, c.pl->nshot));
@@ -1795,12 +1737,13 @@ hipError_t adj_inject(const StepCtx &c, int it, const float *G) {
 }
 
 hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
-                    double *misfit) {
+                    double *misfit, int s0, int s1) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    long long n = (long long)pl.g.nt * pl.rec_off[pl.nshot];
-    hipLaunchKernelGGL(k_residual, dim3(pl.npartial), dim3(256), 0, c.st, dcal, dobs, G, n,
-                       (float)pl.g.dt, w.partial);
+    const long long o = (long long)pl.g.nt * pl.rec_off[s0];
+    const long long n = (long long)pl.g.nt * pl.rec_off[s1] - o;
+    hipLaunchKernelGGL(k_residual, dim3(pl.npartial), dim3(256), 0, c.st, dcal + o, dobs + o,
+                       G + o, n, (float)pl.g.dt, w.partial);
     hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(256), 0, c.st, (const double *)w.partial,
                        pl.npartial, misfit ? misfit : w.misfit_tmp, 0.5 * pl.g.dt);
     return hipGetLastError();
@@ -1851,13 +1794,13 @@ hipError_t born_step(const StepCtx &c, int it, const float *dkappa) {
 }
 
 hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
-                           float *g1, float *g2) {
+                           float *g1, float *g2, int s0, int s1) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    auto rs = [&](int a) -> const float * { return w.acc_r[a] ? w.acc_r[a] + (size_t)s0 * pl.P : nullptr; };
     hipLaunchKernelGGL(k_finalize_family, dim3(blocks(pl.I)), dim3(256), 0, c.st, pl.geom,
-                       (const float *)w.acc_g, (const float *)w.acc_r[0],
-                       (const float *)w.acc_r[1], (const float *)w.acc_r[2], w.model, pl.nshot,
-                       vp, rho, family, g1, g2);
+                       (const float *)(w.acc_g + (size_t)s0 * pl.I), rs(0), rs(1), rs(2), w.model,
+                       s1 - s0, vp, rho, family, g1, g2);
     return hipGetLastError();
 }
 
@@ -1875,27 +1818,29 @@ hipError_t launch_laplacian(const smi_grid *g, const float *in, float *out, hipS
 constexpr float kNormEps = 1e-3f;
 
 hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum,
-                    float *image_norm) {
+                    float *image_norm, int s0, int s1) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    const int ns = s1 - s0;
+    const size_t o = (size_t)s0 * pl.I;
     if (image_norm) {
         unsigned *mx = (unsigned *)w.partial;
-        hipLaunchKernelGGL(k_fill_u32, dim3(blocks(pl.nshot)), dim3(256), 0, c.st, mx, pl.nshot, 0u);
-        hipLaunchKernelGGL(k_shot_max, dim3(std::min<unsigned>(blocks(pl.I), 1024u), pl.nshot),
-                           dim3(256), 0, c.st, (const float *)w.acc_l, pl.I, mx);
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks(ns)), dim3(256), 0, c.st, mx, ns, 0u);
+        hipLaunchKernelGGL(k_shot_max, dim3(std::min<unsigned>(blocks(pl.I), 1024u), ns),
+                           dim3(256), 0, c.st, (const float *)(w.acc_l + o), pl.I, mx);
         hipLaunchKernelGGL(k_finalize_norm, dim3(blocks(pl.I)), dim3(256), 0, c.st,
-                           (const float *)w.acc_i, (const float *)w.acc_l, pl.nshot, pl.I,
+                           (const float *)(w.acc_i + o), (const float *)(w.acc_l + o), ns, pl.I,
                            (const unsigned *)mx, kNormEps, image_norm);
     }
     if (grad)
         hipLaunchKernelGGL(k_finalize_grad, dim3(blocks(pl.I)), dim3(256), 0, c.st,
-                           (const float *)w.acc_g, pl.nshot, pl.I, vp, (float)pl.g.dt, grad);
+                           (const float *)(w.acc_g + o), ns, pl.I, vp, (float)pl.g.dt, grad);
     if (image)
         hipLaunchKernelGGL(k_finalize_sum, dim3(blocks(pl.I)), dim3(256), 0, c.st,
-                           (const float *)w.acc_i, pl.nshot, pl.I, image);
+                           (const float *)(w.acc_i + o), ns, pl.I, image);
     if (illum)
         hipLaunchKernelGGL(k_finalize_sum, dim3(blocks(pl.I)), dim3(256), 0, c.st,
-                           (const float *)w.acc_l, pl.nshot, pl.I, illum);
+                           (const float *)(w.acc_l + o), ns, pl.I, illum);
     return hipGetLastError();
 }
 

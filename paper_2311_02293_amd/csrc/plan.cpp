@@ -305,6 +305,37 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
         }
         pl.rec_toff.push_back((int)pl.rec_tcell.size());
     }
+    // gather form of the adjoint-source injection: per shot, the distinct nodes of its
+    // receivers' operators in ascending cell order, each with its (receiver, weight) pairs in
+    // ascending receiver order
+    pl.inj_shot.clear();
+    pl.inj_cell.clear();
+    pl.inj_rec.clear();
+    pl.inj_w.clear();
+    pl.inj_off.assign(1, 0);
+    for (int s = 0; s < pl.nshot; ++s) {
+        std::vector<std::pair<long long, int>> ct;   // (cell, tap index), taps in receiver order
+        for (int r = pl.rec_off[s]; r < pl.rec_off[s + 1]; ++r)
+            for (int t = pl.rec_toff[r]; t < pl.rec_toff[r + 1]; ++t) ct.emplace_back(pl.rec_tcell[t], t);
+        std::stable_sort(ct.begin(), ct.end(),
+                         [](const std::pair<long long, int> &a, const std::pair<long long, int> &b) {
+                             return a.first < b.first;
+                         });
+        for (size_t i = 0; i < ct.size(); ++i) {
+            if (i == 0 || ct[i].first != ct[i - 1].first) {
+                if (i) pl.inj_off.push_back((int)pl.inj_rec.size());
+                pl.inj_shot.push_back(s);
+                pl.inj_cell.push_back(ct[i].first);
+            }
+            const int t = ct[i].second;
+            // receiver of tap t: taps of receiver r are rec_toff[r] .. rec_toff[r+1)
+            const int r = (int)(std::upper_bound(pl.rec_toff.begin(), pl.rec_toff.end(), t) -
+                                pl.rec_toff.begin()) - 1;
+            pl.inj_rec.push_back(r);
+            pl.inj_w.push_back(pl.rec_tw[t]);
+        }
+        if (!ct.empty()) pl.inj_off.push_back((int)pl.inj_rec.size());
+    }
 
     pl.save = job != SMI_JOB_FORWARD;
     pl.adjoint = pl.save;
@@ -433,6 +464,8 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                        sizeof(long long) * (size_t)ns + 64);
     pl.off_taps = take(sizeof(int) * (pl.src_toff.size() + pl.rec_toff.size()) +
                        (sizeof(long long) + sizeof(float)) * (pl.src_tcell.size() + pl.rec_tcell.size()) + 64);
+    pl.off_inj = take((sizeof(int) * 2 + sizeof(long long)) * pl.inj_cell.size() +
+                      (sizeof(int) + sizeof(float)) * pl.inj_rec.size() + 64);
     size_t fld = sizeof(float) * (size_t)ns * ((size_t)pl.P * (1 + pl.nd) +
                  2 * (size_t)(G.psz[0] + G.psz[1] + G.psz[2]));
     pl.off_fields = take(fld);
@@ -445,6 +478,9 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.off_rho = pl.rho_acc ? take(sizeof(float) * pl.nd * (size_t)ns * (size_t)pl.P) : 0;
     pl.off_G = pl.need_G ? take(sizeof(float) * (size_t)nt * R) : 0;
     pl.off_dcal = pl.need_dcal ? take(sizeof(float) * (size_t)nt * R) : 0;
+    // tail slack: the fused 2D step reads (and never uses) up to kTailCols columns of a
+    // field or model array past the ghost frame of the last shot
+    take(sizeof(float) * (size_t)kTailCols * pl.ld1);
     pl.bytes = o;
     return SMI_OK;
 }
@@ -491,6 +527,21 @@ Views views(const Plan &pl, void *ws) {
         w.src_toff = (int *)q;
         q += sizeof(int) * pl.src_toff.size();
         w.recv.toff = (int *)q;
+    }
+    {
+        // injection gather: cells (8-byte) first, then shots, offsets, receivers, weights
+        const size_t U = pl.inj_cell.size(), T = pl.inj_rec.size();
+        char *q = b + pl.off_inj;
+        w.inj.U = (int)U;
+        w.inj.cell = (long long *)q;
+        q += sizeof(long long) * U;
+        w.inj.shot = (int *)q;
+        q += sizeof(int) * U;
+        w.inj.off = (int *)q;
+        q += sizeof(int) * (U + 1);
+        w.inj.rec = (int *)q;
+        q += sizeof(int) * T;
+        w.inj.w = (float *)q;
     }
     auto fields = [&](size_t off) {
         Fields f{};

@@ -25,6 +25,7 @@ constexpr int kMaxN = 4;       // half order (orders 4 and 8)
 constexpr int kMaxBlocks = 12; // band blocks per save level: 3 axes x {p, v} x {left, right}
 constexpr int GH = 2 * kMaxN;  // ghost nodes per side and axis (>= the 2N-1 halo of a fused step)
 constexpr int kTaps = 4;       // half-width (saved levels) of the decimated-band interpolator
+constexpr int kTailCols = 32;  // columns of workspace slack after the last region (see plan.cpp)
 constexpr double kKaiserBeta = 6.31;
 
 // ---------------------------------------------------------------- device-side views
@@ -79,6 +80,20 @@ struct BandDesc {
     BandBlock blk[kMaxBlocks];
 };
 
+// Adjoint-source injection as a gather (eq. 8, the transpose of the receiver sampling): the
+// distinct nodes that receiver operators touch, per shot in ascending cell order.  Node u (shot
+// shot[u], cell offset cell[u] inside that shot's field) receives kappa sum_t w[t] G[rec[t]] over
+// t in off[u] .. off[u+1), contributions in ascending receiver order: a fixed summation order,
+// no atomics, so gradients and images are bit-stable from run to run.
+struct Inj {
+    int U;
+    int *shot;          // [U]
+    long long *cell;    // [U]
+    int *off;           // [U + 1]
+    int *rec;           // [T] receiver index (into Recv)
+    float *w;           // [T] operator weight
+};
+
 struct Recv {           // flattened receivers of all shots
     int R;
     int *shot;          // [R]
@@ -116,6 +131,10 @@ struct Plan {
     std::vector<long long> src_tcell, rec_tcell;
     std::vector<float> src_tw, rec_tw;
     bool src_multi = false;        // some source spreads over several nodes
+    // the gather form of the adjoint-source injection (see Inj)
+    std::vector<int> inj_shot, inj_off, inj_rec;
+    std::vector<long long> inj_cell;
+    std::vector<float> inj_w;
     BandDesc band{};
     int nsave = 0;      // saved band levels k dr, k = 0 .. nsave-1
     int nrun = 0;       // forward steps: nt, or past nt until the last saved level (dr > 1)
@@ -125,7 +144,7 @@ struct Plan {
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
     size_t off_rho = 0;
-    size_t off_taps = 0, off_fin = 0;
+    size_t off_taps = 0, off_fin = 0, off_inj = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
@@ -160,6 +179,7 @@ struct Views {
     Cpml cpml;
     int *fbox, *abox, *rbox;
     Recv recv;
+    Inj inj;
     long long *src_cell;  // [nshot] source cell offset inside one shot's field
     int *src_toff;        // [nshot + 1] source operators (see Plan)
     long long *src_tcell;
@@ -197,6 +217,9 @@ struct StepCtx {
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
     int rev = 0;            // 2D reverse step: 0 by batch size, 1 two launches, 2 five launches
+    bool step2d = false;    // 2D forward: the fused marching step (step2d.hip), levels in two buffers
+    int run = 32;           // its run of columns per wavefront (32 or 64)
+    int depth = 2;          // and the columns it loads ahead (1, 2 or 4)
     // receiver sampling of forward step ext_it into ext_dcal, carried by the next forward
     // step's v launch (register-blocked kernels only, see march_forward); -1: none pending
     int ext_it = -1;
@@ -220,6 +243,11 @@ hipError_t adj_step_y3(const StepCtx &c, int it, bool image);
 // dst); false if not provided for this plan
 bool fused_fwd_available(const Plan &pl);
 hipError_t fwd_step_fused(const StepCtx &c, const Fields &src, const Fields &dst, int it);
+// fused marching 2D forward step (step2d.hip): level it from src, level it + 1 to dst, every
+// shot in one launch; carries the receivers of step c.ext_it (sampled from src) and, with
+// c.save_p_slot >= 0, the bands of level it (from src) on extra workgroups
+bool step2d_available(const Plan &pl);
+hipError_t fwd_step_2d(const StepCtx &c, const Fields &src, const Fields &dst, int it);
 hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p = nullptr);
 // p += sign dt stf[it] / dV through the operators of the sources that spread over several
 // nodes (one-tap sources are injected inside the p kernels); nothing when there are none
@@ -232,10 +260,12 @@ hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsna
 hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a);
 hipError_t adj_inject(const StepCtx &c, int it, const float *G);
 hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image);
+// residual, G = dt r and misfit of the shots [s0, s1) (their slice of dcal / dobs / G)
 hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
-                    double *misfit);
+                    double *misfit, int s0, int s1);
+// shot reduction (fixed order) of the shots [s0, s1) into the outputs
 hipError_t finalize(const StepCtx &c, const float *vp, float *grad, float *image, float *illum,
-                    float *image_norm);
+                    float *image_norm, int s0, int s1);
 // density part of eq. (7): accumulate v~ D+p on the faces of reverse step it
 hipError_t rho_faces(const StepCtx &c, int it);
 // tangent-linear step: the perturbation field (q) over the forward box, with the secondary
@@ -243,7 +273,7 @@ hipError_t rho_faces(const StepCtx &c, int it);
 hipError_t born_step(const StepCtx &c, int it, const float *dkappa);
 // gradients of a parametrisation family (1: Vp, rho; 2: Vp, Ip) from the kappa and face sums
 hipError_t finalize_family(const StepCtx &c, const float *vp, const float *rho, int family,
-                           float *g1, float *g2);
+                           float *g1, float *g2, int s0, int s1);
 hipError_t launch_laplacian(const smi_grid *g, const float *in, float *out, hipStream_t st);
 
 }  // namespace smi

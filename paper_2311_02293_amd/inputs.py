@@ -275,6 +275,25 @@ def config4(n=400, nt=3000, dr=10, nshot=4, seed=1004, rec_step=2) -> Job:
     return job
 
 
+def hyperbolic_event(job: "Job", depth: float, v: float, t0: Optional[float] = None) -> List[np.ndarray]:
+    """Synthetic observed data: one reflection event per trace, the job's wavelet delayed by
+    the two-way time sqrt((2 depth / v)^2 + (offset / v)^2) of a flat reflector under a
+    homogeneous overburden, scaled by 1 / (v t) (spherical spreading).  A closed-form stand-in
+    for recorded data (no modelling run); list of [nt, nrec_s] float64 arrays per shot."""
+    g = job.grid
+    fm = g.fm
+    t0 = 1.2 / fm if t0 is None else t0
+    t = np.arange(g.nt) * g.dt
+    out = []
+    for s in range(job.acq.nshot):
+        a, b = int(job.acq.rec_off[s]), int(job.acq.rec_off[s + 1])
+        h = np.sqrt(np.sum((job.acq.rec[a:b, 1:] - job.acq.src[s, 1:]) ** 2, axis=1))
+        tr = np.sqrt((2.0 * depth / v) ** 2 + (h / v) ** 2)
+        arg = (math.pi * fm * (t[:, None] - tr[None, :] - t0)) ** 2
+        out.append((1.0 - 2.0 * arg) * np.exp(-arg) / (v * tr[None, :]))
+    return out
+
+
 def homogeneous(ndim: int, n: int, d: float, c: float, rho: float = 1000.0) -> np.ndarray:
     shape = (n, n, n) if ndim == 3 else (n, n)
     return np.full(shape, c, np.float32), np.full(shape, rho, np.float32)

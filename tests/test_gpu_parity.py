@@ -753,29 +753,91 @@ def test_bench_workload_at_full_size_matches_oracle_on_sampled_shots(ctx):
     got = split(dcal, job)
     ref = oracle_dcal(job, shots=[0, job.acq.nshot - 1], box=1)
     for k, s in enumerate([0, job.acq.nshot - 1]):
-        e = rel_l2(got[s], ref[k])
-        say("full-size shot", s, "rel L2", e)
+        e, wt = rel_l2(got[s], ref[k]), worst_trace(got[s], ref[k])
+        say("full-size shot", s, "rel L2", e, "worst trace", wt)
         assert got[s].shape == (4000, 1500)
         assert e <= 1e-4
+        assert wt <= 1e-3
+
+
+def worst_trace(got, ref, floor=1e-2):
+    """Largest relative L2 error over the traces (columns) holding at least `floor` of the
+    largest trace norm."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    n = np.linalg.norm(ref, axis=0)
+    keep = n >= floor * n.max()
+    return float(np.max(np.linalg.norm(got - ref, axis=0)[keep] / n[keep]))
+
+
+def worst_cell(got, ref):
+    """Largest absolute error over the cells, relative to the largest reference value."""
+    ref = np.asarray(ref, np.float64)
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref)) / np.max(np.abs(ref)))
 
 
 def test_gradient_at_full_size_matches_oracle_for_one_shot(ctx):
     """The gradient workload's grid and time axis (300 x 900, order 8, nt 4000, box on) for one
-    shot, with dobs = 0 (J = dt/2 sum dcal^2): misfit and dJ/dVp against the oracle."""
+    shot, with the residual against data of the true model (+10 % Gaussian anomaly).
+      * The reverse pass (reconstruction, adjoint propagation, eq. 7) driven by the oracle's own
+        adjoint source G = dt (dcal - dobs): dJ/dVp against the oracle, globally (<= 1e-4 rel L2)
+        and cell by cell (<= 1e-4 of the largest value).
+      * The whole of smi_fwi_grad: the misfit (<= 1e-4), and the gradient equal to the reverse
+        pass driven by the call's own residual (1e-6).  Against the oracle that gradient is
+        held to 2e-2 only: shot 0 lies 4.4 km from the anomaly, its residual is the small
+        difference of two seismograms, and the FP32 seismogram's error (about 1e-7 of the
+        direct wave) reaches the residual and, amplified by the adjoint near the surface, the
+        gradient (measured 9e-3)."""
     from oracle import oracle as O
     import torch
     full = I.config3()
-    job = with_bounds(I.Job(full.grid, full.vp, full.rho, full.acq.shot(0), full.stf[:1].copy()))
-    say("full-size gradient, one shot", job.grid.n1, job.grid.n2, job.grid.nt)
-    dobs = [np.zeros((job.grid.nt, int(job.acq.rec_off[1])))]
-    ref_g, ref_J = O.fwi_grad(job, dobs, box=1, vmax=float(job.grid.vpmax))
+    job = I.Job(full.grid, full.vp, full.rho, full.acq.shot(0), full.stf[:1].copy())
+    job = with_bounds(job, [full.extra["vp_true"]])
+    vmax = float(job.grid.vpmax)
+    g = job.grid
+    say("full-size gradient, one shot", g.n1, g.n2, g.nt)
+    dobs = O.forward_job(job, vp=full.extra["vp_true"], box=1, vmax=vmax)[0]
+    gr = O.og_grid(g, vmax=vmax, box=1)
+    src, rec, st, rt = O.shot_ops(g, job.acq, 0)
+    fw = O.forward(gr, job.vp, job.rho, src, job.stf[0], rec, bands=True, final=True)
+    ref_J, G = O.misfit(fw["dcal"], dobs, g.dt)
+    r = O.adjoint(gr, job.vp, job.rho, src, job.stf[0], rec, G, bands=fw["bands"],
+                  final=fw["final"], want=("gk",))
+    ref_g = (2.0 * job.rho.astype(np.float64).ravel() * job.vp.astype(np.float64).ravel()
+             * r["gk"]).reshape(job.vp.shape)
     vp, rho, stf = dev(job)
-    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf,
-                           torch.zeros(job.grid.nt * int(job.acq.rec_off[1]), device="cuda"))
-    g = g.cpu().numpy().reshape(job.vp.shape)
-    say("full-size gradient rel L2", rel_l2(g, ref_g), "J", float(J.cpu()[0]), ref_J)
-    assert abs(float(J.cpu()[0]) - ref_J) <= 1e-4 * ref_J
-    assert rel_l2(g, ref_g) <= 1e-4
+    # reverse pass on the oracle's adjoint source
+    _, _, state = ctx.forward(g, job.acq, vp, rho, stf, save=True)
+    Gt = torch.from_numpy(G.ravel().astype(np.float32)).cuda()
+    out = ctx.adjoint_reconstruct(state, Gt, grad=True, image=False, illum=False)
+    ga = out["grad"].cpu().numpy().reshape(job.vp.shape)
+    ea, wa = rel_l2(ga, ref_g), worst_cell(ga, ref_g)
+    say(f"reverse pass on the oracle's residual: rel L2 {ea:.2e}, worst cell {wa:.2e}")
+    assert ea <= 1e-4
+    assert wa <= 1e-4
+    # the whole gradient call
+    gb, J, dc = ctx.fwi_grad(g, job.acq, vp, rho, stf,
+                             torch.from_numpy(dobs.ravel().astype(np.float32)).cuda(),
+                             want_dcal=True)
+    gb = gb.cpu().numpy().reshape(job.vp.shape)
+    dc = dc.cpu().numpy().reshape(fw["dcal"].shape)
+    J = float(J.cpu()[0])
+    res = np.linalg.norm(fw["dcal"] - dobs)
+    ratio = np.linalg.norm(dc - fw["dcal"]) / res
+    eb = rel_l2(gb, ref_g)
+    say(f"smi_fwi_grad: J {J:.6e} / {ref_J:.6e}, gradient rel L2 {eb:.2e}; seismogram error / "
+        f"residual {ratio:.2e} (residual {res / np.linalg.norm(dobs):.2e} of the data)")
+    assert abs(J - ref_J) <= 1e-4 * ref_J
+    assert eb <= 2e-2
+    # the call's gradient is the reverse pass on its own residual
+    _, _, state = ctx.forward(g, job.acq, vp, rho, stf, save=True)
+    # the call's own FP32 arithmetic: r = dcal - dobs, G = dt r
+    rf = dc.astype(np.float32) - dobs.astype(np.float32)
+    Gc = torch.from_numpy((np.float32(g.dt) * rf).ravel()).cuda()
+    gc = ctx.adjoint_reconstruct(state, Gc, grad=True, image=False, illum=False)["grad"]
+    ec = rel_l2(gc.cpu().numpy().reshape(job.vp.shape), gb)
+    say(f"smi_fwi_grad against the reverse pass on its own residual: {ec:.2e}")
+    assert ec <= 1e-6
 
 
 def test_3d_rtm_grid_at_full_size_matches_oracle_on_a_sampled_shot(ctx):
@@ -789,10 +851,68 @@ def test_3d_rtm_grid_at_full_size_matches_oracle_on_a_sampled_shot(ctx):
     ctx.poll_status()
     got = split(dcal, job)
     ref = oracle_dcal(job, shots=[0], box=1)[0]
-    e = rel_l2(got[0], ref)
-    say("full-size 3D shot 0 rel L2", e)
+    e, wt = rel_l2(got[0], ref), worst_trace(got[0], ref)
+    say("full-size 3D shot 0 rel L2", e, "worst trace", wt)
     assert got[0].shape == (300, 40000)
     assert e <= 1e-4
+    assert wt <= 1e-3
+
+
+def test_3d_rtm_at_its_own_settings_matches_oracle(ctx):
+    """The 3D RTM at its own settings on a 160^3 grid: 12.5 m, order 8, 20 absorbing layers,
+    box on, bands decimated by dr = 10 (the paper's 3D default, Sec. 4.2), nt 600, two shots in
+    one launch, 80 x 80 surface receivers each, a reflection hyperbola as observed data.  The
+    call returns each shot's image and illumination (shot groups); shot 0 against the oracle
+    (image, illumination <= 1e-4 rel L2 and cell by cell; the source field rebuilt from the
+    decimated bands <= 1e-5 against the oracle's own reconstruction); the two shots' results
+    sum, bitwise, to the image of the same call without groups."""
+    from oracle import oracle as O
+    import torch
+    job = I.config4(n=160, nt=600, dr=10, nshot=2)
+    job = with_bounds(job, [job.extra["vp_true"]])
+    vmax = float(job.grid.vpmax)
+    g = job.grid
+    dobs = I.hyperbolic_event(job, depth=0.25 * g.n1 * g.d1, v=2000.0)
+    G = [g.dt * d for d in dobs]
+    npts = job.vp.size
+    levels = [0, 150, 300, 450, 599]
+    say("3D RTM at 160^3, dr", g.dr, "nt", g.nt, "shots", job.acq.nshot)
+    vp, rho, stf = dev(job)
+    Gt = torch.from_numpy(np.concatenate([x.ravel() for x in G]).astype(np.float32)).cuda()
+    try:
+        ctx.set_shot_groups([0, 1, 2])
+        _, _, state = ctx.forward(g, job.acq, vp, rho, stf, save=True)
+        out = ctx.adjoint_reconstruct(state, Gt, grad=False, image=True, illum=True,
+                                      snaps=levels, nshot=2)
+    finally:
+        ctx.set_shot_groups(None)
+    ctx.poll_status()
+    im = out["image"].cpu().numpy().reshape(2, *job.vp.shape)
+    il = out["illum"].cpu().numpy().reshape(2, *job.vp.shape)
+    rec = out["snaps"].cpu().numpy()[0].astype(np.float64)
+    _, _, state = ctx.forward(g, job.acq, vp, rho, stf, save=True)
+    whole = ctx.adjoint_reconstruct(state, Gt, grad=False, image=True, illum=True)
+    np.testing.assert_array_equal(im[0] + im[1], whole["image"].cpu().numpy().reshape(job.vp.shape))
+    np.testing.assert_array_equal(il[0] + il[1], whole["illum"].cpu().numpy().reshape(job.vp.shape))
+    # the oracle, shot 0
+    gr = O.og_grid(g, vmax=vmax, box=1)
+    src, rcv, st, rt = O.shot_ops(g, job.acq, 0)
+    say("oracle forward, shot 0")
+    fw = O.forward(gr, job.vp, job.rho, src, job.stf[0], rcv, bands=True, final=True, st=st, rt=rt)
+    say("oracle reverse, shot 0")
+    r = O.adjoint(gr, job.vp, job.rho, src, job.stf[0], rcv, G[0], bands=fw["bands"],
+                  final=fw["final"], want=("image", "illum"), st=st, rt=rt, snaps=levels)
+    ref_rec = r["snaps"]
+    ref_i = r["image"].reshape(job.vp.shape)
+    ref_l = r["illum"].reshape(job.vp.shape)
+    ei, el = rel_l2(im[0], ref_i), rel_l2(il[0], ref_l)
+    wi, wl = worst_cell(im[0], ref_i), worst_cell(il[0], ref_l)
+    er = np.max(np.linalg.norm(rec - ref_rec, axis=1)) / np.max(np.linalg.norm(ref_rec, axis=1))
+    say(f"3D RTM dr 10: image {ei:.2e} (worst cell {wi:.2e}), illum {el:.2e} "
+        f"(worst cell {wl:.2e}), reconstructed field {er:.2e}")
+    assert max(ei, el) <= 1e-4
+    assert max(wi, wl) <= 1e-4
+    assert er <= 1e-5
 
 
 def test_non_finite_values_are_reported(ctx):
