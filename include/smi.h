@@ -188,6 +188,25 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
                        smi_state **state_out, const int *snap_it, int nsnap, float *snaps,
                        void *ws, size_t ws_bytes, void *hip_stream);
 
+/* Size of the static workspace of smi_forward_static, per device (bytes). */
+#define SMI_STATIC_WS_BYTES (64u << 20)
+
+/* smi_forward (no state, no snapshots) for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation.  The workspace
+ * is a static device buffer of SMI_STATIC_WS_BYTES that the library keeps on each device from
+ * the first context created there until the process ends; the caller passes only inputs and
+ * outputs (vp, rho, stf, dcal as in smi_forward).  The call allocates nothing, captures no graph
+ * and records no timing events (SMI_OPT_GRAPH and SMI_OPT_TIMING are ignored for it).
+ * SMI_E_WORKSPACE, before any device work, when the job's SMI_JOB_FORWARD workspace exceeds
+ * SMI_STATIC_WS_BYTES (a 2D order-8 grid of about 1.5 M padded cells per shot fits); SMI_E_HIP
+ * when the buffer's device address could not be obtained.  Every call on one device uses that
+ * device's one buffer, which keeps the last call's contents (each call clears what it needs):
+ * calls that overlap in time on one device, on any streams or contexts, race -- serialise
+ * them. */
+smi_status smi_forward_static(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                              const float *vp, const float *rho, const float *stf, float *dcal,
+                              void *hip_stream);
+
 /* Reverse loop of Alg. 2 on a saved forward pass (consumes the state).
  *   adj_src  device, layout of dcal: the adjoint source G injected as p~[rec] += kappa G[it]
  *            before reverse step it (eq. 8 in the scaled variable p~ = kappa pbar).

@@ -65,6 +65,8 @@ def lib():
                                           C.POINTER(C.c_size_t)]
         L.smi_forward.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp,
                                   C.POINTER(vp), C.POINTER(C.c_int), C.c_int, vp, vp, C.c_size_t, vp]
+        L.smi_forward_static.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp,
+                                         vp, vp]
         L.smi_adjoint_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int),
                                               C.c_int, vp, vp]
         L.smi_rtm_image.argtypes = [vp, C.POINTER(SmiGrid), C.POINTER(SmiAcq), vp, vp, vp, vp, vp,
@@ -251,6 +253,18 @@ class Context:
         self._check(rc)
         state = State(self, st, (ws, vp, rho, stf)) if save else None
         return dcal, out_snaps, state
+
+    def forward_static(self, grid, acq, vp, rho, stf, *, dcal=None, stream=None):
+        """smi_forward_static: smi_forward without a workspace argument (the library's static
+        device buffer).  Returns dcal."""
+        import torch
+        g = make_grid(grid)
+        a = _Acq(acq)
+        if dcal is None:
+            dcal = torch.empty(grid.nt * a.nrec_total, dtype=torch.float32, device=vp.device)
+        self._check(lib().smi_forward_static(self.h, C.byref(g), C.byref(a.c), _ptr(vp), _ptr(rho),
+                                             _ptr(stf), _ptr(dcal), _stream(stream)))
+        return dcal
 
     def adjoint_reconstruct(self, state: State, adj_src, *, grad=True, grad_rho=False,
                             image=True, illum=True, image_norm=False, snaps: Sequence[int] = (),

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,9 +17,41 @@
 using smi::Plan;
 using smi::Views;
 
+// ---------------------------------------------------------------- static workspace
+// The workspace of smi_forward_static: a file-scope device array of SMI_STATIC_WS_BYTES.  Each
+// GPU the library runs on holds its own copy until the process ends.  Host code never hands
+// the array's name to a kernel or a copy (on the host it is only a stand-in symbol): the
+// array's address on a device comes from hipGetSymbolAddress, taken once per device, with that
+// device current, when the first context on it is created.
+static __device__ __align__(256) unsigned char scratch[SMI_STATIC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the static workspace on `dev` (the current device); looked up once per device.
+hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[dev] = p;
+    return e != hipSuccess ? e : (p ? hipSuccess : hipErrorInvalidSymbol);
+}
+
+void *scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 struct smi_ctx {
     int device = 0;
     std::string err;
+    std::string scratch_err;   // why the static workspace is unavailable (empty: available)
     int opt_kernel = 0;
     int opt_graph = 0;
     int opt_chunk = 0;
@@ -546,6 +579,12 @@ smi_status smi_ctx_create(int hip_device, smi_ctx **out) {
     if (hipSetDevice(hip_device) != hipSuccess) return SMI_E_HIP;
     smi_ctx *c = new smi_ctx();
     c->device = hip_device;
+    // set-up of the static workspace on this device (a failure only disables smi_forward_static)
+    const hipError_t e = scratch_setup(hip_device);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->scratch_err = std::string("static workspace: hipGetSymbolAddress: ") + hipGetErrorString(e);
+    }
     *out = c;
     return SMI_OK;
 }
@@ -627,6 +666,35 @@ smi_status smi_forward(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq, c
     if (s != SMI_OK) return s;
     if (state_out) *state_out = stt.release();
     return SMI_OK;
+}
+
+smi_status smi_forward_static(smi_ctx *ctx, const smi_grid *grid, const smi_acq *acq,
+                              const float *vp, const float *rho, const float *stf, float *dcal,
+                              void *hip_stream) {
+    if (!ctx) return SMI_E_ARG;
+    if (!grid || !acq) return fail(ctx, SMI_E_ARG, "grid / acq is NULL");
+    void *ws = scratch_of(ctx->device);
+    if (!ws || !ctx->scratch_err.empty())
+        return fail(ctx, SMI_E_HIP, ctx->scratch_err.empty() ? "static workspace unavailable" : ctx->scratch_err);
+    size_t need = 0;
+    smi_status s = smi_workspace_bytes(ctx, grid, acq, SMI_JOB_FORWARD, &need);
+    if (s != SMI_OK) return s;
+    if (need > (size_t)SMI_STATIC_WS_BYTES) {
+        char b[200];
+        snprintf(b, sizeof b, "this job needs a %zu-byte workspace; the static workspace holds %zu",
+                 need, (size_t)SMI_STATIC_WS_BYTES);
+        return fail(ctx, SMI_E_WORKSPACE, b);
+    }
+    // nothing that creates runtime objects: no graph capture, no timing events
+    const int graph = ctx->opt_graph, timing = ctx->opt_timing;
+    ctx->opt_graph = 0;
+    ctx->opt_timing = 0;
+    std::unique_ptr<smi_state> stt;
+    s = forward_common(ctx, grid, acq, SMI_JOB_FORWARD, vp, rho, stf, dcal, nullptr, 0, nullptr,
+                       ws, (size_t)SMI_STATIC_WS_BYTES, (hipStream_t)hip_stream, stt);
+    ctx->opt_graph = graph;
+    ctx->opt_timing = timing;
+    return s;
 }
 
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
