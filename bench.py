@@ -33,7 +33,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(job, steps: int):
+def cpu_baseline(job, steps: int, one_thread_steps: int = 200):
     """The FP64 oracle on the host cores: one shot, `steps` time steps at full spatial size,
     computing box off (the plain definition); rate in GPts/s of the same cell-step count."""
     from oracle import oracle as O
@@ -48,9 +48,27 @@ def cpu_baseline(job, steps: int):
     dt = time.perf_counter() - t0
     cells = O.padded_size(gr) * steps
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": cells / dt / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 shot x {steps} of {job.grid.nt} steps, full padded grid "
-                      f"{g.n1 + 2 * g.nb}x{g.n2 + 2 * g.nb}, FP64, box off; {dt:.1f} s"}
+    out = {"value": cells / dt / 1e9, "unit": "GPts/s", "cores": threads, "kind": "oracle",
+           "sample": f"1 shot x {steps} of {job.grid.nt} steps, full padded grid "
+                     f"{g.n1 + 2 * g.nb}x{g.n2 + 2 * g.nb}, FP64, box off; {dt:.1f} s"}
+    # the same oracle on one thread (OpenMP runtime of the oracle's library), a shorter sample
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        g1 = copy.copy(g)
+        g1.nt = one_thread_steps
+        gr1 = O.og_grid(g1, vmax=float(job.grid.vpmax), box=0)
+        t0 = time.perf_counter()
+        O.forward(gr1, job.vp, job.rho, src, job.stf[0][:one_thread_steps], rec)
+        d1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["one_thread"] = {"value": O.padded_size(gr1) * one_thread_steps / d1 / 1e9,
+                             "unit": "GPts/s", "cores": 1,
+                             "sample": f"1 shot x {one_thread_steps} steps; {d1:.1f} s"}
+    except OSError:
+        out["one_thread"] = None
+    return out
 
 
 def probe_copy(torch, gib: float = 1.0, reps: int = 20):
@@ -165,6 +183,67 @@ def latency(torch, graph: bool = False, only: str = "", reps_override: int = 0):
         del ws, dobs
 
 
+def reverse_leg(torch, reps: int = 5, timing_every: int = 32):
+    """The 2D FWI gradient workload (300 x 900, order 8, 32 shots, nt 4000, box on, bands at
+    every step): per-call p50 / p99 of smi_fwi_grad, GPts/s of its forward + adjoint +
+    reconstruction cell updates, and the reverse iteration's algorithmic GB/s from device-
+    stamped events around every `timing_every`-th reverse iteration of one more call.  The
+    observed data are the same library's forward data of the true model (synthetic)."""
+    from paper_2311_02293_amd import binding as B
+    from paper_2311_02293_amd import inputs as I
+    job = I.config3()
+    vt = job.extra["vp_true"]
+    job.grid.vpmin = float(min(job.vp.min(), vt.min()))
+    job.grid.vpmax = float(max(job.vp.max(), vt.max()))
+    vp, rho, stf = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (job.vp, job.rho, job.stf))
+    ctx = B.Context(0)
+    stream = torch.cuda.current_stream()
+    ws = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_GRAD))
+    dobs, _, _ = ctx.forward(job.grid, job.acq, torch.from_numpy(vt).cuda(), rho, stf)
+
+    def call():
+        ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs, ws=ws, stream=stream)
+    print("bench: reverse leg warm-up", file=sys.stderr, flush=True)
+    call()
+    torch.cuda.synchronize()
+    ms = []
+    for r in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+        print(f"bench: reverse leg rep {r}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    upd = sum(ctx.last_counts())
+    fwd_bytes, rev_bytes = ctx.last_bytes()
+    ctx.set_option(B.OPT_TIMING, timing_every)
+    call()
+    torch.cuda.synchronize()
+    rms, rby, rn = ctx.kernel_timing(3)
+    fv, fb, _ = ctx.kernel_timing(1)
+    fp, _, _ = ctx.kernel_timing(2)
+    fs_bytes = ctx.kernel_timing(0)[1]
+    ctx.set_option(B.OPT_TIMING, 0)
+    rev_GBps = rby / (rms / 1e3) / 1e9 if rms > 0 else None
+    fwd_us = (fv + fp) * 1e3
+    out = {"workload": job.name, "call": "smi_fwi_grad", "reps": reps, "warmup": 1,
+           "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
+           "value": upd / (np.median(ms) / 1e3) / 1e9, "unit": "GPts/s",
+           "gpts_per_call": upd,
+           "whole_call_alg_GBps": (fwd_bytes + rev_bytes) / (np.median(ms) / 1e3) / 1e9,
+           "reverse_step": {"avg_us": rms * 1e3, "alg_bytes": rby, "samples": rn,
+                            "achieved_GBps": rev_GBps, "peak_GBps": HBM_PEAK_GBS,
+                            "frac": rev_GBps / HBM_PEAK_GBS if rev_GBps else None,
+                            "what": "one reverse iteration of Alg. 2 over 32 shots (adjoint "
+                                    "source, source removal, reconstruction with the gradient "
+                                    "sum, adjoint step), first launch to end of last"},
+           "forward_step": {"avg_us": fwd_us, "alg_bytes": fs_bytes,
+                            "achieved_GBps": fs_bytes / (fwd_us / 1e6) / 1e9 if fwd_us > 0 else None}}
+    del ws, dobs
+    return out
+
+
 def serve(torch, njobs: int):
     """Served stream of mixed requests: a capacity run (every request queued at t = 0), then the
     same requests arriving as a Poisson stream at 0.7 x that capacity (latency p50 / p99), then
@@ -266,6 +345,10 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the library's default kernels instead of the autotuner's pick")
+    ap.add_argument("--no-reverse", action="store_true",
+                    help="skip the reverse leg (the 2D FWI gradient workload)")
     ap.add_argument("--kernel", type=int, default=-1,
                     help="SMI_OPT_KERNEL for the timed forward (-1: the library's default)")
     ap.add_argument("--chunk", type=int, default=-1, help="SMI_OPT_CHUNK (-1: default)")
@@ -300,6 +383,10 @@ def main():
         ctx.set_option(B.OPT_KERNEL, args.kernel)
     if args.chunk >= 0:
         ctx.set_option(B.OPT_CHUNK, args.chunk)
+    # the library picks the step kernels by timing them (first call of the shape: the warm-up)
+    tuned = args.kernel < 0 and not args.no_autotune
+    if tuned:
+        ctx.set_option(B.OPT_AUTOTUNE, 1)
     nrec = int(job.acq.rec_off[-1])
     dcal = torch.empty(job.grid.nt * nrec, dtype=torch.float32, device=dev)
     ws = ctx.workspace(ctx.workspace_bytes(job.grid, job.acq, B.JOB_FORWARD))
@@ -338,8 +425,10 @@ def main():
         kt[name] = {"avg_us": kms * 1e3, "alg_bytes": kby, "samples": kn,
                     "GBps": kby / (kms / 1e3) / 1e9 if kms > 0 else None}
     ctx.set_option(B.OPT_TIMING, 0)
+    pick = ctx.tuning_report() if tuned else ""
     # duration of the step = the two kernels' own durations (the span from the start of the v
-    # kernel to the end of the p kernel also holds the launch gap between them)
+    # kernel to the end of the p kernel also holds the launch gap between them); a fused step
+    # is one kernel (reported as the first, the second reports nothing)
     step_us = kt["v_kernel"]["avg_us"] + kt["p_kernel"]["avg_us"]
     step_bytes = kt["step_span"]["alg_bytes"]
     achieved = step_bytes / (step_us / 1e6) / 1e9 if step_us > 0 else None
@@ -359,11 +448,25 @@ def main():
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS if achieved else None,
                         "traffic": counter_traffic(),
-                        "kernel": "forward time step: v kernel + p kernel (k_march_v, k_march_p) "
-                                  "over 16 shots",
+                        "kernel": ("forward time step over 16 shots, " +
+                                   ("fused v + p kernel (k_step2d)" if kt["p_kernel"]["samples"] == 0
+                                    else "v kernel + p kernel (k_march_v, k_march_p)")),
                         "alg_bytes_per_launch": step_bytes, "avg_launch_us": step_us,
                         "kernels": kt, "whole_job_alg_GBps": whole_job_GBps,
                         "whole_job_alg_bytes": alg_bytes}}
+
+    if tuned:
+        # the library's default kernels on the same workload, for comparison with the pick
+        ctx.set_option(B.OPT_AUTOTUNE, 0)
+        step()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out["autotune"] = {"pick": pick, "default_kernels_ms_per_step": a.elapsed_time(b),
+                           "picked_ms_per_step": total_ms / args.steps}
+        print(f"bench: autotuner {pick}", file=sys.stderr, flush=True)
 
     if not args.no_plain:
         # plain stepper: one shot per launch, separate v and p kernels, box off
@@ -384,6 +487,11 @@ def main():
                         "gpts_per_step": pg,
                         "what": "one shot per launch, separate v and p kernels, box off",
                         "batched_speedup_wall": pms / (total_ms / args.steps)}
+
+    if not args.no_reverse:
+        print("bench: reverse leg", file=sys.stderr, flush=True)
+        del ws
+        out["reverse"] = reverse_leg(torch)
 
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)

@@ -112,8 +112,13 @@ typedef enum {
                                 lane sweep kernels in the order of SMI_OPT_TILEMAP; 5: as 0, and
                                 in 3D half steps that march along y (SMI_OPT_CHUNK = 100 BX + CY:
                                 BX = 4 or 8 x-columns of 64 z cells per wavefront, CY = 16,
-                                32 or 64 y-planes per workgroup, 32 at order 4; 0: 832).  With a free surface, 2 and the y-marching
-                                kernels of 5 give way to the kernels of 0. */
+                                32 or 64 y-planes per workgroup, 32 at order 4; 0: 832); 6: as 0,
+                                and in 2D forward passes the fused marching step (v and p of
+                                every shot in one launch, levels in two buffers, SMI_OPT_CHUNK
+                                = 100 D + C: runs of C = 32 or 64 columns per wavefront, loads
+                                issued D = 1, 2 or 4 columns ahead; 0: D 2, C 32).  With a free
+                                surface, 2, 6 and the y-marching kernels of 5 give way to the
+                                kernels of 0. */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and
                                 buffers) and replayed on later calls; up to 8 graphs are kept
@@ -124,9 +129,11 @@ typedef enum {
                                 the tiled variant (64 rows x 4 C columns per workgroup, p and
                                 the new v staged in LDS) */
     SMI_OPT_TIMING = 3,      /* S > 0: every S-th forward time step of the batched kernels
-                                is launched with device-stamped start / stop events (read with
+                                is launched with device-stamped start / stop events, and every
+                                S-th reverse iteration is bracketed by events (read with
                                 smi_kernel_timing); 0: off (default).  Setting it clears the
-                                samples collected so far. */
+                                samples collected so far.  Reverse loops are not replayed as
+                                graphs while it is on. */
     SMI_OPT_TILEMAP = 4,     /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
                                 then x-block); 1 each of the 8 XCDs takes a contiguous range of
                                 x-blocks, so tiles that share halos share an L2; 2 (3D, kernel
@@ -136,12 +143,27 @@ typedef enum {
                                 grad_vp = dJ/dVp at fixed rho, grad_rho = dJ/drho at fixed Vp;
                                 2 (Vp, Ip = rho Vp): grad_vp = dJ/dVp at fixed Ip, grad_rho =
                                 dJ/dIp at fixed Vp */
-    SMI_OPT_REVERSE = 6      /* 2D reverse step of the default kernels: 0 (default) two launches
+    SMI_OPT_REVERSE = 6,     /* 2D reverse step of the default kernels: 0 (default) two launches
                                 per step (reconstruction of p with the adjoint v update and the p
                                 bands; then reconstruction of v with the adjoint p update and the
                                 v bands) for batches of up to 8 M padded cells, five launches
                                 above; 1 always two; 2 always five.  Same results. */
+    SMI_OPT_AUTOTUNE = 7     /* 1: the library picks the kernels per plan shape (geometry, shots,
+                                nt, box, dr, job kind) by timing them on the device: the first
+                                forward pass of a shape times every forward candidate (kernel
+                                family, cells per lane, tile order, the fused 2D step's run width
+                                and look-ahead) on 24 steps spread over the schedule, on cleared
+                                fields, and runs with the fastest (one blocking wait per shape);
+                                the first 2D reverse pass of a shape alternates its two reverse-
+                                step forms on every 16th iteration and the next reverse pass
+                                keeps the faster.  Every candidate gives the default's results.
+                                smi_tuning_report tells the last pick.  0: off (default);
+                                2: forget the picks made so far (the switch stays as it was). */
 } smi_option;
+
+/* Text of the autotuner's last pick on this context (candidates, their times per step, the
+ * pick), or "" before any (never NULL). */
+const char *smi_tuning_report(const smi_ctx *ctx);
 
 /* Create a context on HIP device `hip_device`. */
 smi_status smi_ctx_create(int hip_device, smi_ctx **out);
@@ -294,9 +316,9 @@ smi_status smi_last_counts(const smi_ctx *ctx, double *fwd, double *adj, double 
  * move it.  Used to express throughput as a fraction of the HBM roofline. */
 smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_bytes);
 
-/* Durations of the forward time-step kernels sampled (SMI_OPT_TIMING) since the option was
- * last set, over every forward pass run on this context meanwhile.  Waits for the sampled
- * kernels to finish.
+/* Durations of the forward time-step kernels (which 0-2) or of whole reverse iterations
+ * (which 3) sampled (SMI_OPT_TIMING) since the option was last set, over every forward or
+ * reverse pass run on this context meanwhile.  Waits for the sampled work to finish.
  *   which 0: the whole step (start of the v kernel to the end of the p kernel), with the
  *            algorithmic bytes of the step as the method defines it (fields read and written
  *            once, CPML memory variables, the model once per step for the batch);
@@ -304,7 +326,12 @@ smi_status smi_last_bytes(const smi_ctx *ctx, double *fwd_bytes, double *rev_byt
  *            writes v_a, CPML variables of p, dt beta_a);
  *         2: the p kernel (eq. 3, second row, source injection) and its bytes (reads v_a, reads
  *            and writes p, CPML variables of v, dt kappa).
- *   With the fused 2D step (SMI_OPT_KERNEL 2) the step is one kernel: which 0 and 1 both
+ *         3: a reverse iteration of Alg. 2 (adjoint source, source removal, reconstruction,
+ *            adjoint step, accumulators; from its first launch to the end of its last, gaps
+ *            between launches included) and its algorithmic bytes (adjoint and reconstructed
+ *            fields read and written once, CPML variables, model, restored bands, adjoint
+ *            sources, and the accumulators the call computes).
+ *   With a fused 2D step (SMI_OPT_KERNEL 2 or 6) the step is one kernel: which 0 and 1 both
  *   report it, with the step's bytes, and which 2 reports nothing (0 ms, 0 bytes).
  *   avg_ms     mean kernel duration over the samples (ms);
  *   avg_bytes  mean algorithmic bytes of the sampled launches;

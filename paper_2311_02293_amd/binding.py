@@ -20,6 +20,7 @@ STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
           -8: "SMI_E_NONFINITE"}
 JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD, JOB_BORN = 0, 1, 2, 3, 4
 OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY, OPT_REVERSE = 0, 1, 2, 3, 4, 5, 6
+OPT_AUTOTUNE = 7
 
 
 class SmiError(RuntimeError):
@@ -58,6 +59,8 @@ def lib():
         L.smi_ctx_destroy.restype = None
         L.smi_last_error.argtypes = [vp]
         L.smi_last_error.restype = C.c_char_p
+        L.smi_tuning_report.argtypes = [vp]
+        L.smi_tuning_report.restype = C.c_char_p
         L.smi_set_option.argtypes = [vp, C.c_int, C.c_int]
         L.smi_set_shot_groups.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
         L.smi_check.argtypes = [vp, C.POINTER(SmiGrid), C.c_double, C.c_double]
@@ -172,6 +175,10 @@ class Context:
     def set_option(self, option: int, value: int):
         self._check(lib().smi_set_option(self.h, option, value))
         self.options[option] = value
+
+    def tuning_report(self) -> str:
+        """smi_tuning_report: the autotuner's last pick on this context."""
+        return lib().smi_tuning_report(self.h).decode()
 
     def set_shot_groups(self, shot_off=None):
         """smi_set_shot_groups: reduced outputs per group of consecutive shots (None: off).

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -72,10 +73,36 @@ struct smi_ctx {
     std::vector<double> sample_bytes;   // [samples][3], as Plan::step_bytes
     std::vector<int> sample_nk;         // kernels of the sampled step (2, or 1 for the fused step)
     size_t nsample = 0;
+    // reverse steps sampled by SMI_OPT_TIMING: events around every opt_timing-th reverse
+    // iteration (rev_events[2 k], [2 k + 1]) and that step's algorithmic bytes
+    std::vector<hipEvent_t> rev_events;
+    std::vector<double> rev_sample_bytes;
+    size_t nrev = 0;
     // shot groups (smi_set_shot_groups): offsets [ngroup + 1]; empty = one group of all shots
     std::vector<int> groups;
+    // autotuner (SMI_OPT_AUTOTUNE): the kernel choice picked per plan shape, the reverse-form
+    // samples of a first reverse call still to be read, and the text of the last pick
+    int opt_autotune = 0;
+    struct Pick {
+        bool fwd = false, rev = false;     // forward kernels / 2D reverse form tuned
+        int march = 0, run = 32, depth = 2, rev_form = 0;
+        bool xcd = false, ymap = false, step2d = false;
+    };
+    std::map<std::string, Pick> picks;
+    struct RevTune {
+        std::string key;
+        std::vector<hipEvent_t> ev;        // [2 k], [2 k + 1] around sampled iteration k
+        std::vector<int> form;             // its reverse form (1 or 2)
+    };
+    std::vector<RevTune> rev_tunes;
+    std::vector<hipEvent_t> tune_events;
+    std::string tune_report;
     ~smi_ctx() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : rev_events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : tune_events) (void)hipEventDestroy(e);
+        for (auto &r : rev_tunes)
+            for (hipEvent_t e : r.ev) (void)hipEventDestroy(e);
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
         if (cap) (void)hipStreamDestroy(cap);
     }
@@ -91,6 +118,34 @@ struct smi_state {
 };
 
 namespace {
+
+// The plan shape an autotuner pick holds for: geometry, batch, schedule and job kind.
+std::string shape_key(const Plan &pl) {
+    char b[256];
+    snprintf(b, sizeof b, "%d %d %d %d %d %d %d %d %d %d %d %d", pl.nd, pl.N, pl.n[0], pl.n[1],
+             pl.n[2], pl.g.nb, pl.nshot, pl.g.nt, pl.g.box, pl.g.dr, pl.g.freesurf, (int)pl.save);
+    return b;
+}
+
+// Apply an autotuner pick (SMI_OPT_AUTOTUNE) for this plan shape over the kernel options:
+// the forward kernels to a forward pass, the reverse form to a reverse pass.
+void apply_pick(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl, bool forward) {
+    if (!ctx->opt_autotune || c.plain) return;
+    auto it = ctx->picks.find(shape_key(pl));
+    if (it == ctx->picks.end()) return;
+    const smi_ctx::Pick &p = it->second;
+    if (forward && p.fwd) {
+        c.march = p.march;
+        c.xcd = p.xcd;
+        c.ymap = p.ymap;
+        c.step2d = p.step2d;
+        c.run = p.run;
+        c.depth = p.depth;
+        c.zl = false;
+        c.y3 = 0;
+    }
+    if (!forward && p.rev) c.rev = p.rev_form;
+}
 
 // Kernel choice of a step context from the context options.  Default: register-blocked half
 // steps, 4 cells per lane with the XCD-contiguous order in 2D, 2 cells per lane in the plain
@@ -336,6 +391,144 @@ smi_status check_snaps(smi_ctx *ctx, const smi_grid *g, const int *snap_it, int 
     return SMI_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+
+// Forward candidates for a plan: kernel family, cells per lane, tile order, and the run width
+// and look-ahead of the fused 2D step.  Every candidate gives the default's results (bitwise
+// for the register-blocked kernels and the fused step, as the parity tests check).
+struct Cand {
+    int march;
+    bool xcd, ymap, step2d;
+    int run, depth;
+    const char *name;
+};
+
+std::vector<Cand> fwd_candidates(const Plan &pl) {
+    std::vector<Cand> v;
+    if (pl.nd == 2) {
+        v.push_back({4, true, false, false, 32, 2, "march4-xcd"});
+        v.push_back({2, true, false, false, 32, 2, "march2-xcd"});
+        v.push_back({8, true, false, false, 32, 2, "march8-xcd"});
+        v.push_back({4, false, false, false, 32, 2, "march4-plain"});
+        if (smi::step2d_available(pl)) {
+            v.push_back({4, true, false, true, 32, 2, "fused-c32-d2"});
+            v.push_back({4, true, false, true, 64, 2, "fused-c64-d2"});
+            v.push_back({4, true, false, true, 32, 4, "fused-c32-d4"});
+        }
+    } else {
+        v.push_back({2, false, false, false, 32, 2, "march2-plain"});
+        v.push_back({4, false, false, false, 32, 2, "march4-plain"});
+        v.push_back({2, true, false, false, 32, 2, "march2-xcd"});
+        v.push_back({2, false, true, false, 32, 2, "march2-ystrip"});
+    }
+    return v;
+}
+
+void set_cand(smi::StepCtx &c, const Cand &q) {
+    c.march = q.march;
+    c.xcd = q.xcd;
+    c.ymap = q.ymap;
+    c.step2d = q.step2d;
+    c.run = q.run;
+    c.depth = q.depth;
+    c.zl = false;
+    c.y3 = 0;
+}
+
+smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipStream_t st);
+
+// Time every forward candidate on the same steps -- three windows of 8 consecutive steps at
+// 30, 60 and 90 % of the schedule, so the boxes are those the call will run -- with events
+// around each candidate's launches (gaps between dependent launches included), keep the
+// fastest for this plan shape, and clear the fields the timing runs wrote.  Blocks until the
+// timing runs are done (once per plan shape and context).
+smi_status tune_forward(smi_ctx *ctx, const Plan &pl, const Views &w, smi::StepCtx &c,
+                        hipStream_t st) {
+    const std::vector<Cand> cands = fwd_candidates(pl);
+    constexpr int K = 8;
+    std::vector<int> steps;
+    for (double f : {0.3, 0.6, 0.9}) {
+        const int s0 = (int)(f * std::max(0, pl.nrun - K));
+        for (int k = 0; k < K && s0 + k < pl.nrun; ++k) steps.push_back(s0 + k);
+    }
+    while (ctx->tune_events.size() < 2 * cands.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e), "tuning event");
+        ctx->tune_events.push_back(e);
+    }
+    smi::StepCtx t = c;
+    t.st = st;
+    t.ev = nullptr;
+    t.ext_it = -1;
+    t.save_p_slot = t.save_v_slot = -1;
+    for (size_t q = 0; q < cands.size(); ++q) {
+        set_cand(t, cands[q]);
+        HIPCHK(hipEventRecord(ctx->tune_events[2 * q], st), "tuning event");
+        for (int it : steps)
+            HIPCHK(t.step2d ? smi::fwd_step_2d(t, w.f, w.f2, it) : smi::fwd_step(t, it), "tuning step");
+        HIPCHK(hipEventRecord(ctx->tune_events[2 * q + 1], st), "tuning event");
+    }
+    HIPCHK(hipEventSynchronize(ctx->tune_events[2 * cands.size() - 1]), "tuning sync");
+    size_t best = 0;
+    float best_ms = 0.f;
+    std::string rep = "forward " + shape_key(pl) + ":";
+    for (size_t q = 0; q < cands.size(); ++q) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->tune_events[2 * q], ctx->tune_events[2 * q + 1]), "tuning time");
+        char b[96];
+        snprintf(b, sizeof b, " %s %.1f us/step;", cands[q].name, 1e3 * ms / steps.size());
+        rep += b;
+        if (q == 0 || ms < best_ms) { best = q; best_ms = ms; }
+    }
+    rep += std::string(" pick ") + cands[best].name;
+    smi_ctx::Pick &p = ctx->picks[shape_key(pl)];
+    p.fwd = true;
+    p.march = cands[best].march;
+    p.xcd = cands[best].xcd;
+    p.ymap = cands[best].ymap;
+    p.step2d = cands[best].step2d;
+    p.run = cands[best].run;
+    p.depth = cands[best].depth;
+    ctx->tune_report = rep;
+    set_cand(c, cands[best]);
+    // the timing runs wrote both field sets (and receivers and bands the loop rewrites)
+    smi_status s = zero_fields(ctx, pl, w.f, st);
+    if (s == SMI_OK && pl.dbuf) s = zero_fields(ctx, pl, w.f2, st);
+    return s;
+}
+
+// Read the reverse-form samples of an earlier reverse call on this plan shape (their events
+// completed long ago) and keep the faster form.
+smi_status read_rev_tune(smi_ctx *ctx, const std::string &key) {
+    for (size_t i = 0; i < ctx->rev_tunes.size(); ++i) {
+        smi_ctx::RevTune &r = ctx->rev_tunes[i];
+        if (r.key != key) continue;
+        double t[3] = {0, 0, 0};
+        int n[3] = {0, 0, 0};
+        for (size_t k = 0; k < r.form.size(); ++k) {
+            HIPCHK(hipEventSynchronize(r.ev[2 * k + 1]), "tuning sync");
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r.ev[2 * k], r.ev[2 * k + 1]), "tuning time");
+            t[r.form[k]] += ms;
+            ++n[r.form[k]];
+        }
+        smi_ctx::Pick &p = ctx->picks[key];
+        p.rev = true;
+        if (n[1] && n[2]) {
+            const double a = t[1] / n[1], b = t[2] / n[2];
+            p.rev_form = a <= b ? 1 : 2;
+            char buf[160];
+            snprintf(buf, sizeof buf, "reverse %s: two-launch %.1f us/step; five-launch %.1f us/step; pick %s",
+                     key.c_str(), 1e3 * a, 1e3 * b, a <= b ? "two-launch" : "five-launch");
+            ctx->tune_report = buf;
+        }
+        for (hipEvent_t e : r.ev) (void)hipEventDestroy(e);
+        ctx->rev_tunes.erase(ctx->rev_tunes.begin() + i);
+        return SMI_OK;
+    }
+    return SMI_OK;
+}
+
 // Alg. 2, forward loop: [save bands] -> v, p update with source -> record.
 smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float *vp,
                        const float *rho, const float *stf, float *dcal, const int *snap_it,
@@ -347,6 +540,11 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     if (s != SMI_OK) return s;
     smi::StepCtx c{&pl, &w, stf, st, false};
     configure(c, ctx, pl);
+    apply_pick(c, ctx, pl, true);
+    if (ctx->opt_autotune && !c.plain && !ctx->picks[shape_key(pl)].fwd) {
+        s = tune_forward(ctx, pl, w, c, st);
+        if (s != SMI_OK) return s;
+    }
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == 0) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
     const bool f2d = c.step2d;
@@ -481,23 +679,70 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     if (want_r)
         HIPCHK(hipMemsetAsync(w.acc_r[0], 0, sizeof(float) * pl.nd * (size_t)pl.nshot * pl.P, st),
                "density sums clear");
+    const std::string key = shape_key(pl);
+    if (ctx->opt_autotune) {
+        s = read_rev_tune(ctx, key);
+        if (s != SMI_OK) return s;
+    }
     smi::StepCtx c{&pl, &w, stt->stf, st, false};
     configure(c, ctx, pl);
+    apply_pick(c, ctx, pl, false);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    const bool timed = ctx->opt_timing > 0;
+    // 2D reverse form not yet tuned for this shape: sampled iterations of this call alternate
+    // the two forms (bitwise the same results), timed by events read on the next call
+    const bool rev_tune = ctx->opt_autotune && pl.nd == 2 && !c.plain && c.march == 4 && !c.zl &&
+                          !ctx->picks[key].rev && pl.g.nt >= 64;
+    smi_ctx::RevTune rt;
+    rt.key = key;
+    const int base_rev = c.rev;
     auto loop = [&](hipStream_t ls) -> smi_status {
         c.st = ls;
         for (int it = pl.g.nt - 1; it >= 0; --it) {
+            // sampled reverse step: the device stamps an event before its first launch and
+            // after its last
+            hipEvent_t *ev = nullptr;
+            if (timed && it % ctx->opt_timing == 0) {
+                const size_t k = ctx->nrev;
+                while (ctx->rev_events.size() < 2 * (k + 1)) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e), "timing event");
+                    ctx->rev_events.push_back(e);
+                }
+                const double *q = &pl.rev_bytes[4 * (size_t)it];
+                ctx->rev_sample_bytes.push_back(q[0] + (want_g ? q[1] : 0.0) +
+                                                (want_i && (image || image_norm) ? q[2] : 0.0) +
+                                                (want_i && (illum || image_norm) ? q[3] : 0.0));
+                ctx->nrev = k + 1;
+                ev = &ctx->rev_events[2 * k];
+                HIPCHK(hipEventRecord(ev[0], ls), "timing event");
+            }
             if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
             HIPCHK(smi::src_taps(c, it, w.f.p, -1.f), "source removal");
-            HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+            if (rev_tune && it % 16 == 7) {
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0), "tuning event");
+                HIPCHK(hipEventCreate(&e1), "tuning event");
+                rt.ev.push_back(e0);
+                rt.ev.push_back(e1);
+                rt.form.push_back(rt.form.size() % 2 ? 2 : 1);
+                c.rev = rt.form.back();
+                HIPCHK(hipEventRecord(e0, ls), "tuning event");
+                HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+                HIPCHK(hipEventRecord(e1, ls), "tuning event");
+                c.rev = base_rev;
+            } else {
+                HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+            }
             if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
+            if (ev) HIPCHK(hipEventRecord(ev[1], ls), "timing event");
             for (int k = 0; k < nsnap; ++k)
                 if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
         }
         return SMI_OK;
     };
-    if (ctx->opt_graph) {
+    if (ctx->opt_graph && !timed && !rev_tune) {
         Key k = plan_key('R', pl, c);
         k.put(stt->ws).put(stt->stf).put(G).put(snaps).put(nsnap).put(adj).put(want_g);
         k.put(want_i).put(want_r);
@@ -507,6 +752,8 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
         s = loop(st);
     }
     c.st = st;
+    if (rev_tune && !rt.form.empty()) ctx->rev_tunes.push_back(rt);
+    else for (hipEvent_t e : rt.ev) (void)hipEventDestroy(e);
     if (s != SMI_OK) return s;
     // one output array per shot group, each the fixed-order sum over its own shots
     const size_t ng = grp.size() - 1;
@@ -601,11 +848,21 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && value >= 0 && value <= 2) { ctx->opt_xcd = value; return SMI_OK; }
     if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
+    if (option == SMI_OPT_AUTOTUNE && (value == 0 || value == 1 || value == 2)) {
+        if (value == 2) {   // forget the picks
+            ctx->picks.clear();
+            value = ctx->opt_autotune;
+        }
+        ctx->opt_autotune = value;
+        return SMI_OK;
+    }
     if (option == SMI_OPT_TIMING && value >= 0) {
         ctx->opt_timing = value;
         ctx->nsample = 0;
         ctx->sample_bytes.clear();
         ctx->sample_nk.clear();
+        ctx->nrev = 0;
+        ctx->rev_sample_bytes.clear();
         return SMI_OK;
     }
     return fail(ctx, SMI_E_ARG, "unknown option or value");
@@ -686,16 +943,20 @@ smi_status smi_forward_static(smi_ctx *ctx, const smi_grid *grid, const smi_acq 
         return fail(ctx, SMI_E_WORKSPACE, b);
     }
     // nothing that creates runtime objects: no graph capture, no timing events
-    const int graph = ctx->opt_graph, timing = ctx->opt_timing;
+    const int graph = ctx->opt_graph, timing = ctx->opt_timing, tune = ctx->opt_autotune;
     ctx->opt_graph = 0;
     ctx->opt_timing = 0;
+    ctx->opt_autotune = 0;
     std::unique_ptr<smi_state> stt;
     s = forward_common(ctx, grid, acq, SMI_JOB_FORWARD, vp, rho, stf, dcal, nullptr, 0, nullptr,
                        ws, (size_t)SMI_STATIC_WS_BYTES, (hipStream_t)hip_stream, stt);
     ctx->opt_graph = graph;
     ctx->opt_timing = timing;
+    ctx->opt_autotune = tune;
     return s;
 }
+
+const char *smi_tuning_report(const smi_ctx *ctx) { return ctx ? ctx->tune_report.c_str() : ""; }
 
 smi_status smi_adjoint_reconstruct(smi_ctx *ctx, smi_state *state, const float *adj_src,
                                    float *grad_vp, float *grad_rho, float *image, float *illum,
@@ -859,8 +1120,23 @@ smi_status smi_laplacian(smi_ctx *ctx, const smi_grid *grid, const float *in, fl
 
 smi_status smi_kernel_timing(smi_ctx *ctx, int which, double *avg_ms, double *avg_bytes,
                              int *nsamples) {
-    if (!ctx || which < 0 || which > 2) return fail(ctx, SMI_E_ARG, "which must be 0, 1 or 2");
+    if (!ctx || which < 0 || which > 3) return fail(ctx, SMI_E_ARG, "which must be 0, 1, 2 or 3");
     double ms = 0, by = 0;
+    if (which == 3) {
+        for (size_t k = 0; k < ctx->nrev; ++k) {
+            hipError_t e = hipEventSynchronize(ctx->rev_events[2 * k + 1]);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, ctx->rev_events[2 * k], ctx->rev_events[2 * k + 1]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "kernel timing");
+            ms += t;
+            by += ctx->rev_sample_bytes[k];
+        }
+        const double n = (double)ctx->nrev;
+        if (avg_ms) *avg_ms = n > 0 ? ms / n : 0.0;
+        if (avg_bytes) *avg_bytes = n > 0 ? by / n : 0.0;
+        if (nsamples) *nsamples = (int)ctx->nrev;
+        return SMI_OK;
+    }
     for (size_t k = 0; k < ctx->nsample; ++k) {
         const bool one = ctx->sample_nk[k] == 1;
         if (one && which == 2) continue;          // a fused step has no second kernel

@@ -207,8 +207,10 @@ void algorithmic_bytes(Plan &pl) {
     double R = pl.rec_off[ns];
     double bf = 0, br = 0;
     pl.step_bytes.assign((size_t)pl.nrun * 3, 0.0);
+    pl.rev_bytes.assign(pl.adjoint ? (size_t)nt * 4 : 0, 0.0);
     for (int it = 0; it < pl.nrun; ++it) {
         double maxf = 0, maxa = 0, sb = 0, sv = 0, sp = 0;
+        double rb0 = 0, rg = 0, ri = 0, rl = 0;
         const bool adj_it = pl.adjoint && it < nt;
         for (int s = 0; s < ns; ++s) {
             const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
@@ -224,9 +226,10 @@ void algorithmic_bytes(Plan &pl) {
                 double va = (double)std::max(0, ab[1] - ab[0]) * std::max(0, ab[3] - ab[2]) *
                             std::max(0, ab[5] - ab[4]);
                 double vr = (double)(rb[1] - rb[0]) * (rb[3] - rb[2]) * (rb[5] - rb[4]);
-                br += 8.0 * (nd + 1) * va + 16.0 * box_slab_cells(pl, ab);
-                br += 8.0 * (nd + 1) * vr + (12.0 + 8.0) * vr;      // p~ read, gradient, illumination
-                br += 12.0 * va;                                    // image
+                rb0 += 8.0 * (nd + 1) * va + 16.0 * box_slab_cells(pl, ab) + 8.0 * (nd + 1) * vr;
+                rg += 12.0 * vr;                                    // p~ read, gradient
+                rl += 8.0 * vr;                                     // illumination
+                ri += 12.0 * va;                                    // image
                 maxa = std::max(maxa, std::max(va, vr));
             }
         }
@@ -237,7 +240,12 @@ void algorithmic_bytes(Plan &pl) {
         bf += sb + (it < nt ? 8.0 * R : 0.0);
         if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
         const double restore = pl.g.dr == 1 || it % pl.g.dr == 0 ? 8.0 : 4.0 * (2 * kTaps + 1);
-        if (adj_it) br += 4.0 * (nd + 1) * maxa + 8.0 * R + restore * (double)ns * pl.band.B;
+        if (adj_it) {
+            rb0 += 4.0 * (nd + 1) * maxa + 8.0 * R + restore * (double)ns * pl.band.B;
+            double *q = &pl.rev_bytes[4 * (size_t)it];
+            q[0] = rb0; q[1] = rg; q[2] = ri; q[3] = rl;
+            br += rb0 + rg + ri + rl;
+        }
     }
     pl.bytes_fwd = bf;
     pl.bytes_rev = pl.adjoint ? br : 0;

@@ -158,6 +158,10 @@ struct Plan {
     // (fields read and written once), then the v and the p kernel as launched separately
     // (each reads the other field)
     std::vector<double> step_bytes;
+    // [nt][4] algorithmic bytes of reverse step it: the part every reverse step moves (adjoint
+    // and reconstructed fields, CPML variables, model, restored bands, adjoint sources), then
+    // the gradient, image and illumination accumulators
+    std::vector<double> rev_bytes;
 };
 
 // Build and validate a plan.  Returns SMI_OK or an error with `err` filled.

@@ -45,7 +45,9 @@ def test_cpu_baseline_reports_rate_threads_and_sample():
     from paper_2311_02293_amd import inputs as I
     job = I.config2(n1=60, n2=120, nt=50, nshot=2)
     job.grid.vpmax = float(job.vp.max())
-    out = bench.cpu_baseline(job, 20)
+    out = bench.cpu_baseline(job, 20, one_thread_steps=10)
     assert out["kind"] == "oracle" and out["unit"] == "GPts/s"
     assert out["value"] > 0 and out["cores"] >= 1
     assert "20 of 50 steps" in out["sample"]
+    one = out["one_thread"]
+    assert one["cores"] == 1 and one["value"] > 0 and "10 steps" in one["sample"]
