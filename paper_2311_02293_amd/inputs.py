@@ -305,19 +305,82 @@ class StreamJob:
     kind: str              # "forward2d" | "grad2d" | "forward3d"
     arrival: float         # seconds after stream start
     job: Job
+    model_key: Optional[str] = None   # requests with equal keys share grid, model and wavelet
+
+
+_CLASSES = ("forward2d", "grad2d", "forward3d")
+
+
+def _survey(cls: str, k: int, seed: int, scale: float, nt2d: int, nt3d: int, ntgrad: int):
+    """Survey k of a job class of the served stream: grid, model, density and wavelet, built
+    from its own seeded generator (independent of the arrival draws)."""
+    r = np.random.default_rng([seed, _CLASSES.index(cls), k])
+    fm = float(r.uniform(10.0, 15.0))
+    if cls == "forward2d":
+        n1 = max(16, int(r.integers(200, 801) * scale))
+        n2 = max(16, int(r.integers(600, 2001) * scale))
+        nt = max(20, int(nt2d * scale))
+        g = Grid(ndim=2, n1=n1, n2=n2, d1=10.0, d2=10.0, nb=20, order=8, nt=nt, dt=0.8e-3,
+                 fm=fm, box=1)
+        vp = dipping_layers_2d(n1, n2, 10.0, seed=int(r.integers(1 << 30)))
+        return {"grid": g, "vp": vp, "rho": gardner(vp), "extra": {},
+                "stf": ricker(nt, g.dt, fm)[None, :].astype(np.float32)}
+    if cls == "grad2d":
+        n1, n2 = max(16, int(300 * scale)), max(16, int(900 * scale))
+        nt = max(20, int(ntgrad * scale))
+        j = config3(n1=n1, n2=n2, nt=nt, nshot=1, seed=int(r.integers(1 << 30)))
+        j.grid.fm = fm
+        return {"grid": j.grid, "vp": j.vp, "rho": j.rho, "extra": {"vp_true": j.extra["vp_true"]},
+                "stf": ricker(nt, j.grid.dt, fm)[None, :].astype(np.float32)}
+    n = max(12, int(r.integers(200, 351) * scale))
+    nt = max(20, int(nt3d * scale))
+    g = Grid(ndim=3, n1=n, n2=n, n3=n, d1=12.5, d2=12.5, d3=12.5, nb=20, order=8, nt=nt,
+             dt=1e-3, fm=fm, box=1)
+    vp = flat_layers_3d(n, 12.5)
+    return {"grid": g, "vp": vp, "rho": gardner(vp), "extra": {},
+            "stf": ricker(nt, g.dt, fm)[None, :].astype(np.float32)}
 
 
 def stream_config5(njobs=300, rate=1.0, seed=1005, scale=1.0, nt2d=3000, nt3d=1500,
-                   ntgrad=4000) -> List[StreamJob]:
+                   ntgrad=4000, pool=0) -> List[StreamJob]:
     """Served stream: Poisson arrivals; 60% 2D forward (nz~U[200,800], nx~U[600,2000]),
     30% 2D gradient (config-3 sizes, 1 shot), 10% 3D forward (side~U[200,350]); order 8,
-    fm~U[10,15], seeded layered models. `scale` shrinks every size for tests."""
+    fm~U[10,15], seeded layered models. `scale` shrinks every size for tests.
+
+    pool = 0: every request has its own grid and model.  pool > 0: each class draws its
+    requests from `pool` seeded surveys (grid, model and wavelet; model_key "<class>-<k>"),
+    and a request is one shot of its survey at a seeded surface position, with the survey's
+    receiver spread -- the stream of many shots over few models that a modelling or inversion
+    service sees, where requests of one survey can share a launch."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
+    surveys = {}
     for k in range(njobs):
         t += rng.exponential(1.0 / rate)
         u = rng.uniform()
+        if pool > 0:
+            cls = "forward2d" if u < 0.6 else ("grad2d" if u < 0.9 else "forward3d")
+            key = f"{cls}-{int(rng.integers(pool))}"
+            if key not in surveys:
+                surveys[key] = _survey(cls, int(key.rsplit("-", 1)[1]), seed, scale, nt2d,
+                                       nt3d, ntgrad)
+            sv = surveys[key]
+            g = sv["grid"]
+            if g.ndim == 2:
+                sx = float(rng.integers(g.n2)) * g.d2
+                acq = _surface_line(np.array([sx]), 2 * g.d1, np.arange(g.n2) * g.d2, 2 * g.d1)
+            else:
+                n = g.n1
+                sx, sy = (float(v) * g.d2 for v in rng.integers(n, size=2))
+                ys, xs = np.meshgrid(np.arange(0, n, 2), np.arange(0, n, 2), indexing="ij")
+                rec = np.stack([np.full(xs.size, 2 * g.d1), xs.ravel() * g.d2, ys.ravel() * g.d3], 1)
+                acq = Acquisition(np.array([[2 * g.d1, sx, sy]]),
+                                  np.array([0, rec.shape[0]], np.int32), rec)
+            j = Job(g, sv["vp"], sv["rho"], acq, sv["stf"], name=f"{cls}-{k}")
+            j.extra.update(sv["extra"])
+            out.append(StreamJob(cls, t, j, model_key=key))
+            continue
         fm = float(rng.uniform(10.0, 15.0))
         if u < 0.6:
             n1 = max(16, int(rng.integers(200, 801) * scale))

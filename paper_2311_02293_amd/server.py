@@ -5,13 +5,21 @@ The server keeps a FIFO queue; at every scheduling pass it
 
   * merges queued requests that share a grid and a model (same `model_key`) and a job kind
     into one multi-shot call (the library runs all shots of a call in one launch per step);
-  * admits calls while their HBM footprint (workspace from smi_workspace_bytes + model, data
-    and result buffers) fits the remaining budget and a stream is free -- later, smaller calls
+    requests that arrive while a call runs join the next call of their model.  Each member
+    of a merged call gets its own result: its traces of the forward data, or its own
+    gradient, misfit, image and illumination (the call runs with one shot group per
+    request, so the library reduces each request's shots on their own);
+  * admits calls while their HBM footprint (workspace from smi_workspace_bytes + data and
+    result buffers) fits the remaining budget and a stream is free -- later, smaller calls
     may pass a call that does not fit yet (backfill);
   * launches each admitted call on its own HIP stream, so calls admitted while others run
     overlap on the device;
   * polls completion events, frees the call's memory and records per-request latency
-    (completion - arrival).
+    (completion - arrival) and the call's algorithmic HBM bytes.
+
+Models stay on the device between calls: `HipBackend` keeps the device copies of (vp, rho)
+per model_key in a bounded cache (least recently used first out, never while a call uses
+them), so a request on a resident model uploads only its wavelet (and observed data).
 
 A failing request (validation error) fails alone; the rest of the stream continues.  The
 scheduling logic is independent of the device: `HipBackend` runs calls through the C ABI,
@@ -21,8 +29,9 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import threading
 import time
-from collections import deque
+from collections import OrderedDict, deque
 from typing import Any, Dict, List, Optional
 
 import numpy as np
@@ -73,14 +82,61 @@ def merge_requests(reqs: List[Request]) -> I.Job:
     return I.Job(base.grid, base.vp, base.rho, acq, stf, name="+".join(r.job.name for r in reqs))
 
 
+class _ModelCache:
+    """Device copies of (vp, rho) per model_key within `cap` bytes, least recently used out
+    first; an entry that an in-flight call uses is never evicted.  An upload is enqueued on
+    the stream of the call that needs it; a call on another stream waits for its event."""
+
+    def __init__(self, cap: int):
+        self.cap = cap
+        self.used = 0
+        self.d: "OrderedDict[str, dict]" = OrderedDict()
+        self.lock = threading.Lock()
+        self.hits = 0
+        self.misses = 0
+
+    def acquire(self, key, job, torch, dev, stream):
+        nb = 4 * (job.vp.size + job.rho.size)
+        with self.lock:
+            e = self.d.get(key)
+            if e is not None:
+                self.d.move_to_end(key)
+                e["users"] += 1
+                self.hits += 1
+                return e
+            self.misses += 1
+            for k in [k for k, v in self.d.items() if v["users"] == 0]:
+                if self.used + nb <= self.cap:
+                    break
+                self.used -= self.d.pop(k)["bytes"]
+            if self.used + nb > self.cap:
+                return None                  # no room: the call uploads a private copy
+            with torch.cuda.stream(stream):
+                vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(dev)
+                rho = torch.from_numpy(np.ascontiguousarray(job.rho)).to(dev)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            e = {"vp": vp, "rho": rho, "ready": ev, "users": 1, "bytes": nb}
+            self.d[key] = e
+            self.used += nb
+            return e
+
+    def release(self, key):
+        with self.lock:
+            e = self.d.get(key)
+            if e is not None:
+                e["users"] -= 1
+
+
 class HipBackend:
     """Runs calls through libsmi on one device: one HIP stream, one library context and one
     host thread per in-flight slot.  Enqueueing a call's time loop costs a few microseconds of
     host time per launch, which for small single-shot calls is as long as the device work, so
     the slots enqueue in parallel (the library call releases the interpreter lock; a context
-    is used by one thread at a time)."""
+    is used by one thread at a time).  Models with a model_key stay resident in a bounded
+    device cache of `cache_frac` of the free memory."""
 
-    def __init__(self, device: int = 0, nstreams: int = 4):
+    def __init__(self, device: int = 0, nstreams: int = 4, cache_frac: float = 0.1):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         from . import binding as B
@@ -91,48 +147,72 @@ class HipBackend:
         self.ctx = self.ctxs[0]
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(nstreams)]
         self.pool = ThreadPoolExecutor(max_workers=nstreams)
+        free, _ = torch.cuda.mem_get_info(self.dev)
+        self.models = _ModelCache(int(cache_frac * free))
 
     def budget(self, frac: float = 0.85) -> int:
+        """Bytes the calls' own buffers may take: a share of the free memory, less what the
+        model cache may hold."""
         free, _ = self.torch.cuda.mem_get_info(self.dev)
-        return int(frac * free)
+        return int(frac * (free + self.models.used)) - self.models.cap
 
-    def footprint(self, job: I.Job, kind: str) -> int:
+    def footprint(self, job: I.Job, kind: str, model_key: Optional[str] = None) -> int:
         B = self.B
         jobtype = {"forward": B.JOB_FORWARD, "grad": B.JOB_GRAD, "rtm": B.JOB_RTM}[kind]
         ws = self.ctx.workspace_bytes(job.grid, job.acq, jobtype)
         nrec = int(job.acq.rec_off[-1])
         data = 4 * job.grid.nt * nrec * (2 if kind != "forward" else 1)
-        model = 4 * job.grid.npts * (2 + (2 if kind != "forward" else 0))
-        return ws + data + model + 4 * job.stf.size
+        results = 4 * job.grid.npts * (2 if kind != "forward" else 0) * max(1, job.acq.nshot)
+        model = 0 if model_key is not None else 4 * job.grid.npts * 2
+        return ws + data + results + model + 4 * job.stf.size
 
-    def _run(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
+    def _run(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int,
+             parts: List[int], model_key: Optional[str]):
         torch = self.torch
         st = self.streams[slot]
         ctx = self.ctxs[slot]
+        ent = self.models.acquire(model_key, job, torch, self.dev, st) if model_key else None
         with torch.cuda.stream(st):
-            vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(self.dev)
-            rho = torch.from_numpy(np.ascontiguousarray(job.rho)).to(self.dev)
+            if ent is not None:
+                st.wait_event(ent["ready"])
+                vp, rho = ent["vp"], ent["rho"]
+            else:
+                vp = torch.from_numpy(np.ascontiguousarray(job.vp)).to(self.dev)
+                rho = torch.from_numpy(np.ascontiguousarray(job.rho)).to(self.dev)
             stf = torch.from_numpy(np.ascontiguousarray(job.stf)).to(self.dev)
             jt = {"forward": self.B.JOB_FORWARD, "grad": self.B.JOB_GRAD, "rtm": self.B.JOB_RTM}[kind]
             ws = torch.empty(ctx.workspace_bytes(job.grid, job.acq, jt), dtype=torch.uint8,
                              device=self.dev)
-            if kind == "forward":
-                out, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=st)
-                keep = (vp, rho, stf, ws, out)
-            else:
-                d = torch.from_numpy(np.ascontiguousarray(dobs, np.float32)).to(self.dev)
-                if kind == "grad":
-                    g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
-                    out = (g, J)
+            groups = np.concatenate([[0], np.cumsum(parts)]).astype(np.int32)
+            try:
+                if kind == "forward":
+                    out, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf, ws=ws, stream=st)
+                    keep = (vp, rho, stf, ws, out)
                 else:
-                    out = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
-                keep = (vp, rho, stf, ws, d, out)
+                    d = torch.from_numpy(np.ascontiguousarray(dobs, np.float32)).to(self.dev)
+                    # one shot group per request: each gets its own reduced outputs
+                    ctx.set_shot_groups(groups if len(parts) > 1 else None)
+                    if kind == "grad":
+                        g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                        out = (g, J)
+                    else:
+                        out = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, d, ws=ws, stream=st)
+                    keep = (vp, rho, stf, ws, d, out)
+            finally:
+                if kind != "forward" and len(parts) > 1:
+                    ctx.set_shot_groups(None)
             ev = torch.cuda.Event()
             ev.record(st)
-        return {"ev": ev, "out": out, "keep": keep, "gpts": sum(ctx.last_counts())}
+        return {"ev": ev, "out": out, "keep": keep, "gpts": sum(ctx.last_counts()),
+                "bytes": sum(ctx.last_bytes()), "groups": groups, "kind": kind,
+                "rec_off": np.asarray(job.acq.rec_off), "nt": job.grid.nt,
+                "npts": job.grid.npts}
 
-    def launch(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int):
-        return {"fut": self.pool.submit(self._run, job, kind, dobs, slot)}
+    def launch(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int,
+               parts: Optional[List[int]] = None, model_key: Optional[str] = None):
+        parts = parts or [job.acq.nshot]
+        return {"fut": self.pool.submit(self._run, job, kind, dobs, slot, parts, model_key),
+                "key": model_key}
 
     def done(self, h) -> bool:
         f = h["fut"]
@@ -140,15 +220,37 @@ class HipBackend:
             return False
         return f.exception() is not None or f.result()["ev"].query()
 
-    def result(self, h):
-        out = h["fut"].result()["out"]          # re-raises an error of the call
-        if isinstance(out, tuple):
-            return tuple(None if o is None else o.cpu().numpy() for o in out)
-        return out.cpu().numpy()
+    def results(self, h) -> list:
+        """One result per request of the call, in the order of `parts`: the request's own
+        traces (forward), (gradient, misfit) or (image, illumination)."""
+        r = h["fut"].result()                   # re-raises an error of the call
+        grp, n = r["groups"], len(r["groups"]) - 1
+        if r["kind"] == "forward":
+            d = r["out"].cpu().numpy()
+            off, nt = r["rec_off"], r["nt"]
+            return [d[nt * int(off[grp[k]]): nt * int(off[grp[k + 1]])] for k in range(n)]
+        host = tuple(None if o is None else o.cpu().numpy() for o in r["out"])
+        npts = r["npts"]
+        out = []
+        for k in range(n):
+            if r["kind"] == "grad":
+                out.append((host[0][k * npts:(k + 1) * npts], host[1][k:k + 1]))
+            else:
+                out.append(tuple(None if o is None else o[k * npts:(k + 1) * npts] for o in host))
+        return out
+
+    def finish(self, h):
+        """The call has ended: its model may leave the cache again."""
+        if h.get("key"):
+            self.models.release(h["key"])
 
     def gpts(self, h) -> float:
         f = h["fut"]
         return f.result()["gpts"] if f.exception() is None else 0.0
+
+    def nbytes(self, h) -> float:
+        f = h["fut"]
+        return f.result()["bytes"] if f.exception() is None else 0.0
 
     def now(self) -> float:
         return time.perf_counter()
@@ -172,24 +274,33 @@ class FakeBackend:
     def budget(self, frac: float = 0.85) -> int:
         return 1 << 60
 
-    def footprint(self, job, kind) -> int:
+    def footprint(self, job, kind, model_key=None) -> int:
         return self.fp(job, kind)
 
-    def launch(self, job, kind, dobs, slot):
+    def launch(self, job, kind, dobs, slot, parts=None, model_key=None):
         if self.fail(job, kind):
             raise RuntimeError("SMI_E_ARG: injected failure")
-        h = {"end": self.t + self.cost(job, kind), "job": job, "slot": slot}
+        parts = parts or [job.acq.nshot]
+        h = {"end": self.t + self.cost(job, kind), "job": job, "slot": slot, "parts": parts}
         self.launched.append((self.t, job.name, slot))
         return h
 
     def done(self, h) -> bool:
         return self.t >= h["end"] - 1e-15
 
-    def result(self, h):
-        return h["job"].name
+    def results(self, h):
+        """Per request: the call's name and the request's shot range in the call."""
+        off = np.concatenate([[0], np.cumsum(h["parts"])])
+        return [(h["job"].name, int(off[k]), int(off[k + 1])) for k in range(len(h["parts"]))]
+
+    def finish(self, h):
+        pass
 
     def gpts(self, h) -> float:
         return 0.0
+
+    def nbytes(self, h) -> float:
+        return float(self.fp(h["job"], "forward"))
 
     def now(self) -> float:
         return self.t
@@ -242,6 +353,8 @@ class ShotServer:
         used = 0
         outcomes: Dict[int, Outcome] = {}
         total_gpts = 0.0
+        total_bytes = 0.0
+        calls: List[int] = []         # requests per completed call
         while pending or queue or inflight:
             now = be.now() - t0
             while pending and pending[0].arrival <= now:
@@ -251,8 +364,9 @@ class ShotServer:
             for h, rs, fp, slot in inflight:
                 if be.done(h):
                     tdone = be.now() - t0
+                    be.finish(h)
                     try:
-                        res = be.result(h)
+                        res = be.results(h)
                     except Exception as e:      # an error raised while the call ran
                         for r in rs:
                             outcomes[r.rid] = Outcome(r.rid, r.kind, False, error=str(e))
@@ -261,9 +375,11 @@ class ShotServer:
                         continue
                     for k, r in enumerate(rs):
                         outcomes[r.rid] = Outcome(r.rid, r.kind, True, tdone - r.arrival,
-                                                  res if len(rs) == 1 else (k, res),
-                                                  gpts=be.gpts(h) / len(rs), batch=len(rs))
+                                                  res[k], gpts=be.gpts(h) / len(rs),
+                                                  batch=len(rs))
                     total_gpts += be.gpts(h)
+                    total_bytes += be.nbytes(h)
+                    calls.append(len(rs))
                     used -= fp
                     free_slots.append(slot)
                 else:
@@ -277,8 +393,9 @@ class ShotServer:
                         break
                     job = merge_requests(grp) if len(grp) > 1 else grp[0].job
                     kind = grp[0].kind
+                    key = grp[0].model_key if len({r.model_key for r in grp}) == 1 else None
                     try:
-                        fp = be.footprint(job, kind)
+                        fp = be.footprint(job, kind, key)
                     except Exception as e:      # validation error: this request fails alone
                         for r in grp:
                             outcomes[r.rid] = Outcome(r.rid, r.kind, False, error=str(e))
@@ -297,7 +414,7 @@ class ShotServer:
                         dobs = np.concatenate([np.ravel(r.dobs) for r in grp])
                     slot = free_slots.pop()
                     try:
-                        h = be.launch(job, kind, dobs, slot)
+                        h = be.launch(job, kind, dobs, slot, [r.job.acq.nshot for r in grp], key)
                     except Exception as e:
                         free_slots.append(slot)
                         for r in grp:
@@ -322,4 +439,10 @@ class ShotServer:
                 "p99": float(np.percentile(lat, 99)) if lat.size else math.nan,
                 "makespan": makespan, "gpts": total_gpts,
                 "gpts_per_s": total_gpts / makespan if makespan > 0 else math.nan,
+                # algorithmic HBM bytes of every completed call (the library's count of the
+                # fields, model and tables a call must move) over the makespan
+                "alg_bytes": total_bytes,
+                "alg_GBps": total_bytes / makespan / 1e9 if makespan > 0 else math.nan,
+                "calls": len(calls), "merged_calls": sum(1 for c in calls if c > 1),
+                "requests_per_call": float(np.mean(calls)) if calls else math.nan,
                 "failed": sum(1 for o in outcomes.values() if not o.ok)}

@@ -83,3 +83,44 @@ def test_request_above_the_budget_is_rejected():
     srv = ShotServer(be, budget_bytes=10, max_inflight=2)
     out = srv.run([Request("forward", tiny_job("huge"), 0.0)])
     assert not out["outcomes"][0].ok and "budget" in out["outcomes"][0].error
+
+
+def test_members_of_a_merged_call_get_their_own_shots():
+    """Each member of a merged call gets the result of its own shots: the backend is told the
+    request boundaries, and the server hands request k the k-th part."""
+    be = FakeBackend(cost=lambda job, kind: 0.001 * job.acq.nshot)
+    srv = ShotServer(be, budget_bytes=100, max_inflight=1)
+    reqs = [Request("grad", tiny_job("a"), 0.0, model_key="m", dobs=np.zeros(1))]
+    reqs += [Request("grad", tiny_job(f"b{k}", nshot=k + 1), 0.0001, model_key="m",
+                     dobs=np.zeros(1)) for k in range(3)]
+    out = srv.run(reqs)
+    assert out["outcomes"][0].result == ("a", 0, 1)
+    ranges = [o.result[1:] for o in out["outcomes"][1:]]
+    assert ranges == [(0, 1), (1, 3), (3, 6)]
+    assert {o.result[0] for o in out["outcomes"][1:]} == {"b0+b1+b2"}
+    assert out["calls"] == 2 and out["merged_calls"] == 1
+    assert out["requests_per_call"] == 2.0
+
+
+def test_survey_pool_stream_shares_models_across_requests():
+    jobs = I.stream_config5(njobs=40, rate=10.0, seed=7, scale=0.05, pool=3)
+    keys = [sj.model_key for sj in jobs]
+    assert all(k is not None for k in keys)
+    assert len(set(keys)) < len(keys)               # several requests per survey
+    by = {}
+    for sj in jobs:
+        by.setdefault(sj.model_key, []).append(sj)
+    for key, grp in by.items():
+        cls = key.rsplit("-", 1)[0]
+        assert all(sj.kind == cls for sj in grp)
+        g0 = grp[0].job
+        for sj in grp[1:]:
+            assert sj.job.grid is g0.grid and sj.job.vp is g0.vp and sj.job.rho is g0.rho
+            np.testing.assert_array_equal(sj.job.stf, g0.stf)
+        assert all(sj.job.acq.nshot == 1 for sj in grp)
+    # the same seed gives the same stream; pool=0 keeps one model per request
+    again = I.stream_config5(njobs=40, rate=10.0, seed=7, scale=0.05, pool=3)
+    assert [(a.arrival, a.model_key, tuple(a.job.acq.src[0])) for a in jobs] == \
+           [(b.arrival, b.model_key, tuple(b.job.acq.src[0])) for b in again]
+    solo = I.stream_config5(njobs=10, rate=10.0, seed=7, scale=0.05)
+    assert all(sj.model_key is None for sj in solo)
