@@ -116,9 +116,12 @@ typedef enum {
                                 and in 2D forward passes the fused marching step (v and p of
                                 every shot in one launch, levels in two buffers, SMI_OPT_CHUNK
                                 = 100 D + C: runs of C = 32 or 64 columns per wavefront, loads
-                                issued D = 1, 2 or 4 columns ahead; 0: D 2, C 32).  With a free
-                                surface, 2, 6 and the y-marching kernels of 5 give way to the
-                                kernels of 0. */
+                                issued D = 1, 2 or 4 columns ahead; 0: D 2, C 32); 7: as 0, and
+                                in 2D forward passes the tiled fused step (v and p of every
+                                shot in one launch, one workgroup per 64-row x C-column tile
+                                with its halos staged in LDS; SMI_OPT_CHUNK = C = 32 or 64,
+                                else 32).  With a free surface, 2, 6, 7 and the y-marching
+                                kernels of 5 give way to the kernels of 0. */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and
                                 buffers) and replayed on later calls; up to 8 graphs are kept

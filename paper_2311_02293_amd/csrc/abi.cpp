@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "smi_internal.hpp"
 
 using smi::Plan;
@@ -28,6 +30,16 @@ static __device__ __align__(256) unsigned char scratch[SMI_STATIC_WS_BYTES];
 
 namespace {
 constexpr int kMaxDevices = 64;
+
+// A roctx range over one host phase of a call (plan and upload, autotuning, time loop, reverse
+// loop), for timelines taken with a marker trace; without a profiler the push and pop return
+// at once.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices] = {};
 
@@ -169,6 +181,13 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
         c.run = ctx->opt_chunk % 100 == 64 ? 64 : 32;
         const int d = ctx->opt_chunk / 100;
         c.depth = d == 1 || d == 4 ? d : 2;
+    } else if (ctx->opt_kernel == 7) {
+        // the tiled fused 2D forward step (other passes and 3D: the kernels of 0)
+        c.march = pl.nd == 2 ? 4 : 2;
+        c.xcd = pl.nd == 2;
+        c.step2d = smi::step2d_available(pl);
+        c.run = ctx->opt_chunk == 64 ? 64 : 32;
+        c.depth = 0;
     } else if (ctx->opt_kernel == 0) {
         c.march = pl.nd == 2 ? 4 : 2;
         c.xcd = pl.nd == 2;
@@ -414,6 +433,8 @@ std::vector<Cand> fwd_candidates(const Plan &pl) {
             v.push_back({4, true, false, true, 32, 2, "fused-c32-d2"});
             v.push_back({4, true, false, true, 64, 2, "fused-c64-d2"});
             v.push_back({4, true, false, true, 32, 4, "fused-c32-d4"});
+            v.push_back({4, true, false, true, 32, 0, "tile-32"});
+            v.push_back({4, true, false, true, 64, 0, "tile-64"});
         }
     } else {
         v.push_back({2, false, false, false, 32, 2, "march2-plain"});
@@ -444,6 +465,7 @@ smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipSt
 // timing runs are done (once per plan shape and context).
 smi_status tune_forward(smi_ctx *ctx, const Plan &pl, const Views &w, smi::StepCtx &c,
                         hipStream_t st) {
+    Range range("smi autotune forward");
     const std::vector<Cand> cands = fwd_candidates(pl);
     constexpr int K = 8;
     std::vector<int> steps;
@@ -533,6 +555,7 @@ smi_status read_rev_tune(smi_ctx *ctx, const std::string &key) {
 smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float *vp,
                        const float *rho, const float *stf, float *dcal, const int *snap_it,
                        int nsnap, float *snaps, hipStream_t st) {
+    Range range("smi forward");
     smi_status s = upload(ctx, pl, w, st);
     if (s != SMI_OK) return s;
     HIPCHK(smi::launch_model_prep(pl, w, vp, rho, st), "model prep");
@@ -661,6 +684,7 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
 smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad,
                        float *grad_rho, float *image, float *illum, float *image_norm,
                        const int *snap_it, int nsnap, float *snaps, hipStream_t st) {
+    Range range("smi reverse");
     const Plan &pl = stt->plan;
     Views w = smi::views(pl, stt->ws);
     bool adj = G != nullptr;
@@ -842,7 +866,7 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 6) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 7) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }

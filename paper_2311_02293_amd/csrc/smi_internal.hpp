@@ -222,8 +222,8 @@ struct StepCtx {
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
     int rev = 0;            // 2D reverse step: 0 by batch size, 1 two launches, 2 five launches
     bool step2d = false;    // 2D forward: the fused marching step (step2d.hip), levels in two buffers
-    int run = 32;           // its run of columns per wavefront (32 or 64)
-    int depth = 2;          // and the columns it loads ahead (1, 2 or 4)
+    int run = 32;           // its run of columns per wavefront or tile (32 or 64)
+    int depth = 2;          // and the columns it loads ahead (1, 2 or 4); 0: the tiled step
     // receiver sampling of forward step ext_it into ext_dcal, carried by the next forward
     // step's v launch (register-blocked kernels only, see march_forward); -1: none pending
     int ext_it = -1;

@@ -384,6 +384,320 @@ __global__ __launch_bounds__(256) void k_step2d(Geom g, Fields A, Fields B, Mode
     }
 }
 
+// ---------------------------------------------------------------------------- tiled step
+// One workgroup per (shot, 64-row strip, TX-column run), NW = TX / 8 wavefronts.  Every load of
+// the tile is issued at once, before any arithmetic (the workgroup's whole input is in flight,
+// so a few resident workgroups per CU keep HBM busy), then:
+//   1. p^n of the tile and of its halos (2N - 1 rows above and below the tile's columns,
+//      2N - 1 columns either side of its rows) goes to LDS; barrier;
+//   2. the new v_x on the tile's rows over the columns [xb - N, xb + TX + N - 1) (N halo
+//      columns left, N - 1 right, computed again by the neighbouring tile) and the new v_z on
+//      the tile's columns over the rows [zs - N, zs + 64 + N - 1), both from p^n in LDS,
+//      go to LDS (and the tile's own cells to HBM); barrier;
+//   3. the new p on the tile from both, plus the one-tap source.
+// A lane is one row of the strip (z is the contiguous axis); wavefront w owns the p and v_z
+// columns [xb + 8 w, xb + 8 w + 8) and a share of the v_x columns.  The arithmetic, the box
+// rules (a cell outside the shot's computing box keeps its old level; only the tile's own
+// cells inside the box are stored) and the CPML memory variables are those of the half-step
+// kernels, term by term, so both give bitwise the same fields.  Loads read columns no further
+// than 2N - 2 past the padded grid (clamped): the values there only reach cells not stored.
+template <int N, int TX>
+struct T2 {
+    static constexpr int HP = 2 * N - 1;          // p halo (rows or columns) per side
+    static constexpr int NW = TX / 8;             // wavefronts
+    static constexpr int NT = 64 * NW;            // threads
+    static constexpr int LDP = 64 + 2 * HP;       // LDS rows per p column
+    static constexpr int PC = TX + 2 * HP;        // p columns in LDS, from xb - HP
+    static constexpr int VXC = TX + 2 * N - 1;    // v_x columns, from xb - N
+    static constexpr int LDZ = 64 + 2 * N - 1;    // LDS rows per v_z column, from zs - N
+    static constexpr int PMC = (PC + NW - 1) / NW;     // p columns each wavefront loads
+    static constexpr int VCW = (VXC + NW - 1) / NW;    // v_x columns per wavefront
+    static constexpr int NH = 2 * HP * TX;             // p halo-row cells of the tile's columns
+    static constexpr int HPT = (NH + NT - 1) / NT;     // of them per thread
+    static constexpr int NVH = (2 * N - 1) * TX;       // v_z halo-row cells
+    static constexpr int LDS = PC * LDP + VXC * 64 + TX * LDZ;    // floats
+    static_assert(NVH <= NT, "one v_z halo cell per thread at most");
+};
+
+template <int N, int TX, bool ZP, bool XP>
+__device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fields &B,
+                                       const Model &m, const Cpml &cp, unsigned rbytes,
+                                       const int b0, const int b1, const int b2, const int b3,
+                                       int s, int zs, int xb, int x0, int x1, int scol, int sr,
+                                       float amp, float *Pn, float *VX, float *VZ) {
+    using K = T2<N, TX>;
+    constexpr int HP = K::HP, NW = K::NW, NT = K::NT, LDP = K::LDP, PC = K::PC;
+    constexpr int VXC = K::VXC, LDZ = K::LDZ, PMC = K::PMC, VCW = K::VCW;
+    constexpr int NH = K::NH, HPT = K::HPT, NVH = K::NVH;
+    const int t = (int)threadIdx.x;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const char *rb = (const char *)m.kdt;     // the region starts with the model
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)rb, (short)0, (int)rbytes, 0x00020000);
+    auto off = [&](const float *p) { return (unsigned)((const char *)p - rb); };
+    const long long so = (long long)s * g.P;
+    const unsigned colb = 4u * (unsigned)g.ld1;
+    const int cmax = g.M[1] + HP - 1;         // last column a load reads
+    auto col = [&](int c) { return (unsigned)min(c, cmax) * colb; };
+    const int r = zs + lane;
+    const bool own = r >= b0 && r < b1;
+    const bool rowok = r >= 0 && r < g.M[0];
+    const unsigned vr = 4u * (unsigned)(g.org + r);
+    const unsigned a_kdt = 0u, a_bdz = off(m.bdt[0]), a_bdx = off(m.bdt[1]);
+    const unsigned a_pA = off(A.p + so), a_vzA = off(A.v[0] + so), a_vxA = off(A.v[1] + so);
+    const unsigned a_pB = off(B.p + so), a_vzB = off(B.v[0] + so), a_vxB = off(B.v[1] + so);
+    const unsigned a_pzA = off(A.psp[0] + (long long)s * g.psz[0]);
+    const unsigned a_vpzA = off(A.psv[0] + (long long)s * g.psz[0]);
+    const unsigned a_pzB = off(B.psp[0] + (long long)s * g.psz[0]);
+    const unsigned a_vpzB = off(B.psv[0] + (long long)s * g.psz[0]);
+    const unsigned a_pxA = off(A.psp[1] + (long long)s * g.psz[1]);
+    const unsigned a_vpxA = off(A.psv[1] + (long long)s * g.psz[1]);
+    const unsigned a_pxB = off(B.psp[1] + (long long)s * g.psz[1]);
+    const unsigned a_vpxB = off(B.psv[1] + (long long)s * g.psz[1]);
+    const unsigned wz = 4u * (unsigned)g.W;   // bytes per column of a z slab
+    auto xslab = [&](int c) { return c >= 0 && c < g.M[1] ? slab_index(c, g.M[1], g.nb) : -1; };
+    auto zcol = [&](int j) { return wz * (unsigned)min(max(j, 0), g.M[1] - 1); };
+    const int zci = ZP && rowok ? slab_index(r, g.M[0], g.nb) : -1;
+    const unsigned vzi = 4u * (unsigned)(zci >= 0 ? zci : 0);
+    const unsigned vxr = 4u * (unsigned)(rowok ? r : 0);
+    float zah = 0.f, zbh = 0.f, zai = 0.f, zbi = 0.f;
+    if (ZP && zci >= 0) {
+        zah = cp.a_h[0][r];
+        zbh = cp.b_h[0][r];
+        zai = cp.a_i[0][r];
+        zbi = cp.b_i[0][r];
+    }
+    // the v_z halo cell of this thread: column xb + hc, row rv
+    const bool hv = t < NVH;
+    const int hc = hv ? t / (2 * N - 1) : 0, hh = hv ? t % (2 * N - 1) : 0;
+    const int rv = hh < N ? zs - N + hh : zs + 64 + (hh - N);
+    const bool hrow = hv && rv >= 0 && rv < g.M[0];
+    const int zch = ZP && hrow ? slab_index(rv, g.M[0], g.nb) : -1;
+    float hah = 0.f, hbh = 0.f;
+    if (ZP && zch >= 0) {
+        hah = cp.a_h[0][rv];
+        hbh = cp.b_h[0][rv];
+    }
+
+    // ---- 1. every load of the tile
+    float pm[PMC];
+#pragma unroll
+    for (int k = 0; k < PMC; ++k) {
+        const int q = wv + NW * k;
+        pm[k] = q < PC ? bld(rs, vr, a_pA + col(xb - HP + q)) : 0.f;
+    }
+    float ph[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int i = t + NT * k;
+        const int ci = i / (2 * HP), h = i % (2 * HP);
+        const int row = h < HP ? zs - HP + h : zs + 64 + (h - HP);
+        ph[k] = i < NH ? bld(rs, 4u * (unsigned)(g.org + row) + col(xb + ci), a_pA) : 0.f;
+    }
+    const int vc0 = wv * VCW;                 // first v_x column of this wavefront (from xb - N)
+    float vxo[VCW], bx[VCW], psx[VCW];
+#pragma unroll
+    for (int k = 0; k < VCW; ++k) {
+        const int c = xb - N + vc0 + k;
+        const bool in = vc0 + k < VXC;
+        vxo[k] = in ? bld(rs, vr, a_vxA + col(c)) : 0.f;
+        bx[k] = in ? bld(rs, vr, a_bdx + col(c)) : 0.f;
+        psx[k] = 0.f;
+        if (XP && in) {
+            const int xc = xslab(c);
+            if (xc >= 0) psx[k] = bld(rs, vxr, a_pxA + (unsigned)xc * colb);
+        }
+    }
+    const int j0 = xb + 8 * wv;               // first p / v_z column of this wavefront
+    float vzo[8], bz[8], kd[8], psz[8], pvz[8], pvx[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = j0 + k;
+        vzo[k] = bld(rs, vr, a_vzA + col(j));
+        bz[k] = bld(rs, vr, a_bdz + col(j));
+        kd[k] = bld(rs, vr, a_kdt + col(j));
+        psz[k] = pvz[k] = pvx[k] = 0.f;
+        if (ZP) {
+            psz[k] = bld(rs, vzi, a_pzA + zcol(j));
+            pvz[k] = bld(rs, vzi, a_vpzA + zcol(j));
+        }
+        if (XP) {
+            const int xc = xslab(j);
+            if (xc >= 0) pvx[k] = bld(rs, vxr, a_vpxA + (unsigned)xc * colb);
+        }
+    }
+    float hvo = 0.f, hbz = 0.f, hpz = 0.f;
+    if (hv) {
+        const unsigned hr = 4u * (unsigned)(g.org + rv) + col(xb + hc);
+        hvo = bld(rs, hr, a_vzA);
+        hbz = bld(rs, hr, a_bdz);
+        if (ZP) hpz = bld(rs, 4u * (unsigned)(zch >= 0 ? zch : 0), a_pzA + zcol(xb + hc));
+    }
+#pragma unroll
+    for (int k = 0; k < PMC; ++k) {
+        const int q = wv + NW * k;
+        if (q < PC) Pn[q * LDP + HP + lane] = pm[k];
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int i = t + NT * k;
+        const int ci = i / (2 * HP), h = i % (2 * HP);
+        if (i < NH) Pn[(ci + HP) * LDP + (h < HP ? h : 64 + h)] = ph[k];
+    }
+    __syncthreads();
+
+    // ---- 2. new v_x (x part of eq. 3 first row) and new v_z (z part), CPML
+    {
+        float w[VCW + 2 * N - 1];             // p^n of this row at LDS columns vc0 ..
+#pragma unroll
+        for (int d = 0; d < VCW + 2 * N - 1; ++d)
+            w[d] = vc0 + d < PC ? Pn[(vc0 + d) * LDP + HP + lane] : 0.f;
+#pragma unroll
+        for (int k = 0; k < VCW; ++k) {
+            if (vc0 + k >= VXC) break;
+            const int c = xb - N + vc0 + k;
+            float e = 0.f;
+#pragma unroll
+            for (int l = 1; l <= N; ++l) e += g.c[1][l - 1] * (w[k + N - 1 + l] - w[k + N - l]);
+            const bool mine = c >= x0 && c < x1;
+            if (XP) {
+                const int xc = xslab(c);
+                if (xc >= 0) {
+                    const float psi = cp.b_h[1][c] * psx[k] + cp.a_h[1][c] * e;
+                    if (own && mine) bst(rs, vxr, a_pxB + (unsigned)xc * colb, psi);
+                    e += psi;
+                }
+            }
+            const float vxn = c >= b2 && c < b3 ? vxo[k] - bx[k] * e : vxo[k];
+            if (own && mine) bst(rs, vr, a_vxB + col(c), vxn);
+            VX[(vc0 + k) * 64 + lane] = vxn;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = j0 + k;
+        const float *P = Pn + (8 * wv + k + HP) * LDP + HP + lane;
+        float ez = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) ez += g.c[0][l - 1] * (P[l] - P[1 - l]);
+        const bool mine = j >= x0 && j < x1;
+        if (ZP) {
+            const float psi = zbh * psz[k] + zah * ez;
+            if (own && mine && zci >= 0) bst(rs, vzi, a_pzB + zcol(j), psi);
+            ez = zci >= 0 ? ez + psi : ez;
+        }
+        const float vzn = own ? vzo[k] - bz[k] * ez : vzo[k];
+        if (own && mine) bst(rs, vr, a_vzB + col(j), vzn);
+        VZ[(8 * wv + k) * LDZ + N + lane] = vzn;
+    }
+    if (hv) {
+        const float *P = Pn + (hc + HP) * LDP + (hh < N ? HP - N + hh : 64 + HP + hh - N);
+        float hz = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) hz += g.c[0][l - 1] * (P[l] - P[1 - l]);
+        if (ZP) {
+            const float psi = hbh * hpz + hah * hz;
+            hz = zch >= 0 ? hz + psi : hz;
+        }
+        VZ[hc * LDZ + (hh < N ? hh : 64 + hh)] = rv >= b0 && rv < b1 ? hvo - hbz * hz : hvo;
+    }
+    __syncthreads();
+
+    // ---- 3. new p (eq. 3 second row): z part, then x part, CPML, source
+    const float samp = r == sr ? amp : 0.f;
+    float u[8 + 2 * N - 1];                   // new v_x of this row at columns j0 - N ..
+#pragma unroll
+    for (int d = 0; d < 8 + 2 * N - 1; ++d) u[d] = VX[(8 * wv + d) * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int j = j0 + k;
+        const float *V = VZ + (8 * wv + k) * LDZ + N + lane;
+        float dz = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) dz += g.c[0][l - 1] * (V[l - 1] - V[-l]);
+        const bool mine = j >= x0 && j < x1;
+        if (ZP) {
+            const float psi = zbi * pvz[k] + zai * dz;
+            if (own && mine && zci >= 0) bst(rs, vzi, a_vpzB + zcol(j), psi);
+            dz = zci >= 0 ? dz + psi : dz;
+        }
+        float dx = 0.f;
+#pragma unroll
+        for (int l = 1; l <= N; ++l) dx += g.c[1][l - 1] * (u[k + N + l - 1] - u[k + N - l]);
+        if (XP) {
+            const int xc = xslab(j);
+            if (xc >= 0) {
+                const float psi = cp.b_i[1][j] * pvx[k] + cp.a_i[1][j] * dx;
+                if (own && mine) bst(rs, vxr, a_vpxB + (unsigned)xc * colb, psi);
+                dx += psi;
+            }
+        }
+        float sdiv = 0.f;
+        sdiv += dz;
+        sdiv += dx;
+        float pn = Pn[(8 * wv + k + HP) * LDP + HP + lane] - kd[k] * sdiv;
+        if (j == scol) pn += samp;
+        if (own && mine) bst(rs, vr, a_pB + col(j), pn);
+    }
+}
+
+template <int N, int TX>
+__global__ __launch_bounds__(8 * TX) void k_tile2d(Geom g, Fields A, Fields B, Model m,
+                                                          Cpml cp, const int *__restrict__ box,
+                                                          S2 sg, const long long *__restrict__ src_cell,
+                                                          const float *__restrict__ stf, int nt,
+                                                          int it, Ext ex, BandArg sv) {
+    using K = T2<N, TX>;
+    static_assert(K::NT == 8 * TX, "the launch bound is the block size");
+    __shared__ float lds[K::LDS];
+    const int bid = (int)blockIdx.x;
+    if (bid >= sg.nmain) {
+        // side work, as in k_step2d, on the first 256 threads of the block
+        if (threadIdx.x >= 256) return;
+        const int q = bid - sg.nmain;
+        if (q < sg.nrecb) {
+            const int nthr = sg.nrecb * 256;
+            for (int rr = q * 256 + (int)threadIdx.x; rr < ex.rv.R; rr += nthr)
+                sample_receiver(g, A.p, ex.rv, ex.dcal, ex.it, ex.status, rr);
+        } else if (sv.buf) {
+            band_lin(g, A, sv, q - sg.nrecb, (int)threadIdx.x, 0, 2);
+        }
+        return;
+    }
+    // the workgroup's tile (uniform): shot fastest, then strip, then run
+    const int L = xcd_remap(bid, sg.nmain);
+    const int s = L % sg.nshot;
+    const int tt = L / sg.nshot;
+    const int k = tt % sg.nstrip;
+    const int rr = tt / sg.nstrip;
+    const int *b = box + 6 * s;
+    const int b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+    const int zs = sg.z0 + 64 * k;
+    if (zs >= b1 || zs + 64 <= b0) return;
+    const int xb = TX * (sg.run0 + rr);
+    const int x0 = max(xb, b2), x1 = min(xb + TX, b3);
+    if (x0 >= x1) return;
+    const long long sc = src_cell[s];
+    const float amp = sc >= 0 && it < nt ? src_amp(g.src_scale, stf[(long long)s * nt + it]) : 0.f;
+    const int sr = sc >= 0 ? (int)((sc - g.org) % g.ld1) : -1;
+    const int scol = sc >= 0 ? (int)((sc - g.org) / g.ld1) : -1 - (1 << 20);
+    // the slab variants when the tile with its halos touches an absorbing slab
+    const bool zp = zs - N < g.nb || zs + 64 + N - 1 > g.M[0] - g.nb - 1;
+    const bool xp = xb - N < g.nb || xb + TX + N - 1 > g.M[1] - g.nb - 1;
+    float *Pn = lds;
+    float *VX = lds + K::PC * K::LDP;
+    float *VZ = VX + K::VXC * 64;
+    const unsigned rn = sg.rbytes;
+    if (zp) {
+        if (xp) tile2d<N, TX, true, true>(g, A, B, m, cp, rn, b0, b1, b2, b3, s, zs, xb, x0, x1, scol, sr, amp, Pn, VX, VZ);
+        else tile2d<N, TX, true, false>(g, A, B, m, cp, rn, b0, b1, b2, b3, s, zs, xb, x0, x1, scol, sr, amp, Pn, VX, VZ);
+    } else {
+        if (xp) tile2d<N, TX, false, true>(g, A, B, m, cp, rn, b0, b1, b2, b3, s, zs, xb, x0, x1, scol, sr, amp, Pn, VX, VZ);
+        else tile2d<N, TX, false, false>(g, A, B, m, cp, rn, b0, b1, b2, b3, s, zs, xb, x0, x1, scol, sr, amp, Pn, VX, VZ);
+    }
+}
+
 unsigned nblocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 // bytes from the model to the end of the second field set: the span of the step's buffer
@@ -445,6 +759,56 @@ hipError_t step2d_t(const StepCtx &c, const Fields &src, const Fields &dst, int 
     return hipGetLastError();
 }
 
+template <int N, int TX>
+hipError_t tile2d_t(const StepCtx &c, const Fields &src, const Fields &dst, int it) {
+    using K = T2<N, TX>;
+    const Plan &pl = *c.pl;
+    const Views &w = *c.w;
+    const int *tab = &pl.fbox[(size_t)it * pl.nshot * 6];
+    int u[4] = {1 << 30, -1, 1 << 30, -1};
+    for (int s = 0; s < pl.nshot; ++s) {
+        const int *b = tab + 6 * s;
+        if (b[1] <= b[0] || b[3] <= b[2]) continue;
+        u[0] = std::min(u[0], b[0]);
+        u[1] = std::max(u[1], b[1]);
+        u[2] = std::min(u[2], b[2]);
+        u[3] = std::max(u[3], b[3]);
+    }
+    S2 sg{};
+    sg.nshot = pl.nshot;
+    sg.rbytes = (unsigned)region_bytes(pl);
+    if (u[1] > u[0] && u[3] > u[2]) {
+        sg.z0 = zalign(u[0]);
+        sg.nstrip = (u[1] - sg.z0 + 63) / 64;
+        sg.run0 = u[2] / TX;
+        sg.nrun = (u[3] - 1) / TX - sg.run0 + 1;
+        sg.nmain = (int)((long long)pl.nshot * sg.nstrip * sg.nrun);
+    }
+    const bool ext = c.ext_it >= 0 && w.recv.R > 0;
+    sg.nrecb = ext ? (int)std::min<long long>(nblocks(w.recv.R), 1024) : 0;
+    BandArg sv{};
+    int nband = 0;
+    if (c.save_p_slot >= 0) {
+        const int nqb = (int)((pl.band.B + 255) / 256);
+        sv = BandArg{w.bdesc, w.bands + (size_t)c.save_p_slot * pl.band.B,
+                     (long long)pl.nsave * pl.band.B, nqb, pl.nshot};
+        nband = pl.nshot * nqb;
+    }
+    const Ext ex{w.recv, c.ext_dcal, ext ? c.ext_it : -1, w.status};
+    const unsigned grid = (unsigned)(sg.nmain + sg.nrecb + nband);
+    if (grid == 0) return hipSuccess;
+    const int *box = (const int *)(w.fbox + (size_t)it * pl.nshot * 6);
+    if (c.ev)
+        hipExtLaunchKernelGGL((k_tile2d<N, TX>), dim3(grid), dim3(K::NT), 0, c.st, c.ev[0], c.ev[1], 0,
+                              pl.geom, src, dst, w.model, w.cpml, box, sg,
+                              (const long long *)w.src_cell, c.stf, pl.g.nt, it, ex, sv);
+    else
+        hipLaunchKernelGGL((k_tile2d<N, TX>), dim3(grid), dim3(K::NT), 0, c.st, pl.geom, src, dst,
+                           w.model, w.cpml, box, sg, (const long long *)w.src_cell, c.stf,
+                           pl.g.nt, it, ex, sv);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // 2D, two field sets, no free surface, and a region a buffer resource can span
@@ -457,6 +821,11 @@ hipError_t fwd_step_2d(const StepCtx &c, const Fields &src, const Fields &dst, i
     const Plan &pl = *c.pl;
     const int C = c.run == 64 ? 64 : 32;
     const int D = c.depth;
+    if (D == 0) {               // the tiled step
+        if (pl.N == 4) return C == 64 ? tile2d_t<4, 64>(c, src, dst, it) : tile2d_t<4, 32>(c, src, dst, it);
+        if (pl.N == 2) return C == 64 ? tile2d_t<2, 64>(c, src, dst, it) : tile2d_t<2, 32>(c, src, dst, it);
+        return hipErrorInvalidValue;
+    }
     if (pl.N == 4) {
         if (C == 64) return D == 4 ? step2d_t<4, 64, 4>(c, src, dst, it)
                           : D == 1 ? step2d_t<4, 64, 1>(c, src, dst, it) : step2d_t<4, 64, 2>(c, src, dst, it);

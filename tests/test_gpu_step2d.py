@@ -1,6 +1,7 @@
-"""GPU: the fused marching 2D step (SMI_OPT_KERNEL 6) against the half-step kernels and the
-oracle: seismograms, and gradients / images of reverse passes whose forward pass ran on it
-(bands saved by its side work, decimated bands, off-grid points, both run widths)."""
+"""GPU: the fused 2D steps -- marching (SMI_OPT_KERNEL 6) and tiled (SMI_OPT_KERNEL 7) --
+against the half-step kernels and the oracle: seismograms, and gradients / images of reverse
+passes whose forward pass ran on them (bands saved by their side work, decimated bands,
+off-grid points, every run or tile width)."""
 import numpy as np
 import pytest
 
@@ -36,9 +37,14 @@ def _compare(name, a, b, tol=1e-6):
     assert e <= tol
 
 
-@pytest.mark.parametrize("run", [32, 64, 132, 432, 464])
+# (SMI_OPT_KERNEL, SMI_OPT_CHUNK): the marching step's run widths and load depths, the tiled
+# step's tile widths
+VARIANTS = [(6, 32), (6, 64), (6, 132), (6, 432), (6, 464), (7, 32), (7, 64)]
+
+
+@pytest.mark.parametrize("kernel,run", VARIANTS)
 @pytest.mark.parametrize("case", ["box", "nobox", "offgrid", "order4"])
-def test_fused_step_seismograms(ctx, run, case):
+def test_fused_step_seismograms(ctx, kernel, run, case):
     from oracle import oracle as O
     box = 0 if case == "nobox" else 1
     job = with_bounds(I.config2(n1=96, n2=260, nt=500, nshot=3, box=box))
@@ -52,9 +58,9 @@ def test_fused_step_seismograms(ctx, run, case):
         job.grid.fm = 7.0          # five points per wavelength at order 4
     vp, rho, stf = dev(job)
     ref = ctx.forward(job.grid, job.acq, vp, rho, stf)[0].cpu().numpy()
-    got = _run(ctx, 6, run, lambda: ctx.forward(job.grid, job.acq, vp, rho, stf)[0].cpu().numpy())
+    got = _run(ctx, kernel, run, lambda: ctx.forward(job.grid, job.acq, vp, rho, stf)[0].cpu().numpy())
     ctx.poll_status()
-    _compare(f"{case} run {run} seismograms", got, ref)
+    _compare(f"kernel {kernel} {case} run {run} seismograms", got, ref)
     want = O.forward_job(job, vmax=float(job.grid.vpmax), box=0)
     from paper_2311_02293_amd import binding as B
     import torch
@@ -65,8 +71,9 @@ def test_fused_step_seismograms(ctx, run, case):
         assert e <= 1e-4
 
 
-@pytest.mark.parametrize("dr,run", [(1, 32), (3, 32), (1, 432)])
-def test_fused_forward_then_reverse(ctx, dr, run):
+@pytest.mark.parametrize("kernel,dr,run", [(6, 1, 32), (6, 3, 32), (6, 1, 432), (7, 1, 32),
+                                           (7, 3, 64)])
+def test_fused_forward_then_reverse(ctx, kernel, dr, run):
     """Gradient and image whose forward pass (bands saved by the fused step's side work, and
     with dr > 1 the run past nt) ran on the fused step, against the half-step kernels."""
     import torch
@@ -84,10 +91,10 @@ def test_fused_forward_then_reverse(ctx, dr, run):
         return [t.cpu().numpy() for t in (g, J, dc, im, il)]
 
     ref = both()
-    got = _run(ctx, 6, run, both)
+    got = _run(ctx, kernel, run, both)
     ctx.poll_status()
     for name, a, b in zip(("grad", "misfit", "dcal", "image", "illum"), got, ref):
-        _compare(f"dr {dr} {name}", a, b)
+        _compare(f"kernel {kernel} dr {dr} {name}", a, b)
     if dr == 1:
         ref_g, ref_J = O.fwi_grad(job, dobs, vmax=float(job.grid.vpmax), box=0)
         e = rel_l2(got[0].reshape(job.vp.shape), ref_g)
