@@ -94,9 +94,15 @@ def probe_copy(torch, gib: float = 1.0, reps: int = 20):
 # only while the kernel source is the one the counters were taken on.
 COUNTERS = os.path.join(ROOT, "profiles", "step_kernels_2d_order8_16shots_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_02293_amd", "csrc", "kernels.hip")
+# the library's default step configuration on the batched 2D workload, by the autotuner's name:
+# register-blocked marching kernels, 4 cells per lane, tiles dealt round-robin over the XCDs
+DEFAULT_CONFIG = "march4-xcd"
 
 
-def counter_traffic():
+def counter_traffic(config: str):
+    """HBM bytes per step from the counter file, or None unless the counters were taken on the
+    same kernel source and the same step kernel configuration (`config`, the autotuner's name
+    of the timed configuration)."""
     import hashlib
     try:
         kv = {}
@@ -107,7 +113,7 @@ def counter_traffic():
                     kv[k.strip()] = v.strip()
         with open(KERNEL_SRC, "rb") as f:
             src = hashlib.sha256(f.read()).hexdigest()
-        if kv.get("kernel_source_sha256") != src:
+        if kv.get("kernel_source_sha256") != src or kv.get("kernel_config") != config:
             return None
         return float(kv["traffic_bytes_per_step"])
     except (OSError, KeyError, ValueError):
@@ -244,16 +250,19 @@ def reverse_leg(torch, reps: int = 5, timing_every: int = 32):
     return out
 
 
-def serve(torch, njobs: int):
-    """Served stream of mixed requests: a capacity run (every request queued at t = 0), then the
-    same requests arriving as a Poisson stream at 0.7 x that capacity (latency p50 / p99), then
-    every request alone on the plain stepper (one shot per launch, box off)."""
+def serve(torch, njobs: int, pool: int = 6):
+    """Served stream of mixed requests, one shot each, over `pool` seeded surveys per job class
+    (the models stay resident on the device; requests of one survey that queue together share
+    a launch): a capacity run (every request queued at t = 0), then the same requests arriving
+    as a Poisson stream at 0.7 x that capacity (latency p50 / p99, algorithmic GB/s and its
+    fraction of HBM peak), then every request alone on the plain stepper (one shot per launch,
+    box off)."""
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
     from paper_2311_02293_amd.server import HipBackend, Request, ShotServer
 
     be = HipBackend(0, nstreams=4)
-    jobs = I.stream_config5(njobs=njobs, rate=1.0, seed=1005)
+    jobs = I.stream_config5(njobs=njobs, rate=1.0, seed=1005, pool=pool)
     gaps = np.diff([0.0] + [sj.arrival for sj in jobs])     # unit-rate exponential gaps
     reqs = []
     for sj in jobs:
@@ -262,7 +271,7 @@ def serve(torch, njobs: int):
         j.grid.vpmin = float(min(v.min() for v in vs))
         j.grid.vpmax = float(1.02 * max(v.max() for v in vs))
         kind = "grad" if sj.kind == "grad2d" else "forward"
-        r = Request(kind, j, arrival=0.0)
+        r = Request(kind, j, arrival=0.0, model_key=sj.model_key)
         if kind == "grad":          # observed data: forward of the true model, before the stream
             rho = torch.from_numpy(j.rho).cuda()
             stf = torch.from_numpy(j.stf).cuda()
@@ -288,7 +297,9 @@ def serve(torch, njobs: int):
     print("bench: plain stepper, every request alone", file=sys.stderr, flush=True)
     be.ctx.set_option(B.OPT_KERNEL, 1)
     plain_s, plain_gpts = 0.0, 0.0
-    for r in reqs:
+    for k, r in enumerate(reqs):
+        if k % 50 == 0:
+            print(f"bench: plain request {k}", file=sys.stderr, flush=True)
         j = r.job
         box = j.grid.box
         j.grid.box = 0
@@ -308,10 +319,19 @@ def serve(torch, njobs: int):
         "metric": "served shot stream: requests/s, GPts/s, latency p50/p99",
         "requests": njobs, "mix": {"forward2d": counts[("forward", 2)], "grad2d": counts[("grad", 2)],
                                    "forward3d": counts[("forward", 3)]},
+        "surveys_per_class": pool,
         "capacity": {"requests_per_s": capacity, "GPts_s": cap["gpts_per_s"] / 1e9,
-                     "makespan_s": cap["makespan"], "failed": cap["failed"]},
+                     "makespan_s": cap["makespan"], "failed": cap["failed"],
+                     "alg_GBps": cap["alg_GBps"], "hbm_frac": cap["alg_GBps"] / HBM_PEAK_GBS,
+                     "calls": cap["calls"], "merged_calls": cap["merged_calls"],
+                     "requests_per_call": cap["requests_per_call"]},
         "stream": {"arrival_rate_per_s": rate, "p50_s": st["p50"], "p99_s": st["p99"],
-                   "GPts_s": st["gpts_per_s"] / 1e9, "makespan_s": st["makespan"], "failed": st["failed"]},
+                   "GPts_s": st["gpts_per_s"] / 1e9, "makespan_s": st["makespan"], "failed": st["failed"],
+                   "alg_GBps": st["alg_GBps"], "hbm_frac": st["alg_GBps"] / HBM_PEAK_GBS,
+                   "calls": st["calls"], "merged_calls": st["merged_calls"],
+                   "requests_per_call": st["requests_per_call"]},
+        "model_cache": {"hits": be.models.hits, "misses": be.models.misses,
+                        "resident_bytes": be.models.used},
         "plain_alone": {"requests_per_s": njobs / plain_s, "GPts_s_full_grid": plain_gpts / plain_s / 1e9,
                         "total_s": plain_s,
                         "what": "each request alone, one shot per launch, separate v and p kernels, box off"},
@@ -345,8 +365,13 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="served-stream mode: N jobs of the mixed request stream (2D forward, "
                          "2D gradient, 3D forward) instead of the batched-forward benchmark")
+    ap.add_argument("--pool", type=int, default=6,
+                    help="with --serve: seeded surveys (models) per job class of the stream")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the library's default kernels instead of the autotuner's pick")
+    ap.add_argument("--reverse-only", action="store_true",
+                    help="only the reverse leg (the 2D FWI gradient workload), its object printed "
+                         "as the one JSON line: for traces of the reverse loop")
     ap.add_argument("--no-reverse", action="store_true",
                     help="skip the reverse leg (the 2D FWI gradient workload)")
     ap.add_argument("--kernel", type=int, default=-1,
@@ -363,10 +388,13 @@ def main():
         probe_copy(torch)
         return
     if args.serve > 0:
-        serve(torch, args.serve)
+        serve(torch, args.serve, pool=args.pool)
         return
     if args.latency or args.latency_graph:
         latency(torch, graph=args.latency_graph, only=args.workload, reps_override=args.reps)
+        return
+    if args.reverse_only:
+        print(json.dumps(reverse_leg(torch)), flush=True)
         return
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
@@ -426,6 +454,10 @@ def main():
                     "GBps": kby / (kms / 1e3) / 1e9 if kms > 0 else None}
     ctx.set_option(B.OPT_TIMING, 0)
     pick = ctx.tuning_report() if tuned else ""
+    # the timed step configuration by the autotuner's name for it (the library's default on
+    # this workload when nothing was tuned)
+    config = pick.rsplit("pick ", 1)[-1].strip() if pick else (
+        DEFAULT_CONFIG if args.kernel < 0 and args.chunk < 0 else "")
     # duration of the step = the two kernels' own durations (the span from the start of the v
     # kernel to the end of the p kernel also holds the launch gap between them); a fused step
     # is one kernel (reported as the first, the second reports nothing)
@@ -447,7 +479,7 @@ def main():
                                      * job.acq.nshot * job.grid.nt / (np.mean(ms) / 1e3) / 1e9,
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                        "traffic": counter_traffic(),
+                        "traffic": counter_traffic(config), "config": config,
                         "kernel": ("forward time step over 16 shots, " +
                                    ("fused v + p kernel (k_step2d)" if kt["p_kernel"]["samples"] == 0
                                     else "v kernel + p kernel (k_march_v, k_march_p)")),
@@ -456,15 +488,23 @@ def main():
                         "whole_job_alg_bytes": alg_bytes}}
 
     if tuned:
-        # the library's default kernels on the same workload, for comparison with the pick
+        # the library's default kernels on the same workload, timed the same way (the same
+        # number of jobs, with the same device timing samples), for comparison with the pick
         ctx.set_option(B.OPT_AUTOTUNE, 0)
         step()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        step()
-        b.record(stream)
+        ctx.set_option(B.OPT_TIMING, args.timing_every)
         torch.cuda.synchronize()
-        out["autotune"] = {"pick": pick, "default_kernels_ms_per_step": a.elapsed_time(b),
+        dms = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            step()
+            b.record(stream)
+            torch.cuda.synchronize()
+            dms.append(a.elapsed_time(b))
+        ctx.set_option(B.OPT_TIMING, 0)
+        out["autotune"] = {"pick": pick, "default_config": DEFAULT_CONFIG,
+                           "default_kernels_ms_per_step": float(np.mean(dms)),
                            "picked_ms_per_step": total_ms / args.steps}
         print(f"bench: autotuner {pick}", file=sys.stderr, flush=True)
 

@@ -30,14 +30,16 @@ def test_counter_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     src.write_bytes(b"// a kernel source\n")
     cnt = tmp_path / "counters.txt"
     cnt.write_text("# header: a comment line\ntraffic_bytes_per_step: 12345\n"
+                   "kernel_config: march4-xcd\n"
                    "kernel_source_sha256: %s\n" % hashlib.sha256(src.read_bytes()).hexdigest())
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
     monkeypatch.setattr(bench, "COUNTERS", str(cnt))
-    assert bench.counter_traffic() == 12345.0
+    assert bench.counter_traffic("march4-xcd") == 12345.0
+    assert bench.counter_traffic("march2-xcd") is None   # counters of another configuration
     src.write_bytes(b"// a kernel source, changed\n")
-    assert bench.counter_traffic() is None      # any change to the source voids the figure
+    assert bench.counter_traffic("march4-xcd") is None   # any change to the source voids it
     monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.txt"))
-    assert bench.counter_traffic() is None
+    assert bench.counter_traffic("march4-xcd") is None
 
 
 def test_cpu_baseline_reports_rate_threads_and_sample():
