@@ -120,29 +120,43 @@ def counter_traffic(config: str):
         return None
 
 
-def latency(torch, graph: bool = False, only: str = "", reps_override: int = 0):
+def latency(torch, graph: bool = False, only: str = "", reps_override: int = 0,
+            kernel: int = -1, chunk: int = -1, nt: int = 0):
     """Per-call latency of the four fixed workloads: repetitions of the library call after two
     warm-ups, each timed with events on the call's stream; one JSON line per workload.  With
     `graph`, the two forward workloads with their time loops replayed as HIP graphs.  `only`
-    keeps the workloads whose name contains it; `reps_override` > 0 replaces the repetitions."""
+    keeps the workloads whose name contains it; `reps_override` > 0 replaces the repetitions;
+    `kernel` / `chunk` >= 0 set SMI_OPT_KERNEL / SMI_OPT_CHUNK; `nt` > 0 shortens the runs."""
     from paper_2311_02293_amd import binding as B
     from paper_2311_02293_amd import inputs as I
 
     ctx = B.Context(0)
     if graph:
         ctx.set_option(B.OPT_GRAPH, 1)
+    if kernel >= 0:
+        ctx.set_option(B.OPT_KERNEL, kernel)
+    if chunk >= 0:
+        ctx.set_option(B.OPT_CHUNK, chunk)
     stream = torch.cuda.current_stream()
+    def full_grid_3d(nt: int = 3000):
+        # the 3D RTM's grid, model and shots, forward only, box off: every step updates the
+        # whole padded grid (the step's steady state, which the box reaches after ~1000 steps)
+        job = I.config4(nt=nt)
+        job.grid.box = 0
+        return job
     cases = [("2d-forward-201x201-order4-1shot", I.config1, "forward", 20),
              ("2d-batched-forward-500x1500-order8-16shots", I.config2, "forward", 20),
              ("2d-fwi-gradient-300x900-order8-32shots", I.config3, "grad", 20),
-             ("3d-rtm-400^3-order8-4shots-dr10", I.config4, "rtm", 2)]
+             ("3d-rtm-400^3-order8-4shots-dr10", I.config4, "rtm", 2),
+             ("3d-full-grid-forward-400^3-order8-4shots", full_grid_3d, "forward", 2)]
     if graph:
         cases = [c for c in cases if c[2] == "forward"]
-    cases = [c for c in cases if only in c[0]]
+    # the full-grid 3D forward runs only when named
+    cases = [c for c in cases if only in c[0] and (only or not c[0].startswith("3d-full-grid"))]
     if not cases:
         raise SystemExit(f"no latency workload matches {only!r}")
     for name, make, kind, reps in cases:
-        job = make()
+        job = make(nt=nt) if nt > 0 else make()
         reps = reps_override if reps_override > 0 else reps
         vs = [job.vp] + ([job.extra["vp_true"]] if "vp_true" in job.extra else [])
         job.grid.vpmin = float(min(v.min() for v in vs))
@@ -182,6 +196,7 @@ def latency(torch, graph: bool = False, only: str = "", reps_override: int = 0):
             print(f"bench: {name} rep {r}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
         upd = sum(ctx.last_counts())
         print(json.dumps({"metric": "per-call latency", "workload": name, "call": kind,
+                          "nt": job.grid.nt, "kernel_option": kernel, "chunk_option": chunk,
                           "graph_replay": graph, "reps": reps,
                           "warmup": 2, "p50_ms": percentile(ms, 50), "p99_ms": percentile(ms, 99),
                           "GPts_s": upd / (np.median(ms) / 1e3) / 1e9,
@@ -391,7 +406,8 @@ def main():
         serve(torch, args.serve, pool=args.pool)
         return
     if args.latency or args.latency_graph:
-        latency(torch, graph=args.latency_graph, only=args.workload, reps_override=args.reps)
+        latency(torch, graph=args.latency_graph, only=args.workload, reps_override=args.reps,
+                kernel=args.kernel, chunk=args.chunk, nt=args.nt if args.nt != 4000 else 0)
         return
     if args.reverse_only:
         print(json.dumps(reverse_leg(torch)), flush=True)

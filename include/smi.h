@@ -120,8 +120,13 @@ typedef enum {
                                 in 2D forward passes the tiled fused step (v and p of every
                                 shot in one launch, one workgroup per 64-row x C-column tile
                                 with its halos staged in LDS; SMI_OPT_CHUNK = C = 32 or 64,
-                                else 32).  With a free surface, 2, 6, 7 and the y-marching
-                                kernels of 5 give way to the kernels of 0. */
+                                else 32); 8: as 0, and in 3D forward and adjoint half steps
+                                on plane tiles marching along y (64 z-rows per workgroup, the
+                                y-stencil in registers, the plane's z- and x-halo staged in
+                                LDS; SMI_OPT_CHUNK = CY + 1000 F: CY = 16, 32 or 64 y-planes per
+                                workgroup, tile form F = 0: 2 x-cells per lane x 8 wavefronts,
+                                1: 4 x 8, 2: 2 x 16; 0 selects 2016).  With a free surface, 2, 6, 7,
+                                8 and the y-marching kernels of 5 give way to the kernels of 0. */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and
                                 buffers) and replayed on later calls; up to 8 graphs are kept

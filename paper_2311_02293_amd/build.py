@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmi.so")
-SOURCES = ["kernels.hip", "fused2d.hip", "step2d.hip", "ymarch3d.hip", "plan.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "fused2d.hip", "step2d.hip", "ymarch3d.hip", "yplane3d.hip", "plan.cpp",
+           "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions in device code

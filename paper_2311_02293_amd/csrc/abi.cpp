@@ -97,7 +97,7 @@ struct smi_ctx {
     int opt_autotune = 0;
     struct Pick {
         bool fwd = false, rev = false;     // forward kernels / 2D reverse form tuned
-        int march = 0, run = 32, depth = 2, rev_form = 0;
+        int march = 0, run = 32, depth = 2, rev_form = 0, yp = 0, y3 = 0;
         bool xcd = false, ymap = false, step2d = false;
     };
     std::map<std::string, Pick> picks;
@@ -153,8 +153,9 @@ void apply_pick(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl, bool forwar
         c.step2d = p.step2d;
         c.run = p.run;
         c.depth = p.depth;
+        c.yp = p.yp;
         c.zl = false;
-        c.y3 = 0;
+        c.y3 = p.y3;
     }
     if (!forward && p.rev) c.rev = p.rev_form;
 }
@@ -173,6 +174,7 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     c.step2d = false;
     c.run = 32;
     c.depth = 2;
+    c.yp = 0;
     if (ctx->opt_kernel == 6) {
         // the fused marching 2D forward step (other passes and 3D: the kernels of 0)
         c.march = pl.nd == 2 ? 4 : 2;
@@ -181,6 +183,14 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
         c.run = ctx->opt_chunk % 100 == 64 ? 64 : 32;
         const int d = ctx->opt_chunk / 100;
         c.depth = d == 1 || d == 4 ? d : 2;
+    } else if (ctx->opt_kernel == 8) {
+        // the plane-tiled y-marching 3D half steps (2D: the kernels of 0)
+        c.march = pl.nd == 2 ? 4 : 2;
+        c.xcd = pl.nd == 2;
+        // SMI_OPT_CHUNK = CY + 1000 form (0: 2016, the fastest measured)
+        const int code = ctx->opt_chunk > 0 ? ctx->opt_chunk : 2016;
+        const int cy = code % 1000, form = code / 1000;
+        c.yp = smi::yp_available(pl) ? 1000 * (form <= 2 ? form : 0) + (cy == 16 || cy == 64 ? cy : 32) : 0;
     } else if (ctx->opt_kernel == 7) {
         // the tiled fused 2D forward step (other passes and 3D: the kernels of 0)
         c.march = pl.nd == 2 ? 4 : 2;
@@ -251,7 +261,7 @@ Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
     Key k;
     k.put(tag).put(pl.geom).put(pl.band).put(pl.nshot).put(pl.nrun).put(pl.nsave);
     k.put(pl.save).put(pl.g.nt).put(pl.g.dr).put(c.plain).put(c.march).put(c.xcd).put(c.zl).put(c.rev).put(c.ymap);
-    k.put(c.y3).put(pl.chunk).put(c.step2d).put(c.run).put(c.depth);
+    k.put(c.y3).put(pl.chunk).put(c.step2d).put(c.run).put(c.depth).put(c.yp);
     k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
     k.put(pl.src_multi).vec(pl.src_toff).vec(pl.src_cell).vec(pl.inj_off);
     return k;
@@ -420,6 +430,7 @@ struct Cand {
     bool xcd, ymap, step2d;
     int run, depth;
     const char *name;
+    int yp = 0, y3 = 0;
 };
 
 std::vector<Cand> fwd_candidates(const Plan &pl) {
@@ -441,6 +452,10 @@ std::vector<Cand> fwd_candidates(const Plan &pl) {
         v.push_back({4, false, false, false, 32, 2, "march4-plain"});
         v.push_back({2, true, false, false, 32, 2, "march2-xcd"});
         v.push_back({2, false, true, false, 32, 2, "march2-ystrip"});
+        if (smi::yp_available(pl)) {
+            v.push_back({2, false, false, false, 32, 2, "yplane-2x16", 2016});
+        }
+        if (smi::y3_available(pl)) v.push_back({2, false, false, false, 32, 2, "ymarch-8x32", 0, 832});
     }
     return v;
 }
@@ -452,8 +467,9 @@ void set_cand(smi::StepCtx &c, const Cand &q) {
     c.step2d = q.step2d;
     c.run = q.run;
     c.depth = q.depth;
+    c.yp = q.yp;
     c.zl = false;
-    c.y3 = 0;
+    c.y3 = q.y3;
 }
 
 smi_status zero_fields(smi_ctx *ctx, const Plan &pl, const smi::Fields &f, hipStream_t st);
@@ -511,6 +527,8 @@ smi_status tune_forward(smi_ctx *ctx, const Plan &pl, const Views &w, smi::StepC
     p.step2d = cands[best].step2d;
     p.run = cands[best].run;
     p.depth = cands[best].depth;
+    p.yp = cands[best].yp;
+    p.y3 = cands[best].y3;
     ctx->tune_report = rep;
     set_cand(c, cands[best]);
     // the timing runs wrote both field sets (and receivers and bands the loop rewrites)
@@ -866,7 +884,7 @@ const char *smi_last_error(const smi_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (!ctx) return SMI_E_ARG;
-    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 7) { ctx->opt_kernel = value; return SMI_OK; }
+    if (option == SMI_OPT_KERNEL && value >= 0 && value <= 8) { ctx->opt_kernel = value; return SMI_OK; }
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }

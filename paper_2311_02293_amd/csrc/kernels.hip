@@ -1420,6 +1420,7 @@ hipError_t fwd_step_t(const StepCtx &c, int it) {
         if (c.march == 8) return c.zl ? fn<ND, N, 8, true>(__VA_ARGS__) : fn<ND, N, 8, false>(__VA_ARGS__); \
         return c.zl ? fn<ND, N, 4, true>(__VA_ARGS__) : fn<ND, N, 4, false>(__VA_ARGS__);          \
     } while (0)
+    if (!c.plain && c.yp && ND == 3) return fwd_step_yp(c, it);
     if (!c.plain && c.y3 && ND == 3) return fwd_step_y3(c, it);
     if (!c.plain && c.march) SMI_MARCH(fwd_march_t, c, it);
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
@@ -1539,6 +1540,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
         auto recon = [&]() -> hipError_t { SMI_MARCH(recon_march_t, c, it, grad, image); };
         hipError_t e = recon();
         if (e != hipSuccess) return e;
+        if (c.yp && ND == 3) return adj_step_yp(c, it, image);
         if (c.y3 && ND == 3) return adj_step_y3(c, it, image);
         SMI_MARCH(adj_march_t, c, it, image);
     }
@@ -1609,7 +1611,7 @@ hipError_t fwd_step(const StepCtx &c, int it) { SMI_DISPATCH(fwd_step_t, c, it);
 
 bool march_forward(const StepCtx &c) {
     // (the y-strip order uses a one-dimensional grid: no planes to carry other work)
-    return !c.plain && c.march && !(c.y3 && c.pl->nd == 3) && !c.ymap;
+    return !c.plain && c.march && !((c.y3 || c.yp) && c.pl->nd == 3) && !c.ymap;
 }
 
 hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {

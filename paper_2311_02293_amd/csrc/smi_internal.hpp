@@ -220,6 +220,7 @@ struct StepCtx {
     int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)
+    int yp = 0;             // 3D: plane-tiled half steps marching along y, CY planes (0: off)
     int rev = 0;            // 2D reverse step: 0 by batch size, 1 two launches, 2 five launches
     bool step2d = false;    // 2D forward: the fused marching step (step2d.hip), levels in two buffers
     int run = 32;           // its run of columns per wavefront or tile (32 or 64)
@@ -243,6 +244,9 @@ bool march_forward(const StepCtx &c);
 bool y3_available(const Plan &pl);
 hipError_t fwd_step_y3(const StepCtx &c, int it);
 hipError_t adj_step_y3(const StepCtx &c, int it, bool image);
+bool yp_available(const Plan &pl);
+hipError_t fwd_step_yp(const StepCtx &c, int it);
+hipError_t adj_step_yp(const StepCtx &c, int it, bool image);
 // fused 2D forward step (v, p, CPML, source in one kernel, level n from src, level n + 1 to
 // dst); false if not provided for this plan
 bool fused_fwd_available(const Plan &pl);

@@ -530,6 +530,58 @@ def test_y_march_3d_matches_sweep_kernels(ctx, code):
     assert rel_l2(split(dcal_t(got), job)[1], o) <= 1e-4
 
 
+# (case, SMI_OPT_CHUNK): y-planes per workgroup + 1000 x tile form (0: 2 cells per lane x 8
+# wavefronts, 1: 4 x 8, 2: 2 x 16)
+@pytest.mark.parametrize("case,cy", [("box", 32), ("box", 16), ("box", 64), ("box", 1032),
+                                     ("box", 2032), ("nobox", 32), ("offgrid", 32), ("order4", 32)])
+def test_plane_tiled_3d_equals_default_bitwise(ctx, case, cy):
+    """3D half steps on plane tiles marching along y (SMI_OPT_KERNEL 8): forward data,
+    gradient, image and illumination equal to the default kernels' to rounding (1e-6 rel L2,
+    and 1e-5 of the largest value in every element) -- several z, x tiles and y strips per shot
+    with the box on and off, off-grid points, order 4 -- and the data against the oracle."""
+    from paper_2311_02293_amd import binding as B
+    job = I.config4(n=56, nt=150, dr=1, nshot=2, rec_step=4)
+    if case == "nobox":
+        job.grid.box = 0
+    if case == "offgrid":
+        job.acq.src[:, 1] += 0.3 * job.grid.d2
+        job.acq.src[:, 2] += 0.6 * job.grid.d3
+        job.acq.rec[:, 0] += 0.41 * job.grid.d1
+    if case == "order4":
+        job.grid.order = 4
+        job.grid.nb = 12
+        job.grid.fm = 5.0
+    job = with_bounds(job)
+    say("plane-tiled 3D", case, cy, job.grid)
+    vp, rho, stf = dev(job)
+
+    def run():
+        d, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+        dobs = (0.9 * d).contiguous()
+        g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+        im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs)
+        return [t.cpu().numpy() for t in (d, g, im, il)]
+    ref = run()
+    ctx.set_option(B.OPT_KERNEL, 8)
+    ctx.set_option(B.OPT_CHUNK, cy)
+    try:
+        got = run()
+    finally:
+        ctx.set_option(B.OPT_KERNEL, 0)
+        ctx.set_option(B.OPT_CHUNK, 0)
+    ctx.poll_status()
+    for name, a, b in zip(("data", "grad", "image", "illum"), got, ref):
+        same = np.array_equal(a, b)
+        e = rel_l2(a, b)
+        w = float(np.max(np.abs(a.astype(np.float64) - b)) / np.max(np.abs(b)))
+        say(f"  {name}: rel L2 {e:.2e}, worst element {w:.2e} of the peak, bitwise {same}")
+        assert e <= 1e-6 and w <= 1e-5
+    o = oracle_dcal(job, shots=[1], box=0)[0]
+    e = rel_l2(split(dcal_t(got[0]), job)[1], o)
+    say(f"  shot 1 against the oracle {e:.2e}")
+    assert e <= 1e-4
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_born_matches_oracle(ctx, ndim):
     """Tangent-linear (Born) data of a kappa perturbation against the oracle's linearisation
