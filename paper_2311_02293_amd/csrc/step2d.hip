@@ -480,70 +480,60 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
         hbh = cp.b_h[0][rv];
     }
 
-    // ---- 1. every load of the tile.  None sits under a branch (a branch around a load makes
-    // the compiler wait for it, and for every load before it, where the branch ends): loads a
-    // thread does not need read a clamped, valid node, or -- the memory variables of columns
-    // outside the x slabs -- an offset past the resource's end, which returns 0 without a
-    // memory access.
-    constexpr unsigned OOB = 0x80000000u;
+    // ---- 1. every load of the tile
     float pm[PMC];
 #pragma unroll
     for (int k = 0; k < PMC; ++k) {
-        const int q = min(wv + NW * k, PC - 1);
-        pm[k] = bld(rs, vr, a_pA + col(xb - HP + q));
+        const int q = wv + NW * k;
+        pm[k] = q < PC ? bld(rs, vr, a_pA + col(xb - HP + q)) : 0.f;
     }
     float ph[HPT];
 #pragma unroll
     for (int k = 0; k < HPT; ++k) {
-        const int i = min(t + NT * k, NH - 1);
+        const int i = t + NT * k;
         const int ci = i / (2 * HP), h = i % (2 * HP);
         const int row = h < HP ? zs - HP + h : zs + 64 + (h - HP);
-        ph[k] = bld(rs, 4u * (unsigned)(g.org + row) + col(xb + ci), a_pA);
+        ph[k] = i < NH ? bld(rs, 4u * (unsigned)(g.org + row) + col(xb + ci), a_pA) : 0.f;
     }
     const int vc0 = wv * VCW;                 // first v_x column of this wavefront (from xb - N)
-    float vxo[VCW], bx[VCW], psx[VCW], axh[VCW], bxh[VCW];
+    float vxo[VCW], bx[VCW], psx[VCW];
 #pragma unroll
     for (int k = 0; k < VCW; ++k) {
-        const int c = xb - N + min(vc0 + k, VXC - 1);
-        vxo[k] = bld(rs, vr, a_vxA + col(c));
-        bx[k] = bld(rs, vr, a_bdx + col(c));
-        psx[k] = axh[k] = bxh[k] = 0.f;
-        if (XP) {
+        const int c = xb - N + vc0 + k;
+        const bool in = vc0 + k < VXC;
+        vxo[k] = in ? bld(rs, vr, a_vxA + col(c)) : 0.f;
+        bx[k] = in ? bld(rs, vr, a_bdx + col(c)) : 0.f;
+        psx[k] = 0.f;
+        if (XP && in) {
             const int xc = xslab(c);
-            psx[k] = bld(rs, xc >= 0 ? vxr : OOB, a_pxA + (unsigned)max(xc, 0) * colb);
-            if (xc >= 0) {
-                axh[k] = cp.a_h[1][c];
-                bxh[k] = cp.b_h[1][c];
-            }
+            if (xc >= 0) psx[k] = bld(rs, vxr, a_pxA + (unsigned)xc * colb);
         }
     }
     const int j0 = xb + 8 * wv;               // first p / v_z column of this wavefront
-    float vzo[8], bz[8], kd[8], psz[8], pvz[8], pvx[8], axi[8], bxi[8];
+    float vzo[8], bz[8], kd[8], psz[8], pvz[8], pvx[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int j = j0 + k;
         vzo[k] = bld(rs, vr, a_vzA + col(j));
         bz[k] = bld(rs, vr, a_bdz + col(j));
         kd[k] = bld(rs, vr, a_kdt + col(j));
-        psz[k] = pvz[k] = pvx[k] = axi[k] = bxi[k] = 0.f;
+        psz[k] = pvz[k] = pvx[k] = 0.f;
         if (ZP) {
             psz[k] = bld(rs, vzi, a_pzA + zcol(j));
             pvz[k] = bld(rs, vzi, a_vpzA + zcol(j));
         }
         if (XP) {
             const int xc = xslab(j);
-            pvx[k] = bld(rs, xc >= 0 ? vxr : OOB, a_vpxA + (unsigned)max(xc, 0) * colb);
-            if (xc >= 0) {
-                axi[k] = cp.a_i[1][j];
-                bxi[k] = cp.b_i[1][j];
-            }
+            if (xc >= 0) pvx[k] = bld(rs, vxr, a_vpxA + (unsigned)xc * colb);
         }
     }
-    // (threads without a v_z halo cell load the first one's values and never use them)
-    const unsigned hr = 4u * (unsigned)(g.org + rv) + col(xb + hc);
-    const float hvo = bld(rs, hr, a_vzA);
-    const float hbz = bld(rs, hr, a_bdz);
-    const float hpz = ZP ? bld(rs, 4u * (unsigned)(zch >= 0 ? zch : 0), a_pzA + zcol(xb + hc)) : 0.f;
+    float hvo = 0.f, hbz = 0.f, hpz = 0.f;
+    if (hv) {
+        const unsigned hr = 4u * (unsigned)(g.org + rv) + col(xb + hc);
+        hvo = bld(rs, hr, a_vzA);
+        hbz = bld(rs, hr, a_bdz);
+        if (ZP) hpz = bld(rs, 4u * (unsigned)(zch >= 0 ? zch : 0), a_pzA + zcol(xb + hc));
+    }
 #pragma unroll
     for (int k = 0; k < PMC; ++k) {
         const int q = wv + NW * k;
@@ -574,7 +564,7 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
             if (XP) {
                 const int xc = xslab(c);
                 if (xc >= 0) {
-                    const float psi = bxh[k] * psx[k] + axh[k] * e;
+                    const float psi = cp.b_h[1][c] * psx[k] + cp.a_h[1][c] * e;
                     if (own && mine) bst(rs, vxr, a_pxB + (unsigned)xc * colb, psi);
                     e += psi;
                 }
@@ -638,7 +628,7 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
         if (XP) {
             const int xc = xslab(j);
             if (xc >= 0) {
-                const float psi = bxi[k] * pvx[k] + axi[k] * dx;
+                const float psi = cp.b_i[1][j] * pvx[k] + cp.a_i[1][j] * dx;
                 if (own && mine) bst(rs, vxr, a_vpxB + (unsigned)xc * colb, psi);
                 dx += psi;
             }
