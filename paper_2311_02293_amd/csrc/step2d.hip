@@ -399,8 +399,9 @@ __global__ __launch_bounds__(256) void k_step2d(Geom g, Fields A, Fields B, Mode
 // columns [xb + 8 w, xb + 8 w + 8) and a share of the v_x columns.  The arithmetic, the box
 // rules (a cell outside the shot's computing box keeps its old level; only the tile's own
 // cells inside the box are stored) and the CPML memory variables are those of the half-step
-// kernels, term by term, so both give bitwise the same fields.  Loads read columns no further
-// than 2N - 2 past the padded grid (clamped): the values there only reach cells not stored.
+// kernels, term by term, so both give bitwise the same fields.  Loads past the padded grid
+// read what lies there (or 0 past the region's resource): the values reach only cells that
+// are not stored.
 template <int N, int TX>
 struct T2 {
     static constexpr int HP = 2 * N - 1;          // p halo (rows or columns) per side
@@ -438,8 +439,11 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
     auto off = [&](const float *p) { return (unsigned)((const char *)p - rb); };
     const long long so = (long long)s * g.P;
     const unsigned colb = 4u * (unsigned)g.ld1;
-    const int cmax = g.M[1] + HP - 1;         // last column a load reads
-    auto col = [&](int c) { return (unsigned)min(c, cmax) * colb; };
+    // column offsets are not clamped: every access goes through the region's resource, and
+    // one past its end reads 0 and writes nothing; a store a lane must not make goes to such
+    // an offset instead of sitting under a branch (no exec-mask juggling per store)
+    constexpr unsigned OOB = 0x80000000u;
+    auto col = [&](int c) { return (unsigned)c * colb; };
     const int r = zs + lane;
     const bool own = r >= b0 && r < b1;
     const bool rowok = r >= 0 && r < g.M[0];
@@ -565,12 +569,12 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
                 const int xc = xslab(c);
                 if (xc >= 0) {
                     const float psi = cp.b_h[1][c] * psx[k] + cp.a_h[1][c] * e;
-                    if (own && mine) bst(rs, vxr, a_pxB + (unsigned)xc * colb, psi);
+                    bst(rs, own && mine ? vxr : OOB, a_pxB + (unsigned)xc * colb, psi);
                     e += psi;
                 }
             }
             const float vxn = c >= b2 && c < b3 ? vxo[k] - bx[k] * e : vxo[k];
-            if (own && mine) bst(rs, vr, a_vxB + col(c), vxn);
+            bst(rs, own && mine ? vr : OOB, a_vxB + col(c), vxn);
             VX[(vc0 + k) * 64 + lane] = vxn;
         }
     }
@@ -584,11 +588,11 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
         const bool mine = j >= x0 && j < x1;
         if (ZP) {
             const float psi = zbh * psz[k] + zah * ez;
-            if (own && mine && zci >= 0) bst(rs, vzi, a_pzB + zcol(j), psi);
+            bst(rs, own && mine && zci >= 0 ? vzi : OOB, a_pzB + zcol(j), psi);
             ez = zci >= 0 ? ez + psi : ez;
         }
         const float vzn = own ? vzo[k] - bz[k] * ez : vzo[k];
-        if (own && mine) bst(rs, vr, a_vzB + col(j), vzn);
+        bst(rs, own && mine ? vr : OOB, a_vzB + col(j), vzn);
         VZ[(8 * wv + k) * LDZ + N + lane] = vzn;
     }
     if (hv) {
@@ -619,7 +623,7 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
         const bool mine = j >= x0 && j < x1;
         if (ZP) {
             const float psi = zbi * pvz[k] + zai * dz;
-            if (own && mine && zci >= 0) bst(rs, vzi, a_vpzB + zcol(j), psi);
+            bst(rs, own && mine && zci >= 0 ? vzi : OOB, a_vpzB + zcol(j), psi);
             dz = zci >= 0 ? dz + psi : dz;
         }
         float dx = 0.f;
@@ -629,7 +633,7 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
             const int xc = xslab(j);
             if (xc >= 0) {
                 const float psi = cp.b_i[1][j] * pvx[k] + cp.a_i[1][j] * dx;
-                if (own && mine) bst(rs, vxr, a_vpxB + (unsigned)xc * colb, psi);
+                bst(rs, own && mine ? vxr : OOB, a_vpxB + (unsigned)xc * colb, psi);
                 dx += psi;
             }
         }
@@ -638,7 +642,7 @@ __device__ __forceinline__ void tile2d(const Geom &g, const Fields &A, const Fie
         sdiv += dx;
         float pn = Pn[(8 * wv + k + HP) * LDP + HP + lane] - kd[k] * sdiv;
         if (j == scol) pn += samp;
-        if (own && mine) bst(rs, vr, a_pB + col(j), pn);
+        bst(rs, own && mine ? vr : OOB, a_pB + col(j), pn);
     }
 }
 
