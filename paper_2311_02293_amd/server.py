@@ -121,6 +121,10 @@ class _ModelCache:
             self.used += nb
             return e
 
+    def resident(self, key) -> bool:
+        with self.lock:
+            return key in self.d
+
     def release(self, key):
         with self.lock:
             e = self.d.get(key)
@@ -163,7 +167,9 @@ class HipBackend:
         nrec = int(job.acq.rec_off[-1])
         data = 4 * job.grid.nt * nrec * (2 if kind != "forward" else 1)
         results = 4 * job.grid.npts * (2 if kind != "forward" else 0) * max(1, job.acq.nshot)
-        model = 0 if model_key is not None else 4 * job.grid.npts * 2
+        # the model counts unless it is resident already (an upload into the cache, or a private
+        # copy when the cache has no room, both need the bytes)
+        model = 0 if model_key is not None and self.models.resident(model_key) else 4 * job.grid.npts * 2
         return ws + data + results + model + 4 * job.stf.size
 
     def _run(self, job: I.Job, kind: str, dobs: Optional[np.ndarray], slot: int,
