@@ -256,9 +256,12 @@ def reverse_leg(torch, reps: int = 5, timing_every: int = 32):
            "reverse_step": {"avg_us": rms * 1e3, "alg_bytes": rby, "samples": rn,
                             "achieved_GBps": rev_GBps, "peak_GBps": HBM_PEAK_GBS,
                             "frac": rev_GBps / HBM_PEAK_GBS if rev_GBps else None,
-                            "what": "one reverse iteration of Alg. 2 over 32 shots (adjoint "
-                                    "source, source removal, reconstruction with the gradient "
-                                    "sum, adjoint step), first launch to end of last"},
+                            "what": "one reverse iteration of Alg. 2 (adjoint source, source "
+                                    "removal, reconstruction with the gradient sum, adjoint "
+                                    "step) over one group of the shots, first launch to end of "
+                                    "last: the reverse loop runs once per group of shots whose "
+                                    "reverse state fits the last-level cache (SMI_OPT_REV_GROUP; "
+                                    "two groups of 16 here)"},
            "forward_step": {"avg_us": fwd_us, "alg_bytes": fs_bytes,
                             "achieved_GBps": fs_bytes / (fwd_us / 1e6) / 1e9 if fwd_us > 0 else None}}
     del ws, dobs

@@ -156,7 +156,7 @@ typedef enum {
                                 bands; then reconstruction of v with the adjoint p update and the
                                 v bands) for batches of up to 8 M padded cells, five launches
                                 above; 1 always two; 2 always five.  Same results. */
-    SMI_OPT_AUTOTUNE = 7     /* 1: the library picks the kernels per plan shape (geometry, shots,
+    SMI_OPT_AUTOTUNE = 7,    /* 1: the library picks the kernels per plan shape (geometry, shots,
                                 nt, box, dr, job kind) by timing them on the device: the first
                                 forward pass of a shape times every forward candidate (kernel
                                 family, cells per lane, tile order, the fused 2D step's run width
@@ -167,6 +167,14 @@ typedef enum {
                                 keeps the faster.  Every candidate gives the default's results.
                                 smi_tuning_report tells the last pick.  0: off (default);
                                 2: forget the picks made so far (the switch stays as it was). */
+    SMI_OPT_REV_GROUP = 8    /* 2D reverse passes (Alg. 2 reverse loop) run the loop once per
+                                group of consecutive shots: 0 (default) the largest equal groups
+                                whose reverse state (source and adjoint fields, CPML variables,
+                                accumulators) fits 224 MiB, 7/8 of the device's last-level
+                                cache, so that each group's launches keep it there; k > 0 at
+                                most k shots per group (k >= the shot count: one loop over all
+                                shots).  3D passes and the plain stepper run one loop.  Same
+                                results for every value. */
 } smi_option;
 
 /* Text of the autotuner's last pick on this context (candidates, their times per step, the

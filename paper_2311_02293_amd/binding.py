@@ -21,6 +21,7 @@ STATUS = {0: "SMI_OK", -1: "SMI_E_ARG", -2: "SMI_E_CFL", -3: "SMI_E_DISPERSION",
 JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD, JOB_BORN = 0, 1, 2, 3, 4
 OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY, OPT_REVERSE = 0, 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE = 7
+OPT_REV_GROUP = 8
 
 
 class SmiError(RuntimeError):

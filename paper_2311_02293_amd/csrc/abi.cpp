@@ -69,6 +69,7 @@ struct smi_ctx {
     int opt_graph = 0;
     int opt_chunk = 0;
     int opt_rev = 0;
+    int opt_rev_group = 0;      // SMI_OPT_REV_GROUP: 0 by the cache budget, k: at most k shots
     int opt_xcd = 0;
     int opt_family = 1;
     void *last_ws = nullptr;
@@ -238,6 +239,8 @@ smi_status hip_fail(smi_ctx *c, hipError_t e, const char *where) {
 // ---------------------------------------------------------------- captured time loops
 
 constexpr size_t kMaxGraphs = 8;
+// reverse state of one group of shots in a 2D reverse pass: 7/8 of the 256 MB last-level cache
+constexpr double kRevGroupBudget = 224.0 * 1024 * 1024;
 
 struct Key {
     std::string b;
@@ -731,6 +734,12 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     apply_pick(c, ctx, pl, false);
     for (int k = 0; k < nsnap; ++k)
         if (snap_it[k] == pl.g.nt) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
+    // 2D: the reverse loop runs once per group of shots, each group small enough that its
+    // reverse state (source and adjoint fields, memory variables, accumulators) stays in the
+    // last-level cache between its launches; every shot's arithmetic is the same as in one
+    // loop over all shots, and the outputs are reduced per shot afterwards
+    const std::vector<int> rg = c.plain ? std::vector<int>{0, pl.nshot}
+                                        : smi::rev_groups(pl, kRevGroupBudget, ctx->opt_rev_group, want_r);
     const bool timed = ctx->opt_timing > 0;
     // 2D reverse form not yet tuned for this shape: sampled iterations of this call alternate
     // the two forms (bitwise the same results), timed by events read on the next call
@@ -741,47 +750,54 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     const int base_rev = c.rev;
     auto loop = [&](hipStream_t ls) -> smi_status {
         c.st = ls;
-        for (int it = pl.g.nt - 1; it >= 0; --it) {
-            // sampled reverse step: the device stamps an event before its first launch and
-            // after its last
-            hipEvent_t *ev = nullptr;
-            if (timed && it % ctx->opt_timing == 0) {
-                const size_t k = ctx->nrev;
-                while (ctx->rev_events.size() < 2 * (k + 1)) {
-                    hipEvent_t e;
-                    HIPCHK(hipEventCreate(&e), "timing event");
-                    ctx->rev_events.push_back(e);
+        for (size_t gi = 0; gi + 1 < rg.size(); ++gi) {
+            c.s0 = rg[gi];
+            c.s1 = rg[gi + 1];
+            for (int it = pl.g.nt - 1; it >= 0; --it) {
+                // sampled reverse step: the device stamps an event before its first launch and
+                // after its last
+                hipEvent_t *ev = nullptr;
+                if (timed && it % ctx->opt_timing == 0) {
+                    const size_t k = ctx->nrev;
+                    while (ctx->rev_events.size() < 2 * (k + 1)) {
+                        hipEvent_t e;
+                        HIPCHK(hipEventCreate(&e), "timing event");
+                        ctx->rev_events.push_back(e);
+                    }
+                    double q[4];
+                    smi::rev_iter_bytes(pl, it, c.s0, c.s1, q);
+                    ctx->rev_sample_bytes.push_back(q[0] + (want_g ? q[1] : 0.0) +
+                                                    (want_i && (image || image_norm) ? q[2] : 0.0) +
+                                                    (want_i && (illum || image_norm) ? q[3] : 0.0));
+                    ctx->nrev = k + 1;
+                    ev = &ctx->rev_events[2 * k];
+                    HIPCHK(hipEventRecord(ev[0], ls), "timing event");
                 }
-                const double *q = &pl.rev_bytes[4 * (size_t)it];
-                ctx->rev_sample_bytes.push_back(q[0] + (want_g ? q[1] : 0.0) +
-                                                (want_i && (image || image_norm) ? q[2] : 0.0) +
-                                                (want_i && (illum || image_norm) ? q[3] : 0.0));
-                ctx->nrev = k + 1;
-                ev = &ctx->rev_events[2 * k];
-                HIPCHK(hipEventRecord(ev[0], ls), "timing event");
+                if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
+                HIPCHK(smi::src_taps(c, it, w.f.p, -1.f), "source removal");
+                if (rev_tune && it % 16 == 7) {
+                    hipEvent_t e0, e1;
+                    HIPCHK(hipEventCreate(&e0), "tuning event");
+                    HIPCHK(hipEventCreate(&e1), "tuning event");
+                    rt.ev.push_back(e0);
+                    rt.ev.push_back(e1);
+                    rt.form.push_back(rt.form.size() % 2 ? 2 : 1);
+                    c.rev = rt.form.back();
+                    HIPCHK(hipEventRecord(e0, ls), "tuning event");
+                    HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+                    HIPCHK(hipEventRecord(e1, ls), "tuning event");
+                    c.rev = base_rev;
+                } else {
+                    HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+                }
+                if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
+                if (ev) HIPCHK(hipEventRecord(ev[1], ls), "timing event");
+                for (int k = 0; k < nsnap; ++k)
+                    if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
             }
-            if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
-            HIPCHK(smi::src_taps(c, it, w.f.p, -1.f), "source removal");
-            if (rev_tune && it % 16 == 7) {
-                hipEvent_t e0, e1;
-                HIPCHK(hipEventCreate(&e0), "tuning event");
-                HIPCHK(hipEventCreate(&e1), "tuning event");
-                rt.ev.push_back(e0);
-                rt.ev.push_back(e1);
-                rt.form.push_back(rt.form.size() % 2 ? 2 : 1);
-                c.rev = rt.form.back();
-                HIPCHK(hipEventRecord(e0, ls), "tuning event");
-                HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
-                HIPCHK(hipEventRecord(e1, ls), "tuning event");
-                c.rev = base_rev;
-            } else {
-                HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
-            }
-            if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
-            if (ev) HIPCHK(hipEventRecord(ev[1], ls), "timing event");
-            for (int k = 0; k < nsnap; ++k)
-                if (snap_it[k] == it) HIPCHK(smi::snap(c, w.f, snaps, k, nsnap), "snap");
         }
+        c.s0 = 0;
+        c.s1 = -1;
         return SMI_OK;
     };
     if (ctx->opt_graph && !timed && !rev_tune) {
@@ -789,6 +805,7 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
         k.put(stt->ws).put(stt->stf).put(G).put(snaps).put(nsnap).put(adj).put(want_g);
         k.put(want_i).put(want_r);
         for (int q = 0; q < nsnap; ++q) k.put(snap_it[q]);
+        for (int v : rg) k.put(v);
         s = graph_run(ctx, k.b, st, loop);
     } else {
         s = loop(st);
@@ -888,6 +905,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_GRAPH && (value == 0 || value == 1)) { ctx->opt_graph = value; return SMI_OK; }
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
+    if (option == SMI_OPT_REV_GROUP && value >= 0) { ctx->opt_rev_group = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && value >= 0 && value <= 2) { ctx->opt_xcd = value; return SMI_OK; }
     if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
     if (option == SMI_OPT_AUTOTUNE && (value == 0 || value == 1 || value == 2)) {

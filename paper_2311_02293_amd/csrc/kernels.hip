@@ -243,6 +243,7 @@ struct MG {
     // is read once from HBM for all shots.  3D shot-inner order (ymap = 3): grid plane z holds
     // y-strip z / per of shot z % per, so one strip of every shot runs before the next strip
     int gz, gx, per, ntile, ymap;
+    int sb = 0;         // first shot of the launch: the shot indices of the tile map count from it
 };
 
 // the band cells of every shot over the blocks from grid plane z0 on (one lane per cell)
@@ -282,7 +283,7 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         const long long slot = rk >> 3;
         const long long r = slot / mg.per;
         const int sx = (int)(r / mg.gz);
-        c.s = shot0 + front + (int)(slot % mg.per);
+        c.s = mg.sb + shot0 + front + (int)(slot % mg.per);
         const int *b = box + 6 * c.s;
         c.z = zalign(b[0]) + ((int)(r % mg.gz) * 4 + wv) * 64 + lane;
         c.lo = b[2] + ((int)(rk & 7) * mg.nxc + sx) * CM;
@@ -293,7 +294,7 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.zb1 = b[1];
         c.run = sx < mg.nxc && c.lo < c.hi && c.z - lane < b[1];
     } else if (ND == 2) {
-        c.s = shot0 + (int)blockIdx.z;
+        c.s = mg.sb + shot0 + (int)blockIdx.z;
         const int *b = box + 6 * c.s;
         c.z = zalign(b[0]) + (bz * 4 + wv) * 64 + lane;
         c.lo = b[2] + bx * CM;
@@ -305,9 +306,9 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
         c.run = c.lo < c.hi && c.z - lane < b[1];
     } else {
         int strip = (int)blockIdx.z % mg.nmarch;
-        c.s = shot0 + (int)blockIdx.z / mg.nmarch;
+        c.s = mg.sb + shot0 + (int)blockIdx.z / mg.nmarch;
         if (SI && mg.ymap == 3) {       // shot-inner: consecutive planes take one strip of every shot
-            c.s = shot0 + (int)blockIdx.z % mg.per;
+            c.s = mg.sb + shot0 + (int)blockIdx.z % mg.per;
             strip = (int)blockIdx.z / mg.per;
         }
         int zb3 = bz, xg3 = bx;
@@ -321,7 +322,7 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
             xg3 = r % mg.gx;
             r /= mg.gx;
             zb3 = r % mg.gz;
-            c.s = shot0 + r / mg.gz;
+            c.s = mg.sb + shot0 + r / mg.gz;
         }
         const int *b = box + 6 * c.s;
         c.z = zalign(b[0]) + zb3 * 64 + lane;
@@ -900,10 +901,11 @@ struct Taps {
 };
 
 __global__ __launch_bounds__(256) void k_band_mix(Geom g, Fields f, BandDesc bd, const float *buf,
-                                                  long long shot_stride, Taps tp, int which) {
+                                                  long long shot_stride, int shot0, Taps tp,
+                                                  int which) {
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= bd.B) return;
-    int s = blockIdx.y;
+    int s = shot0 + (int)blockIdx.y;
     int b = 0;
 #pragma unroll 1
     while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
@@ -938,8 +940,8 @@ __global__ __launch_bounds__(256) void k_src_taps(Geom g, float *p, const long l
                                                   const long long *__restrict__ tcell,
                                                   const float *__restrict__ tw,
                                                   const float *__restrict__ stf, int nt, int it,
-                                                  float sign) {
-    const int s = blockIdx.y;
+                                                  float sign, int shot0) {
+    const int s = shot0 + (int)blockIdx.y;
     if (src_cell[s] >= 0) return;
     const int t = toff[s] + blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= toff[s + 1]) return;
@@ -958,9 +960,9 @@ __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, flo
 // co-located receivers give the same bits on every run.
 __global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *__restrict__ kdt,
                                                 Recv rv, Inj in, const float *__restrict__ G,
-                                                int it, float inv_dt) {
+                                                int it, float inv_dt, int s0, int s1) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= in.U) return;
+    if (u >= in.U || in.shot[u] < s0 || in.shot[u] >= s1) return;
     float acc = 0.f;
     for (int t = in.off[u]; t < in.off[u + 1]; ++t) {
         const int r = in.rec[t];
@@ -1094,8 +1096,9 @@ __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ f, 
 template <int ND, int N>
 __global__ __launch_bounds__(256) void k_rho_faces(Geom g, Fields f, Fields q, float *acc0,
                                                    float *acc1, float *acc2,
-                                                   const int *__restrict__ rbox, int ny) {
-    const int s = (int)blockIdx.z / ny;
+                                                   const int *__restrict__ rbox, int ny,
+                                                   int shot0) {
+    const int s = shot0 + (int)blockIdx.z / ny;
     const int *b = rbox + 6 * s;
     Cell c;
     c.s = s;
@@ -1202,10 +1205,10 @@ __global__ __launch_bounds__(256) void k_free_surface(Geom g, float *f, int shot
 
 // interior p of every shot -> snaps[s][k][...]
 __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
-                                              int k, int nsnap) {
+                                              int k, int nsnap, int shot0) {
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= g.I) return;
-    int s = blockIdx.y;
+    int s = shot0 + (int)blockIdx.y;
     int iz = (int)(i % g.n[0]);
     long long r = i / g.n[0];
     int ix = (int)(r % g.n[1]);
@@ -1289,6 +1292,7 @@ MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0
         const int ntile = (s1 - s0) * gz * gx * nm;
         const int per = (ntile + 7) / 8;
         L.mg = MG{nm, 0, gz, gx, per, ntile, 1};
+        L.mg.sb = s0;
         L.grid = dim3((unsigned)(8 * per), 1u, 1u);
         return L;
     }
@@ -1301,6 +1305,7 @@ MLaunch march_launch(const Plan &pl, const std::vector<int> &tab, int it, int s0
     for (int s = s0 + 1; same && s < s1; ++s)
         same = std::equal(b0, b0 + 6, &tab[((size_t)it * pl.nshot + s) * 6]);
     if (same) L.mg = pl.nd == 2 ? MG{nm, nxc, gz, 0, s1 - s0, 0, 2} : MG{nm, nxc, 0, 0, s1 - s0, 0, 3};
+    L.mg.sb = s0;
     L.grid = dim3((unsigned)(xcd ? 8 * gz : gz), (unsigned)(xcd ? nxc : gx), (unsigned)((s1 - s0) * nm));
     return L;
 }
@@ -1392,11 +1397,12 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
+    const int s0 = c.s0, s1 = shot_end(c);
+    MLaunch L = march_launch(pl, pl.abox, it, s0, s1, CM, c.xcd, c.ymap);
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr}, BandArg{}, 0);
-    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
+    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
     if (image)
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                            w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
@@ -1407,7 +1413,7 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
                            (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                            (const float *)w.f.p, w.acc_i, BandArg{}, 0);
     hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, s0, s1);
 }
 
 template <int ND, int N>
@@ -1458,7 +1464,7 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
-    MLaunch L = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd, c.ymap);
+    MLaunch L = march_launch(pl, pl.rbox, it, c.s0, shot_end(c), CM, c.xcd, c.ymap);
     if (!L.empty) {
 #define SMI_MRECON_P(G_, L_)                                                                   \
     hipLaunchKernelGGL((k_march_recon_p<ND, N, CM, ZL, G_, L_>), L.grid, L.block, 0, c.st, pl.geom, \
@@ -1488,20 +1494,21 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
     const Views &w = *c.w;
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
-    const MLaunch LR = march_launch(pl, pl.rbox, it, 0, pl.nshot, CM, c.xcd);
-    const MLaunch LA = march_launch(pl, pl.abox, it, 0, pl.nshot, CM, c.xcd);
+    const int s0 = c.s0, s1 = shot_end(c), ns = s1 - s0;
+    const MLaunch LR = march_launch(pl, pl.rbox, it, s0, s1, CM, c.xcd);
+    const MLaunch LA = march_launch(pl, pl.abox, it, s0, s1, CM, c.xcd);
     const bool band = pl.g.dr == 1;
     const BandArg ba{w.bdesc, w.bands + (size_t)it * pl.band.B, (long long)pl.nsave * pl.band.B,
-                     (int)((pl.band.B + 255) / 256), pl.nshot};
-    dim3 grid(std::max(LR.grid.x, LA.grid.x), std::max(LR.grid.y, LA.grid.y), 2u * pl.nshot);
+                     (int)((pl.band.B + 255) / 256), ns, s0};
+    dim3 grid(std::max(LR.grid.x, LA.grid.x), std::max(LR.grid.y, LA.grid.y), 2u * ns);
     if (band) {
         const long long per = (long long)grid.x * grid.y;
-        grid.z += (unsigned)(((long long)pl.nshot * ba.nqb + per - 1) / per);
+        grid.z += (unsigned)(((long long)ns * ba.nqb + per - 1) / per);
     }
     const dim3 block(64, 4, 1);
 #define SMI_RPV(G_, L_, B_)                                                                    \
     hipLaunchKernelGGL((k_rev_pv<N, CM, G_, L_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,   \
-                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, pl.nshot,                         \
+                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, ns,                               \
                        (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_g, w.acc_l, ba)
 #define SMI_RPV_B(G_, L_) do { if (band) SMI_RPV(G_, L_, true); else SMI_RPV(G_, L_, false); } while (0)
     if (grad && image) SMI_RPV_B(true, true);
@@ -1511,16 +1518,16 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
 #undef SMI_RPV_B
 #undef SMI_RPV
     if (!band) SMI_TRY(band_restore(c, it, 2));      // interpolated levels: one launch of their own
-    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, 0, pl.nshot));
+    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
 #define SMI_RVP(I_, B_)                                                                        \
     hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,       \
-                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, pl.nshot,                         \
+                       w.model, w.cpml, rb, ab, LR.mg, LA.mg, ns,                               \
                        (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_i, ba)
     if (image) { if (band) SMI_RVP(true, true); else SMI_RVP(true, false); }
     else { if (band) SMI_RVP(false, true); else SMI_RVP(false, false); }
 #undef SMI_RVP
     hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, 0, pl.nshot);
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, s0, s1);
 }
 
 template <int ND, int N>
@@ -1531,8 +1538,9 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     // 300 x 900, 30 % less host time on one); above, where the host keeps ahead and the two
     // orders measure the same, the five-launch order keeps consecutive kernels on one field.
     constexpr double kPairCells = 8.0e6;
+    const int sa = c.s0, se = shot_end(c);
     if constexpr (ND == 2) {
-        const bool small = (double)pl.nshot * (double)pl.P <= kPairCells;
+        const bool small = (double)(se - sa) * (double)pl.P <= kPairCells;
         if (!c.plain && c.march == 4 && !c.zl && (c.rev == 1 || (c.rev == 0 && small)))
             return rev_pair_t<N>(c, it, grad, image);
     }
@@ -1546,10 +1554,10 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     }
     const int *rb = w.rbox + (size_t)it * pl.nshot * 6;
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
-    int step = c.plain ? 1 : pl.nshot;
+    const int step = c.plain ? 1 : se - sa;
     // source field: p^{it} (with the gradient read of p~ before the adjoint step)
-    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
-        int s1 = std::min(pl.nshot, s0 + step);
+    for (int s0 = sa; s0 < se; s0 += step) {
+        int s1 = std::min(se, s0 + step);
         Launch L = box_launch(pl, pl.rbox, it, s0, s1, c.xcd);
         if (L.empty) continue;
 #define SMI_RECON_P(G_, L_)                                                                    \
@@ -1564,8 +1572,8 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     }
     hipError_t e = band_restore(c, it, 0);
     if (e != hipSuccess) return e;
-    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
-        int s1 = std::min(pl.nshot, s0 + step);
+    for (int s0 = sa; s0 < se; s0 += step) {
+        int s1 = std::min(se, s0 + step);
         Launch L = box_launch(pl, pl.rbox, it, s0, s1, c.xcd);
         if (L.empty) continue;
         hipLaunchKernelGGL((k_recon_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
@@ -1574,8 +1582,8 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     e = band_restore(c, it, 1);
     if (e != hipSuccess) return e;
     // adjoint field: one step of the same solver (eq. 8), image with p^{it}
-    for (int s0 = 0; s0 < pl.nshot; s0 += step) {
-        int s1 = std::min(pl.nshot, s0 + step);
+    for (int s0 = sa; s0 < se; s0 += step) {
+        int s1 = std::min(se, s0 + step);
         Launch L = box_launch(pl, pl.abox, it, s0, s1, c.xcd);
         if (L.empty) continue;
         hipLaunchKernelGGL((k_step_v<ND, N>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
@@ -1630,15 +1638,17 @@ hipError_t src_taps(const StepCtx &c, int it, float *p, float sign) {
     const Plan &pl = *c.pl;
     if (!pl.src_multi) return hipSuccess;
     const Views &w = *c.w;
+    const int s0 = c.s0, s1 = shot_end(c);
     int most = 0;
-    for (int s = 0; s < pl.nshot; ++s) most = std::max(most, pl.src_toff[s + 1] - pl.src_toff[s]);
-    hipLaunchKernelGGL(k_src_taps, dim3(blocks(most), pl.nshot), dim3(256), 0, c.st, pl.geom, p,
+    for (int s = s0; s < s1; ++s) most = std::max(most, pl.src_toff[s + 1] - pl.src_toff[s]);
+    if (most == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_src_taps, dim3(blocks(most), s1 - s0), dim3(256), 0, c.st, pl.geom, p,
                        (const long long *)w.src_cell, (const int *)w.src_toff,
                        (const long long *)w.src_tcell, (const float *)w.src_tw, c.stf, pl.g.nt,
-                       it, sign);
+                       it, sign, s0);
     // an injection on a free-surface grid is followed by the images of what it added (the
     // removal in the reconstruction is not: the rows above the surface come from the bands)
-    if (sign > 0.f) SMI_TRY(fs_launch(pl, c.st, p, 1, 0, pl.nshot));
+    if (sign > 0.f) SMI_TRY(fs_launch(pl, c.st, p, 1, s0, s1));
     return hipGetLastError();
 }
 
@@ -1688,10 +1698,11 @@ hipError_t band_restore(const StepCtx &c, int it, int which) {
     long long ss = (long long)pl.nsave * pl.band.B;
     const int dr = pl.g.dr;
     const int k0 = it / dr;
+    const int s0 = c.s0, ns = shot_end(c) - c.s0;
     if (it % dr == 0) {
-        hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
+        hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), ns), dim3(256), 0, c.st,
                            pl.geom, w.f, pl.band, w.bands + (size_t)k0 * pl.band.B,
-                           (const float *)nullptr, ss, 0, 1, which, 0.f);
+                           (const float *)nullptr, ss, s0, 1, which, 0.f);
         return hipGetLastError();
     }
     Taps tp{};
@@ -1707,8 +1718,8 @@ hipError_t band_restore(const StepCtx &c, int it, int which) {
     }
     tp.n = n;
     for (int j = 0; j < n; ++j) { tp.slot[j] = sl[j]; tp.w[j] = (float)(wk[j] / ws); }
-    hipLaunchKernelGGL(k_band_mix, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st,
-                       pl.geom, w.f, pl.band, (const float *)w.bands, ss, tp, which);
+    hipLaunchKernelGGL(k_band_mix, dim3(blocks(pl.band.B), ns), dim3(256), 0, c.st,
+                       pl.geom, w.f, pl.band, (const float *)w.bands, ss, s0, tp, which);
     return hipGetLastError();
 }
 
@@ -1722,19 +1733,21 @@ hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a) {
 
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap) {
     const Plan &pl = *c.pl;
-    hipLaunchKernelGGL(k_snap, dim3(blocks(pl.I), pl.nshot), dim3(256), 0, c.st, pl.geom,
-                       (const float *)f.p, snaps, k, nsnap);
+    hipLaunchKernelGGL(k_snap, dim3(blocks(pl.I), shot_end(c) - c.s0), dim3(256), 0, c.st,
+                       pl.geom, (const float *)f.p, snaps, k, nsnap, c.s0);
     return hipGetLastError();
 }
 
 hipError_t adj_inject(const StepCtx &c, int it, const float *G) {
     const Views &w = *c.w;
     if (w.inj.U == 0) return hipSuccess;
+    const int s0 = c.s0, s1 = shot_end(c);
     hipLaunchKernelGGL(k_inject, dim3(blocks(w.inj.U)), dim3(256), 0, c.st, c.pl->geom, w.q.p,
-                       (const float *)w.model.kdt, w.recv, w.inj, G, it, (float)(1.0 / c.pl->g.dt));
+                       (const float *)w.model.kdt, w.recv, w.inj, G, it, (float)(1.0 / c.pl->g.dt),
+                       s0, s1);
     // the injected adjoint sources get their images too (the transpose of the sampling of a
     // mirrored field)
-    SMI_TRY(fs_launch(*c.pl, c.st, w.q.p, 1, 0, c.pl->nshot));
+    SMI_TRY(fs_launch(*c.pl, c.st, w.q.p, 1, s0, s1));
     return hipGetLastError();
 }
 
@@ -1755,18 +1768,19 @@ template <int ND, int N>
 hipError_t rho_faces_t(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
+    const int s0 = c.s0, s1 = shot_end(c);
     int ez = 0, ex = 0, ey = 0;
-    for (int s = 0; s < pl.nshot; ++s) {
+    for (int s = s0; s < s1; ++s) {
         const int *b = &pl.rbox[((size_t)it * pl.nshot + s) * 6];
         ez = std::max(ez, b[1] - b[0] + 1);
         ex = std::max(ex, b[3] - b[2] + 1);
         ey = std::max(ey, ND == 3 ? b[5] - b[4] + 1 : 1);
     }
     const int ny = std::max(1, ey);
-    dim3 grid((unsigned)((ez + 63) / 64), (unsigned)((ex + 3) / 4), (unsigned)(pl.nshot * ny));
+    dim3 grid((unsigned)((ez + 63) / 64), (unsigned)((ex + 3) / 4), (unsigned)((s1 - s0) * ny));
     hipLaunchKernelGGL((k_rho_faces<ND, N>), grid, dim3(64, 4, 1), 0, c.st, pl.geom, w.f, w.q,
                        w.acc_r[0], w.acc_r[1], w.acc_r[2],
-                       (const int *)(w.rbox + (size_t)it * pl.nshot * 6), ny);
+                       (const int *)(w.rbox + (size_t)it * pl.nshot * 6), ny, s0);
     return hipGetLastError();
 }
 

@@ -202,6 +202,27 @@ static double box_slab_cells(const Plan &pl, const int *b) {
     return tot;
 }
 
+void rev_iter_bytes(const Plan &pl, int it, int s0, int s1, double out[4]) {
+    const int ns = pl.nshot, nd = pl.nd;
+    double rb0 = 0, rg = 0, ri = 0, rl = 0, maxa = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
+        const int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
+        double va = (double)std::max(0, ab[1] - ab[0]) * std::max(0, ab[3] - ab[2]) *
+                    std::max(0, ab[5] - ab[4]);
+        double vr = (double)(rb[1] - rb[0]) * (rb[3] - rb[2]) * (rb[5] - rb[4]);
+        rb0 += 8.0 * (nd + 1) * va + 16.0 * box_slab_cells(pl, ab) + 8.0 * (nd + 1) * vr;
+        rg += 12.0 * vr;                                    // p~ read, gradient
+        rl += 8.0 * vr;                                     // illumination
+        ri += 12.0 * va;                                    // image
+        maxa = std::max(maxa, std::max(va, vr));
+    }
+    const double restore = pl.g.dr == 1 || it % pl.g.dr == 0 ? 8.0 : 4.0 * (2 * kTaps + 1);
+    rb0 += 4.0 * (nd + 1) * maxa + 8.0 * (pl.rec_off[s1] - pl.rec_off[s0]) +
+           restore * (double)(s1 - s0) * pl.band.B;
+    out[0] = rb0; out[1] = rg; out[2] = ri; out[3] = rl;
+}
+
 void algorithmic_bytes(Plan &pl) {
     const int nt = pl.g.nt, ns = pl.nshot, nd = pl.nd;
     double R = pl.rec_off[ns];
@@ -209,9 +230,7 @@ void algorithmic_bytes(Plan &pl) {
     pl.step_bytes.assign((size_t)pl.nrun * 3, 0.0);
     pl.rev_bytes.assign(pl.adjoint ? (size_t)nt * 4 : 0, 0.0);
     for (int it = 0; it < pl.nrun; ++it) {
-        double maxf = 0, maxa = 0, sb = 0, sv = 0, sp = 0;
-        double rb0 = 0, rg = 0, ri = 0, rl = 0;
-        const bool adj_it = pl.adjoint && it < nt;
+        double maxf = 0, sb = 0, sv = 0, sp = 0;
         for (int s = 0; s < ns; ++s) {
             const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
             double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
@@ -220,18 +239,6 @@ void algorithmic_bytes(Plan &pl) {
             sv += (4.0 + 8.0 * nd) * vf + 8.0 * slab;
             sp += (4.0 * nd + 8.0) * vf + 8.0 * slab;
             maxf = std::max(maxf, vf);
-            if (adj_it) {
-                const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
-                const int *rb = &pl.rbox[((size_t)it * ns + s) * 6];
-                double va = (double)std::max(0, ab[1] - ab[0]) * std::max(0, ab[3] - ab[2]) *
-                            std::max(0, ab[5] - ab[4]);
-                double vr = (double)(rb[1] - rb[0]) * (rb[3] - rb[2]) * (rb[5] - rb[4]);
-                rb0 += 8.0 * (nd + 1) * va + 16.0 * box_slab_cells(pl, ab) + 8.0 * (nd + 1) * vr;
-                rg += 12.0 * vr;                                    // p~ read, gradient
-                rl += 8.0 * vr;                                     // illumination
-                ri += 12.0 * va;                                    // image
-                maxa = std::max(maxa, std::max(va, vr));
-            }
         }
         sb += 4.0 * (nd + 1) * maxf;
         pl.step_bytes[3 * (size_t)it] = sb;
@@ -239,16 +246,38 @@ void algorithmic_bytes(Plan &pl) {
         pl.step_bytes[3 * (size_t)it + 2] = sp + 4.0 * maxf;
         bf += sb + (it < nt ? 8.0 * R : 0.0);
         if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
-        const double restore = pl.g.dr == 1 || it % pl.g.dr == 0 ? 8.0 : 4.0 * (2 * kTaps + 1);
-        if (adj_it) {
-            rb0 += 4.0 * (nd + 1) * maxa + 8.0 * R + restore * (double)ns * pl.band.B;
+        if (pl.adjoint && it < nt) {
             double *q = &pl.rev_bytes[4 * (size_t)it];
-            q[0] = rb0; q[1] = rg; q[2] = ri; q[3] = rl;
-            br += rb0 + rg + ri + rl;
+            rev_iter_bytes(pl, it, 0, ns, q);
+            br += q[0] + q[1] + q[2] + q[3];
         }
     }
     pl.bytes_fwd = bf;
     pl.bytes_rev = pl.adjoint ? br : 0;
+}
+
+std::vector<int> rev_groups(const Plan &pl, double budget, int max_per, bool rho) {
+    const int ns = pl.nshot;
+    int per = ns;
+    if (pl.nd == 2 && ns > 1) {
+        if (max_per > 0) {
+            per = std::min(ns, max_per);
+        } else {
+            // source and adjoint fields, their memory variables, the three accumulators and
+            // (when the pass keeps them) the density face sums of one shot
+            const Geom &g = pl.geom;
+            double fl = 2.0 * (pl.nd + 1) * (double)pl.P + 3.0 * (double)pl.I;
+            for (int a = 0; a < pl.nd; ++a) fl += 4.0 * (double)g.psz[a];
+            if (rho) fl += (double)pl.nd * pl.P;
+            per = std::max(1, std::min(ns, (int)(budget / (4.0 * fl))));
+        }
+        // equal groups: as many as the cap asks for, their sizes differing by one at most
+        const int ng = (ns + per - 1) / per;
+        std::vector<int> off(ng + 1);
+        for (int k = 0; k <= ng; ++k) off[k] = (int)((long long)ns * k / ng);
+        return off;
+    }
+    return {0, ns};
 }
 
 smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double vmin,

@@ -53,7 +53,8 @@ struct BandArg {
     float *buf;         // saved level of shot 0 (nullptr: nothing to do)
     long long stride;   // floats between shots
     int nqb;            // 256-cell blocks per shot
-    int nshot;
+    int nshot;          // shots of the launch
+    int s0 = 0;         // the first of them
 };
 
 // dcal[it][r] = sum over the taps of receiver r of w p (Alg. 2 recording; one tap on a node)
@@ -71,9 +72,10 @@ __device__ __forceinline__ void sample_receiver(const Geom &g, const float *__re
 // 256 takes one cell)
 __device__ __forceinline__ void band_lin(const Geom &g, const Fields &f, const BandArg &ba,
                                          long long lin, int t, int dir, int which) {
-    const int s = (int)(lin / ba.nqb);
-    if (s < ba.nshot)
-        band_cell(g, f, *ba.bd, ba.buf, nullptr, ba.stride, s, (lin % ba.nqb) * 256 + t, dir, which, 0.f);
+    const int j = (int)(lin / ba.nqb);
+    if (j < ba.nshot)
+        band_cell(g, f, *ba.bd, ba.buf, nullptr, ba.stride, ba.s0 + j, (lin % ba.nqb) * 256 + t, dir,
+                  which, 0.f);
 }
 
 }  // namespace smi
