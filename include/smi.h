@@ -167,7 +167,7 @@ typedef enum {
                                 keeps the faster.  Every candidate gives the default's results.
                                 smi_tuning_report tells the last pick.  0: off (default);
                                 2: forget the picks made so far (the switch stays as it was). */
-    SMI_OPT_REV_GROUP = 8    /* 2D reverse passes (Alg. 2 reverse loop) run the loop once per
+    SMI_OPT_REV_GROUP = 8,   /* 2D reverse passes (Alg. 2 reverse loop) run the loop once per
                                 group of consecutive shots: 0 (default) the largest equal groups
                                 whose reverse state (source and adjoint fields, CPML variables,
                                 accumulators) fits 224 MiB, 7/8 of the device's last-level
@@ -175,6 +175,13 @@ typedef enum {
                                 most k shots per group (k >= the shot count: one loop over all
                                 shots).  3D passes and the plain stepper run one loop.  Same
                                 results for every value. */
+    SMI_OPT_FWD_GROUP = 9    /* 2D forward passes of the default (register-blocked) kernels run
+                                the time loop once per group of consecutive shots, as
+                                SMI_OPT_REV_GROUP does for reverse passes: 0 (default) the
+                                largest equal groups whose fields (p, v and the CPML variables)
+                                fit 224 MiB; k > 0 at most k shots per group.  The fused steps
+                                (SMI_OPT_KERNEL 2, 6, 7), 3D passes and the plain stepper run
+                                one loop.  Same results for every value. */
 } smi_option;
 
 /* Text of the autotuner's last pick on this context (candidates, their times per step, the

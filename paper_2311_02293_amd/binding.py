@@ -22,6 +22,7 @@ JOB_FORWARD, JOB_FORWARD_SAVE, JOB_RTM, JOB_GRAD, JOB_BORN = 0, 1, 2, 3, 4
 OPT_KERNEL, OPT_GRAPH, OPT_CHUNK, OPT_TIMING, OPT_TILEMAP, OPT_FAMILY, OPT_REVERSE = 0, 1, 2, 3, 4, 5, 6
 OPT_AUTOTUNE = 7
 OPT_REV_GROUP = 8
+OPT_FWD_GROUP = 9
 
 
 class SmiError(RuntimeError):

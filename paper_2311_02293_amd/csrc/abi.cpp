@@ -70,6 +70,7 @@ struct smi_ctx {
     int opt_chunk = 0;
     int opt_rev = 0;
     int opt_rev_group = 0;      // SMI_OPT_REV_GROUP: 0 by the cache budget, k: at most k shots
+    int opt_fwd_group = 0;      // SMI_OPT_FWD_GROUP: the same for 2D forward passes
     int opt_xcd = 0;
     int opt_family = 1;
     void *last_ws = nullptr;
@@ -239,8 +240,8 @@ smi_status hip_fail(smi_ctx *c, hipError_t e, const char *where) {
 // ---------------------------------------------------------------- captured time loops
 
 constexpr size_t kMaxGraphs = 8;
-// reverse state of one group of shots in a 2D reverse pass: 7/8 of the 256 MB last-level cache
-constexpr double kRevGroupBudget = 224.0 * 1024 * 1024;
+// state of one group of shots in a 2D forward or reverse pass: 7/8 of the 256 MB last-level cache
+constexpr double kGroupBudget = 224.0 * 1024 * 1024;
 
 struct Key {
     std::string b;
@@ -601,92 +602,120 @@ smi_status run_forward(smi_ctx *ctx, const Plan &pl, const Views &w, const float
     const bool timed = ctx->opt_timing > 0 && !c.plain;
     const bool defer = !fused && smi::march_forward(c);
     const size_t state_bytes = sizeof(float) * (size_t)pl.nshot * (size_t)pl.P * (1 + pl.nd);
+    // 2D, register-blocked kernels: the time loop runs once per group of shots whose fields stay
+    // in the last-level cache between the launches of a step (one group when all of them fit);
+    // every shot's arithmetic is the one of a single loop
+    const std::vector<int> fg = pl.nd == 2 && !c.plain && !fused && c.march > 0
+                                    ? smi::fwd_groups(pl, kGroupBudget, ctx->opt_fwd_group)
+                                    : std::vector<int>{0, pl.nshot};
+    // level nt of (p, v) of the current group: from src into dst (same layout, every shot)
+    auto copy_state = [&](float *dst, const float *src, hipStream_t ls) -> hipError_t {
+        if (c.s0 == 0 && smi::shot_end(c) == pl.nshot)
+            return hipMemcpyAsync(dst, src, state_bytes, hipMemcpyDeviceToDevice, ls);
+        const size_t n = (size_t)(smi::shot_end(c) - c.s0) * (size_t)pl.P;
+        for (int k = 0; k <= pl.nd; ++k) {
+            const size_t o = ((size_t)k * pl.nshot + c.s0) * (size_t)pl.P;
+            const hipError_t e = hipMemcpyAsync(dst + o, src + o, sizeof(float) * n,
+                                                hipMemcpyDeviceToDevice, ls);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     auto loop = [&](hipStream_t ls) -> smi_status {
     c.st = ls;
-    for (int it = 0; it < pl.nrun; ++it) {
-        // fused steps alternate between the two buffers: level it lives in cur
-        const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
-        const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
-        // saved levels: on the register-blocked path the p cells of level it ride on this
-        // step's v launch and its v cells rode on the previous step's p launch
-        c.save_p_slot = c.save_v_slot = -1;
-        if (pl.save && it % dr == 0) {
-            // the fused marching step reads level it from cur and carries the whole saved level
-            if (f2d || (defer && it > 0)) c.save_p_slot = it / dr;
-            else HIPCHK(smi::band_save(c, cur, it / dr), "band save");
-        }
-        if (pl.save && defer && (it + 1) % dr == 0 && it + 1 < pl.nrun) c.save_v_slot = (it + 1) / dr;
-        if (timed && it % ctx->opt_timing == 0) {
-            const size_t k = ctx->nsample;
-            while (ctx->events.size() < 4 * (k + 1)) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e), "timing event");
-                ctx->events.push_back(e);
-            }
-            const double *sb = &pl.step_bytes[3 * (size_t)it];
-            // the fused step is one kernel: it carries the step's bytes as its "first" kernel
-            const double row[3] = {sb[0], fused ? sb[0] : sb[1], fused ? 0.0 : sb[2]};
-            ctx->sample_bytes.insert(ctx->sample_bytes.end(), row, row + 3);
-            ctx->sample_nk.push_back(fused ? 1 : 2);
-            ctx->nsample = k + 1;
-            c.ev = &ctx->events[4 * k];
-        }
-        if (f2d) {
-            // receivers of step it - 1 are sampled by this launch from cur (level it)
-            HIPCHK(smi::fwd_step_2d(c, cur, nxt, it), "forward step");
-            c.ev = nullptr;
-            c.ext_it = -1;
-            if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
-            if (it < nt) {
-                c.ext_it = it;
-                c.ext_dcal = dcal;
-            }
-        } else if (fused) {
-            HIPCHK(smi::fwd_step_fused(c, cur, nxt, it), "forward step");
-            c.ev = nullptr;
-            if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
-            if (it < nt) HIPCHK(smi::extract(c, it, dcal, nxt.p), "extract");
-        } else {
-            // the register-blocked kernels sample the receivers of step it inside the v launch
-            // of step it + 1 (the v update leaves p alone); the last one is sampled below
-            HIPCHK(smi::fwd_step(c, it), "forward step");
-            c.ev = nullptr;
-            c.ext_it = -1;
-            if (it < nt) HIPCHK(smi::src_taps(c, it, w.f.p, 1.f), "source");
-            if (it < nt && defer) {
-                c.ext_it = it;
-                c.ext_dcal = dcal;
-            } else if (it < nt) {
-                HIPCHK(smi::extract(c, it, dcal), "extract");
-            }
-        }
-        for (int k = 0; k < nsnap; ++k)
-            if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
-        if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
-            HIPCHK(hipMemcpyAsync(w.fin, nxt.p, state_bytes, hipMemcpyDeviceToDevice, ls), "final copy");
-    }
-    if (c.ext_it >= 0) {
-        // the last sampled step: level ext_it + 1 is in the second buffer after an odd step of
-        // the fused steps
-        const bool second = fused && ((c.ext_it + 1) & 1);
-        HIPCHK(smi::extract(c, c.ext_it, dcal, second ? w.f2.p : w.f.p), "extract");
+    for (size_t gi = 0; gi + 1 < fg.size(); ++gi) {
+        c.s0 = fg[gi];
+        c.s1 = fg[gi + 1];
         c.ext_it = -1;
+        for (int it = 0; it < pl.nrun; ++it) {
+            // fused steps alternate between the two buffers: level it lives in cur
+            const smi::Fields &cur = fused && (it & 1) ? w.f2 : w.f;
+            const smi::Fields &nxt = fused && !(it & 1) ? w.f2 : w.f;
+            // saved levels: on the register-blocked path the p cells of level it ride on this
+            // step's v launch and its v cells rode on the previous step's p launch
+            c.save_p_slot = c.save_v_slot = -1;
+            if (pl.save && it % dr == 0) {
+                // the fused marching step reads level it from cur and carries the whole saved level
+                if (f2d || (defer && it > 0)) c.save_p_slot = it / dr;
+                else HIPCHK(smi::band_save(c, cur, it / dr), "band save");
+            }
+            if (pl.save && defer && (it + 1) % dr == 0 && it + 1 < pl.nrun) c.save_v_slot = (it + 1) / dr;
+            if (timed && it % ctx->opt_timing == 0) {
+                const size_t k = ctx->nsample;
+                while (ctx->events.size() < 4 * (k + 1)) {
+                    hipEvent_t e;
+                    HIPCHK(hipEventCreate(&e), "timing event");
+                    ctx->events.push_back(e);
+                }
+                double sb[3];
+                smi::step_bytes_of(pl, it, c.s0, smi::shot_end(c), sb);
+                // the fused step is one kernel: it carries the step's bytes as its "first" kernel
+                const double row[3] = {sb[0], fused ? sb[0] : sb[1], fused ? 0.0 : sb[2]};
+                ctx->sample_bytes.insert(ctx->sample_bytes.end(), row, row + 3);
+                ctx->sample_nk.push_back(fused ? 1 : 2);
+                ctx->nsample = k + 1;
+                c.ev = &ctx->events[4 * k];
+            }
+            if (f2d) {
+                // receivers of step it - 1 are sampled by this launch from cur (level it)
+                HIPCHK(smi::fwd_step_2d(c, cur, nxt, it), "forward step");
+                c.ev = nullptr;
+                c.ext_it = -1;
+                if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
+                if (it < nt) {
+                    c.ext_it = it;
+                    c.ext_dcal = dcal;
+                }
+            } else if (fused) {
+                HIPCHK(smi::fwd_step_fused(c, cur, nxt, it), "forward step");
+                c.ev = nullptr;
+                if (it < nt) HIPCHK(smi::src_taps(c, it, nxt.p, 1.f), "source");
+                if (it < nt) HIPCHK(smi::extract(c, it, dcal, nxt.p), "extract");
+            } else {
+                // the register-blocked kernels sample the receivers of step it inside the v launch
+                // of step it + 1 (the v update leaves p alone); the last one is sampled below
+                HIPCHK(smi::fwd_step(c, it), "forward step");
+                c.ev = nullptr;
+                c.ext_it = -1;
+                if (it < nt) HIPCHK(smi::src_taps(c, it, w.f.p, 1.f), "source");
+                if (it < nt && defer) {
+                    c.ext_it = it;
+                    c.ext_dcal = dcal;
+                } else if (it < nt) {
+                    HIPCHK(smi::extract(c, it, dcal), "extract");
+                }
+            }
+            for (int k = 0; k < nsnap; ++k)
+                if (snap_it[k] == it + 1) HIPCHK(smi::snap(c, nxt, snaps, k, nsnap), "snap");
+            if (w.fin && it + 1 == nt)   // level nt: the reverse pass starts from here
+                HIPCHK(copy_state(w.fin, nxt.p, ls), "final copy");
+        }
+        if (c.ext_it >= 0) {
+            // the last sampled step: level ext_it + 1 is in the second buffer after an odd step of
+            // the fused steps
+            const bool second = fused && ((c.ext_it + 1) & 1);
+            HIPCHK(smi::extract(c, c.ext_it, dcal, second ? w.f2.p : w.f.p), "extract");
+            c.ext_it = -1;
+        }
+        if (fused && (pl.nrun & 1)) {
+            // the final level is in the second buffer; the reverse pass works on the first
+            HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, ls),
+                   "final state copy");
+        }
+        if (pl.save && dr > 1) {
+            HIPCHK(smi::band_save(c, w.f, pl.nsave - 1), "band save (last level)");
+            HIPCHK(copy_state(w.f.p, w.fin, ls), "final restore");
+        }
     }
-    if (fused && (pl.nrun & 1)) {
-        // the final level is in the second buffer; the reverse pass works on the first
-        HIPCHK(hipMemcpyAsync(w.f.p, w.f2.p, field_bytes(pl), hipMemcpyDeviceToDevice, ls),
-               "final state copy");
-    }
-    if (pl.save && dr > 1) {
-        HIPCHK(smi::band_save(c, w.f, pl.nsave - 1), "band save (last level)");
-        HIPCHK(hipMemcpyAsync(w.f.p, w.fin, state_bytes, hipMemcpyDeviceToDevice, ls), "final restore");
-    }
+    c.s0 = 0;
+    c.s1 = -1;
     return SMI_OK;
     };
     if (ctx->opt_graph && !timed) {
         Key k = plan_key('F', pl, c);
         k.put(fused).put(w.status).put(stf).put(dcal).put(snaps).put(nsnap);
         for (int q = 0; q < nsnap; ++q) k.put(snap_it[q]);
+        for (int v : fg) k.put(v);
         s = graph_run(ctx, k.b, st, loop);
     } else {
         s = loop(st);
@@ -739,7 +768,7 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
     // last-level cache between its launches; every shot's arithmetic is the same as in one
     // loop over all shots, and the outputs are reduced per shot afterwards
     const std::vector<int> rg = c.plain ? std::vector<int>{0, pl.nshot}
-                                        : smi::rev_groups(pl, kRevGroupBudget, ctx->opt_rev_group, want_r);
+                                        : smi::rev_groups(pl, kGroupBudget, ctx->opt_rev_group, want_r);
     const bool timed = ctx->opt_timing > 0;
     // 2D reverse form not yet tuned for this shape: sampled iterations of this call alternate
     // the two forms (bitwise the same results), timed by events read on the next call
@@ -906,6 +935,7 @@ smi_status smi_set_option(smi_ctx *ctx, int option, int value) {
     if (option == SMI_OPT_CHUNK && value >= 0 && value <= 9999) { ctx->opt_chunk = value; return SMI_OK; }
     if (option == SMI_OPT_REVERSE && value >= 0 && value <= 2) { ctx->opt_rev = value; return SMI_OK; }
     if (option == SMI_OPT_REV_GROUP && value >= 0) { ctx->opt_rev_group = value; return SMI_OK; }
+    if (option == SMI_OPT_FWD_GROUP && value >= 0) { ctx->opt_fwd_group = value; return SMI_OK; }
     if (option == SMI_OPT_TILEMAP && value >= 0 && value <= 2) { ctx->opt_xcd = value; return SMI_OK; }
     if (option == SMI_OPT_FAMILY && (value == 1 || value == 2)) { ctx->opt_family = value; return SMI_OK; }
     if (option == SMI_OPT_AUTOTUNE && (value == 0 || value == 1 || value == 2)) {

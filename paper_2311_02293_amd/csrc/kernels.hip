@@ -1233,6 +1233,20 @@ hipError_t fs_launch(const Plan &pl, hipStream_t st, float *f, int mode, int s0,
     return hipGetLastError();
 }
 
+// the receivers of the context's shots: a view of the flattened receiver table, in which the
+// receivers of a shot are consecutive and follow those of the shot before
+Recv group_recv(const StepCtx &c) {
+    Recv r = c.w->recv;
+    const Plan &pl = *c.pl;
+    const int r0 = pl.rec_off[c.s0], r1 = pl.rec_off[shot_end(c)];
+    r.R = r1 - r0;
+    r.shot += r0;
+    r.obase += r0;
+    r.stride += r0;
+    r.toff += r0;
+    return r;
+}
+
 // launch geometry of one step over a box table row: max extents over the shots [s0, s1)
 struct Launch {
     dim3 grid, block;
@@ -1338,15 +1352,17 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     // the forward half steps keep the shot-outer order (the shots' boxes differ while the
     // source fields grow, and the p update is compiled without the shot-inner order)
-    MLaunch L = march_launch(pl, pl.fbox, it, 0, pl.nshot, CM, c.xcd, c.ymap, false);
-    const bool ext = c.ext_it >= 0 && w.recv.R > 0;
+    const int g0 = c.s0, g1 = shot_end(c), gn = g1 - g0;
+    MLaunch L = march_launch(pl, pl.fbox, it, g0, g1, CM, c.xcd, c.ymap, false);
+    const Recv rv = group_recv(c);
+    const bool ext = c.ext_it >= 0 && rv.R > 0;
     if (L.empty) {
         // nothing to update: the carried work runs on its own
         if (c.save_p_slot >= 0) SMI_TRY(band_save_part(c, w.f, c.save_p_slot, 0));
         if (c.save_v_slot >= 0) SMI_TRY(band_save_part(c, w.f, c.save_v_slot, 1));
         return ext ? extract(c, c.ext_it, c.ext_dcal) : hipSuccess;
     }
-    const Ext ex{w.recv, c.ext_dcal, ext ? c.ext_it : -1, w.status};
+    const Ext ex{rv, c.ext_dcal, ext ? c.ext_it : -1, w.status};
     dim3 gv = L.grid;
     if (ext) gv.z += L.mg.nmarch;
     const int s0 = ext ? -1 : 0;
@@ -1355,40 +1371,40 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     const int nqb = (int)((pl.band.B + 255) / 256);
     auto band_planes = [&](const dim3 &gr) {
         const long long per = (long long)gr.x * gr.y;
-        return (unsigned)(((long long)pl.nshot * nqb + per - 1) / per);
+        return (unsigned)(((long long)gn * nqb + per - 1) / per);
     };
     const long long sstride = (long long)pl.nsave * pl.band.B;
     BandArg svp{}, svv{};
     int zp = 0, zv = 0;
     if (c.save_p_slot >= 0) {
-        svp = BandArg{w.bdesc, w.bands + (size_t)c.save_p_slot * pl.band.B, sstride, nqb, pl.nshot};
+        svp = BandArg{w.bdesc, w.bands + (size_t)c.save_p_slot * pl.band.B, sstride, nqb, gn, g0};
         zp = (int)gv.z;
         gv.z += band_planes(gv);
     }
     dim3 gp = L.grid;
     if (c.save_v_slot >= 0) {
-        svv = BandArg{w.bdesc, w.bands + (size_t)c.save_v_slot * pl.band.B, sstride, nqb, pl.nshot};
+        svv = BandArg{w.bdesc, w.bands + (size_t)c.save_v_slot * pl.band.B, sstride, nqb, gn, g0};
         zv = (int)gp.z;
         gp.z += band_planes(gp);
     }
     if (c.ev) {
         hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, c.ev[0], c.ev[1],
                               0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex, svp, zp);
-        SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
+        SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, g0, g1));
         hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                               (const float *)nullptr, (float *)nullptr, svv, zv);
-        return fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
+        return fs_launch(pl, c.st, w.f.p, 1, g0, g1);
     }
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, pl.geom, w.f, w.model,
                        w.cpml, box, s0, L.mg, ex, svp, zp);
-    SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, 0, pl.nshot));
+    SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, g0, g1));
     hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
                        pl.g.nt, it, (const float *)nullptr, (float *)nullptr, svv, zv);
     hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.f.p, 1, 0, pl.nshot);
+    return e != hipSuccess ? e : fs_launch(pl, c.st, w.f.p, 1, g0, g1);
 }
 
 // adjoint half steps with the marching kernels (image with the source field when asked)
@@ -1628,9 +1644,10 @@ hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {
 
 hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p) {
     const Views &w = *c.w;
-    if (w.recv.R == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_extract, dim3(blocks(w.recv.R)), dim3(256), 0, c.st, c.pl->geom,
-                       p ? p : (const float *)w.f.p, w.recv, dcal, it, w.status);
+    const Recv rv = group_recv(c);
+    if (rv.R == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3(blocks(rv.R)), dim3(256), 0, c.st, c.pl->geom,
+                       p ? p : (const float *)w.f.p, rv, dcal, it, w.status);
     return hipGetLastError();
 }
 
@@ -1656,9 +1673,9 @@ hipError_t band_save_part(const StepCtx &c, const Fields &f, int slot, int which
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     long long ss = (long long)pl.nsave * pl.band.B;
-    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
-                       f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
-                       ss, 0, 0, which, 0.f);
+    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), shot_end(c) - c.s0), dim3(256), 0, c.st,
+                       pl.geom, f, pl.band, w.bands + (size_t)slot * pl.band.B,
+                       (const float *)nullptr, ss, c.s0, 0, which, 0.f);
     return hipGetLastError();
 }
 
@@ -1666,9 +1683,9 @@ hipError_t band_save(const StepCtx &c, const Fields &f, int slot) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     long long ss = (long long)pl.nsave * pl.band.B;
-    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), pl.nshot), dim3(256), 0, c.st, pl.geom,
-                       f, pl.band, w.bands + (size_t)slot * pl.band.B, (const float *)nullptr,
-                       ss, 0, 0, 2, 0.f);
+    hipLaunchKernelGGL(k_band, dim3(blocks(pl.band.B), shot_end(c) - c.s0), dim3(256), 0, c.st,
+                       pl.geom, f, pl.band, w.bands + (size_t)slot * pl.band.B,
+                       (const float *)nullptr, ss, c.s0, 0, 2, 0.f);
     return hipGetLastError();
 }
 

@@ -223,28 +223,33 @@ void rev_iter_bytes(const Plan &pl, int it, int s0, int s1, double out[4]) {
     out[0] = rb0; out[1] = rg; out[2] = ri; out[3] = rl;
 }
 
+void step_bytes_of(const Plan &pl, int it, int s0, int s1, double row[3]) {
+    const int ns = pl.nshot, nd = pl.nd;
+    double maxf = 0, sb = 0, sv = 0, sp = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
+        double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
+        const double slab = box_slab_cells(pl, fb);
+        sb += 8.0 * (nd + 1) * vf + 16.0 * slab;
+        sv += (4.0 + 8.0 * nd) * vf + 8.0 * slab;
+        sp += (4.0 * nd + 8.0) * vf + 8.0 * slab;
+        maxf = std::max(maxf, vf);
+    }
+    row[0] = sb + 4.0 * (nd + 1) * maxf;
+    row[1] = sv + 4.0 * nd * maxf;
+    row[2] = sp + 4.0 * maxf;
+}
+
 void algorithmic_bytes(Plan &pl) {
-    const int nt = pl.g.nt, ns = pl.nshot, nd = pl.nd;
+    const int nt = pl.g.nt, ns = pl.nshot;
     double R = pl.rec_off[ns];
     double bf = 0, br = 0;
     pl.step_bytes.assign((size_t)pl.nrun * 3, 0.0);
     pl.rev_bytes.assign(pl.adjoint ? (size_t)nt * 4 : 0, 0.0);
     for (int it = 0; it < pl.nrun; ++it) {
-        double maxf = 0, sb = 0, sv = 0, sp = 0;
-        for (int s = 0; s < ns; ++s) {
-            const int *fb = &pl.fbox[((size_t)it * ns + s) * 6];
-            double vf = (double)(fb[1] - fb[0]) * (fb[3] - fb[2]) * (fb[5] - fb[4]);
-            const double slab = box_slab_cells(pl, fb);
-            sb += 8.0 * (nd + 1) * vf + 16.0 * slab;
-            sv += (4.0 + 8.0 * nd) * vf + 8.0 * slab;
-            sp += (4.0 * nd + 8.0) * vf + 8.0 * slab;
-            maxf = std::max(maxf, vf);
-        }
-        sb += 4.0 * (nd + 1) * maxf;
-        pl.step_bytes[3 * (size_t)it] = sb;
-        pl.step_bytes[3 * (size_t)it + 1] = sv + 4.0 * nd * maxf;
-        pl.step_bytes[3 * (size_t)it + 2] = sp + 4.0 * maxf;
-        bf += sb + (it < nt ? 8.0 * R : 0.0);
+        double *row = &pl.step_bytes[3 * (size_t)it];
+        step_bytes_of(pl, it, 0, ns, row);
+        bf += row[0] + (it < nt ? 8.0 * R : 0.0);
         if (pl.save && it % pl.g.dr == 0) bf += 8.0 * (double)ns * pl.band.B;
         if (pl.adjoint && it < nt) {
             double *q = &pl.rev_bytes[4 * (size_t)it];
@@ -256,28 +261,57 @@ void algorithmic_bytes(Plan &pl) {
     pl.bytes_rev = pl.adjoint ? br : 0;
 }
 
+// equal groups of at most per shots (sizes differing by one at most)
+static std::vector<int> equal_groups(int ns, int per) {
+    const int ng = (ns + per - 1) / per;
+    std::vector<int> off(ng + 1);
+    for (int k = 0; k <= ng; ++k) off[k] = (int)((long long)ns * k / ng);
+    return off;
+}
+
+// mean over the steps [0, nsteps) of one shot's box volume, averaged over the shots
+static double mean_box_cells(const Plan &pl, const std::vector<int> &tab, int nsteps) {
+    const int ns = pl.nshot;
+    double v = 0;
+    for (int it = 0; it < nsteps; ++it)
+        for (int s = 0; s < ns; ++s) {
+            const int *b = &tab[((size_t)it * ns + s) * 6];
+            v += (double)std::max(0, b[1] - b[0]) * std::max(0, b[3] - b[2]) * std::max(0, b[5] - b[4]);
+        }
+    return nsteps > 0 ? v / ((double)nsteps * ns) : 0.0;
+}
+
+// memory variables of one shot that a box of `cells` cells touches, scaled from the slabs'
+// share of the padded grid
+static double psi_cells(const Plan &pl, double cells) {
+    double all = 0;
+    for (int a = 0; a < pl.nd; ++a) all += (double)pl.geom.psz[a];
+    return all * cells / (double)((long long)pl.M[0] * pl.M[1] * pl.M[2]);
+}
+
+std::vector<int> fwd_groups(const Plan &pl, double budget, int max_per) {
+    const int ns = pl.nshot;
+    if (pl.nd != 2 || ns <= 1) return {0, ns};
+    if (max_per > 0) return equal_groups(ns, std::min(ns, max_per));
+    // the fields one shot's computing box touches on average over the schedule, with their
+    // memory variables (the model is shared)
+    const double vf = mean_box_cells(pl, pl.fbox, pl.nrun);
+    const double fl = (pl.nd + 1) * vf + 2.0 * psi_cells(pl, vf);
+    return equal_groups(ns, std::max(1, std::min(ns, (int)(budget / (4.0 * fl)))));
+}
+
 std::vector<int> rev_groups(const Plan &pl, double budget, int max_per, bool rho) {
     const int ns = pl.nshot;
-    int per = ns;
-    if (pl.nd == 2 && ns > 1) {
-        if (max_per > 0) {
-            per = std::min(ns, max_per);
-        } else {
-            // source and adjoint fields, their memory variables, the three accumulators and
-            // (when the pass keeps them) the density face sums of one shot
-            const Geom &g = pl.geom;
-            double fl = 2.0 * (pl.nd + 1) * (double)pl.P + 3.0 * (double)pl.I;
-            for (int a = 0; a < pl.nd; ++a) fl += 4.0 * (double)g.psz[a];
-            if (rho) fl += (double)pl.nd * pl.P;
-            per = std::max(1, std::min(ns, (int)(budget / (4.0 * fl))));
-        }
-        // equal groups: as many as the cap asks for, their sizes differing by one at most
-        const int ng = (ns + per - 1) / per;
-        std::vector<int> off(ng + 1);
-        for (int k = 0; k <= ng; ++k) off[k] = (int)((long long)ns * k / ng);
-        return off;
-    }
-    return {0, ns};
+    if (pl.nd != 2 || ns <= 1) return {0, ns};
+    if (max_per > 0) return equal_groups(ns, std::min(ns, max_per));
+    // on average over the reverse steps: the source field and the accumulators over the
+    // reconstruction region, the adjoint field over the adjoint box, their memory variables,
+    // and (when the pass keeps them) the density face sums
+    const int nt = pl.g.nt;
+    const double vr = mean_box_cells(pl, pl.rbox, nt), va = mean_box_cells(pl, pl.abox, nt);
+    double fl = (pl.nd + 1) * (vr + va) + 3.0 * vr + 2.0 * (psi_cells(pl, vr) + psi_cells(pl, va));
+    if (rho) fl += (double)pl.nd * vr;
+    return equal_groups(ns, std::max(1, std::min(ns, (int)(budget / (4.0 * fl)))));
 }
 
 smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double vmin,

@@ -169,14 +169,21 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                      double vmax, Plan &pl, std::string &err);
 smi_status check_grid(const smi_grid *g, double vmin, double vmax, std::string &err);
 void algorithmic_bytes(Plan &pl);
+// algorithmic bytes of forward step it over the shots [s0, s1), as a row of Plan::step_bytes
+void step_bytes_of(const Plan &pl, int it, int s0, int s1, double row[3]);
+// shot groups of a 2D forward pass of the register-blocked kernels: the fields one group's
+// computing boxes touch on average over the schedule (with their memory variables) within
+// `budget` bytes; max_per > 0 caps a group instead
+std::vector<int> fwd_groups(const Plan &pl, double budget, int max_per);
 // algorithmic bytes of reverse iteration it over the shots [s0, s1): out[0] the adjoint and
 // reconstruction steps with band restores, adjoint sources and the model read once, out[1] the
 // gradient sum, out[2] the image sum, out[3] the illumination sum
 void rev_iter_bytes(const Plan &pl, int it, int s0, int s1, double out[4]);
 // shot groups of a 2D reverse pass: boundaries 0 = g[0] < g[1] < ... = nshot, so that the
-// reverse state of one group (source and adjoint fields, memory variables, accumulators) stays
-// within `budget` bytes (one group when it all fits, or outside 2D; rho: the pass keeps the
-// density face sums); max_per > 0 caps a group at that many shots instead
+// reverse state one group touches on average over the reverse steps (source field and
+// accumulators over the reconstruction region, adjoint field over the adjoint box, memory
+// variables) stays within `budget` bytes (one group when it all fits, or outside 2D; rho: the
+// pass keeps the density face sums); max_per > 0 caps a group at that many shots instead
 std::vector<int> rev_groups(const Plan &pl, double budget, int max_per, bool rho);
 void cpml_profiles(const Plan &pl, int axis, std::vector<float> &a_i, std::vector<float> &b_i,
                    std::vector<float> &a_h, std::vector<float> &b_h);
@@ -243,8 +250,9 @@ struct StepCtx {
     // of step it (-1: none)
     int save_p_slot = -1;
     int save_v_slot = -1;
-    // reverse loop: the shots [s0, s1) its launches cover (s1 < 0: every shot).  A 2D reverse
-    // pass may run its shots in groups, one reverse loop per group (see rev_groups)
+    // the shots [s0, s1) the launches of a time loop cover (s1 < 0: every shot): 2D forward and
+    // reverse passes may run their shots in groups, one time loop per group (fwd_groups,
+    // rev_groups)
     int s0 = 0;
     int s1 = -1;
 };

@@ -151,14 +151,15 @@ def test_grouped_reverse_as_graph_equals_eager(ctx):
 
 
 def test_automatic_groups_of_a_large_gradient_match_the_oracle(ctx):
-    """A 2D gradient whose reverse state (32 shots of 300 x 900, about 13 MB each) exceeds the
-    224 MiB group budget runs its reverse loop in automatic groups; it equals the one-loop
-    result bitwise, and two of its shots' gradients, run alone, agree with the oracle (observed
-    data: 0.9 times the oracle's data of the true model)."""
+    """A 2D gradient whose reverse state (32 shots of 300 x 900 with the computing box off,
+    about 13 MB each) exceeds the 224 MiB group budget runs its reverse loop in automatic
+    groups; it equals the one-loop result bitwise, and two of its shots' gradients, run alone,
+    agree with the oracle (observed data: 0.9 times the oracle's data of the true model)."""
     import torch
     from oracle import oracle as O
     from paper_2311_02293_amd import binding as B
     job = I.config3(nt=300, nshot=32)
+    job.grid.box = 0
     job = with_bounds(job, [job.extra["vp_true"]])
     vp, rho, stf = dev(job)
     d = _dobs(ctx, job)

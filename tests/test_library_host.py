@@ -106,7 +106,7 @@ def test_binding_constants_match_the_header():
     for short in ("FORWARD", "FORWARD_SAVE", "RTM", "GRAD", "BORN"):
         assert decl["SMI_JOB_" + short] == getattr(B, "JOB_" + short), short
     for short in ("KERNEL", "GRAPH", "CHUNK", "TIMING", "TILEMAP", "FAMILY", "REVERSE", "AUTOTUNE",
-                  "REV_GROUP"):
+                  "REV_GROUP", "FWD_GROUP"):
         assert decl["SMI_OPT_" + short] == getattr(B, "OPT_" + short), short
     body = txt[txt.index("typedef struct {", txt.index("smi_grid") - 2000):txt.index("} smi_grid;")]
     fields = re.findall(r"\b(?:int|double)\s+([a-z0-9_, ]+);", body)
