@@ -170,7 +170,8 @@ typedef enum {
     SMI_OPT_REV_GROUP = 8,   /* 2D reverse passes (Alg. 2 reverse loop) run the loop once per
                                 group of consecutive shots: 0 (default) the largest equal groups
                                 whose reverse state (source and adjoint fields, CPML variables,
-                                accumulators) fits 224 MiB, 7/8 of the device's last-level
+                                accumulators), as their computing boxes touch it on average over
+                                the reverse steps, fits 224 MiB, 7/8 of the device's last-level
                                 cache, so that each group's launches keep it there; k > 0 at
                                 most k shots per group (k >= the shot count: one loop over all
                                 shots).  3D passes and the plain stepper run one loop.  Same
@@ -178,7 +179,8 @@ typedef enum {
     SMI_OPT_FWD_GROUP = 9    /* 2D forward passes of the default (register-blocked) kernels run
                                 the time loop once per group of consecutive shots, as
                                 SMI_OPT_REV_GROUP does for reverse passes: 0 (default) the
-                                largest equal groups whose fields (p, v and the CPML variables)
+                                largest equal groups whose fields (p, v and the CPML variables),
+                                as their computing boxes touch them on average over the steps,
                                 fit 224 MiB; k > 0 at most k shots per group.  The fused steps
                                 (SMI_OPT_KERNEL 2, 6, 7), 3D passes and the plain stepper run
                                 one loop.  Same results for every value. */
