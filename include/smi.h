@@ -154,8 +154,9 @@ typedef enum {
     SMI_OPT_REVERSE = 6,     /* 2D reverse step of the default kernels: 0 (default) two launches
                                 per step (reconstruction of p with the adjoint v update and the p
                                 bands; then reconstruction of v with the adjoint p update and the
-                                v bands) for batches of up to 8 M padded cells, five launches
-                                above; 1 always two; 2 always five.  Same results. */
+                                v bands) when the shots of a reverse loop (SMI_OPT_REV_GROUP)
+                                hold up to 8 M padded cells, five launches above; 1 always two;
+                                2 always five.  Same results. */
     SMI_OPT_AUTOTUNE = 7,    /* 1: the library picks the kernels per plan shape (geometry, shots,
                                 nt, box, dr, job kind) by timing them on the device: the first
                                 forward pass of a shape times every forward candidate (kernel

@@ -842,7 +842,7 @@ __global__ __launch_bounds__(256) void k_march_recon_v(Geom g, Fields f, Model m
 
 // ---------------------------------------------------------------- saved boundaries (Sec. 4.2)
 
-// one lane per band cell; blockIdx.y = shot
+// one lane per band cell; shot shot0 + blockIdx.y
 __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, float *buf,
                                               const float *buf2, long long shot_stride, int shot0,
                                               int dir, int which, float wt) {
@@ -933,7 +933,7 @@ __global__ __launch_bounds__(256) void k_extract(Geom g, const float *__restrict
 }
 
 // p += sign (dt / dV) stf[s][it] w_t on the nodes of the operators of the sources that spread
-// over several nodes (blockIdx.y = shot; one-tap sources have src_cell >= 0 and are injected
+// over several nodes (shot shot0 + blockIdx.y; one-tap sources have src_cell >= 0 and are injected
 // inside the p kernels)
 __global__ __launch_bounds__(256) void k_src_taps(Geom g, float *p, const long long *__restrict__ src_cell,
                                                   const int *__restrict__ toff,
@@ -957,7 +957,8 @@ __global__ __launch_bounds__(256) void k_scale(const float *__restrict__ in, flo
 // p~ += kappa sum_r w_r G[it][r] on every node that receiver operators touch (eq. 8 source in
 // the scaled adjoint variable; the transpose of the sampling).  One lane per distinct node sums
 // its contributions in the plan's fixed order (ascending receiver), so overlapping operators and
-// co-located receivers give the same bits on every run.
+// co-located receivers give the same bits on every run.  Nodes of shots outside [s0, s1) are
+// left to the reverse loop of their own shot group.
 __global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *__restrict__ kdt,
                                                 Recv rv, Inj in, const float *__restrict__ G,
                                                 int it, float inv_dt, int s0, int s1) {
@@ -1203,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_free_surface(Geom g, float *f, int shot
         for (int k = 1; k <= g.N; ++k) c[-k] = -c[k];
 }
 
-// interior p of every shot -> snaps[s][k][...]
+// interior p of shot shot0 + blockIdx.y -> snaps[s][k][...]
 __global__ __launch_bounds__(256) void k_snap(Geom g, const float *__restrict__ p, float *snaps,
                                               int k, int nsnap, int shot0) {
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1550,9 +1551,10 @@ template <int ND, int N>
 hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
-    // Batches up to 8 M padded cells take the two-launch step (10 % faster on 8 shots of
-    // 300 x 900, 30 % less host time on one); above, where the host keeps ahead and the two
-    // orders measure the same, the five-launch order keeps consecutive kernels on one field.
+    // Launches over up to 8 M padded cells (the shots of the reverse loop's group) take the
+    // two-launch step (10 % faster on 8 shots of 300 x 900, 30 % less host time on one);
+    // above, where the host keeps ahead and the two orders measure the same, the five-launch
+    // order keeps consecutive kernels on one field.
     constexpr double kPairCells = 8.0e6;
     const int sa = c.s0, se = shot_end(c);
     if constexpr (ND == 2) {
