@@ -103,7 +103,10 @@ typedef struct {
 typedef enum {
     SMI_OPT_KERNEL = 0,      /* 0 (default): register-blocked half-step kernels, every shot of
                                 the batch in one launch per half step, 4 cells per lane and
-                                the XCD-contiguous order in 2D, 2 cells per lane in 3D;
+                                the XCD-contiguous order in 2D; in 3D the forward and adjoint
+                                half steps of 5 (marching along y, SMI_OPT_CHUNK 432) where
+                                they apply, register-blocked kernels with 2 cells per lane
+                                elsewhere;
                                 1: plain stepper -- one shot per launch, one cell per lane;
                                 2: fused 2D step (v and p in one marching kernel,
                                 double-buffered levels); 3: register-blocked kernels with
@@ -112,7 +115,7 @@ typedef enum {
                                 lane sweep kernels in the order of SMI_OPT_TILEMAP; 5: as 0, and
                                 in 3D half steps that march along y (SMI_OPT_CHUNK = 100 BX + CY:
                                 BX = 4 or 8 x-columns of 64 z cells per wavefront, CY = 16,
-                                32 or 64 y-planes per workgroup, 32 at order 4; 0: 832); 6: as 0,
+                                32 or 64 y-planes per workgroup, 32 at order 4; 0: 432); 6: as 0,
                                 and in 2D forward passes the fused marching step (v and p of
                                 every shot in one launch, levels in two buffers, SMI_OPT_CHUNK
                                 = 100 D + C: runs of C = 32 or 64 columns per wavefront, loads
@@ -125,7 +128,7 @@ typedef enum {
                                 y-stencil in registers, the plane's z- and x-halo staged in
                                 LDS; SMI_OPT_CHUNK = CY + 1000 F: CY = 16, 32 or 64 y-planes per
                                 workgroup, tile form F = 0: 2 x-cells per lane x 8 wavefronts,
-                                1: 4 x 8, 2: 2 x 16; 0 selects 2016).  With a free surface, 2, 6, 7,
+                                1: 4 x 8, 2: 2 x 16; 0 selects 32).  With a free surface, 2, 6, 7,
                                 8 and the y-marching kernels of 5 give way to the kernels of 0. */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and

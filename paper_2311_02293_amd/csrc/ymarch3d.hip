@@ -27,11 +27,20 @@ template <int BX>
 __device__ __forceinline__ Tile tile_of(const Geom &g, const int *__restrict__ box, int nstrip,
                                         int cy) {
     Tile t;
-    t.s = (int)blockIdx.z / nstrip;
-    const int strip = (int)blockIdx.z % nstrip;
+    // the grid's blocks in XCD-contiguous ranges (consecutive blocks go to different XCDs),
+    // z-tile fastest, then x-tile, y-strip and shot: the workgroups resident on one XCD cover a
+    // block of neighbouring tiles of one strip, whose halo planes they read from the same L2
+    const int G = (int)(gridDim.x * gridDim.y * gridDim.z);
+    const int L = xcd_remap((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), G);
+    const int zt = L % (int)gridDim.x;
+    int r = L / (int)gridDim.x;
+    const int xt = r % (int)gridDim.y;
+    r /= (int)gridDim.y;
+    t.s = r / nstrip;
+    const int strip = r % nstrip;
     const int *b = box + 6 * t.s;
-    t.z0 = zalign(b[0]) + (int)blockIdx.x * 64;
-    t.x0 = b[2] + (int)blockIdx.y * BX;
+    t.z0 = zalign(b[0]) + zt * 64;
+    t.x0 = b[2] + xt * BX;
     t.ylo = b[4] + strip * cy;
     t.yhi = min(t.ylo + cy, b[5]);
     t.z = t.z0 + (int)threadIdx.x;

@@ -61,13 +61,17 @@ struct YPTile {
 template <int TX>
 __device__ __forceinline__ YPTile yp_tile(const int *__restrict__ box, const YPMap &mp, int cy) {
     YPTile t;
+    // tiles in XCD-contiguous ranges, z-tile fastest, then x-tile, y-strip and shot: the
+    // workgroups resident on one XCD at a time cover a block of neighbouring tiles of one strip,
+    // so the halo rows and columns one reads are the planes its neighbours read as well, from
+    // the same L2
     const int L = xcd_remap((int)blockIdx.x, mp.ntile);
-    t.s = L % mp.nshot;
-    int r = L / mp.nshot;
-    const int strip = r % mp.nstrip;
-    r /= mp.nstrip;
+    const int zt = L % mp.nzt;
+    int r = L / mp.nzt;
     const int xt = r % mp.nxt;
-    const int zt = r / mp.nxt;
+    r /= mp.nxt;
+    const int strip = r % mp.nstrip;
+    t.s = r / mp.nstrip;
     const int *b = box + 6 * t.s;
     t.z0 = zalign(b[0]) + 64 * zt;
     t.x0 = b[2] + TX * xt;

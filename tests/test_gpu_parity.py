@@ -496,7 +496,7 @@ def test_graph_replays_match_eager(ctx, variant):
         ctx.set_option(B.OPT_GRAPH, 0)
 
 
-@pytest.mark.parametrize("code", [832, 416, 464, 816])
+@pytest.mark.parametrize("code", [432, 832, 416, 464, 816])
 def test_y_march_3d_matches_sweep_kernels(ctx, code):
     """3D half steps marching along y (register window along y, LDS plane tiles for z and x):
     forward data, FWI gradient and RTM image agree with the one-cell-per-lane sweep kernels to
