@@ -148,8 +148,10 @@ typedef enum {
     SMI_OPT_TILEMAP = 4,     /* tile order of SMI_OPT_KERNEL 3 and 4: 0 plain (z-block fastest,
                                 then x-block); 1 each of the 8 XCDs takes a contiguous range of
                                 x-blocks, so tiles that share halos share an L2; 2 (3D, kernel
-                                3) each XCD takes a contiguous range of tiles ordered y-strip
-                                fastest, so a tile's y-neighbours run just before it there */
+                                3) each XCD takes a contiguous range of tiles ordered z-block
+                                fastest, then x-group, y-strip and shot, so the tiles resident
+                                on one XCD are neighbours that read the same halo planes (the
+                                order of the default's 3D register-blocked kernels) */
     SMI_OPT_FAMILY = 5,      /* parametrisation of the gradients (Sec. 2.2): 1 (default) (Vp, rho):
                                 grad_vp = dJ/dVp at fixed rho, grad_rho = dJ/drho at fixed Vp;
                                 2 (Vp, Ip = rho Vp): grad_vp = dJ/dVp at fixed Ip, grad_rho =

@@ -183,7 +183,12 @@ void configure(smi::StepCtx &c, const smi_ctx *ctx, const Plan &pl) {
     // tiles, 32 planes per workgroup) wherever they apply -- 8.5 % faster on the whole 3D RTM and
     // 15 % on the full-grid step than the register-blocked kernels, which remain option 3
     const int y3_default = pl.nd == 3 && smi::y3_available(pl) ? 432 : 0;
-    if (ctx->opt_kernel == 0 || ctx->opt_kernel == 6 || ctx->opt_kernel == 7) c.y3 = y3_default;
+    if (ctx->opt_kernel == 0 || ctx->opt_kernel == 6 || ctx->opt_kernel == 7) {
+        c.y3 = y3_default;
+        // the register-blocked 3D kernels (the reconstruction, and every half step where the
+        // y-marching ones do not apply) in the XCD-contiguous z-fastest order
+        c.ymap = pl.nd == 3;
+    }
     if (ctx->opt_kernel == 6) {
         // the fused marching 2D forward step (other passes and 3D: the kernels of 0)
         c.march = pl.nd == 2 ? 4 : 2;
@@ -462,7 +467,7 @@ std::vector<Cand> fwd_candidates(const Plan &pl) {
         v.push_back({2, false, false, false, 32, 2, "march2-plain"});
         v.push_back({4, false, false, false, 32, 2, "march4-plain"});
         v.push_back({2, true, false, false, 32, 2, "march2-xcd"});
-        v.push_back({2, false, true, false, 32, 2, "march2-ystrip"});
+        v.push_back({2, false, true, false, 32, 2, "march2-zfast"});
         if (smi::yp_available(pl)) {
             v.push_back({2, false, false, false, 32, 2, "yplane-2x8", 32});
         }

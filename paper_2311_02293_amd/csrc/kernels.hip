@@ -233,10 +233,11 @@ struct MG {
     int nmarch;         // march strips per shot along the march axis (3D: grid z = strip + nmarch shot)
     int nxc;            // > 0: XCD-contiguous order, blockIdx.x & 7 = XCD, which takes nxc
                         // consecutive blocks of x (2D: march strips, 3D: 4-column groups)
-    // 3D y-strip order (ymap = 1, one-dimensional grid): the tiles (shot, z-block, x-group,
-    // y-strip), y-strip fastest, are cut into 8 contiguous ranges of `per` tiles, one per XCD
-    // (blockIdx.x & 7), so that a tile's y-neighbours run just before it on the same XCD and
-    // its y-halo planes are still in that XCD's L2.
+    // 3D XCD-contiguous order (ymap = 1, one-dimensional grid): the tiles (shot, y-strip,
+    // x-group, z-block), z-block fastest, are cut into 8 contiguous ranges of `per` tiles, one
+    // per XCD (blockIdx.x & 7), so that the workgroups resident on one XCD at a time cover a
+    // block of neighbouring columns of one strip, whose halo columns and planes they read from
+    // the same L2.
     // 2D shot-inner order (ymap = 2; every shot of the launch has the same box): XCD k still
     // takes the strips [k nxc, (k + 1) nxc), but its consecutive workgroups run one tile of
     // every shot (`per` shots, then gz z-blocks, then the strips), so the model under a tile
@@ -317,12 +318,12 @@ __device__ __forceinline__ MCell mcell_of(const int *__restrict__ box, int shot0
             const int t = ((int)blockIdx.x & 7) * mg.per + ((int)blockIdx.x >> 3);
             live = t < mg.ntile;
             const int tt = live ? t : 0;
-            strip = tt % mg.nmarch;
-            int r = tt / mg.nmarch;
+            zb3 = tt % mg.gz;
+            int r = tt / mg.gz;
             xg3 = r % mg.gx;
             r /= mg.gx;
-            zb3 = r % mg.gz;
-            c.s = mg.sb + shot0 + r / mg.gz;
+            strip = r % mg.nmarch;
+            c.s = mg.sb + shot0 + r / mg.nmarch;
         }
         const int *b = box + 6 * c.s;
         c.z = zalign(b[0]) + zb3 * 64 + lane;
@@ -1636,7 +1637,7 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
 hipError_t fwd_step(const StepCtx &c, int it) { SMI_DISPATCH(fwd_step_t, c, it); }
 
 bool march_forward(const StepCtx &c) {
-    // (the y-strip order uses a one-dimensional grid: no planes to carry other work)
+    // (the XCD-contiguous 3D order uses a one-dimensional grid: no planes to carry other work)
     return !c.plain && c.march && !((c.y3 || c.yp) && c.pl->nd == 3) && !c.ymap;
 }
 

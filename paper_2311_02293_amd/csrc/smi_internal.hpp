@@ -232,7 +232,7 @@ struct StepCtx {
     // the p launch (ev[2], ev[3]) of this step, taken by the device around each kernel
     const hipEvent_t *ev = nullptr;
     bool xcd = false;       // XCD-contiguous tile order of the sweep kernels
-    bool ymap = false;      // 3D register-blocked kernels: y-strip-fastest tile order per XCD
+    bool ymap = false;      // 3D register-blocked kernels: XCD-contiguous z-fastest tile order
     int march = 0;          // > 0: register-blocked kernels with this many cells per lane (2, 4, 8)
     bool zl = false;        // register-blocked kernels take z-neighbours from LDS
     int y3 = 0;             // 3D: half steps marching along y, tile code 100 BX + CY (0: off)

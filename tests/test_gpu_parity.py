@@ -156,7 +156,7 @@ def test_marching_kernels_match_sweep_kernels(ctx, ndim, cm, tmap):
         ctx.set_option(B.OPT_KERNEL, 0)
     ctx.set_option(B.OPT_KERNEL, 3)
     ctx.set_option(B.OPT_CHUNK, cm)
-    ctx.set_option(B.OPT_TILEMAP, tmap)     # 2: 3D y-strip-fastest order per XCD
+    ctx.set_option(B.OPT_TILEMAP, tmap)     # 2: 3D XCD-contiguous z-fastest order
     try:
         got, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
         g, _, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
