@@ -184,10 +184,13 @@ typedef enum {
                                 results for every value. */
     SMI_OPT_FWD_GROUP = 9    /* 2D forward passes of the default (register-blocked) kernels run
                                 the time loop once per group of consecutive shots, as
-                                SMI_OPT_REV_GROUP does for reverse passes: 0 (default) the
-                                largest equal groups whose fields (p, v and the CPML variables),
-                                as their computing boxes touch them on average over the steps,
-                                fit 224 MiB; k > 0 at most k shots per group.  The fused steps
+                                SMI_OPT_REV_GROUP does for reverse passes: 0 (default) one
+                                loop while the fields (p, v and the CPML variables) under every
+                                shot's computing box fit 224 MiB at every step, else the count
+                                of equal groups (at most 16) of least modelled time over the
+                                schedule of boxes (a fixed cost per launch, and a higher cost
+                                per cell at steps where a group's fields exceed 224 MiB);
+                                k > 0 at most k shots per group.  The fused steps
                                 (SMI_OPT_KERNEL 2, 6, 7), 3D passes and the plain stepper run
                                 one loop.  Same results for every value. */
 } smi_option;

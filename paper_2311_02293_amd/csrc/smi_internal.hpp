@@ -171,9 +171,9 @@ smi_status check_grid(const smi_grid *g, double vmin, double vmax, std::string &
 void algorithmic_bytes(Plan &pl);
 // algorithmic bytes of forward step it over the shots [s0, s1), as a row of Plan::step_bytes
 void step_bytes_of(const Plan &pl, int it, int s0, int s1, double row[3]);
-// shot groups of a 2D forward pass of the register-blocked kernels: the fields one group's
-// computing boxes touch on average over the schedule (with their memory variables) within
-// `budget` bytes; max_per > 0 caps a group instead
+// shot groups of a 2D forward pass of the register-blocked kernels: one group while every
+// step's fields (with their memory variables) fit `budget` bytes, else the group count of least
+// modelled cost over the schedule of boxes; max_per > 0 caps a group instead
 std::vector<int> fwd_groups(const Plan &pl, double budget, int max_per);
 // algorithmic bytes of reverse iteration it over the shots [s0, s1): out[0] the adjoint and
 // reconstruction steps with band restores, adjoint sources and the model read once, out[1] the
