@@ -280,6 +280,7 @@ Key plan_key(char tag, const Plan &pl, const smi::StepCtx &c) {
     k.put(c.y3).put(pl.chunk).put(c.step2d).put(c.run).put(c.depth).put(c.yp);
     k.vec(pl.fbox).vec(pl.abox).vec(pl.rbox).vec(pl.rec_off);
     k.put(pl.src_multi).vec(pl.src_toff).vec(pl.src_cell).vec(pl.inj_off);
+    k.put(pl.inj_fused).put(pl.inj_zlo).put(pl.inj_nrow);
     return k;
 }
 
@@ -392,6 +393,9 @@ smi_status upload(smi_ctx *ctx, const Plan &pl, const Views &w, hipStream_t st) 
         HIPCHK(hipMemcpyAsync(w.inj.rec, pl.inj_rec.data(), T * sizeof(int), hipMemcpyHostToDevice, st), "inj");
         HIPCHK(hipMemcpyAsync(w.inj.w, pl.inj_w.data(), T * sizeof(float), hipMemcpyHostToDevice, st), "inj");
     }
+    if (w.injmap)
+        HIPCHK(hipMemcpyAsync(w.injmap, pl.inj_map.data(), pl.inj_map.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st), "inj");
     HIPCHK(hipMemcpyAsync(w.src_cell, pl.src_cell.data(), pl.nshot * sizeof(long long),
                           hipMemcpyHostToDevice, st), "src");
     HIPCHK(hipMemcpyAsync(w.src_toff, pl.src_toff.data(), pl.src_toff.size() * sizeof(int),
@@ -794,6 +798,8 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
         for (size_t gi = 0; gi + 1 < rg.size(); ++gi) {
             c.s0 = rg[gi];
             c.s1 = rg[gi + 1];
+            // the adjoint sources of this level were added by the previous reverse step
+            bool injected = false;
             for (int it = pl.g.nt - 1; it >= 0; --it) {
                 // sampled reverse step: the device stamps an event before its first launch and
                 // after its last
@@ -814,7 +820,7 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
                     ev = &ctx->rev_events[2 * k];
                     HIPCHK(hipEventRecord(ev[0], ls), "timing event");
                 }
-                if (adj) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
+                if (adj && !injected) HIPCHK(smi::adj_inject(c, it, G), "adjoint source");
                 HIPCHK(smi::src_taps(c, it, w.f.p, -1.f), "source removal");
                 if (rev_tune && it % 16 == 7) {
                     hipEvent_t e0, e1;
@@ -825,11 +831,13 @@ smi_status run_reverse(smi_ctx *ctx, smi_state *stt, const float *G, float *grad
                     rt.form.push_back(rt.form.size() % 2 ? 2 : 1);
                     c.rev = rt.form.back();
                     HIPCHK(hipEventRecord(e0, ls), "tuning event");
-                    HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+                    HIPCHK(smi::rev_step(c, it, want_g, want_i, adj ? G : nullptr, &injected),
+                           "reverse step");
                     HIPCHK(hipEventRecord(e1, ls), "tuning event");
                     c.rev = base_rev;
                 } else {
-                    HIPCHK(smi::rev_step(c, it, want_g, want_i), "reverse step");
+                    HIPCHK(smi::rev_step(c, it, want_g, want_i, adj ? G : nullptr, &injected),
+                           "reverse step");
                 }
                 if (want_r) HIPCHK(smi::rho_faces(c, it), "density faces");
                 if (ev) HIPCHK(hipEventRecord(ev[1], ls), "timing event");

@@ -495,14 +495,51 @@ __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml
     march_v_body<ND, N, CM, ZL>(g, f, m, cp, box, shot0, mg, ex, sv, sv_z0);
 }
 
+// Adjoint sources of node u at level it (eq. 8, the transpose of the receiver sampling): the
+// weighted sum of its receivers' samples in the plan's fixed order, and its addition to p~.
+// Both the gather kernel and the adjoint p update that adds the injection itself use these
+// two, so either way gives the same bits.
+__device__ __forceinline__ float inj_sum(const int *__restrict__ off, const int *__restrict__ rec,
+                                         const float *__restrict__ w,
+                                         const long long *__restrict__ obase,
+                                         const int *__restrict__ stride,
+                                         const float *__restrict__ G, int it, int u) {
+    float acc = 0.f;
+    for (int t = off[u]; t < off[u + 1]; ++t) {
+        const int r = rec[t];
+        acc = __builtin_fmaf(w[t], G[obase[r] + (long long)it * stride[r]], acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float inj_add(float p, float kdt, float inv_dt, float acc) {
+    return __builtin_fmaf(kdt * inv_dt, acc, p);
+}
+
+// the injection of level it that an adjoint p update adds on the lanes owning the nodes (2D)
+struct InjArg {
+    const int *map;         // [nshot][nrow][m1] node of (shot, z - zlo, x), or -1
+    int zlo, nrow, m1;
+    const int *off, *rec;   // the gather (Inj)
+    const float *w;
+    const long long *obase; // the receivers (Recv)
+    const int *stride;
+    const float *G;
+    int it;
+    float inv_dt;
+};
+
 // p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
-// first, as in k_march_v.
-template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG>
+// first, as in k_march_v.  INJ (2D adjoint update): p~ then takes the adjoint sources of the
+// next reverse level at the nodes, after the image has read it (a pass of its own after the
+// update, so that the update keeps its registers and schedule).
+template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG, bool INJ = false>
 __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
-                                                 const float *__restrict__ pf, float *acc_i, BandArg sv, int sv_z0) {
+                                                 const float *__restrict__ pf, float *acc_i, BandArg sv, int sv_z0,
+                                                 InjArg ia = InjArg{}) {
     // the v band cells of the next level (the p update leaves v alone), on the planes from sv_z0
     if (sv.buf && (int)blockIdx.z >= sv_z0) {
         band_part(g, f, sv, sv_z0, 0, 1);
@@ -588,6 +625,22 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
                 (unsigned)iy < (unsigned)g.n[2]) {
                 long long ii = c.s * g.I + iz + (long long)g.n[0] * (ix + (long long)g.n[1] * iy);
                 acc_i[ii] += g.dt * pn * pf[so0 + c.k];
+            }
+        }
+    }
+    // the next level's adjoint sources on this lane's nodes (2D: the lane's cells are one row),
+    // added to the stored p~ after the update above, as the gather launch would add them
+    if (INJ && ND == 2 && (unsigned)(mc.z - ia.zlo) < (unsigned)ia.nrow) {
+        const int *__restrict__ row = ia.map + ((long long)mc.s * ia.nrow + (mc.z - ia.zlo)) * ia.m1;
+#pragma unroll
+        for (int t = 0; t < CM; ++t) {
+            if (t >= cnt) break;
+            const int u = row[mc.lo + t];
+            if (u >= 0) {
+                const long long k = as_cell<ND>(g, mc, mc.lo + t).k;
+                float *q = f.p + so0 + k;
+                *q = inj_add(*q, m.kdt[k], ia.inv_dt,
+                             inj_sum(ia.off, ia.rec, ia.w, ia.obase, ia.stride, ia.G, ia.it, u));
             }
         }
     }
@@ -877,19 +930,21 @@ __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Mode
         band_part(g, f, ba, 2 * nshot, 1, 0);
 }
 
-template <int N, int CM, bool IMG, bool BAND>
-__global__ __launch_bounds__(256) void k_rev_vp(Geom g, Fields f, Fields q, Model m, Cpml cp,
+// INJ: the adjoint p update also adds the adjoint sources of level it - 1 (ia), which the next
+// reverse step would otherwise inject with a launch of its own
+template <int N, int CM, bool IMG, bool BAND, bool INJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_rev_vp(Geom g, Fields f, Fields q, Model m, Cpml cp,
                                                 const int *__restrict__ rb,
                                                 const int *__restrict__ ab, MG mgr, MG mga,
                                                 int nshot, const long long *__restrict__ src_cell,
                                                 const float *__restrict__ stf, int nt, int it,
-                                                float *acc_i, BandArg ba) {
+                                                float *acc_i, BandArg ba, InjArg ia) {
     const int bz = (int)blockIdx.z;
     if (bz < nshot)
         march_recon_v_body<2, N, CM, false>(g, f, m, rb, 0, mgr);
     else if (bz < 2 * nshot)
-        march_p_body<2, N, CM, false, false, IMG>(g, q, m, cp, ab, -nshot, mga, src_cell, stf, nt,
-                                                  it, f.p, acc_i, BandArg{}, 0);
+        march_p_body<2, N, CM, false, false, IMG, INJ>(g, q, m, cp, ab, -nshot, mga, src_cell, stf,
+                                                       nt, it, f.p, acc_i, BandArg{}, 0, ia);
     else if (BAND)
         band_part(g, f, ba, 2 * nshot, 1, 1);
 }
@@ -965,13 +1020,10 @@ __global__ __launch_bounds__(256) void k_inject(Geom g, float *qp, const float *
                                                 int it, float inv_dt, int s0, int s1) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= in.U || in.shot[u] < s0 || in.shot[u] >= s1) return;
-    float acc = 0.f;
-    for (int t = in.off[u]; t < in.off[u + 1]; ++t) {
-        const int r = in.rec[t];
-        acc += in.w[t] * G[rv.obase[r] + (long long)it * rv.stride[r]];
-    }
+    const float acc = inj_sum(in.off, in.rec, in.w, rv.obase, rv.stride, G, it, u);
     const long long c = in.cell[u];
-    qp[in.shot[u] * g.P + c] += kdt[c] * inv_dt * acc;
+    float *q = qp + in.shot[u] * g.P + c;
+    *q = inj_add(*q, kdt[c], inv_dt, acc);
 }
 
 // ---------------------------------------------------------------- misfit (eq. 6)
@@ -1504,9 +1556,10 @@ hipError_t recon_march_t(const StepCtx &c, int it, bool grad, bool image) {
     return hipGetLastError();
 }
 
-// the two-launch reverse step of the 2D default path (see k_rev_pv)
+// the two-launch reverse step of the 2D default path (see k_rev_pv); G: the adjoint sources
+// of level it - 1 join the second launch (k_rev_vp with INJ), or null
 template <int N>
-hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
+hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image, const float *G) {
     constexpr int CM = 4;
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
@@ -1537,19 +1590,27 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image) {
 #undef SMI_RPV
     if (!band) SMI_TRY(band_restore(c, it, 2));      // interpolated levels: one launch of their own
     SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
-#define SMI_RVP(I_, B_)                                                                        \
-    hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,       \
+    InjArg ia{};
+    if (G) {
+        ia = InjArg{w.injmap, pl.inj_zlo, pl.inj_nrow, pl.M[1], w.inj.off, w.inj.rec, w.inj.w,
+                    w.recv.obase, w.recv.stride, G, it - 1, (float)(1.0 / pl.g.dt)};
+    }
+#define SMI_RVP(I_, B_, J_)                                                                    \
+    hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_, J_>), grid, block, 0, c.st, pl.geom, w.f, w.q,   \
                        w.model, w.cpml, rb, ab, LR.mg, LA.mg, ns,                               \
-                       (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_i, ba)
-    if (image) { if (band) SMI_RVP(true, true); else SMI_RVP(true, false); }
-    else { if (band) SMI_RVP(false, true); else SMI_RVP(false, false); }
+                       (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_i, ba, ia)
+#define SMI_RVP_J(I_, B_) do { if (G) SMI_RVP(I_, B_, true); else SMI_RVP(I_, B_, false); } while (0)
+    if (image) { if (band) SMI_RVP_J(true, true); else SMI_RVP_J(true, false); }
+    else { if (band) SMI_RVP_J(false, true); else SMI_RVP_J(false, false); }
+#undef SMI_RVP_J
 #undef SMI_RVP
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, s0, s1);
 }
 
 template <int ND, int N>
-hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
+hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image, const float *Gn,
+                      bool *fused) {
     const Plan &pl = *c.pl;
     const Views &w = *c.w;
     // Launches over up to 8 M padded cells (the shots of the reverse loop's group) take the
@@ -1560,8 +1621,11 @@ hipError_t rev_step_t(const StepCtx &c, int it, bool grad, bool image) {
     const int sa = c.s0, se = shot_end(c);
     if constexpr (ND == 2) {
         const bool small = (double)(se - sa) * (double)pl.P <= kPairCells;
-        if (!c.plain && c.march == 4 && !c.zl && (c.rev == 1 || (c.rev == 0 && small)))
-            return rev_pair_t<N>(c, it, grad, image);
+        if (!c.plain && c.march == 4 && !c.zl && (c.rev == 1 || (c.rev == 0 && small))) {
+            const bool inj = Gn && it > 0 && pl.inj_fused;
+            if (fused) *fused = inj;
+            return rev_pair_t<N>(c, it, grad, image, inj ? Gn : nullptr);
+        }
     }
     if (!c.plain && c.march) {
         auto recon = [&]() -> hipError_t { SMI_MARCH(recon_march_t, c, it, grad, image); };
@@ -1641,8 +1705,10 @@ bool march_forward(const StepCtx &c) {
     return !c.plain && c.march && !((c.y3 || c.yp) && c.pl->nd == 3) && !c.ymap;
 }
 
-hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image) {
-    SMI_DISPATCH(rev_step_t, c, it, grad, image);
+hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image, const float *Gn,
+                    bool *fused) {
+    if (fused) *fused = false;
+    SMI_DISPATCH(rev_step_t, c, it, grad, image, Gn, fused);
 }
 
 hipError_t extract(const StepCtx &c, int it, float *dcal, const float *p) {

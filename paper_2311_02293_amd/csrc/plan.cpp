@@ -554,6 +554,52 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     G.fs = g->freesurf;
     G.src_scale = (float)(g->dt / (hs[0] * hs[1] * (pl.nd == 3 ? hs[2] : 1.0)));
 
+    // node map of the adjoint-source gather (see Plan::inj_map): the adjoint p update of
+    // reverse step it + 1 adds the injection of step it on the lanes that own the nodes when
+    // every node of a shot lies inside that shot's adjoint box at every such step
+    pl.inj_map.clear();
+    pl.inj_zlo = pl.inj_nrow = 0;
+    pl.inj_fused = false;
+    if (pl.adjoint && pl.nd == 2 && g->freesurf == 0 && !pl.inj_cell.empty()) {
+        const int U = (int)pl.inj_cell.size();
+        std::vector<int> nz(U), nx(U);
+        std::vector<int> bb((size_t)ns * 4);   // per shot: node rows and columns, min and max
+        for (int s = 0; s < ns; ++s) {
+            bb[4 * s] = bb[4 * s + 2] = 1 << 30;
+            bb[4 * s + 1] = bb[4 * s + 3] = -1;
+        }
+        int zlo = 1 << 30, zhi = -1;
+        for (int u = 0; u < U; ++u) {
+            const long long rel = pl.inj_cell[u] - pl.org;   // z + ld1 x, nodes inside the model
+            nx[u] = (int)(rel / pl.ld1);
+            nz[u] = (int)(rel - (long long)nx[u] * pl.ld1);
+            zlo = std::min(zlo, nz[u]);
+            zhi = std::max(zhi, nz[u]);
+            int *q = &bb[4 * (size_t)pl.inj_shot[u]];
+            q[0] = std::min(q[0], nz[u]);
+            q[1] = std::max(q[1], nz[u]);
+            q[2] = std::min(q[2], nx[u]);
+            q[3] = std::max(q[3], nx[u]);
+        }
+        const int nrow = zhi - zlo + 1;
+        bool ok = (size_t)ns * nrow * pl.M[1] <= kInjMapCap;
+        for (int it = 1; ok && it < nt; ++it)
+            for (int s = 0; ok && s < ns; ++s) {
+                const int *q = &bb[4 * (size_t)s];
+                if (q[1] < 0) continue;
+                const int *ab = &pl.abox[((size_t)it * ns + s) * 6];
+                ok = q[0] >= ab[0] && q[1] < ab[1] && q[2] >= ab[2] && q[3] < ab[3];
+            }
+        if (ok) {
+            pl.inj_map.assign((size_t)ns * nrow * pl.M[1], -1);
+            for (int u = 0; u < U; ++u)
+                pl.inj_map[((size_t)pl.inj_shot[u] * nrow + (nz[u] - zlo)) * pl.M[1] + nx[u]] = u;
+            pl.inj_zlo = zlo;
+            pl.inj_nrow = nrow;
+            pl.inj_fused = true;
+        }
+    }
+
     // workspace layout
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
@@ -573,6 +619,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
                        (sizeof(long long) + sizeof(float)) * (pl.src_tcell.size() + pl.rec_tcell.size()) + 64);
     pl.off_inj = take((sizeof(int) * 2 + sizeof(long long)) * pl.inj_cell.size() +
                       (sizeof(int) + sizeof(float)) * pl.inj_rec.size() + 64);
+    pl.off_injmap = take(sizeof(int) * pl.inj_map.size() + 64);
     size_t fld = sizeof(float) * (size_t)ns * ((size_t)pl.P * (1 + pl.nd) +
                  2 * (size_t)(G.psz[0] + G.psz[1] + G.psz[2]));
     pl.off_fields = take(fld);
@@ -649,6 +696,7 @@ Views views(const Plan &pl, void *ws) {
         w.inj.rec = (int *)q;
         q += sizeof(int) * T;
         w.inj.w = (float *)q;
+        w.injmap = pl.inj_map.empty() ? nullptr : (int *)(b + pl.off_injmap);
     }
     auto fields = [&](size_t off) {
         Fields f{};

@@ -26,6 +26,7 @@ constexpr int kMaxBlocks = 12; // band blocks per save level: 3 axes x {p, v} x 
 constexpr int GH = 2 * kMaxN;  // ghost nodes per side and axis (>= the 2N-1 halo of a fused step)
 constexpr int kTaps = 4;       // half-width (saved levels) of the decimated-band interpolator
 constexpr int kTailCols = 32;  // columns of workspace slack after the last region (see plan.cpp)
+constexpr size_t kInjMapCap = size_t(1) << 22;   // entries of the largest adjoint-source node map
 constexpr double kKaiserBeta = 6.31;
 
 // ---------------------------------------------------------------- device-side views
@@ -135,6 +136,14 @@ struct Plan {
     std::vector<int> inj_shot, inj_off, inj_rec;
     std::vector<long long> inj_cell;
     std::vector<float> inj_w;
+    // 2D reverse passes: the adjoint p update of reverse step it + 1 adds the injection of step
+    // it itself, on the lanes that own the nodes, when every node lies inside its shot's adjoint
+    // box at every step and there is no free surface (inj_fused).  inj_map[(s inj_nrow + z -
+    // inj_zlo) M[1] + x] is the node of shot s at padded (z, x), or -1, over the rows
+    // [inj_zlo, inj_zlo + inj_nrow) that hold nodes.
+    std::vector<int> inj_map;
+    int inj_zlo = 0, inj_nrow = 0;
+    bool inj_fused = false;
     BandDesc band{};
     int nsave = 0;      // saved band levels k dr, k = 0 .. nsave-1
     int nrun = 0;       // forward steps: nt, or past nt until the last saved level (dr > 1)
@@ -144,7 +153,7 @@ struct Plan {
     size_t off_model = 0, off_cpml = 0, off_tables = 0, off_recv = 0;
     size_t off_fields = 0, off_fields2 = 0, off_adj = 0, off_bands = 0, off_acc = 0, off_G = 0, off_dcal = 0;
     size_t off_rho = 0;
-    size_t off_taps = 0, off_fin = 0, off_inj = 0;
+    size_t off_taps = 0, off_fin = 0, off_inj = 0, off_injmap = 0;
     size_t bytes = 0;
     int npartial = 0;
     bool save = false, adjoint = false, need_G = false, need_dcal = false;
@@ -200,6 +209,7 @@ struct Views {
     int *fbox, *abox, *rbox;
     Recv recv;
     Inj inj;
+    int *injmap;          // Plan::inj_map in device memory (null when the injection is not fused)
     long long *src_cell;  // [nshot] source cell offset inside one shot's field
     int *src_toff;        // [nshot + 1] source operators (see Plan)
     long long *src_tcell;
@@ -290,7 +300,10 @@ hipError_t band_restore(const StepCtx &c, int it, int which);
 hipError_t snap(const StepCtx &c, const Fields &f, float *snaps, int k, int nsnap);
 hipError_t scale_copy(const StepCtx &c, const float *in, float *out, float a);
 hipError_t adj_inject(const StepCtx &c, int it, const float *G);
-hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image);
+// reverse step it; with Gn (the adjoint sources) and it > 0, a step that can also adds the
+// injection of step it - 1 (Plan::inj_fused) and sets *fused, so the caller skips that launch
+hipError_t rev_step(const StepCtx &c, int it, bool grad, bool image, const float *Gn = nullptr,
+                    bool *fused = nullptr);
 // residual, G = dt r and misfit of the shots [s0, s1) (their slice of dcal / dobs / G)
 hipError_t residual(const StepCtx &c, const float *dcal, const float *dobs, float *G,
                     double *misfit, int s0, int s1);

@@ -1023,6 +1023,40 @@ def test_two_and_five_launch_reverse_steps_agree(ctx, dr):
     assert np.abs(out[1][0]).max() > 0 and np.abs(out[1][2]).max() > 0
 
 
+@pytest.mark.parametrize("freesurf", [0, 1])
+@pytest.mark.parametrize("offgrid", [False, True])
+def test_adjoint_sources_added_in_the_adjoint_update_equal_their_own_launch(ctx, offgrid, freesurf):
+    """The two-launch reverse step adds the next level's adjoint sources (eq. 8) inside its
+    adjoint p update when every receiver node stays inside the adjoint box and there is no free
+    surface; the five-launch step injects them with a gather launch of its own.  Gradient,
+    misfit, image and illumination agree bitwise, with receivers on the grid, off the grid with
+    overlapping operators over several rows, and with a free surface (the pair then keeps the
+    gather launch)."""
+    from paper_2311_02293_amd import binding as B
+    job = _grad_job(nt=360, nshot=3)
+    job.grid.freesurf = freesurf
+    if offgrid:
+        job.acq.rec[:, 0] += 0.37 * job.grid.d1
+        xmax = (job.grid.n2 - 1) * job.grid.d2
+        job.acq.rec[:, 1] = np.minimum(job.acq.rec[:, 1] + 0.41 * job.grid.d2, xmax)
+    vp, rho, stf = dev(job)
+    d0, _, _ = ctx.forward(job.grid, job.acq, vp, rho, stf)
+    dobs = (0.7 * d0).contiguous()
+    out = {}
+    try:
+        for mode in (1, 2):
+            ctx.set_option(B.OPT_REVERSE, mode)
+            g, J, _ = ctx.fwi_grad(job.grid, job.acq, vp, rho, stf, dobs)
+            im, il = ctx.rtm_image(job.grid, job.acq, vp, rho, stf, dobs)
+            out[mode] = [t.cpu().numpy() for t in (g, J, im, il)]
+    finally:
+        ctx.set_option(B.OPT_REVERSE, 0)
+    for k, (a, b) in enumerate(zip(out[1], out[2])):
+        say(f"offgrid {offgrid} freesurf {freesurf} output {k}: bitwise {np.array_equal(a, b)}")
+        np.testing.assert_array_equal(a, b)
+    assert np.abs(out[1][0]).max() > 0 and np.abs(out[1][2]).max() > 0
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_order4_reverse_path_matches_oracle(ctx, ndim):
     """Order 4 (N = 2) through the whole path: seismograms, both gradients (family 1), the
