@@ -931,7 +931,9 @@ __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Mode
 }
 
 // INJ: the adjoint p update also adds the adjoint sources of level it - 1 (ia), which the next
-// reverse step would otherwise inject with a launch of its own
+// reverse step would otherwise inject with a launch of its own.  The injection's arguments
+// would take the kernel to 102 scalar registers and seven wavefronts per SIMD (13 % slower);
+// asked for eight, the compiler fits 78 without spilling.
 template <int N, int CM, bool IMG, bool BAND, bool INJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_rev_vp(Geom g, Fields f, Fields q, Model m, Cpml cp,
                                                 const int *__restrict__ rb,
