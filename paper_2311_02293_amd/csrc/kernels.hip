@@ -483,7 +483,17 @@ __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
                 *ps = psi;
                 e += psi;
             }
-            f.v[a][c.s * g.P + c.k] = vo[t][a] - bd[t][a] * e;
+            const float nv = vo[t][a] - bd[t][a] * e;
+            float *vd = f.v[a] + c.s * g.P + c.k;
+            if (a == 0 && g.fs) {
+                // free surface (image method): v_z on the rows nb - N .. nb - 1 mirrors the rows
+                // nb + N - 1 .. nb, written by the lanes of those rows
+                const int zr = c.z - g.nb;
+                if (zr >= 0 || zr < -N) *vd = nv;
+                if (zr >= 0 && zr < N) vd[-1 - 2 * zr] = nv;
+            } else {
+                *vd = nv;
+            }
         }
     }
 }
@@ -618,7 +628,18 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
         }
         float pn = po[t] - kd[t] * sdiv;
         if (SRC && it < nt && c.k == sc) pn += src_amp(g.src_scale, stf[(long long)c.s * nt + it]);
-        f.p[so0 + c.k] = pn;
+        float *pd = f.p + so0 + c.k;
+        if (g.fs) {
+            // free surface (image method): p = 0 on row nb and odd about it, the rows nb - N ..
+            // nb - 1 written by the lanes of rows nb + N .. nb + 1 (the image below still takes
+            // the updated value)
+            const int zr = c.z - g.nb;
+            if (zr > 0 || zr < -N) *pd = pn;
+            else if (zr == 0) *pd = 0.f;
+            if (zr > 0 && zr <= N) pd[-2 * zr] = -pn;
+        } else {
+            *pd = pn;
+        }
         if (IMG) {
             int iz = c.z - g.nb, ix = c.x - g.nb, iy = ND == 3 ? c.y - g.nb : 0;
             if ((unsigned)iz < (unsigned)g.n[0] && (unsigned)ix < (unsigned)g.n[1] &&
@@ -1446,21 +1467,18 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
     if (c.ev) {
         hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, c.ev[0], c.ev[1],
                               0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex, svp, zp);
-        SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, g0, g1));
         hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st,
                               c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                               (const float *)nullptr, (float *)nullptr, svv, zv);
-        return fs_launch(pl, c.st, w.f.p, 1, g0, g1);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, pl.geom, w.f, w.model,
                        w.cpml, box, s0, L.mg, ex, svp, zp);
-    SMI_TRY(fs_launch(pl, c.st, w.f.v[0], 0, g0, g1));
     hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st, pl.geom,
                        w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
                        pl.g.nt, it, (const float *)nullptr, (float *)nullptr, svv, zv);
-    hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.f.p, 1, g0, g1);
+    return hipGetLastError();
 }
 
 // adjoint half steps with the marching kernels (image with the source field when asked)
@@ -1474,7 +1492,6 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     if (L.empty) return hipSuccess;
     hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
                        w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr}, BandArg{}, 0);
-    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
     if (image)
         hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
                            w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
@@ -1484,8 +1501,7 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
                            pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
                            (const long long *)w.src_cell, c.stf, pl.g.nt, it,
                            (const float *)w.f.p, w.acc_i, BandArg{}, 0);
-    hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, s0, s1);
+    return hipGetLastError();
 }
 
 template <int ND, int N>
@@ -1591,7 +1607,6 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image, const flo
 #undef SMI_RPV_B
 #undef SMI_RPV
     if (!band) SMI_TRY(band_restore(c, it, 2));      // interpolated levels: one launch of their own
-    SMI_TRY(fs_launch(pl, c.st, w.q.v[0], 0, s0, s1));
     InjArg ia{};
     if (G) {
         ia = InjArg{w.injmap, pl.inj_zlo, pl.inj_nrow, pl.M[1], w.inj.off, w.inj.rec, w.inj.w,
@@ -1606,8 +1621,7 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image, const flo
     else { if (band) SMI_RVP_J(false, true); else SMI_RVP_J(false, false); }
 #undef SMI_RVP_J
 #undef SMI_RVP
-    hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fs_launch(pl, c.st, w.q.p, 1, s0, s1);
+    return hipGetLastError();
 }
 
 template <int ND, int N>
