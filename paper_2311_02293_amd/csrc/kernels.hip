@@ -657,11 +657,15 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
         for (int t = 0; t < CM; ++t) {
             if (t >= cnt) break;
             const int u = row[mc.lo + t];
-            if (u >= 0) {
+            const int zr = mc.z - g.nb;
+            // with a free surface, the surface row stays 0 and the image rows follow row nb + k
+            if (u >= 0 && !(g.fs && zr <= 0 && zr >= -N)) {
                 const long long k = as_cell<ND>(g, mc, mc.lo + t).k;
                 float *q = f.p + so0 + k;
-                *q = inj_add(*q, m.kdt[k], ia.inv_dt,
-                             inj_sum(ia.off, ia.rec, ia.w, ia.obase, ia.stride, ia.G, ia.it, u));
+                const float pv = inj_add(*q, m.kdt[k], ia.inv_dt,
+                                         inj_sum(ia.off, ia.rec, ia.w, ia.obase, ia.stride, ia.G, ia.it, u));
+                *q = pv;
+                if (g.fs && zr > 0 && zr <= N) q[-2 * zr] = -pv;
             }
         }
     }

@@ -560,7 +560,7 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
     pl.inj_map.clear();
     pl.inj_zlo = pl.inj_nrow = 0;
     pl.inj_fused = false;
-    if (pl.adjoint && pl.nd == 2 && g->freesurf == 0 && !pl.inj_cell.empty()) {
+    if (pl.adjoint && pl.nd == 2 && !pl.inj_cell.empty()) {
         const int U = (int)pl.inj_cell.size();
         std::vector<int> nz(U), nx(U);
         std::vector<int> bb((size_t)ns * 4);   // per shot: node rows and columns, min and max

@@ -138,7 +138,7 @@ struct Plan {
     std::vector<float> inj_w;
     // 2D reverse passes: the adjoint p update of reverse step it + 1 adds the injection of step
     // it itself, on the lanes that own the nodes, when every node lies inside its shot's adjoint
-    // box at every step and there is no free surface (inj_fused).  inj_map[(s inj_nrow + z -
+    // box at every step (inj_fused); with a free surface those lanes also write the images.  inj_map[(s inj_nrow + z -
     // inj_zlo) M[1] + x] is the node of shot s at padded (z, x), or -1, over the rows
     // [inj_zlo, inj_zlo + inj_nrow) that hold nodes.
     std::vector<int> inj_map;

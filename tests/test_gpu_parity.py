@@ -1027,11 +1027,11 @@ def test_two_and_five_launch_reverse_steps_agree(ctx, dr):
 @pytest.mark.parametrize("offgrid", [False, True])
 def test_adjoint_sources_added_in_the_adjoint_update_equal_their_own_launch(ctx, offgrid, freesurf):
     """The two-launch reverse step adds the next level's adjoint sources (eq. 8) inside its
-    adjoint p update when every receiver node stays inside the adjoint box and there is no free
-    surface; the five-launch step injects them with a gather launch of its own.  Gradient,
-    misfit, image and illumination agree bitwise, with receivers on the grid, off the grid with
-    overlapping operators over several rows, and with a free surface (the pair then keeps the
-    gather launch)."""
+    adjoint p update when every receiver node stays inside the adjoint box (with a free surface
+    it also writes their images); the five-launch step injects them with a gather launch of its
+    own and mirrors afterwards.  Gradient, misfit, image and illumination agree bitwise, with
+    receivers on the grid and off the grid with overlapping operators over several rows (near
+    the surface, whose image rows they reach), with and without a free surface."""
     from paper_2311_02293_amd import binding as B
     job = _grad_job(nt=360, nshot=3)
     job.grid.freesurf = freesurf
