@@ -128,8 +128,9 @@ typedef enum {
                                 y-stencil in registers, the plane's z- and x-halo staged in
                                 LDS; SMI_OPT_CHUNK = CY + 1000 F: CY = 16, 32 or 64 y-planes per
                                 workgroup, tile form F = 0: 2 x-cells per lane x 8 wavefronts,
-                                1: 4 x 8, 2: 2 x 16; 0 selects 32).  With a free surface, 2, 6, 7,
-                                8 and the y-marching kernels of 5 give way to the kernels of 0. */
+                                1: 4 x 8, 2: 2 x 16; 0 selects 32).  With a free surface, 2, 6, 7
+                                and 8 give way to the kernels of 0 (the y-marching kernels of 0
+                                and 5 write the image rows themselves). */
     SMI_OPT_GRAPH = 1,       /* 1: the time loops of a call run as a HIP graph, captured the
                                 first time a plan is seen (same geometry, boxes, kernels and
                                 buffers) and replayed on later calls; up to 8 graphs are kept

@@ -133,7 +133,17 @@ __global__ __launch_bounds__(64 * BX) void k_y3_v(Geom g, Fields f, Model m, Cpm
                     *ps = psi;
                     e += psi;
                 }
-                f.v[a][so + k] = cur.vo[a] - cur.bd[a] * e;
+                const float nv = cur.vo[a] - cur.bd[a] * e;
+                float *vd = f.v[a] + so + k;
+                if (a == 0 && g.fs) {
+                    // free surface (image method): v_z on the rows nb - N .. nb - 1 mirrors the
+                    // rows nb + N - 1 .. nb, written by the lanes of those rows
+                    const int zr = t.z - g.nb;
+                    if (zr >= 0 || zr < -N) *vd = nv;
+                    if (zr >= 0 && zr < N) vd[-1 - 2 * zr] = nv;
+                } else {
+                    *vd = nv;
+                }
             }
         }
 #pragma unroll
@@ -229,7 +239,17 @@ __global__ __launch_bounds__(64 * BX) void k_y3_p(Geom g, Fields f, Model m, Cpm
             }
             float pn = cur.po - cur.kd * sdiv;
             if (SRC && it < nt && k == sc) pn += src_amp(g.src_scale, stf[(long long)t.s * nt + it]);
-            f.p[so + k] = pn;
+            float *pd = f.p + so + k;
+            if (g.fs) {
+                // free surface: p = 0 on row nb and odd about it, the rows nb - N .. nb - 1
+                // written by the lanes of rows nb + N .. nb + 1 (the image takes the updated value)
+                const int zr = t.z - g.nb;
+                if (zr > 0 || zr < -N) *pd = pn;
+                else if (zr == 0) *pd = 0.f;
+                if (zr > 0 && zr <= N) pd[-2 * zr] = -pn;
+            } else {
+                *pd = pn;
+            }
             if (IMG) {
                 const int iz = t.z - g.nb, ix = t.x - g.nb, iy = y - g.nb;
                 if ((unsigned)iz < (unsigned)g.n[0] && (unsigned)ix < (unsigned)g.n[1] &&
@@ -331,7 +351,7 @@ hipError_t adj_y3_t(const StepCtx &c, int it, bool image) {
 }  // namespace
 
 // (not with a free surface, whose mirror images the y-marching kernels do not write)
-bool y3_available(const Plan &pl) { return pl.nd == 3 && !pl.g.freesurf; }
+bool y3_available(const Plan &pl) { return pl.nd == 3; }
 
 hipError_t fwd_step_y3(const StepCtx &c, int it) {
     const Plan &pl = *c.pl;
