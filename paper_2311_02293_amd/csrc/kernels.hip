@@ -16,6 +16,7 @@
 // batches runs its reconstruction and adjoint half steps on one shared grid (k_rev_*).  The
 // free surface (image method), the density face sums, the tangent-linear source and the
 // small data kernels (bands, receivers, adjoint sources, misfit, reductions) close the file.
+#include <type_traits>
 #include <algorithm>
 #include <cmath>
 
@@ -387,8 +388,9 @@ __device__ __forceinline__ Cell as_cell(const Geom &g, const MCell &m, int t) {
 // All loads of the lane's CM cells are issued before any arithmetic (the loads are
 // independent, so a wavefront keeps CM times more requests in flight); cells past the end of
 // the march range re-read the last cell and store nothing.  ZL: the z-neighbours come from
-// the wavefront's LDS slice instead of seven unaligned global loads per cell.
-template <int ND, int N, int CM, bool ZL>
+// the wavefront's LDS slice instead of seven unaligned global loads per cell.  FS: the grid
+// has a free surface (the lanes near it write the image rows of v_z).
+template <int ND, int N, int CM, bool ZL, bool FS = false>
 __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  Ext ex, BandArg sv, int sv_z0) {
@@ -485,7 +487,7 @@ __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
             }
             const float nv = vo[t][a] - bd[t][a] * e;
             float *vd = f.v[a] + c.s * g.P + c.k;
-            if (a == 0 && g.fs) {
+            if (FS && a == 0) {
                 // free surface (image method): v_z on the rows nb - N .. nb - 1 mirrors the rows
                 // nb + N - 1 .. nb, written by the lanes of those rows
                 const int zr = c.z - g.nb;
@@ -498,11 +500,11 @@ __device__ __forceinline__ void march_v_body(Geom g, Fields f, Model m, Cpml cp,
     }
 }
 
-template <int ND, int N, int CM, bool ZL>
+template <int ND, int N, int CM, bool ZL, bool FS>
 __global__ __launch_bounds__(256) void k_march_v(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  Ext ex, BandArg sv, int sv_z0) {
-    march_v_body<ND, N, CM, ZL>(g, f, m, cp, box, shot0, mg, ex, sv, sv_z0);
+    march_v_body<ND, N, CM, ZL, FS>(g, f, m, cp, box, shot0, mg, ex, sv, sv_z0);
 }
 
 // Adjoint sources of node u at level it (eq. 8, the transpose of the receiver sampling): the
@@ -542,8 +544,9 @@ struct InjArg {
 // p -= dt kappa sum_a (D-_a v_a + psi_a) [+ source] [image] (eq. 3 second row, CPML); loads
 // first, as in k_march_v.  INJ (2D adjoint update): p~ then takes the adjoint sources of the
 // next reverse level at the nodes, after the image has read it (a pass of its own after the
-// update, so that the update keeps its registers and schedule).
-template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG, bool INJ = false>
+// update, so that the update keeps its registers and schedule).  FS: free surface (the lanes
+// near it write the surface row and the image rows of p).
+template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG, bool INJ = false, bool FS = false>
 __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
@@ -629,7 +632,7 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
         float pn = po[t] - kd[t] * sdiv;
         if (SRC && it < nt && c.k == sc) pn += src_amp(g.src_scale, stf[(long long)c.s * nt + it]);
         float *pd = f.p + so0 + c.k;
-        if (g.fs) {
+        if (FS) {
             // free surface (image method): p = 0 on row nb and odd about it, the rows nb - N ..
             // nb - 1 written by the lanes of rows nb + N .. nb + 1 (the image below still takes
             // the updated value)
@@ -659,26 +662,26 @@ __device__ __forceinline__ void march_p_body(Geom g, Fields f, Model m, Cpml cp,
             const int u = row[mc.lo + t];
             const int zr = mc.z - g.nb;
             // with a free surface, the surface row stays 0 and the image rows follow row nb + k
-            if (u >= 0 && !(g.fs && zr <= 0 && zr >= -N)) {
+            if (u >= 0 && !(FS && zr <= 0 && zr >= -N)) {
                 const long long k = as_cell<ND>(g, mc, mc.lo + t).k;
                 float *q = f.p + so0 + k;
                 const float pv = inj_add(*q, m.kdt[k], ia.inv_dt,
                                          inj_sum(ia.off, ia.rec, ia.w, ia.obase, ia.stride, ia.G, ia.it, u));
                 *q = pv;
-                if (g.fs && zr > 0 && zr <= N) q[-2 * zr] = -pv;
+                if (FS && zr > 0 && zr <= N) q[-2 * zr] = -pv;
             }
         }
     }
 }
 
-template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG>
+template <int ND, int N, int CM, bool ZL, bool SRC, bool IMG, bool FS>
 __global__ __launch_bounds__(256) void k_march_p(Geom g, Fields f, Model m, Cpml cp,
                                                  const int *__restrict__ box, int shot0, MG mg,
                                                  const long long *__restrict__ src_cell,
                                                  const float *__restrict__ stf, int nt, int it,
                                                  const float *__restrict__ pf, float *acc_i, BandArg sv, int sv_z0) {
-    march_p_body<ND, N, CM, ZL, SRC, IMG>(g, f, m, cp, box, shot0, mg, src_cell, stf, nt, it, pf, acc_i,
-                                          sv, sv_z0);
+    march_p_body<ND, N, CM, ZL, SRC, IMG, false, FS>(g, f, m, cp, box, shot0, mg, src_cell, stf, nt,
+                                                     it, pf, acc_i, sv, sv_z0);
 }
 
 // ---------------------------------------------------------------- reconstruction (Sec. 4.2)
@@ -937,7 +940,7 @@ __global__ __launch_bounds__(256) void k_band(Geom g, Fields f, BandDesc bd, flo
 // the v band cells.  The parts of a launch touch disjoint data: the bands lie outside the
 // interior that the reconstruction writes, the adjoint fields are separate, and the v bands are
 // restored only after the gradient has read v^{it+1/2} next to the interior.
-template <int N, int CM, bool GRAD, bool ILL, bool BAND>
+template <int N, int CM, bool GRAD, bool ILL, bool BAND, bool FS>
 __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Model m, Cpml cp,
                                                 const int *__restrict__ rb,
                                                 const int *__restrict__ ab, MG mgr, MG mga,
@@ -949,8 +952,8 @@ __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Mode
         march_recon_p_body<2, N, CM, false, GRAD, ILL>(g, f, m, rb, 0, mgr, src_cell, stf, nt, it,
                                                        q.p, acc_g, acc_l);
     else if (bz < 2 * nshot)
-        march_v_body<2, N, CM, false>(g, q, m, cp, ab, -nshot, mga, Ext{Recv{}, nullptr, -1, nullptr},
-                                      BandArg{}, 0);
+        march_v_body<2, N, CM, false, FS>(g, q, m, cp, ab, -nshot, mga,
+                                          Ext{Recv{}, nullptr, -1, nullptr}, BandArg{}, 0);
     else if (BAND)
         band_part(g, f, ba, 2 * nshot, 1, 0);
 }
@@ -959,7 +962,7 @@ __global__ __launch_bounds__(256) void k_rev_pv(Geom g, Fields f, Fields q, Mode
 // reverse step would otherwise inject with a launch of its own.  The injection's arguments
 // would take the kernel to 102 scalar registers and seven wavefronts per SIMD (13 % slower);
 // asked for eight, the compiler fits 78 without spilling.
-template <int N, int CM, bool IMG, bool BAND, bool INJ>
+template <int N, int CM, bool IMG, bool BAND, bool INJ, bool FS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_rev_vp(Geom g, Fields f, Fields q, Model m, Cpml cp,
                                                 const int *__restrict__ rb,
                                                 const int *__restrict__ ab, MG mgr, MG mga,
@@ -970,8 +973,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     if (bz < nshot)
         march_recon_v_body<2, N, CM, false>(g, f, m, rb, 0, mgr);
     else if (bz < 2 * nshot)
-        march_p_body<2, N, CM, false, false, IMG, INJ>(g, q, m, cp, ab, -nshot, mga, src_cell, stf,
-                                                       nt, it, f.p, acc_i, BandArg{}, 0, ia);
+        march_p_body<2, N, CM, false, false, IMG, INJ, FS>(g, q, m, cp, ab, -nshot, mga, src_cell,
+                                                           stf, nt, it, f.p, acc_i, BandArg{}, 0, ia);
     else if (BAND)
         band_part(g, f, ba, 2 * nshot, 1, 1);
 }
@@ -1468,21 +1471,28 @@ hipError_t fwd_march_t(const StepCtx &c, int it) {
         zv = (int)gp.z;
         gp.z += band_planes(gp);
     }
-    if (c.ev) {
-        hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, c.ev[0], c.ev[1],
-                              0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex, svp, zp);
-        hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st,
-                              c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
-                              (const long long *)w.src_cell, c.stf, pl.g.nt, it,
-                              (const float *)nullptr, (float *)nullptr, svv, zv);
+    // F: a free surface, whose image rows the kernels write themselves
+    auto launch = [&](auto fs) -> hipError_t {
+        constexpr bool F = decltype(fs)::value;
+        if (c.ev) {
+            hipExtLaunchKernelGGL((k_march_v<ND, N, CM, ZL, F>), gv, L.block, 0, c.st, c.ev[0],
+                                  c.ev[1], 0, pl.geom, w.f, w.model, w.cpml, box, s0, L.mg, ex, svp,
+                                  zp);
+            hipExtLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false, F>), gp, L.block, 0, c.st,
+                                  c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
+                                  (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                                  (const float *)nullptr, (float *)nullptr, svv, zv);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL, F>), gv, L.block, 0, c.st, pl.geom, w.f,
+                           w.model, w.cpml, box, s0, L.mg, ex, svp, zp);
+        hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false, F>), gp, L.block, 0, c.st,
+                           pl.geom, w.f, w.model, w.cpml, box, 0, L.mg,
+                           (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                           (const float *)nullptr, (float *)nullptr, svv, zv);
         return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), gv, L.block, 0, c.st, pl.geom, w.f, w.model,
-                       w.cpml, box, s0, L.mg, ex, svp, zp);
-    hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, true, false>), gp, L.block, 0, c.st, pl.geom,
-                       w.f, w.model, w.cpml, box, 0, L.mg, (const long long *)w.src_cell, c.stf,
-                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr, svv, zv);
-    return hipGetLastError();
+    };
+    return pl.g.freesurf ? launch(std::true_type{}) : launch(std::false_type{});
 }
 
 // adjoint half steps with the marching kernels (image with the source field when asked)
@@ -1494,18 +1504,24 @@ hipError_t adj_march_t(const StepCtx &c, int it, bool image) {
     const int s0 = c.s0, s1 = shot_end(c);
     MLaunch L = march_launch(pl, pl.abox, it, s0, s1, CM, c.xcd, c.ymap);
     if (L.empty) return hipSuccess;
-    hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
-                       w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr}, BandArg{}, 0);
-    if (image)
-        hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true>), L.grid, L.block, 0, c.st, pl.geom,
-                           w.q, w.model, w.cpml, ab, 0, L.mg, (const long long *)w.src_cell,
-                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i, BandArg{}, 0);
-    else
-        hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, false>), L.grid, L.block, 0, c.st,
-                           pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
-                           (const long long *)w.src_cell, c.stf, pl.g.nt, it,
-                           (const float *)w.f.p, w.acc_i, BandArg{}, 0);
-    return hipGetLastError();
+    auto launch = [&](auto fs) -> hipError_t {
+        constexpr bool F = decltype(fs)::value;
+        hipLaunchKernelGGL((k_march_v<ND, N, CM, ZL, F>), L.grid, L.block, 0, c.st, pl.geom, w.q,
+                           w.model, w.cpml, ab, 0, L.mg, Ext{w.recv, nullptr, -1, nullptr},
+                           BandArg{}, 0);
+        if (image)
+            hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, true, F>), L.grid, L.block, 0, c.st,
+                               pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
+                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                               (const float *)w.f.p, w.acc_i, BandArg{}, 0);
+        else
+            hipLaunchKernelGGL((k_march_p<ND, N, CM, ZL, false, false, F>), L.grid, L.block, 0,
+                               c.st, pl.geom, w.q, w.model, w.cpml, ab, 0, L.mg,
+                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                               (const float *)w.f.p, w.acc_i, BandArg{}, 0);
+        return hipGetLastError();
+    };
+    return pl.g.freesurf ? launch(std::true_type{}) : launch(std::false_type{});
 }
 
 template <int ND, int N>
@@ -1599,32 +1615,43 @@ hipError_t rev_pair_t(const StepCtx &c, int it, bool grad, bool image, const flo
         grid.z += (unsigned)(((long long)ns * ba.nqb + per - 1) / per);
     }
     const dim3 block(64, 4, 1);
+    // F: a free surface, whose image rows the adjoint half steps write themselves
+    auto first = [&](auto fs) {
+        constexpr bool F = decltype(fs)::value;
 #define SMI_RPV(G_, L_, B_)                                                                    \
-    hipLaunchKernelGGL((k_rev_pv<N, CM, G_, L_, B_>), grid, block, 0, c.st, pl.geom, w.f, w.q,   \
+    hipLaunchKernelGGL((k_rev_pv<N, CM, G_, L_, B_, F>), grid, block, 0, c.st, pl.geom, w.f, w.q, \
                        w.model, w.cpml, rb, ab, LR.mg, LA.mg, ns,                               \
                        (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_g, w.acc_l, ba)
 #define SMI_RPV_B(G_, L_) do { if (band) SMI_RPV(G_, L_, true); else SMI_RPV(G_, L_, false); } while (0)
-    if (grad && image) SMI_RPV_B(true, true);
-    else if (grad) SMI_RPV_B(true, false);
-    else if (image) SMI_RPV_B(false, true);
-    else SMI_RPV_B(false, false);
+        if (grad && image) SMI_RPV_B(true, true);
+        else if (grad) SMI_RPV_B(true, false);
+        else if (image) SMI_RPV_B(false, true);
+        else SMI_RPV_B(false, false);
 #undef SMI_RPV_B
 #undef SMI_RPV
+    };
+    if (pl.g.freesurf) first(std::true_type{});
+    else first(std::false_type{});
     if (!band) SMI_TRY(band_restore(c, it, 2));      // interpolated levels: one launch of their own
     InjArg ia{};
     if (G) {
         ia = InjArg{w.injmap, pl.inj_zlo, pl.inj_nrow, pl.M[1], w.inj.off, w.inj.rec, w.inj.w,
                     w.recv.obase, w.recv.stride, G, it - 1, (float)(1.0 / pl.g.dt)};
     }
+    auto second = [&](auto fs) {
+        constexpr bool F = decltype(fs)::value;
 #define SMI_RVP(I_, B_, J_)                                                                    \
-    hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_, J_>), grid, block, 0, c.st, pl.geom, w.f, w.q,   \
+    hipLaunchKernelGGL((k_rev_vp<N, CM, I_, B_, J_, F>), grid, block, 0, c.st, pl.geom, w.f, w.q, \
                        w.model, w.cpml, rb, ab, LR.mg, LA.mg, ns,                               \
                        (const long long *)w.src_cell, c.stf, pl.g.nt, it, w.acc_i, ba, ia)
 #define SMI_RVP_J(I_, B_) do { if (G) SMI_RVP(I_, B_, true); else SMI_RVP(I_, B_, false); } while (0)
-    if (image) { if (band) SMI_RVP_J(true, true); else SMI_RVP_J(true, false); }
-    else { if (band) SMI_RVP_J(false, true); else SMI_RVP_J(false, false); }
+        if (image) { if (band) SMI_RVP_J(true, true); else SMI_RVP_J(true, false); }
+        else { if (band) SMI_RVP_J(false, true); else SMI_RVP_J(false, false); }
 #undef SMI_RVP_J
 #undef SMI_RVP
+    };
+    if (pl.g.freesurf) second(std::true_type{});
+    else second(std::false_type{});
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 // lane updates only its own cell, so the update stays in place, as for the other half-step
 // kernels.  Lanes and wavefronts outside the shot's box still load and stage their values:
 // they are the halo of the cells inside it.
+#include <type_traits>
 #include <hip/hip_ext.h>
 
 #include "smi_internal.hpp"
@@ -57,7 +58,7 @@ __device__ __forceinline__ int zhalo_row(int z0, int lane) {
     return lane < N ? z0 - N + lane : z0 + 64 + lane - N;
 }
 
-template <int N, int BX, int CY>
+template <int N, int BX, int CY, bool FS>
 __global__ __launch_bounds__(64 * BX) void k_y3_v(Geom g, Fields f, Model m, Cpml cp,
                                                   const int *__restrict__ box, int nstrip) {
     __shared__ float sp[BX + 2 * N][64 + 2 * N];   // p of the plane: [x - x0 + N][z - z0 + N]
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(64 * BX) void k_y3_v(Geom g, Fields f, Model m, Cpm
                 }
                 const float nv = cur.vo[a] - cur.bd[a] * e;
                 float *vd = f.v[a] + so + k;
-                if (a == 0 && g.fs) {
+                if (FS && a == 0) {
                     // free surface (image method): v_z on the rows nb - N .. nb - 1 mirrors the
                     // rows nb + N - 1 .. nb, written by the lanes of those rows
                     const int zr = t.z - g.nb;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(64 * BX) void k_y3_v(Geom g, Fields f, Model m, Cpm
     }
 }
 
-template <int N, int BX, int CY, bool SRC, bool IMG>
+template <int N, int BX, int CY, bool SRC, bool IMG, bool FS>
 __global__ __launch_bounds__(64 * BX) void k_y3_p(Geom g, Fields f, Model m, Cpml cp,
                                                   const int *__restrict__ box, int nstrip,
                                                   const long long *__restrict__ src_cell,
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(64 * BX) void k_y3_p(Geom g, Fields f, Model m, Cpm
             float pn = cur.po - cur.kd * sdiv;
             if (SRC && it < nt && k == sc) pn += src_amp(g.src_scale, stf[(long long)t.s * nt + it]);
             float *pd = f.p + so + k;
-            if (g.fs) {
+            if (FS) {
                 // free surface: p = 0 on row nb and odd about it, the rows nb - N .. nb - 1
                 // written by the lanes of rows nb + N .. nb + 1 (the image takes the updated value)
                 const int zr = t.z - g.nb;
@@ -295,21 +296,26 @@ hipError_t fwd_y3_t(const StepCtx &c, int it) {
     const int *box = w.fbox + (size_t)it * pl.nshot * 6;
     YLaunch L = y3_launch(pl, pl.fbox, it, BX, CY);
     if (L.empty) return hipSuccess;
-    if (c.ev) {
-        hipExtLaunchKernelGGL((k_y3_v<N, BX, CY>), L.grid, L.block, 0, c.st, c.ev[0], c.ev[1], 0,
-                              pl.geom, w.f, w.model, w.cpml, box, L.nstrip);
-        hipExtLaunchKernelGGL((k_y3_p<N, BX, CY, true, false>), L.grid, L.block, 0, c.st, c.ev[2],
-                              c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, L.nstrip,
-                              (const long long *)w.src_cell, c.stf, pl.g.nt, it,
-                              (const float *)nullptr, (float *)nullptr);
+    // F: a free surface, whose image rows the kernels write themselves
+    auto launch = [&](auto fs) -> hipError_t {
+        constexpr bool F = decltype(fs)::value;
+        if (c.ev) {
+            hipExtLaunchKernelGGL((k_y3_v<N, BX, CY, F>), L.grid, L.block, 0, c.st, c.ev[0],
+                                  c.ev[1], 0, pl.geom, w.f, w.model, w.cpml, box, L.nstrip);
+            hipExtLaunchKernelGGL((k_y3_p<N, BX, CY, true, false, F>), L.grid, L.block, 0, c.st,
+                                  c.ev[2], c.ev[3], 0, pl.geom, w.f, w.model, w.cpml, box, L.nstrip,
+                                  (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                                  (const float *)nullptr, (float *)nullptr);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL((k_y3_v<N, BX, CY, F>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
+                           w.cpml, box, L.nstrip);
+        hipLaunchKernelGGL((k_y3_p<N, BX, CY, true, false, F>), L.grid, L.block, 0, c.st, pl.geom,
+                           w.f, w.model, w.cpml, box, L.nstrip, (const long long *)w.src_cell,
+                           c.stf, pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
         return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_y3_v<N, BX, CY>), L.grid, L.block, 0, c.st, pl.geom, w.f, w.model,
-                       w.cpml, box, L.nstrip);
-    hipLaunchKernelGGL((k_y3_p<N, BX, CY, true, false>), L.grid, L.block, 0, c.st, pl.geom, w.f,
-                       w.model, w.cpml, box, L.nstrip, (const long long *)w.src_cell, c.stf,
-                       pl.g.nt, it, (const float *)nullptr, (float *)nullptr);
-    return hipGetLastError();
+    };
+    return pl.g.freesurf ? launch(std::true_type{}) : launch(std::false_type{});
 }
 
 template <int N, int BX, int CY>
@@ -319,17 +325,23 @@ hipError_t adj_y3_t(const StepCtx &c, int it, bool image) {
     const int *ab = w.abox + (size_t)it * pl.nshot * 6;
     YLaunch L = y3_launch(pl, pl.abox, it, BX, CY);
     if (L.empty) return hipSuccess;
-    hipLaunchKernelGGL((k_y3_v<N, BX, CY>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
-                       w.cpml, ab, L.nstrip);
-    if (image)
-        hipLaunchKernelGGL((k_y3_p<N, BX, CY, false, true>), L.grid, L.block, 0, c.st, pl.geom,
-                           w.q, w.model, w.cpml, ab, L.nstrip, (const long long *)w.src_cell,
-                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
-    else
-        hipLaunchKernelGGL((k_y3_p<N, BX, CY, false, false>), L.grid, L.block, 0, c.st, pl.geom,
-                           w.q, w.model, w.cpml, ab, L.nstrip, (const long long *)w.src_cell,
-                           c.stf, pl.g.nt, it, (const float *)w.f.p, w.acc_i);
-    return hipGetLastError();
+    auto launch = [&](auto fs) -> hipError_t {
+        constexpr bool F = decltype(fs)::value;
+        hipLaunchKernelGGL((k_y3_v<N, BX, CY, F>), L.grid, L.block, 0, c.st, pl.geom, w.q, w.model,
+                           w.cpml, ab, L.nstrip);
+        if (image)
+            hipLaunchKernelGGL((k_y3_p<N, BX, CY, false, true, F>), L.grid, L.block, 0, c.st,
+                               pl.geom, w.q, w.model, w.cpml, ab, L.nstrip,
+                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                               (const float *)w.f.p, w.acc_i);
+        else
+            hipLaunchKernelGGL((k_y3_p<N, BX, CY, false, false, F>), L.grid, L.block, 0, c.st,
+                               pl.geom, w.q, w.model, w.cpml, ab, L.nstrip,
+                               (const long long *)w.src_cell, c.stf, pl.g.nt, it,
+                               (const float *)w.f.p, w.acc_i);
+        return hipGetLastError();
+    };
+    return pl.g.freesurf ? launch(std::true_type{}) : launch(std::false_type{});
 }
 
 // tiles: y3 = 100 BX + CY with BX in {4, 8} and CY in {16, 32, 64}; others fall back to 832
