@@ -535,6 +535,11 @@ smi_status make_plan(const smi_grid *g, const smi_acq *acq, smi_job job, double 
         }
     }
     bd.B = off;
+    if (bd.B >= (1LL << 31)) {
+        // the band kernels index the cells of one shot's band with 32-bit integers
+        err = "the saved boundary band of one shot exceeds 2^31 cells";
+        return SMI_E_UNSUPPORTED;
+    }
 
 
     // device geometry

@@ -30,11 +30,13 @@ __device__ __forceinline__ void band_cell(const Geom &g, const Fields &f, const 
     while (b + 1 < bd.nblk && q >= bd.blk[b + 1].off) ++b;
     const BandBlock &bl = bd.blk[b];
     if (which != 2 && bl.field != which) return;
-    long long r = q - bl.off;
-    int z = bl.org[0] + (int)(r % bl.ext[0]);
-    r /= bl.ext[0];
-    int x = bl.org[1] + (int)(r % bl.ext[1]);
-    int y = bl.org[2] + (int)(r / bl.ext[1]);
+    // 32-bit unsigned index arithmetic (a shot's band holds fewer than 2^31 cells; 64-bit
+    // division is emulated and dominated these kernels)
+    const unsigned r0 = (unsigned)(q - bl.off), e0 = (unsigned)bl.ext[0], e1 = (unsigned)bl.ext[1];
+    const unsigned r1 = r0 / e0;
+    int z = bl.org[0] + (int)(r0 - r1 * e0);
+    int x = bl.org[1] + (int)(r1 % e1);
+    int y = bl.org[2] + (int)(r1 / e1);
     long long k = g.org + z + (long long)g.ld1 * x + g.ld2 * y;
     // constant indices only: a dynamic index into the Fields of a reference would place a
     // copy of it in LDS
