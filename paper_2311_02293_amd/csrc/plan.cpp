@@ -299,11 +299,16 @@ std::vector<int> fwd_groups(const Plan &pl, double budget, int max_per) {
     auto bytes = [&](double cells) {
         return 4.0 * ((pl.nd + 1) * cells + 2.0 * psi_cells(pl, cells));
     };
-    // cum[it (ns + 1) + s]: box cells of the shots [0, s) at step it
-    std::vector<double> cum((size_t)nrun * (ns + 1), 0.0);
+    // cum[k (ns + 1) + s]: box cells of the shots [0, s) at step k * stride (the last sample
+    // at the last step, where the boxes are largest); the steps are strided so that the table
+    // stays within about 4 M entries (the boxes grow smoothly)
+    const int stride = (int)std::max<long long>(1, (long long)nrun * (ns + 1) / (4LL << 20));
+    const int nk = (nrun + stride - 1) / stride;
+    std::vector<double> cum((size_t)nk * (ns + 1), 0.0);
     bool spill = false;
-    for (int it = 0; it < nrun; ++it) {
-        double *c = &cum[(size_t)it * (ns + 1)];
+    for (int kk = 0; kk < nk; ++kk) {
+        const int it = kk == nk - 1 ? nrun - 1 : kk * stride;
+        double *c = &cum[(size_t)kk * (ns + 1)];
         for (int s = 0; s < ns; ++s) c[s + 1] = c[s] + box_volume(&pl.fbox[((size_t)it * ns + s) * 6]);
         spill = spill || bytes(c[ns]) > budget;
     }
@@ -321,8 +326,8 @@ std::vector<int> fwd_groups(const Plan &pl, double budget, int max_per) {
         std::vector<int> off(ng + 1);
         for (int k = 0; k <= ng; ++k) off[k] = (int)((long long)ns * k / ng);
         double cost = 0;
-        for (int it = 0; it < nrun; ++it) {
-            const double *c = &cum[(size_t)it * (ns + 1)];
+        for (int kk = 0; kk < nk; ++kk) {
+            const double *c = &cum[(size_t)kk * (ns + 1)];
             for (int k = 0; k < ng; ++k) {
                 const double cells = c[off[k + 1]] - c[off[k]];
                 if (cells > 0) cost += kLaunches + cells * (bytes(cells) > budget ? kMiss : kHit);
